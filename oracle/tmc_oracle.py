@@ -1,0 +1,294 @@
+"""FP64 CPU oracle for the Tensor Monte Carlo (TMC) chain estimator.
+
+TEST INFRASTRUCTURE ONLY.  The library never imports, calls, links or executes
+anything here; only the test-suite, the smoke check and the benchmark's
+CPU-baseline leg do.  It shares no code, constants or helpers with the HIP path.
+
+Paper: L. Aitchison, "Tensor Monte Carlo: Particle Methods for the GPU Era",
+arXiv 1806.08593.  Every function names the passage it follows.
+
+Conventions (0-based layers, layer 0 is adjacent to the data x, layer L-1 is the
+top of the chain):
+    z[l]  [K_l, D_l]      samples of layer l
+    mu[l] [K_{l+1}, D_l]  mean of z_l given sample j of its parent z_{l+1}
+    s[l]  [D_l]           log std of P(z_l | z_{l+1}), shared by all parent samples
+    u[l]  [K_l]           unary log-terms (-log Q(z_l), log-likelihood on layer 0,
+                          log-prior on the top layer)
+    f[l]  [K_l, K_{l+1}]  pairwise log-factor log P(z_l^i | z_{l+1}^j)
+
+Parity pins (tests/test_oracle_*.py) tie each function to something outside
+itself: brute-force enumeration of eq. (is), the IWAE and VAE special cases, the
+exact discrete marginalisation of the Appendix (an HMM evaluated in probability
+space), closed-form linear-Gaussian evidence, scipy's normal log-density,
+finite differences and exact invariants.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from typing import List, Sequence
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# small helpers (kept separate so tests can plant mistakes in them)
+# ---------------------------------------------------------------------------
+
+HALF_LOG_2PI = 0.5 * math.log(2.0 * math.pi)
+
+
+def log_k(K: int) -> float:
+    """ln K_l: the 1/K_l of eq. (is), paid once per latent layer."""
+    return math.log(K)
+
+
+def logsumexp(a: np.ndarray, axis: int) -> np.ndarray:
+    """log sum exp along `axis`, shifted by the exact maximum (the Appendix's
+    numerically stable log-domain product, with x_i = max_j X_ij).  A slice that is
+    all -inf gives -inf (never NaN); NaN propagates."""
+    a = np.asarray(a, dtype=np.float64)
+    m = np.max(a, axis=axis, keepdims=True)
+    m_safe = np.where(np.isfinite(m), m, 0.0)
+    with np.errstate(divide="ignore"):
+        out = np.log(np.sum(np.exp(a - m_safe), axis=axis, keepdims=True)) + m_safe
+    return np.squeeze(out, axis=axis)
+
+
+# ---------------------------------------------------------------------------
+# factors (eq. (fac), Appendix "typical choice of factors", Gaussian conditional
+# of Sec. "Computational costs for TMC and IWAE")
+# ---------------------------------------------------------------------------
+
+def gauss_pair_logfactor(z: np.ndarray, mu: np.ndarray, s: np.ndarray,
+                         chunk: int = 256) -> np.ndarray:
+    """f[i, j] = log N(z^i ; mu^j, diag exp(2 s)), written out by direct difference:
+        sum_d [ -1/2 exp(-2 s_d) (z_id - mu_jd)^2 - s_d - 1/2 log 2 pi ].
+    This is the latent factor P(z_l | z_{l+1}) of the chain model; the 1/Q(z_l) part
+    of the Appendix's factor is a row term and is carried in u[l]."""
+    z = np.asarray(z, np.float64)
+    mu = np.asarray(mu, np.float64)
+    s = np.asarray(s, np.float64)
+    lam = np.exp(-2.0 * s)
+    const = -np.sum(s) - z.shape[1] * HALF_LOG_2PI
+    out = np.empty((z.shape[0], mu.shape[0]))
+    for i0 in range(0, z.shape[0], chunk):
+        diff = z[i0:i0 + chunk, None, :] - mu[None, :, :]
+        out[i0:i0 + chunk] = -0.5 * np.sum(lam * diff * diff, axis=-1) + const
+    return out
+
+
+def gauss_chain_factors(z: Sequence[np.ndarray], mu: Sequence[np.ndarray],
+                        s: Sequence[np.ndarray]) -> List[np.ndarray]:
+    return [gauss_pair_logfactor(z[l], mu[l], s[l]) for l in range(len(mu))]
+
+
+# ---------------------------------------------------------------------------
+# the estimator (eq. (is)) and its chain evaluation (Sec. "Efficient averaging")
+# ---------------------------------------------------------------------------
+
+def brute_force_logp(f: Sequence[np.ndarray], u: Sequence[np.ndarray]) -> float:
+    """eq. (is) written out: log of the average, over every tuple (k_0..k_{L-1}), of
+    exp(sum_l u_l[k_l] + sum_l f_l[k_l, k_{l+1}]).  Exponential in L: tiny chains only."""
+    L = len(u)
+    K = [len(a) for a in u]
+    terms = []
+    for ks in itertools.product(*[range(k) for k in K]):
+        t = sum(u[l][ks[l]] for l in range(L))
+        t += sum(f[l][ks[l], ks[l + 1]] for l in range(L - 1))
+        terms.append(t)
+    return float(logsumexp(np.array(terms), axis=0) - sum(log_k(k) for k in K))
+
+
+def chain_messages(f: Sequence[np.ndarray], u: Sequence[np.ndarray]):
+    """Sum the indices out one at a time, from the top of the chain down (the
+    sum/product swap of Sec. "Efficient averaging", each step a log-domain
+    matrix-vector product as in the Appendix):
+        alpha_{L-1} = u_{L-1}
+        alpha_l[i]  = u_l[i] + logsumexp_j(f_l[i, j] + alpha_{l+1}[j]) - ln K_{l+1}
+        log P_TMC   = logsumexp_i(alpha_0[i]) - ln K_0
+    Returns (log P_TMC, [alpha_0 .. alpha_{L-1}])."""
+    L = len(u)
+    alpha = [None] * L
+    alpha[L - 1] = np.asarray(u[L - 1], np.float64)
+    for l in range(L - 2, -1, -1):
+        K_up = len(u[l + 1])
+        alpha[l] = u[l] + logsumexp(f[l] + alpha[l + 1][None, :], axis=1) - log_k(K_up)
+    logp = float(logsumexp(alpha[0], axis=0) - log_k(len(u[0])))
+    return logp, alpha
+
+
+def chain_logp(f: Sequence[np.ndarray], u: Sequence[np.ndarray]) -> float:
+    return chain_messages(f, u)[0]
+
+
+def chain_marginals(f: Sequence[np.ndarray], u: Sequence[np.ndarray]):
+    """Derivatives of log P_TMC with respect to the log-factors and unaries.
+
+    log P_TMC is a log-sum-exp over index tuples, so d log P / d f_l[i, j] is the
+    weight of all tuples with k_l = i, k_{l+1} = j (a pairwise marginal over sample
+    indices), and d log P / d u_l[k] the weight of tuples with k_l = k.  These follow
+    from bottom-up messages
+        beta_0 = -ln K_0
+        beta_{l+1}[j] = logsumexp_i(beta_l[i] + u_l[i] + f_l[i, j]) - ln K_{l+1}
+    combined with the top-down alpha:
+        G_l[i, j] = exp(beta_l[i] + u_l[i] + f_l[i, j] + alpha_{l+1}[j] - ln K_{l+1} - log P)
+        p_l[k]    = exp(beta_l[k] + alpha_l[k] - log P).
+    Returns (log P, G list, p list)."""
+    L = len(u)
+    logp, alpha = chain_messages(f, u)
+    beta = [None] * L
+    beta[0] = np.full(len(u[0]), -log_k(len(u[0])))
+    for l in range(L - 1):
+        beta[l + 1] = (logsumexp((beta[l] + u[l])[:, None] + f[l], axis=0)
+                       - log_k(len(u[l + 1])))
+    G = []
+    for l in range(L - 1):
+        e = ((beta[l] + u[l])[:, None] + f[l] + alpha[l + 1][None, :]
+             - log_k(len(u[l + 1])) - logp)
+        G.append(np.exp(e))
+    p = [np.exp(beta[l] + alpha[l] - logp) for l in range(L)]
+    return logp, G, p
+
+
+# ---------------------------------------------------------------------------
+# Gaussian chain: value and gradients
+# ---------------------------------------------------------------------------
+
+def gauss_chain_logp(z, mu, s, u) -> float:
+    return chain_logp(gauss_chain_factors(z, mu, s), u)
+
+
+def gauss_chain_grads(z, mu, s, u, chunk: int = 128):
+    """log P_TMC and its gradients with respect to z, mu, s and u for the Gaussian
+    chain (the reparameterised-gradient objective of Sec. "Efficient averaging",
+    obtained there by automatic differentiation).  By the chain rule through the
+    factors, with G the pairwise marginals of `chain_marginals` and lam = exp(-2 s):
+        dz_l[i]  = sum_j G_l[i,j] * (-lam * (z_l[i] - mu_l[j]))
+        dmu_l[j] = sum_i G_l[i,j] * ( lam * (z_l[i] - mu_l[j]))
+        ds_l     = sum_ij G_l[i,j] * ( lam * (z_l[i] - mu_l[j])^2 - 1 )
+        du_l     = p_l
+    The top layer's samples enter only through mu and u, so dz of layer L-1 is 0.
+    Returns (log P, dz list, dmu list, ds list, du list)."""
+    f = gauss_chain_factors(z, mu, s)
+    logp, G, p = chain_marginals(f, u)
+    L = len(u)
+    dz = [np.zeros_like(np.asarray(a, np.float64)) for a in z]
+    dmu, ds = [], []
+    for l in range(L - 1):
+        lam = np.exp(-2.0 * np.asarray(s[l], np.float64))
+        zl = np.asarray(z[l], np.float64)
+        ml = np.asarray(mu[l], np.float64)
+        gmu = np.zeros_like(ml)
+        gs = np.zeros_like(lam)
+        for i0 in range(0, zl.shape[0], chunk):
+            diff = zl[i0:i0 + chunk, None, :] - ml[None, :, :]       # [i, j, d]
+            g = G[l][i0:i0 + chunk, :, None]
+            dz[l][i0:i0 + chunk] = np.sum(g * (-lam * diff), axis=1)
+            gmu += np.sum(g * (lam * diff), axis=0)
+            gs += np.sum(g * (lam * diff * diff - 1.0), axis=(0, 1))
+        dmu.append(gmu)
+        ds.append(gs)
+    return logp, dz, dmu, ds, [np.asarray(a) for a in p]
+
+
+def finite_difference(fun, x: np.ndarray, h: float = 1e-5, idx=None) -> np.ndarray:
+    """Central differences (fun(x + h e) - fun(x - h e)) / 2h at the flat indices
+    `idx` (all entries when None)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    flat = x.reshape(-1)
+    idx = range(flat.size) if idx is None else idx
+    out = []
+    for k in idx:
+        old = flat[k]
+        flat[k] = old + h
+        fp = fun(x)
+        flat[k] = old - h
+        fm = fun(x)
+        flat[k] = old
+        out.append((fp - fm) / (2.0 * h))
+    return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# special cases and closed forms used as pins
+# ---------------------------------------------------------------------------
+
+def iwae_logp(u0: np.ndarray) -> float:
+    """The IWAE estimator of Sec. "Background" in log form: log (1/K) sum_k w_k with
+    log w_k = u0[k]; equal to TMC with a single latent."""
+    return float(logsumexp(np.asarray(u0, np.float64), axis=0) - log_k(len(u0)))
+
+
+def linear_gauss_marginal_covs(W: Sequence[np.ndarray], sigma_z: float,
+                               top_dim: int) -> List[np.ndarray]:
+    """Prior marginal covariances of the linear-Gaussian chain
+    z_{L-1} ~ N(0, I), z_l = W_l z_{l+1} + N(0, sigma_z^2 I)."""
+    L = len(W) + 1
+    cov = [None] * L
+    cov[L - 1] = np.eye(top_dim)
+    for l in range(L - 2, -1, -1):
+        cov[l] = W[l] @ cov[l + 1] @ W[l].T + sigma_z ** 2 * np.eye(W[l].shape[0])
+    return cov
+
+
+def linear_gauss_log_evidence(W, Wx, x, sigma_z: float, sigma_x: float) -> float:
+    """Closed-form log P(x) for the linear-Gaussian chain: x is Gaussian with mean 0
+    and covariance Wx Sigma_0 Wx^T + sigma_x^2 I (all variables jointly Gaussian, as in
+    the paper's toy experiments)."""
+    from scipy.stats import multivariate_normal
+    top = W[-1].shape[1] if len(W) else Wx.shape[1]
+    S0 = linear_gauss_marginal_covs(W, sigma_z, top)[0]
+    C = Wx @ S0 @ Wx.T + sigma_x ** 2 * np.eye(Wx.shape[0])
+    return float(multivariate_normal(mean=np.zeros(len(x)), cov=C).logpdf(x))
+
+
+def linear_gauss_joint_cov(W, Wx, sigma_z, sigma_x):
+    """Joint covariance of (z_0, ..., z_{L-1}, x) for the linear-Gaussian chain; each
+    variable is a linear map of independent standard normals."""
+    L = len(W) + 1
+    D = [W[l].shape[0] for l in range(L - 1)] + [W[-1].shape[1]]
+    dx = Wx.shape[0]
+    # noise blocks: eps_top (D_{L-1}), eps_l (D_l) for l < L-1, eps_x (dx)
+    n_noise = sum(D) + dx
+    A = [None] * L
+    off = {}
+    o = 0
+    for l in range(L):
+        off[l] = o
+        o += D[l]
+    A[L - 1] = np.zeros((D[L - 1], n_noise))
+    A[L - 1][:, off[L - 1]:off[L - 1] + D[L - 1]] = np.eye(D[L - 1])
+    for l in range(L - 2, -1, -1):
+        A[l] = W[l] @ A[l + 1]
+        A[l][:, off[l]:off[l] + D[l]] += sigma_z * np.eye(D[l])
+    Ax = Wx @ A[0]
+    Ax[:, o:o + dx] += sigma_x * np.eye(dx)
+    M = np.vstack(A + [Ax])
+    return M @ M.T, D
+
+
+def linear_gauss_posterior_marginals(W, Wx, x, sigma_z, sigma_x):
+    """Exact posterior P(z_l | x) of every layer (Gaussian conditioning on the joint);
+    returns per-layer (mean, full covariance)."""
+    C, D = linear_gauss_joint_cov(W, Wx, sigma_z, sigma_x)
+    nz = sum(D)
+    Czz, Czx, Cxx = C[:nz, :nz], C[:nz, nz:], C[nz:, nz:]
+    K = np.linalg.solve(Cxx, Czx.T).T
+    m = K @ x
+    P = Czz - K @ Czx.T
+    out, o = [], 0
+    for d in D:
+        out.append((m[o:o + d], P[o:o + d, o:o + d]))
+        o += d
+    return out
+
+
+def hmm_log_evidence(prior_top: np.ndarray, trans: Sequence[np.ndarray],
+                     emit_logp0: np.ndarray) -> float:
+    """Exact log P(x) of a discrete chain by products of probability matrices (no
+    logs inside): v_{L-1} = prior; v_l = T_l v_{l+1}; P(x) = sum_k P(x | state k of
+    layer 0) v_0[k].  trans[l][i, j] = P(z_l = i | z_{l+1} = j)."""
+    v = np.asarray(prior_top, np.float64)
+    for T in reversed(list(trans)):
+        v = T @ v
+    return float(np.log(np.dot(np.exp(emit_logp0), v)))

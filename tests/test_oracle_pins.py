@@ -1,0 +1,312 @@
+"""Pins for the FP64 oracle: each check ties an oracle function to something other
+than itself (a library routine, enumeration of the paper's eq. (is), a special case
+with a textbook answer, a closed form, finite differences or an exact invariant)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+from oracle import tmc_oracle as O
+from workloads import make, linear_gauss
+
+
+def _rand_chain(rng, K, D, scale=1.0):
+    L = len(K)
+    z = [rng.normal(size=(K[l], D[l])) for l in range(L)]
+    mu = [rng.normal(size=(K[l + 1], D[l])) * scale for l in range(L - 1)]
+    s = [rng.uniform(-1.0, 0.0, size=D[l]) for l in range(L - 1)]
+    u = [rng.normal(size=K[l]) * 3.0 for l in range(L)]
+    return z, mu, s, u
+
+
+# --- logsumexp ----------------------------------------------------------------
+
+def test_logsumexp_matches_scipy_and_handles_inf():
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=(7, 13)) * 300.0
+    for ax in (0, 1):
+        np.testing.assert_allclose(O.logsumexp(a, ax), special.logsumexp(a, axis=ax), rtol=1e-14)
+    b = np.array([[-np.inf, -np.inf], [0.0, -np.inf], [np.nan, 1.0]])
+    out = O.logsumexp(b, 1)
+    assert out[0] == -np.inf and out[1] == 0.0 and np.isnan(out[2])
+
+
+# --- factor (T10) ----------------------------------------------------------------
+
+def test_gauss_factor_equals_scipy_normal_logpdf():
+    rng = np.random.default_rng(1)
+    z = rng.normal(size=(5, 7))
+    mu = rng.normal(size=(6, 7))
+    s = rng.uniform(-1.5, 0.5, size=7)
+    f = O.gauss_pair_logfactor(z, mu, s, chunk=2)
+    ref = np.array([[stats.norm.logpdf(z[i], loc=mu[j], scale=np.exp(s)).sum()
+                     for j in range(6)] for i in range(5)])
+    np.testing.assert_allclose(f, ref, rtol=1e-13, atol=1e-12)
+
+
+# --- chain recursion vs enumeration of eq. (is) (T1) ------------------------------
+
+@pytest.mark.parametrize("K", [(8, 8, 8, 8), (3, 5, 2, 4), (1, 6, 3), (4, 1, 5, 2, 3)])
+def test_chain_recursion_equals_brute_force(K):
+    rng = np.random.default_rng(sum(K))
+    D = [3] * len(K)
+    z, mu, s, u = _rand_chain(rng, K, D)
+    f = O.gauss_chain_factors(z, mu, s)
+    assert abs(O.chain_logp(f, u) - O.brute_force_logp(f, u)) < 1e-10
+
+
+def test_c1_recursion_equals_brute_force():
+    w = make("c1", B=4)
+    for c in w.chains:
+        f = O.gauss_chain_factors(c.z, c.mu, c.s)
+        a, b = O.chain_logp(f, c.u), O.brute_force_logp(f, c.u)
+        assert abs(a - b) <= 1e-12 * max(1.0, abs(b))
+
+
+def test_brute_force_small_probability_space():
+    """Enumeration checked in probability space with plain Python products."""
+    rng = np.random.default_rng(3)
+    K = (2, 3, 2)
+    u = [rng.normal(size=k) for k in K]
+    f = [rng.normal(size=(K[0], K[1])), rng.normal(size=(K[1], K[2]))]
+    tot = 0.0
+    for a in range(2):
+        for b in range(3):
+            for c in range(2):
+                tot += (math.exp(u[0][a]) * math.exp(u[1][b]) * math.exp(u[2][c])
+                        * math.exp(f[0][a, b]) * math.exp(f[1][b, c]))
+    assert abs(O.brute_force_logp(f, u) - math.log(tot / 12.0)) < 1e-13
+
+
+# --- special cases (T3, T4) ------------------------------------------------------
+
+def test_single_layer_is_iwae():
+    rng = np.random.default_rng(4)
+    u0 = rng.normal(size=37) * 50.0
+    ref = special.logsumexp(u0) - math.log(37)
+    assert abs(O.chain_logp([], [u0]) - ref) < 1e-12
+    assert abs(O.iwae_logp(u0) - ref) < 1e-12
+
+
+def test_one_sample_per_layer_is_vae():
+    rng = np.random.default_rng(5)
+    K = (1, 1, 1, 1)
+    z, mu, s, u = _rand_chain(rng, K, (4, 4, 4, 4))
+    f = O.gauss_chain_factors(z, mu, s)
+    ref = sum(a[0] for a in u) + sum(a[0, 0] for a in f)
+    assert abs(O.chain_logp(f, u) - ref) < 1e-12
+
+
+# --- exact discrete marginalisation (T2) -----------------------------------------
+
+def _random_hmm(rng, S):
+    L = len(S)
+    prior = rng.dirichlet(np.ones(S[-1]))
+    trans = []
+    for l in range(L - 1):
+        T = rng.dirichlet(np.ones(S[l]), size=S[l + 1]).T      # columns sum to 1
+        trans.append(T)
+    emit = np.log(rng.dirichlet(np.ones(5), size=S[0])[:, 2])  # P(x = 2 | state)
+    return prior, trans, emit
+
+
+def test_hmm_evidence_by_enumeration():
+    rng = np.random.default_rng(6)
+    S = (3, 4, 2)
+    prior, trans, emit = _random_hmm(rng, S)
+    tot = 0.0
+    for a, b, c in itertools.product(range(3), range(4), range(2)):
+        tot += prior[c] * trans[1][b, c] * trans[0][a, b] * math.exp(emit[a])
+    assert abs(O.hmm_log_evidence(prior, trans, emit) - math.log(tot)) < 1e-13
+
+
+@pytest.mark.parametrize("S", [(3, 4, 2), (5, 5, 5, 5, 5), (2, 7, 3, 6)])
+def test_tmc_on_discrete_chain_is_exact_marginal(S):
+    """Appendix, exact marginalisation: K_l = number of states, z_l^k = k, uniform
+    proposal Q = 1/K_l  =>  the TMC estimate is exactly log P(x)."""
+    rng = np.random.default_rng(len(S) * 10 + S[0])
+    prior, trans, emit = _random_hmm(rng, S)
+    L = len(S)
+    f = [np.log(trans[l]) for l in range(L - 1)]
+    u = [np.full(S[l], math.log(S[l])) for l in range(L)]   # -log Q = log K_l
+    u[0] = u[0] + emit
+    u[L - 1] = u[L - 1] + np.log(prior)
+    assert abs(O.chain_logp(f, u) - O.hmm_log_evidence(prior, trans, emit)) < 1e-12
+
+
+# --- closed forms (pins for the linear-Gaussian helpers) -------------------------
+
+def test_linear_gauss_evidence_against_quadrature():
+    # one latent: z ~ N(0,1), x | z ~ N(w z, sx^2)
+    w, sx, x = 1.7, 0.6, 0.9
+    ref = integrate.quad(lambda z: stats.norm.pdf(x, w * z, sx) * stats.norm.pdf(z), -12, 12,
+                         epsabs=1e-14)[0]
+    got = O.linear_gauss_log_evidence([], np.array([[w]]), np.array([x]), 0.5, sx)
+    assert abs(got - math.log(ref)) < 1e-10
+    # two latents: z1 ~ N(0,1), z0 | z1 ~ N(a z1, sz^2), x | z0 ~ N(w z0, sx^2)
+    a, sz = -0.8, 0.5
+    ref2 = integrate.dblquad(
+        lambda z0, z1: stats.norm.pdf(x, w * z0, sx) * stats.norm.pdf(z0, a * z1, sz)
+        * stats.norm.pdf(z1), -10, 10, -10, 10, epsabs=1e-13)[0]
+    got2 = O.linear_gauss_log_evidence([np.array([[a]])], np.array([[w]]), np.array([x]), sz, sx)
+    assert abs(got2 - math.log(ref2)) < 1e-8
+
+
+def test_linear_gauss_posterior_bayes_identity():
+    """log P(x) = log P(x|z) + log P(z) - log P(z|x) at any z, with the joint prior of
+    all layers and the oracle's exact posterior."""
+    w = linear_gauss(B=1, L=3, K=2, D=3, x_dim=4)
+    W, Wx, x = w.extra["W"], w.extra["Wx"], w.extra["x"][0]
+    sz, sx = 0.5, 0.3
+    post = O.linear_gauss_posterior_marginals(W, Wx, x, sz, sx)
+    C, D = O.linear_gauss_joint_cov(W, Wx, sz, sx)
+    nz = sum(D)
+    Czz, Czx, Cxx = C[:nz, :nz], C[:nz, nz:], C[nz:, nz:]
+    mpost = np.concatenate([m for m, _ in post])
+    Ppost = Czz - Czx @ np.linalg.solve(Cxx, Czx.T)
+    rng = np.random.default_rng(7)
+    zz = rng.normal(size=nz)
+    z0 = zz[:D[0]]
+    lx = stats.multivariate_normal(Wx @ z0, sx ** 2 * np.eye(len(x))).logpdf(x)
+    lz = stats.multivariate_normal(np.zeros(nz), Czz).logpdf(zz)
+    lpost = stats.multivariate_normal(mpost, Ppost).logpdf(zz)
+    ev = O.linear_gauss_log_evidence(W, Wx, x, sz, sx)
+    assert abs(ev - (lx + lz - lpost)) < 1e-9
+    # marginal blocks are the diagonal blocks of the full posterior
+    o = 0
+    for (m, P), d in zip(post, D):
+        np.testing.assert_allclose(P, Ppost[o:o + d, o:o + d], atol=1e-12)
+        o += d
+
+
+# --- whole-estimator pins (T6, T5, T7) -------------------------------------------
+
+def test_zero_variance_gives_exact_evidence():
+    """W_l = 0 above layer 0 and Q(z_0) = P(z_0 | x), Q(z_l) = P(z_l): every
+    importance ratio equals P(x), so log P_TMC = log P(x) whatever the samples."""
+    rng = np.random.default_rng(8)
+    L, D, K, dx, sz, sx = 4, 3, 6, 5, 0.5, 0.3
+    W = [np.zeros((D, D)) for _ in range(L - 1)]
+    Wx = rng.normal(size=(dx, D)) / math.sqrt(D)
+    x = rng.normal(size=dx)
+    post = O.linear_gauss_posterior_marginals(W, Wx, x, sz, sx)
+    m0, P0 = post[0]
+    z = [rng.multivariate_normal(m0, P0, size=K)]
+    z += [rng.normal(size=(K, D)) * sz for _ in range(L - 2)] + [rng.normal(size=(K, D))]
+    mu = [z[l + 1] @ W[l].T for l in range(L - 1)]
+    s = [np.full(D, math.log(sz)) for _ in range(L - 1)]
+    u = [None] * L
+    u[0] = (stats.multivariate_normal(np.zeros(dx), sx ** 2 * np.eye(dx)).logpdf(x - z[0] @ Wx.T)
+            - stats.multivariate_normal(m0, P0).logpdf(z[0]))
+    for l in range(1, L - 1):
+        u[l] = -stats.norm.logpdf(z[l], 0.0, sz).sum(-1)
+    u[L - 1] = np.zeros(K)       # Q(z_top) = P(z_top): prior and proposal cancel
+    got = O.gauss_chain_logp(z, mu, s, u)
+    assert abs(got - O.linear_gauss_log_evidence(W, Wx, x, sz, sx)) < 1e-10
+
+
+def _posterior_marginal_proposal(W, Wx, sz, sx, widen=1.0):
+    def prop(b, x):
+        post = O.linear_gauss_posterior_marginals(W, Wx, x, sz, sx)
+        qm = np.stack([m for m, _ in post])
+        qs = np.stack([np.sqrt(np.diag(P)) * widen for _, P in post])
+        return qm, qs
+    return prop
+
+
+def _tmc_ratio_samples(n, K, seed=11):
+    base = linear_gauss(B=1, L=4, K=K, D=8, x_dim=32, seed=seed)
+    W, Wx = base.extra["W"], base.extra["Wx"]
+    w = linear_gauss(B=n, L=4, K=K, D=8, x_dim=32, seed=seed,
+                     proposal=_posterior_marginal_proposal(W, Wx, 0.5, 0.3))
+    out = []
+    for b, c in enumerate(w.chains):
+        ev = O.linear_gauss_log_evidence(W, Wx, w.extra["x"][b], 0.5, 0.3)
+        out.append(O.gauss_chain_logp(c.z, c.mu, c.s, c.u) - ev)
+    return np.array(out)
+
+
+@pytest.mark.slow
+def test_unbiased_against_closed_form_evidence():
+    """E_Q[exp(log P_TMC)] = P(x) (eq. (is) averages unbiased single-tuple estimates).
+    Checked on the linear-Gaussian chain with posterior-marginal proposals, K=64,
+    4000 replicates: the mean ratio exp(log P_TMC - log P(x)) must lie within 4
+    bootstrap standard errors of 1."""
+    d = _tmc_ratio_samples(4000, 64)
+    r = np.exp(d)
+    rng = np.random.default_rng(12)
+    boots = np.array([r[rng.integers(0, len(r), len(r))].mean() for _ in range(400)])
+    se = boots.std()
+    assert abs(r.mean() - 1.0) < 4.0 * se, (r.mean(), se)
+    assert se < 0.1
+
+
+def test_jensen_bound_and_tightening_with_K():
+    """log P(x) >= E[log P_TMC] (Sec. "Background"); the gap shrinks as K grows."""
+    gaps = [np.mean(_tmc_ratio_samples(300, K, seed=13)) for K in (1, 4, 16)]
+    assert all(g < 0 for g in gaps)
+    assert gaps[0] < gaps[1] < gaps[2]
+
+
+# --- gradients (T8, T9) ----------------------------------------------------------
+
+def test_marginals_are_factor_derivatives():
+    rng = np.random.default_rng(14)
+    K = (3, 4, 2)
+    f = [rng.normal(size=(3, 4)) * 2, rng.normal(size=(4, 2)) * 2]
+    u = [rng.normal(size=k) for k in K]
+    logp, G, p = O.chain_marginals(f, u)
+    for l in range(2):
+        fd = O.finite_difference(lambda a: O.chain_logp([a if m == l else f[m] for m in range(2)], u),
+                                 f[l], h=1e-6)
+        np.testing.assert_allclose(G[l].reshape(-1), fd, atol=1e-8)
+    for l in range(3):
+        fd = O.finite_difference(lambda a: O.chain_logp(f, [a if m == l else u[m] for m in range(3)]),
+                                 u[l], h=1e-6)
+        np.testing.assert_allclose(p[l], fd, atol=1e-8)
+
+
+def test_marginal_invariants():
+    rng = np.random.default_rng(15)
+    K = (5, 7, 4, 6)
+    z, mu, s, u = _rand_chain(rng, K, (3, 3, 3, 3))
+    f = O.gauss_chain_factors(z, mu, s)
+    logp, G, p = O.chain_marginals(f, u)
+    for l in range(3):
+        assert abs(G[l].sum() - 1.0) < 1e-12
+        np.testing.assert_allclose(G[l].sum(1), p[l], atol=1e-13)
+        np.testing.assert_allclose(G[l].sum(0), p[l + 1], atol=1e-13)
+    # permutation of one layer's samples leaves log P unchanged
+    perm = rng.permutation(K[1])
+    z2 = list(z); mu2 = list(mu); u2 = list(u)
+    z2[1] = z[1][perm]; u2[1] = u[1][perm]; mu2[0] = mu[0][perm]
+    mu2[1] = mu[1]
+    assert abs(O.gauss_chain_logp(z2, mu2, s, u2) - logp) < 1e-11
+    # adding c to one factor adds c to log P
+    f2 = [a.copy() for a in f]; f2[2] += 3.25
+    assert abs(O.chain_logp(f2, u) - logp - 3.25) < 1e-11
+
+
+def test_gauss_gradients_against_finite_differences():
+    rng = np.random.default_rng(16)
+    K, D = (4, 5, 3, 4), (3, 2, 4, 2)
+    z, mu, s, u = _rand_chain(rng, K, D, scale=0.7)
+    logp, dz, dmu, ds, du = O.gauss_chain_grads(z, mu, s, u, chunk=2)
+    L = len(K)
+
+    def with_(lst, l, a):
+        return [a if m == l else lst[m] for m in range(len(lst))]
+
+    for l in range(L):
+        fd = O.finite_difference(lambda a: O.gauss_chain_logp(with_(z, l, a), mu, s, u), z[l])
+        np.testing.assert_allclose(dz[l].reshape(-1), fd, atol=2e-7)
+        fd = O.finite_difference(lambda a: O.gauss_chain_logp(z, mu, s, with_(u, l, a)), u[l])
+        np.testing.assert_allclose(du[l], fd, atol=2e-7)
+    for l in range(L - 1):
+        fd = O.finite_difference(lambda a: O.gauss_chain_logp(z, with_(mu, l, a), s, u), mu[l])
+        np.testing.assert_allclose(dmu[l].reshape(-1), fd, atol=2e-7)
+        fd = O.finite_difference(lambda a: O.gauss_chain_logp(z, mu, with_(s, l, a), u), s[l])
+        np.testing.assert_allclose(ds[l], fd, atol=2e-7)
+    assert np.all(dz[L - 1] == 0)
