@@ -1,0 +1,223 @@
+/*
+ * tmc.h -- C ABI of libtmc, the MI355X (gfx950) Tensor Monte Carlo chain estimator.
+ *
+ * Paper: L. Aitchison, "Tensor Monte Carlo: Particle Methods for the GPU Era",
+ * arXiv 1806.08593.
+ *
+ * What the library computes.  For each of n_chains independent chains of latent
+ * layers 0..L-1 (layer 0 is adjacent to the data, layer L-1 is the top), with K_l
+ * samples z_l^k of layer l drawn from a proposal, the TMC estimate of eq. (is)
+ * (Sec. "TMC for factorised proposals"):
+ *
+ *   log P_TMC = log [ 1/prod_l K_l * sum_{k_0..k_{L-1}}
+ *                     exp( sum_l u_l[k_l] + sum_{l<L-1} f_l[k_l, k_{l+1}] ) ]
+ *
+ * where the importance ratio has been factorised as in eq. (fac) and the Appendix
+ * "Typical choice of factors":
+ *   u_l[k]       unary log-terms supplied by the caller: -log Q(z_l^k), plus the
+ *                log-likelihood log P(x | z_0^k) on layer 0 and the log-prior of the
+ *                top layer on layer L-1 (a non-factorised proposal of Sec.
+ *                "Non-factorised proposals" also enters here: it is indexed by k_l only);
+ *   f_l[i, j]    the pairwise log-factor log P(z_l^i | z_{l+1}^j).
+ * The sum is evaluated by summing out one index at a time (Sec. "Efficient
+ * averaging"), each step a log-domain matrix-vector product (Appendix "Numerically
+ * stable matrix (tensor) products in the log-domain").
+ *
+ * Two families of entry points:
+ *   tmc_gauss_*      the chained diagonal-Gaussian model of Sec. "Computational costs
+ *                    for TMC and IWAE": f_l[i,j] = log N(z_l^i; mu_l^j, diag exp(2 s_l)),
+ *                    where mu_l^j (the conditional mean produced by the caller's network
+ *                    from parent sample z_{l+1}^j) and s_l (log standard deviation,
+ *                    shared by all parent samples) are inputs.  Gradients with respect
+ *                    to z, mu, s and u are returned for reparameterised training.
+ *   tmc_logfactor_*  any chain whose log-factors f_l are supplied as dense matrices
+ *                    (e.g. the exact discrete marginalisation of the Appendix).
+ *
+ * Memory.  Every data pointer is DEVICE memory on the plan's device unless marked
+ * (host).  The caller allocates and owns every buffer, including the workspace; the
+ * library owns only its plans (descriptor tables, tuned tile choices, graphs).
+ * Execute calls never allocate and never synchronise, so they may be captured into
+ * a hipGraph by the caller.  Inputs are never written.  Outputs are overwritten.
+ *
+ * Layout.  Buffers are flat arrays; the problem descriptor gives the element
+ * offset of each layer's block.  Row-major:
+ *   z  : z_l    [K_l][D_l]        at layers[l].z_off
+ *   mu : mu_l   [K_{l+1}][D_l]    at layers[l].mu_off  (row j = mean given z_{l+1}^j)
+ *   s  : s_l    [D_l]             at layers[l].s_off   (several layers may share one)
+ *   u  : u_l    [K_l]             at layers[l].u_off
+ *   f  : f_l    [K_l][K_{l+1}]    at layers[l].f_off
+ * Gradient buffers use the same offsets as the matching input.  Element type is
+ * double in TMC_FP64 mode and float otherwise; log P and its upstream gradient
+ * are always double, one per chain.
+ *
+ * Errors.  Every call returns a status synchronously (validation and enqueue
+ * failures); tmc_last_error() gives the calling thread's last message.  No C++
+ * exception crosses this interface.  NaN inputs give NaN outputs; a chain whose
+ * weights are all zero (every term -inf) gives log P = -inf, never NaN.
+ *
+ * Threads.  Distinct plans may be used concurrently; one plan must not be used by
+ * two threads or two streams at the same time (its workspace layout and device
+ * tables are shared by its calls).
+ */
+#ifndef TMC_H_
+#define TMC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TMC_ABI_VERSION 1
+
+typedef enum tmc_status {
+  TMC_OK = 0,
+  TMC_ERR_INVALID_ARG = 1,   /* null pointer, bad enum, inconsistent descriptor */
+  TMC_ERR_SHAPE = 2,         /* K or D out of the supported range */
+  TMC_ERR_WORKSPACE = 3,     /* workspace missing or misaligned */
+  TMC_ERR_UNSUPPORTED = 4,   /* valid request the chosen engine cannot run */
+  TMC_ERR_HIP = 5,           /* a HIP runtime call failed (message has the HIP error) */
+  TMC_ERR_NUMERIC = 6,       /* device flagged a non-finite log P (tmc_plan_check) */
+  TMC_ERR_STATE = 7          /* call order violated (e.g. backward without forward) */
+} tmc_status;
+
+/* Arithmetic of the O(K^2) per-entry work.  The O(K) per-row and per-layer
+ * bookkeeping (row/column constants, message offsets, log P) is FP64 in all modes. */
+typedef enum tmc_precision {
+  TMC_FP64 = 0,     /* all per-entry arithmetic in double */
+  TMC_FP32 = 1,     /* factor GEMM on FP32 MFMA, log-sum-exp in float */
+  TMC_BF16X3 = 2    /* factor GEMM on BF16 MFMA with FP32 accumulation, operands split
+                       into bf16 hi+lo parts and summed as hi*hi + hi*lo + lo*hi;
+                       log-sum-exp in float */
+} tmc_precision;
+
+typedef enum tmc_engine {
+  TMC_ENGINE_AUTO = 0,    /* fused for FP32/BF16X3, plain for FP64 */
+  TMC_ENGINE_FUSED = 1,   /* factors recomputed on MFMA inside the message kernels,
+                             never stored (FP32, BF16X3) */
+  TMC_ENGINE_PLAIN = 2    /* factors materialised in the workspace, then streamed by
+                             the log-sum-exp kernels (FP64, FP32) */
+} tmc_engine;
+
+/* Problem flags. */
+#define TMC_FLAG_FORWARD_ONLY 1  /* no backward will follow: the fused forward skips
+                                    the work it does only for gradients */
+#define TMC_FLAG_PERSISTENT 2    /* fused engine: run each pass as one persistent
+                                    launch over a dependency-ordered work queue instead
+                                    of one launch per chain depth */
+
+/* One latent layer of one chain (host struct). */
+typedef struct tmc_layer {
+  int32_t K;       /* samples of this layer, >= 1 */
+  int32_t D;       /* dimension of z_l (and of mu_l, s_l), >= 1 (gauss entry points) */
+  int64_t z_off;   /* element offset of z_l [K][D]; not read for the top layer */
+  int64_t u_off;   /* element offset of u_l [K] */
+  int64_t mu_off;  /* element offset of mu_l [K_{l+1}][D]; ignored for the top layer */
+  int64_t s_off;   /* element offset of s_l [D]; ignored for the top layer.  Layers
+                      (of any chains) may share an s block; their ds is then summed. */
+  int64_t f_off;   /* element offset of f_l [K][K_{l+1}] (logfactor entry points);
+                      ignored for the top layer */
+} tmc_layer;
+
+/* One chain (host struct): layers[first_layer .. first_layer + n_layers - 1],
+ * ordered from the layer next to the data (0) to the top. */
+typedef struct tmc_chain {
+  int32_t n_layers;
+  int32_t first_layer;
+} tmc_chain;
+
+typedef struct tmc_problem {
+  int32_t n_chains;
+  int32_t n_layers;             /* length of layers[] */
+  const tmc_chain* chains;      /* (host) n_chains entries */
+  const tmc_layer* layers;      /* (host) n_layers entries */
+  int32_t precision;            /* tmc_precision */
+  int32_t engine;               /* tmc_engine */
+  int32_t flags;                /* TMC_FLAG_* */
+  int32_t reserved;             /* must be 0 */
+} tmc_problem;
+
+typedef struct tmc_plan* tmc_plan_t;
+
+/* Summary of a plan (host struct filled by tmc_plan_info). */
+typedef struct tmc_plan_info {
+  int64_t factor_entries;       /* sum over chains and layer pairs of K_l * K_{l+1} */
+  int64_t workspace_bytes;
+  int32_t engine;               /* engine actually used */
+  int32_t precision;
+  int32_t max_depth;            /* max chain length L */
+  int32_t tile_rows;            /* fused engine: rows per workgroup tile */
+  int32_t tile_cols;            /* fused engine: columns per inner tile */
+  int32_t waves_per_group;
+} tmc_plan_info;
+
+/* ---- library ---- */
+int tmc_abi_version(void);
+const char* tmc_status_string(tmc_status status);
+/* Last error message of the calling thread ("" if none).  Valid until the next call
+ * on this thread. */
+const char* tmc_last_error(void);
+
+/* ---- plans ---- */
+/* Validates the problem, lays out the workspace, picks tile shapes (tuned table or
+ * defaults) and uploads the descriptor tables to `device`.  Allocates device memory
+ * for those tables (the only allocation the library makes).  Errors:
+ * TMC_ERR_INVALID_ARG (null/bad descriptor, overlapping output ranges, partially
+ * overlapping s blocks), TMC_ERR_SHAPE (K or D outside the engine's limits),
+ * TMC_ERR_UNSUPPORTED (engine/precision combination not provided),
+ * TMC_ERR_HIP. */
+tmc_status tmc_plan_create(const tmc_problem* problem, int device, tmc_plan_t* out);
+tmc_status tmc_plan_destroy(tmc_plan_t plan);
+/* Bytes of device workspace every execute call of this plan needs (256-byte
+ * aligned pointer required).  The forward leaves in it what the backward reads, so
+ * a backward must use the workspace of the forward it differentiates. */
+tmc_status tmc_plan_workspace_size(tmc_plan_t plan, size_t* bytes);
+tmc_status tmc_plan_info_get(tmc_plan_t plan, tmc_plan_info* out);
+/* Synchronises `stream` (a hipStream_t, NULL = default stream) and reports device
+ * flags raised since the last check: TMC_ERR_NUMERIC if some log P was NaN or +inf. */
+tmc_status tmc_plan_check(tmc_plan_t plan, void* stream);
+
+/* ---- Gaussian chain (Sec. "Computational costs for TMC and IWAE") ---- */
+/* Forward: logp[c] (double, n_chains) = log P_TMC of chain c.  Enqueued on `stream`
+ * (hipStream_t).  Workspace receives the messages the backward needs. */
+tmc_status tmc_gauss_fwd(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                         const void* u, double* logp, void* workspace, void* stream);
+/* Backward: given dlogp[c] (double, upstream gradient of each chain's log P), writes
+ * dz (dz of every top layer is 0), dmu, ds (summed over layers sharing an s block)
+ * and du.  Reads the workspace left by the matching tmc_gauss_fwd; z, mu, s, u must
+ * be unchanged since that forward.  Any gradient pointer may be NULL to skip it. */
+tmc_status tmc_gauss_bwd(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                         const void* u, const double* dlogp, void* workspace,
+                         void* dz, void* dmu, void* ds, void* du, void* stream);
+/* Writes the pairwise log-factors f_l [K_l][K_{l+1}] (at layers[l].f_off of `f`) by
+ * direct difference in the plan's precision (FP64 or FP32).  For inspection and for
+ * feeding tmc_logfactor_*; the fused engine never materialises them. */
+tmc_status tmc_gauss_factors(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                             void* f, void* stream);
+
+/* ---- Chains with caller-supplied log-factors ---- */
+tmc_status tmc_logfactor_fwd(tmc_plan_t plan, const void* f, const void* u, double* logp,
+                             void* workspace, void* stream);
+/* df_l[i,j] = dlogp * d log P / d f_l[i,j] (the pairwise posterior marginal over sample
+ * indices), du_l[k] = dlogp * d log P / d u_l[k].  df or du may be NULL. */
+tmc_status tmc_logfactor_bwd(tmc_plan_t plan, const void* f, const void* u,
+                             const double* dlogp, void* workspace, void* df, void* du,
+                             void* stream);
+
+/* ---- graphs ---- */
+/* Record the enqueue of one execute call (same arguments as the call) into a hipGraph
+ * owned by the plan; which = 0 forward, 1 backward.  The pointers are baked into the
+ * graph.  Replay with tmc_plan_graph_launch. */
+tmc_status tmc_plan_graph_capture_gauss(tmc_plan_t plan, int which, const void* z,
+                                        const void* mu, const void* s, const void* u,
+                                        double* logp, const double* dlogp, void* workspace,
+                                        void* dz, void* dmu, void* ds, void* du,
+                                        void* stream);
+tmc_status tmc_plan_graph_launch(tmc_plan_t plan, int which, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMC_H_ */

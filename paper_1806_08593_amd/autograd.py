@@ -1,0 +1,66 @@
+"""torch.autograd wrapper of the Gaussian-chain TMC estimator.
+
+Only marshalling: the forward and backward passes are the library's tmc_gauss_fwd /
+tmc_gauss_bwd kernels.  torch provides device memory, the stream, and carries the
+returned gradients on into the caller's networks (mu and u are functions of the
+caller's parameters and of the reparameterised samples z).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import tmc as T
+
+_DT = {T.TMC_FP64: torch.float64, T.TMC_FP32: torch.float32, T.TMC_BF16X3: torch.float32}
+
+
+class GaussChainTMC:
+    """Batch of B chains with L layers of K samples and width D:
+        z [B, L, K, D], mu [B, L-1, K, D], s [L-1, D] (shared by the batch), u [B, L, K]
+    -> log P_TMC [B] (float64), differentiable in z, mu, s and u.
+    precision: 'fp64' | 'fp32' | 'bf16x3'; engine: 'auto' | 'fused' | 'plain'."""
+
+    def __init__(self, B, L, K, D, precision="fp32", engine="auto", device=0, flags=0):
+        self.shape = (B, L, K, D)
+        self.problem = T.homogeneous_problem(B, L, K, D, precision, engine, flags)
+        self.plan = T.Plan(self.problem, device)
+        self.dtype = _DT[self.problem.c.precision]
+        self.device = torch.device(f"cuda:{device}")
+
+    def _check(self, z, mu, s, u):
+        B, L, K, D = self.shape
+        want = {"z": (z, (B, L, K, D)), "mu": (mu, (B, L - 1, K, D)), "s": (s, (L - 1, D)),
+                "u": (u, (B, L, K))}
+        for name, (t, shp) in want.items():
+            if tuple(t.shape) != shp:
+                raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {shp}")
+            if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
+                raise ValueError(f"{name}: needs a contiguous {self.dtype} tensor on {self.device}")
+
+    def __call__(self, z, mu, s, u):
+        self._check(z, mu, s, u)
+        return _GaussChainFn.apply(z, mu, s, u, self)
+
+
+class _GaussChainFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, z, mu, s, u, runner: GaussChainTMC):
+        ws = runner.plan.new_workspace()
+        logp = torch.empty(runner.shape[0], dtype=torch.float64, device=z.device)
+        T.tmc_gauss_fwd(runner.plan.handle, z, mu, s, u, logp, ws)
+        ctx.save_for_backward(z, mu, s, u)
+        ctx.ws = ws
+        ctx.runner = runner
+        return logp
+
+    @staticmethod
+    def backward(ctx, dlogp):
+        z, mu, s, u = ctx.saved_tensors
+        dlogp = dlogp.to(torch.float64).contiguous()
+        need = ctx.needs_input_grad
+        dz = torch.empty_like(z) if need[0] else None
+        dmu = torch.empty_like(mu) if need[1] else None
+        ds = torch.empty_like(s) if need[2] else None
+        du = torch.empty_like(u) if need[3] else None
+        T.tmc_gauss_bwd(ctx.runner.plan.handle, z, mu, s, u, dlogp, ctx.ws, dz, dmu, ds, du)
+        return dz, dmu, ds, du, None

@@ -1,0 +1,809 @@
+// Host runtime of libtmc: validation, plans (workspace layout, level schedules,
+// device descriptor tables), dispatch to the engines, graphs and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tmc.h"
+#include "fused.h"
+#include "tmc_internal.h"
+#include "tmc_kernels.h"
+
+using namespace tmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+tmc_status fail(tmc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(TMC_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Launch {
+  int off = 0, n = 0;
+};
+
+// Sets the plan's device for the duration of a call and restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct tmc_plan {
+  int device = 0;
+  int prec = TMC_FP32;
+  int engine = TMC_ENGINE_PLAIN;
+  int flags = 0;
+  int n_chains = 0, n_layers = 0, max_depth = 0;
+  int64_t entries = 0;
+  size_t esz = 4;
+  std::vector<ChainDev> chains_h;
+  std::vector<LayerDev> layers_h;
+  WsLayout ws{};
+  // device tables
+  ChainDev* chains_d = nullptr;
+  LayerDev* layers_d = nullptr;
+  Item* items_d = nullptr;
+  int* ints_d = nullptr;         // pair ids, slot layers, slot starts, slot D
+  int64_t* slot_soff_d = nullptr;
+  int* flag_d = nullptr;
+  // schedules (offsets into items_d)
+  Launch factor;                              // all pairs, factor tiles
+  std::vector<Launch> fwd, bwd_vec, bwd_sca;  // per depth step
+  std::vector<int> fwd_maxkc;
+  Launch gmu, gtz;
+  int n_pairs = 0, pair_ids_off = 0;
+  int n_slots = 0, slot_layers_off = 0, slot_start_off = 0, slot_D_off = 0;
+  // fused engine
+  FusedPlan fused;
+  // problems that make one family of entry points unusable (empty = usable)
+  std::string gauss_err, logf_err;
+  // graphs
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  ~tmc_plan() {
+    for (auto& g : graph)
+      if (g) (void)hipGraphExecDestroy(g);
+    fused_release(fused);
+    if (chains_d) (void)hipFree(chains_d);
+    if (layers_d) (void)hipFree(layers_d);
+    if (items_d) (void)hipFree(items_d);
+    if (ints_d) (void)hipFree(ints_d);
+    if (slot_soff_d) (void)hipFree(slot_soff_d);
+    if (flag_d) (void)hipFree(flag_d);
+  }
+};
+
+namespace {
+
+struct Range {
+  int64_t b, e;
+  int who;
+};
+
+// Disjointness of [b, e) ranges; returns index pair of an overlap or -1.
+bool find_overlap(std::vector<Range>& r, int* a, int* b) {
+  std::sort(r.begin(), r.end(), [](const Range& x, const Range& y) {
+    return x.b < y.b || (x.b == y.b && x.e < y.e);
+  });
+  for (size_t i = 1; i < r.size(); ++i)
+    if (r[i].b < r[i - 1].e) {
+      *a = r[i - 1].who;
+      *b = r[i].who;
+      return true;
+    }
+  return false;
+}
+
+tmc_status validate(const tmc_problem* pr, int* engine_out, std::string* gauss_err,
+                    std::string* logf_err) {
+  if (!pr) return fail(TMC_ERR_INVALID_ARG, "problem is NULL");
+  if (pr->n_chains < 0 || pr->n_layers < 0)
+    return fail(TMC_ERR_INVALID_ARG, "negative n_chains or n_layers");
+  if ((pr->n_chains > 0 && !pr->chains) || (pr->n_layers > 0 && !pr->layers))
+    return fail(TMC_ERR_INVALID_ARG, "chains or layers array is NULL");
+  if (pr->reserved != 0) return fail(TMC_ERR_INVALID_ARG, "reserved field must be 0");
+  if (pr->precision < TMC_FP64 || pr->precision > TMC_BF16X3)
+    return fail(TMC_ERR_INVALID_ARG, "unknown precision %d", pr->precision);
+  if (pr->engine < TMC_ENGINE_AUTO || pr->engine > TMC_ENGINE_PLAIN)
+    return fail(TMC_ERR_INVALID_ARG, "unknown engine %d", pr->engine);
+  if (pr->flags & ~(TMC_FLAG_FORWARD_ONLY | TMC_FLAG_PERSISTENT))
+    return fail(TMC_ERR_INVALID_ARG, "unknown flag bits 0x%x", pr->flags);
+  int engine = pr->engine;
+  if (engine == TMC_ENGINE_AUTO)
+    engine = (pr->precision == TMC_FP64 || !kFusedAvailable) ? TMC_ENGINE_PLAIN : TMC_ENGINE_FUSED;
+  if (engine == TMC_ENGINE_PLAIN && pr->precision == TMC_BF16X3)
+    return fail(TMC_ERR_UNSUPPORTED, "the plain engine has no BF16X3 mode");
+  if (engine == TMC_ENGINE_FUSED && pr->precision == TMC_FP64)
+    return fail(TMC_ERR_UNSUPPORTED, "the fused engine has no FP64 mode; use the plain engine");
+  *engine_out = engine;
+
+  std::vector<int> owner(pr->n_layers, -1);
+  for (int c = 0; c < pr->n_chains; ++c) {
+    const tmc_chain& ch = pr->chains[c];
+    if (ch.n_layers < 1) return fail(TMC_ERR_INVALID_ARG, "chain %d has %d layers", c, ch.n_layers);
+    if (ch.first_layer < 0 || (int64_t)ch.first_layer + ch.n_layers > pr->n_layers)
+      return fail(TMC_ERR_INVALID_ARG, "chain %d layer range out of bounds", c);
+    for (int l = ch.first_layer; l < ch.first_layer + ch.n_layers; ++l) {
+      if (owner[l] >= 0)
+        return fail(TMC_ERR_INVALID_ARG, "layer %d belongs to chains %d and %d", l, owner[l], c);
+      owner[l] = c;
+    }
+  }
+  const bool plain = engine == TMC_ENGINE_PLAIN;
+  const int maxK = plain ? kPlainMaxK : kFusedMaxK;
+  const int maxD = plain ? kPlainMaxD : kFusedMaxD;
+  std::vector<Range> rz, ru, rm, rf, rs;
+  bool neg_gauss = false, neg_f = false;
+  for (int c = 0; c < pr->n_chains; ++c) {
+    const tmc_chain& ch = pr->chains[c];
+    for (int q = 0; q < ch.n_layers; ++q) {
+      const int l = ch.first_layer + q;
+      const tmc_layer& L = pr->layers[l];
+      const bool top = q == ch.n_layers - 1;
+      if (L.K < 1 || L.K > maxK)
+        return fail(TMC_ERR_SHAPE, "layer %d: K=%d outside [1, %d]", l, L.K, maxK);
+      if (L.D < 1 || L.D > maxD)
+        return fail(TMC_ERR_SHAPE, "layer %d: D=%d outside [1, %d]", l, L.D, maxD);
+      if (L.u_off < 0) return fail(TMC_ERR_INVALID_ARG, "layer %d: negative u offset", l);
+      ru.push_back({L.u_off, L.u_off + L.K, l});
+      if (L.z_off < 0) neg_gauss = true;
+      rz.push_back({L.z_off, L.z_off + (int64_t)L.K * L.D, l});
+      if (!top) {
+        const tmc_layer& U = pr->layers[l + 1];
+        if (L.mu_off < 0 || L.s_off < 0) neg_gauss = true;
+        if (L.f_off < 0) neg_f = true;
+        rm.push_back({L.mu_off, L.mu_off + (int64_t)U.K * L.D, l});
+        rf.push_back({L.f_off, L.f_off + (int64_t)L.K * U.K, l});
+        rs.push_back({L.s_off, L.s_off + L.D, l});
+      }
+    }
+  }
+  int a, b;
+  if (find_overlap(ru, &a, &b)) return fail(TMC_ERR_INVALID_ARG, "u blocks of layers %d and %d overlap", a, b);
+  // Gaussian entry points need disjoint z and mu blocks and identical-or-disjoint s
+  // blocks; log-factor entry points need disjoint f blocks.  Checked here, reported
+  // when the entry point that needs them is called.
+  char buf[256];
+  gauss_err->clear();
+  logf_err->clear();
+  if (neg_gauss) *gauss_err = "negative z, mu or s offset";
+  else if (find_overlap(rz, &a, &b)) { snprintf(buf, sizeof buf, "z blocks of layers %d and %d overlap", a, b); *gauss_err = buf; }
+  else if (find_overlap(rm, &a, &b)) { snprintf(buf, sizeof buf, "mu blocks of layers %d and %d overlap", a, b); *gauss_err = buf; }
+  else {
+    std::sort(rs.begin(), rs.end(), [](const Range& x, const Range& y) {
+      return x.b < y.b || (x.b == y.b && x.e < y.e);
+    });
+    for (size_t i = 1; i < rs.size(); ++i) {
+      const bool same = rs[i].b == rs[i - 1].b && rs[i].e == rs[i - 1].e;
+      if (!same && rs[i].b < rs[i - 1].e) {
+        snprintf(buf, sizeof buf, "s blocks of layers %d and %d partially overlap", rs[i - 1].who, rs[i].who);
+        *gauss_err = buf;
+        break;
+      }
+    }
+  }
+  if (neg_f) *logf_err = "negative f offset";
+  else if (find_overlap(rf, &a, &b)) { snprintf(buf, sizeof buf, "f blocks of layers %d and %d overlap", a, b); *logf_err = buf; }
+  return TMC_OK;
+}
+
+template <typename T>
+T* wsp(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
+  P->n_chains = pr->n_chains;
+  P->n_layers = pr->n_layers;
+  P->esz = P->prec == TMC_FP64 ? 8 : 4;
+  const size_t esz = P->esz;
+  P->layers_h.assign(pr->n_layers, LayerDev{});
+  P->chains_h.resize(pr->n_chains);
+  int64_t sumK = 0, sum_pairKK = 0, sum_pairKcD = 0, sum_pairD = 0;
+  P->max_depth = 0;
+  P->entries = 0;
+  for (int c = 0; c < pr->n_chains; ++c) {
+    const tmc_chain& ch = pr->chains[c];
+    P->chains_h[c] = ChainDev{ch.n_layers, ch.first_layer, ch.first_layer + ch.n_layers - 1, 0};
+    P->max_depth = std::max(P->max_depth, ch.n_layers);
+    for (int q = 0; q < ch.n_layers; ++q) {
+      const int l = ch.first_layer + q;
+      const tmc_layer& L = pr->layers[l];
+      LayerDev& d = P->layers_h[l];
+      const bool top = q == ch.n_layers - 1;
+      d.K = L.K;
+      d.D = L.D;
+      d.chain = c;
+      d.depth = q;
+      d.up = top ? -1 : l + 1;
+      d.Kc = top ? 0 : pr->layers[l + 1].K;
+      d.z_off = L.z_off;
+      d.u_off = L.u_off;
+      d.mu_off = top ? 0 : L.mu_off;
+      d.s_off = top ? 0 : L.s_off;
+      d.f_off = top ? 0 : L.f_off;
+      d.u_up_off = top ? 0 : pr->layers[l + 1].u_off;
+      d.alpha_off = sumK;
+      d.p_off = sumK;
+      d.rl_off = sumK;
+      sumK += L.K;
+      if (!top) {
+        d.wf_off = sum_pairKK;
+        sum_pairKK += align_up((size_t)L.K * d.Kc, 4);
+        d.gtz_off = sum_pairKcD;
+        sum_pairKcD += (int64_t)d.Kc * L.D;
+        d.dsp_off = sum_pairD;
+        sum_pairD += L.D;
+        P->entries += (int64_t)L.K * d.Kc;
+      }
+    }
+  }
+  for (auto& d : P->layers_h)
+    if (d.up >= 0) {
+      d.alpha_up_off = P->layers_h[d.up].alpha_off;
+      d.p_up_off = P->layers_h[d.up].p_off;
+    }
+
+  // workspace layout
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes, 256);
+    return r;
+  };
+  WsLayout& W = P->ws;
+  W.alpha = take(sumK * 8);
+  W.p = take(sumK * esz);
+  W.rl = take(sumK * esz);
+  W.pairM = take((size_t)pr->n_layers * 8);
+  W.logp = take((size_t)pr->n_chains * 8);
+  W.dsp = take(sum_pairD * esz);
+  if (P->engine == TMC_ENGINE_PLAIN) {
+    W.wf = take(sum_pairKK * esz);
+    W.wg = take(sum_pairKK * esz);
+    W.gtz = take(sum_pairKcD * esz);
+  }
+  W.total = o;
+
+  // schedules
+  std::vector<Item> items;
+  auto begin = [&](Launch& L) { L.off = (int)items.size(); };
+  auto end = [&](Launch& L) { L.n = (int)items.size() - L.off; };
+  const int D1 = P->max_depth - 1;
+  P->fwd.assign(std::max(D1, 0), Launch{});
+  P->fwd_maxkc.assign(std::max(D1, 0), 0);
+  P->bwd_vec.assign(std::max(D1, 0), Launch{});
+  P->bwd_sca.assign(std::max(D1, 0), Launch{});
+  std::vector<int> pairs;
+  for (int l = 0; l < pr->n_layers; ++l)
+    if (P->layers_h[l].up >= 0 && P->layers_h[l].K > 0) pairs.push_back(l);
+  // only layers that belong to a chain
+  {
+    std::vector<char> used(pr->n_layers, 0);
+    for (auto& c : P->chains_h)
+      for (int l = c.first; l <= c.top; ++l) used[l] = 1;
+    std::vector<int> pp;
+    for (int l : pairs)
+      if (used[l]) pp.push_back(l);
+    pairs.swap(pp);
+  }
+  if (P->engine == TMC_ENGINE_PLAIN) {
+    begin(P->factor);
+    for (int l : pairs) {
+      const LayerDev& d = P->layers_h[l];
+      const int nt = ((d.K + kPlainFactorRows - 1) / kPlainFactorRows) *
+                     ((d.Kc + kPlainFactorCols - 1) / kPlainFactorCols);
+      for (int t = 0; t < nt; ++t) items.push_back({l, t});
+    }
+    end(P->factor);
+    for (int t = 0; t < D1; ++t) {
+      begin(P->fwd[t]);
+      for (int l : pairs) {
+        const LayerDev& d = P->layers_h[l];
+        const int L = P->chains_h[d.chain].L;
+        if (d.depth != L - 2 - t) continue;
+        P->fwd_maxkc[t] = std::max(P->fwd_maxkc[t], d.Kc);
+        for (int r = 0; r < d.K; r += kPlainFwdRowsPerBlock) items.push_back({l, r});
+      }
+      end(P->fwd[t]);
+    }
+    const int VV = esz == 4 ? 4 : 2;
+    for (int t = 0; t < D1; ++t) {
+      for (int pass = 0; pass < 2; ++pass) {
+        Launch& Lc = pass == 0 ? P->bwd_vec[t] : P->bwd_sca[t];
+        begin(Lc);
+        for (int l : pairs) {
+          const LayerDev& d = P->layers_h[l];
+          if (d.depth != t) continue;
+          const bool vec = d.Kc >= 64 * VV && d.Kc % VV == 0 && d.f_off % VV == 0 &&
+                           d.wf_off % VV == 0;
+          if (vec != (pass == 0)) continue;
+          const int step = vec ? 64 * VV : 64;
+          for (int j = 0; j < d.Kc; j += step) items.push_back({l, j});
+        }
+        end(Lc);
+      }
+    }
+    begin(P->gmu);
+    for (int l : pairs) {
+      const LayerDev& d = P->layers_h[l];
+      const int nt = ((d.K + kPlainGemmRows - 1) / kPlainGemmRows) * ((d.D + kPlainGemmD - 1) / kPlainGemmD);
+      for (int t = 0; t < nt; ++t) items.push_back({l, t});
+    }
+    end(P->gmu);
+    begin(P->gtz);
+    for (int l : pairs) {
+      const LayerDev& d = P->layers_h[l];
+      const int nt = ((d.Kc + kPlainGemmRows - 1) / kPlainGemmRows) * ((d.D + kPlainGemmD - 1) / kPlainGemmD);
+      for (int t = 0; t < nt; ++t) items.push_back({l, t});
+    }
+    end(P->gtz);
+  }
+
+  // integer tables: pair ids, ds slots (layers grouped by identical s block)
+  std::vector<int> ints;
+  P->n_pairs = (int)pairs.size();
+  P->pair_ids_off = 0;
+  ints.insert(ints.end(), pairs.begin(), pairs.end());
+  std::vector<int> by_s = pairs;
+  std::stable_sort(by_s.begin(), by_s.end(), [&](int a, int b) {
+    return P->layers_h[a].s_off < P->layers_h[b].s_off;
+  });
+  std::vector<int> slot_start;
+  std::vector<int64_t> slot_soff;
+  std::vector<int> slot_D;
+  for (size_t i = 0; i < by_s.size(); ++i) {
+    if (i == 0 || P->layers_h[by_s[i]].s_off != P->layers_h[by_s[i - 1]].s_off) {
+      slot_start.push_back((int)i);
+      slot_soff.push_back(P->layers_h[by_s[i]].s_off);
+      slot_D.push_back(P->layers_h[by_s[i]].D);
+    }
+  }
+  slot_start.push_back((int)by_s.size());
+  P->n_slots = (int)slot_soff.size();
+  P->slot_layers_off = (int)ints.size();
+  ints.insert(ints.end(), by_s.begin(), by_s.end());
+  P->slot_start_off = (int)ints.size();
+  ints.insert(ints.end(), slot_start.begin(), slot_start.end());
+  P->slot_D_off = (int)ints.size();
+  ints.insert(ints.end(), slot_D.begin(), slot_D.end());
+
+  // fused engine layout and schedules
+  if (P->engine == TMC_ENGINE_FUSED) {
+    tmc_status st = fused_build(P->fused, P->prec, P->flags, P->layers_h, P->chains_h, pairs,
+                                P->ws, items);
+    if (st != TMC_OK) return st;
+    P->ws.total = align_up(P->ws.total, 256);
+  }
+
+  // upload
+  auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) return e;
+    if (src) return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return hipSuccess;
+  };
+  HIP_TRY(upload((void**)&P->chains_d, P->chains_h.empty() ? nullptr : P->chains_h.data(),
+                 P->chains_h.size() * sizeof(ChainDev)));
+  HIP_TRY(upload((void**)&P->layers_d, P->layers_h.empty() ? nullptr : P->layers_h.data(),
+                 P->layers_h.size() * sizeof(LayerDev)));
+  HIP_TRY(upload((void**)&P->items_d, items.empty() ? nullptr : items.data(),
+                 items.size() * sizeof(Item)));
+  HIP_TRY(upload((void**)&P->ints_d, ints.empty() ? nullptr : ints.data(), ints.size() * sizeof(int)));
+  HIP_TRY(upload((void**)&P->slot_soff_d, slot_soff.empty() ? nullptr : slot_soff.data(),
+                 slot_soff.size() * sizeof(int64_t)));
+  HIP_TRY(hipMalloc((void**)&P->flag_d, sizeof(int)));
+  HIP_TRY(hipMemset(P->flag_d, 0, sizeof(int)));
+  if (P->engine == TMC_ENGINE_FUSED) {
+    tmc_status st = fused_upload(P->fused);
+    if (st != TMC_OK) return st;
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  return TMC_OK;
+}
+
+tmc_status check_exec(tmc_plan* P, void* ws) {
+  if (!P) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+  if (P->ws.total > 0) {
+    if (!ws) return fail(TMC_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", P->ws.total);
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+      return fail(TMC_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  }
+  return TMC_OK;
+}
+
+#define LAUNCH(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(TMC_ERR_HIP, "kernel launch %s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---- plain engine ----
+template <typename T>
+tmc_status plain_fwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, const T* s,
+                     const T* u, double* logp, void* ws, hipStream_t st) {
+  const WsLayout& W = P->ws;
+  const Item* it = P->items_d;
+  const bool caller = f_caller != nullptr;
+  T* wf = wsp<T>(ws, W.wf);
+  const T* f = caller ? f_caller : wf;
+  if (!caller)
+    LAUNCH(launch_plain_factor<T>(P->layers_d, it + P->factor.off, P->factor.n, z, mu, s, wf, false, st));
+  LAUNCH(launch_init_top<T>(P->chains_d, P->n_chains, P->layers_d, u, wsp<double>(ws, W.alpha), st));
+  for (size_t t = 0; t < P->fwd.size(); ++t)
+    LAUNCH(launch_plain_lse_fwd<T>(P->layers_d, it + P->fwd[t].off, P->fwd[t].n, P->fwd_maxkc[t], f,
+                                   caller, u, wsp<double>(ws, W.alpha), wsp<T>(ws, W.rl),
+                                   wsp<double>(ws, W.pairM), st));
+  LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, wsp<double>(ws, W.alpha), logp,
+                         wsp<double>(ws, W.logp), P->flag_d, st));
+  return TMC_OK;
+}
+
+template <typename T>
+tmc_status plain_bwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, const T* s,
+                     const double* dlogp, void* ws, T* df, T* dz, T* dmu, T* ds, T* du,
+                     hipStream_t st) {
+  const WsLayout& W = P->ws;
+  const Item* it = P->items_d;
+  const bool caller = f_caller != nullptr;
+  const T* f = caller ? f_caller : wsp<T>(ws, W.wf);
+  T* g = caller ? df : wsp<T>(ws, W.wg);
+  T* p = wsp<T>(ws, W.p);
+  LAUNCH(launch_bwd_init<T>(P->chains_d, P->n_chains, P->layers_d, wsp<double>(ws, W.alpha),
+                            wsp<double>(ws, W.logp), dlogp, p, du, dz, st));
+  for (size_t t = 0; t < P->bwd_vec.size(); ++t) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const Launch& L = pass == 0 ? P->bwd_vec[t] : P->bwd_sca[t];
+      LAUNCH(launch_plain_lse_bwd<T>(P->layers_d, it + L.off, L.n, pass == 0, f, caller,
+                                     wsp<double>(ws, W.alpha), wsp<T>(ws, W.rl),
+                                     wsp<double>(ws, W.pairM), dlogp, p, g, caller, caller, du, st));
+    }
+  }
+  if (caller) return TMC_OK;
+  if (dz)
+    LAUNCH(launch_plain_gmu<T>(P->layers_d, it + P->gmu.off, P->gmu.n, g, z, mu, s, p, dlogp, dz, st));
+  if (dmu || ds)
+    LAUNCH(launch_plain_gtz<T>(P->layers_d, it + P->gtz.off, P->gtz.n, g, z, mu, s, p, dlogp,
+                               wsp<T>(ws, W.gtz), dmu, st));
+  if (ds) {
+    LAUNCH(launch_pair_dsp<T>(P->layers_d, P->ints_d + P->pair_ids_off, P->n_pairs, z, mu, s, p,
+                              wsp<T>(ws, W.gtz), dlogp, wsp<T>(ws, W.dsp), st));
+    LAUNCH(launch_ds_reduce<T>(P->ints_d + P->slot_layers_off, P->ints_d + P->slot_start_off,
+                               P->slot_soff_d, P->ints_d + P->slot_D_off, P->n_slots, P->layers_d,
+                               wsp<T>(ws, W.dsp), ds, st));
+  }
+  return TMC_OK;
+}
+
+tmc_status gauss_fwd_impl(tmc_plan* P, const void* z, const void* mu, const void* s,
+                          const void* u, double* logp, void* ws, hipStream_t st) {
+  if (!P->gauss_err.empty()) return fail(TMC_ERR_INVALID_ARG, "%s", P->gauss_err.c_str());
+  if (P->n_chains == 0) return TMC_OK;
+  if (!u || !logp || (P->n_pairs > 0 && (!z || !mu || !s)))
+    return fail(TMC_ERR_INVALID_ARG, "NULL input or output pointer");
+  if (P->engine == TMC_ENGINE_FUSED) {
+    FusedArgs a{};
+    a.z = z; a.mu = mu; a.s = s; a.u = u; a.logp = logp; a.ws = ws; a.stream = st;
+    a.chains_d = P->chains_d; a.layers_d = P->layers_d; a.n_chains = P->n_chains;
+    a.flag_d = P->flag_d; a.ws_layout = &P->ws;
+    return fused_fwd(P->fused, a);
+  }
+  if (P->prec == TMC_FP64)
+    return plain_fwd<double>(P, nullptr, (const double*)z, (const double*)mu, (const double*)s,
+                             (const double*)u, logp, ws, st);
+  return plain_fwd<float>(P, nullptr, (const float*)z, (const float*)mu, (const float*)s,
+                          (const float*)u, logp, ws, st);
+}
+
+tmc_status gauss_bwd_impl(tmc_plan* P, const void* z, const void* mu, const void* s,
+                          const void* u, const double* dlogp, void* ws, void* dz, void* dmu,
+                          void* ds, void* du, hipStream_t st) {
+  if (!P->gauss_err.empty()) return fail(TMC_ERR_INVALID_ARG, "%s", P->gauss_err.c_str());
+  if (P->n_chains == 0) return TMC_OK;
+  if (!dlogp || (P->n_pairs > 0 && (!z || !mu || !s)))
+    return fail(TMC_ERR_INVALID_ARG, "NULL input pointer");
+  if (P->engine == TMC_ENGINE_FUSED) {
+    if (P->flags & TMC_FLAG_FORWARD_ONLY)
+      return fail(TMC_ERR_STATE, "plan was created with TMC_FLAG_FORWARD_ONLY");
+    FusedArgs a{};
+    a.z = z; a.mu = mu; a.s = s; a.u = u; a.dlogp = dlogp; a.ws = ws; a.stream = st;
+    a.dz = dz; a.dmu = dmu; a.ds = ds; a.du = du;
+    a.chains_d = P->chains_d; a.layers_d = P->layers_d; a.n_chains = P->n_chains;
+    a.flag_d = P->flag_d; a.ws_layout = &P->ws;
+    a.ints_d = P->ints_d; a.slot_soff_d = P->slot_soff_d;
+    a.n_slots = P->n_slots; a.slot_layers_off = P->slot_layers_off;
+    a.slot_start_off = P->slot_start_off; a.slot_D_off = P->slot_D_off;
+    return fused_bwd(P->fused, a);
+  }
+  if (P->prec == TMC_FP64)
+    return plain_bwd<double>(P, nullptr, (const double*)z, (const double*)mu, (const double*)s,
+                             dlogp, ws, nullptr, (double*)dz, (double*)dmu, (double*)ds,
+                             (double*)du, st);
+  return plain_bwd<float>(P, nullptr, (const float*)z, (const float*)mu, (const float*)s, dlogp,
+                          ws, nullptr, (float*)dz, (float*)dmu, (float*)ds, (float*)du, st);
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+int tmc_abi_version(void) { return TMC_ABI_VERSION; }
+
+const char* tmc_status_string(tmc_status s) {
+  switch (s) {
+    case TMC_OK: return "TMC_OK";
+    case TMC_ERR_INVALID_ARG: return "TMC_ERR_INVALID_ARG";
+    case TMC_ERR_SHAPE: return "TMC_ERR_SHAPE";
+    case TMC_ERR_WORKSPACE: return "TMC_ERR_WORKSPACE";
+    case TMC_ERR_UNSUPPORTED: return "TMC_ERR_UNSUPPORTED";
+    case TMC_ERR_HIP: return "TMC_ERR_HIP";
+    case TMC_ERR_NUMERIC: return "TMC_ERR_NUMERIC";
+    case TMC_ERR_STATE: return "TMC_ERR_STATE";
+  }
+  return "TMC_ERR_UNKNOWN";
+}
+
+const char* tmc_last_error(void) { return g_err.c_str(); }
+
+tmc_status tmc_plan_create(const tmc_problem* problem, int device, tmc_plan_t* out) {
+  try {
+    if (!out) return fail(TMC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int engine = 0;
+    std::string gerr, ferr;
+    tmc_status st = validate(problem, &engine, &gerr, &ferr);
+    if (st != TMC_OK) return st;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0)
+      return fail(TMC_ERR_HIP, "no HIP device available (%s)", hipGetErrorString(e));
+    if (device < 0 || device >= ndev)
+      return fail(TMC_ERR_INVALID_ARG, "device %d out of range [0, %d)", device, ndev);
+    DeviceGuard g(device);
+    if (!g.ok) return fail(TMC_ERR_HIP, "hipSetDevice(%d) failed", device);
+    tmc_plan* P = new tmc_plan();
+    P->device = device;
+    P->prec = problem->precision;
+    P->engine = engine;
+    P->flags = problem->flags;
+    P->gauss_err = gerr;
+    P->logf_err = ferr;
+    st = build_plan(P, problem);
+    if (st != TMC_OK) {
+      delete P;
+      return st;
+    }
+    *out = P;
+    g_err.clear();
+    return TMC_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(TMC_ERR_INVALID_ARG, "host allocation failed");
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_plan_destroy(tmc_plan_t plan) {
+  if (!plan) return TMC_OK;
+  try {
+    DeviceGuard g(plan->device);
+    delete plan;
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+  return TMC_OK;
+}
+
+tmc_status tmc_plan_workspace_size(tmc_plan_t plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(TMC_ERR_INVALID_ARG, "NULL argument");
+  *bytes = plan->ws.total;
+  return TMC_OK;
+}
+
+tmc_status tmc_plan_info_get(tmc_plan_t plan, tmc_plan_info* out) {
+  if (!plan || !out) return fail(TMC_ERR_INVALID_ARG, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  out->factor_entries = plan->entries;
+  out->workspace_bytes = (int64_t)plan->ws.total;
+  out->engine = plan->engine;
+  out->precision = plan->prec;
+  out->max_depth = plan->max_depth;
+  if (plan->engine == TMC_ENGINE_FUSED) fused_info(plan->fused, out);
+  return TMC_OK;
+}
+
+tmc_status tmc_plan_check(tmc_plan_t plan, void* stream) {
+  if (!plan) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+  try {
+    DeviceGuard g(plan->device);
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, plan->flag_d, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag) {
+      HIP_TRY(hipMemset(plan->flag_d, 0, sizeof(int)));
+      if (flag & kFlagNonFinite) return fail(TMC_ERR_NUMERIC, "a log P was NaN or +inf");
+    }
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+  return TMC_OK;
+}
+
+tmc_status tmc_gauss_fwd(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                         const void* u, double* logp, void* workspace, void* stream) {
+  try {
+    tmc_status st = check_exec(plan, workspace);
+    if (st != TMC_OK) return st;
+    DeviceGuard g(plan->device);
+    return gauss_fwd_impl(plan, z, mu, s, u, logp, workspace, (hipStream_t)stream);
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_gauss_bwd(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                         const void* u, const double* dlogp, void* workspace, void* dz,
+                         void* dmu, void* ds, void* du, void* stream) {
+  try {
+    tmc_status st = check_exec(plan, workspace);
+    if (st != TMC_OK) return st;
+    DeviceGuard g(plan->device);
+    return gauss_bwd_impl(plan, z, mu, s, u, dlogp, workspace, dz, dmu, ds, du,
+                          (hipStream_t)stream);
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_gauss_factors(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                             void* f, void* stream) {
+  try {
+    if (!plan) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+    if (plan->engine != TMC_ENGINE_PLAIN)
+      return fail(TMC_ERR_UNSUPPORTED, "tmc_gauss_factors needs a plain-engine plan");
+    if (!plan->gauss_err.empty()) return fail(TMC_ERR_INVALID_ARG, "%s", plan->gauss_err.c_str());
+    if (!plan->logf_err.empty()) return fail(TMC_ERR_INVALID_ARG, "%s", plan->logf_err.c_str());
+    if (plan->n_pairs == 0) return TMC_OK;
+    if (!z || !mu || !s || !f) return fail(TMC_ERR_INVALID_ARG, "NULL pointer");
+    DeviceGuard g(plan->device);
+    const Item* it = plan->items_d + plan->factor.off;
+    hipStream_t st = (hipStream_t)stream;
+    if (plan->prec == TMC_FP64)
+      LAUNCH(launch_plain_factor<double>(plan->layers_d, it, plan->factor.n, (const double*)z,
+                                         (const double*)mu, (const double*)s, (double*)f, true, st));
+    else
+      LAUNCH(launch_plain_factor<float>(plan->layers_d, it, plan->factor.n, (const float*)z,
+                                        (const float*)mu, (const float*)s, (float*)f, true, st));
+    return TMC_OK;
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_logfactor_fwd(tmc_plan_t plan, const void* f, const void* u, double* logp,
+                             void* workspace, void* stream) {
+  try {
+    tmc_status st = check_exec(plan, workspace);
+    if (st != TMC_OK) return st;
+    if (plan->engine != TMC_ENGINE_PLAIN)
+      return fail(TMC_ERR_UNSUPPORTED, "log-factor entry points need a plain-engine plan");
+    if (!plan->logf_err.empty()) return fail(TMC_ERR_INVALID_ARG, "%s", plan->logf_err.c_str());
+    if (plan->n_chains == 0) return TMC_OK;
+    if (!u || !logp || (plan->n_pairs > 0 && !f)) return fail(TMC_ERR_INVALID_ARG, "NULL pointer");
+    DeviceGuard g(plan->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prec == TMC_FP64)
+      return plain_fwd<double>(plan, (const double*)f, nullptr, nullptr, nullptr, (const double*)u,
+                               logp, workspace, s);
+    return plain_fwd<float>(plan, (const float*)f, nullptr, nullptr, nullptr, (const float*)u, logp,
+                            workspace, s);
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_logfactor_bwd(tmc_plan_t plan, const void* f, const void* u, const double* dlogp,
+                             void* workspace, void* df, void* du, void* stream) {
+  (void)u;
+  try {
+    tmc_status st = check_exec(plan, workspace);
+    if (st != TMC_OK) return st;
+    if (plan->engine != TMC_ENGINE_PLAIN)
+      return fail(TMC_ERR_UNSUPPORTED, "log-factor entry points need a plain-engine plan");
+    if (!plan->logf_err.empty()) return fail(TMC_ERR_INVALID_ARG, "%s", plan->logf_err.c_str());
+    if (plan->n_chains == 0) return TMC_OK;
+    if (!dlogp || (plan->n_pairs > 0 && !f)) return fail(TMC_ERR_INVALID_ARG, "NULL pointer");
+    DeviceGuard g(plan->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->prec == TMC_FP64)
+      return plain_bwd<double>(plan, (const double*)f, nullptr, nullptr, nullptr, dlogp, workspace,
+                               (double*)df, nullptr, nullptr, nullptr, (double*)du, s);
+    return plain_bwd<float>(plan, (const float*)f, nullptr, nullptr, nullptr, dlogp, workspace,
+                            (float*)df, nullptr, nullptr, nullptr, (float*)du, s);
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_plan_graph_capture_gauss(tmc_plan_t plan, int which, const void* z, const void* mu,
+                                        const void* s, const void* u, double* logp,
+                                        const double* dlogp, void* workspace, void* dz, void* dmu,
+                                        void* ds, void* du, void* stream) {
+  try {
+    tmc_status st = check_exec(plan, workspace);
+    if (st != TMC_OK) return st;
+    if (which != 0 && which != 1) return fail(TMC_ERR_INVALID_ARG, "which must be 0 or 1");
+    if (!stream) return fail(TMC_ERR_INVALID_ARG, "graph capture needs a non-default stream");
+    DeviceGuard g(plan->device);
+    hipStream_t hs = (hipStream_t)stream;
+    HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
+    tmc_status rs = which == 0 ? gauss_fwd_impl(plan, z, mu, s, u, logp, workspace, hs)
+                               : gauss_bwd_impl(plan, z, mu, s, u, dlogp, workspace, dz, dmu, ds,
+                                                du, hs);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(hs, &graph);
+    if (rs != TMC_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rs;
+    }
+    if (e != hipSuccess) return fail(TMC_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (plan->graph[which]) {
+      (void)hipGraphExecDestroy(plan->graph[which]);
+      plan->graph[which] = nullptr;
+    }
+    e = hipGraphInstantiate(&plan->graph[which], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(TMC_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return TMC_OK;
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_plan_graph_launch(tmc_plan_t plan, int which, void* stream) {
+  if (!plan) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+  if (which != 0 && which != 1) return fail(TMC_ERR_INVALID_ARG, "which must be 0 or 1");
+  if (!plan->graph[which]) return fail(TMC_ERR_STATE, "no graph captured for which=%d", which);
+  DeviceGuard g(plan->device);
+  HIP_TRY(hipGraphLaunch(plan->graph[which], (hipStream_t)stream));
+  return TMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+// Internal declarations shared by the host runtime and the kernels of libtmc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tmc {
+
+constexpr int kPlainMaxK = 4096;      // plain engine: one column vector must fit in LDS
+constexpr int kPlainMaxD = 4096;
+constexpr int kFusedMaxD = 256;       // fused engine: row operands held in registers
+constexpr int kFusedMaxK = 1 << 16;
+
+// Device flag bits (plan-owned word, read by tmc_plan_check).
+constexpr int kFlagNonFinite = 1;
+
+// Per latent layer of every chain, indexed by the global layer id of the problem.
+// A non-top layer l is the row layer of pair (l, l+1); its fields *_up describe
+// the layer above (the column layer of that pair).
+struct LayerDev {
+  int32_t K, D;          // samples and dimension of this layer
+  int32_t Kc;            // samples of the layer above (0 for a top layer)
+  int32_t chain;         // owning chain
+  int32_t up;            // global id of the layer above, -1 for a top layer
+  int32_t depth;         // index within the chain (0 = next to the data)
+  // caller buffer offsets (elements)
+  int64_t z_off, u_off, mu_off, s_off, f_off;
+  int64_t u_up_off;      // u offset of the layer above
+  // workspace offsets (elements of the region they index)
+  int64_t alpha_off;     // double alpha[K]
+  int64_t p_off;         // T p[K]            (marginal of this layer's samples)
+  int64_t rl_off;        // T rowlse[K]       (row log-sum-exp of the pair's forward)
+  int64_t alpha_up_off;  // alpha of the layer above
+  int64_t p_up_off;      // p of the layer above
+  int64_t wf_off;        // plain: T f/G[K][Kc]
+  int64_t gtz_off;       // plain: T (G^T z)[Kc][D]
+  int64_t dsp_off;       // T ds partial[D] of this pair
+  // fused engine (element offsets into its regions)
+  int64_t opa_off;       // packed row operand (z side)
+  int64_t opb_off;       // packed column operand (mu side)
+  int64_t opbt_off;      // packed mu^T operand (forward P.mu)
+  int64_t opat_off;      // packed z^T operand (backward G^T z)
+  int64_t rterm_off;     // double row constant [Kpad]
+  int64_t cterm_off;     // double column constant [Kcpad]
+  int64_t ev_off;        // float E_softmax[mu] per row [K][D]
+  int64_t cpart_off;     // fused bwd partial column sums
+  int32_t Kpad, Kcpad, Dpad, pad0;
+};
+
+struct ChainDev {
+  int32_t L;
+  int32_t first;         // global id of layer 0
+  int32_t top;           // global id of layer L-1
+  int32_t pad;
+};
+
+struct WsLayout {
+  size_t alpha, p, rl, pairM, logp, flags_unused;
+  size_t wf, wg, gtz, dsp;          // plain engine
+  size_t opa, opb, opbt, opat, rterm, cterm, ev, cpart;   // fused engine
+  size_t total;
+};
+
+// Work item of a level-synchronous launch: a layer (pair) and a block start.
+struct Item {
+  int32_t layer;
+  int32_t start;
+};
+
+}  // namespace tmc

@@ -1,0 +1,59 @@
+// Launchers of the libtmc kernels (host-callable, defined next to their kernels).
+#pragma once
+
+#include "tmc_internal.h"
+
+namespace tmc {
+
+// ---- common (k_common.hip) ----
+template <typename T>
+hipError_t launch_init_top(const ChainDev* chains, int n_chains, const LayerDev* layers,
+                           const T* u, double* alpha, hipStream_t st);
+hipError_t launch_finalize(const ChainDev* chains, int n_chains, const LayerDev* layers,
+                           const double* alpha, double* logp, double* logp_ws, int* flag,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_bwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
+                           const double* alpha, const double* logp_ws, const double* dlogp,
+                           T* p, T* du, T* dz, hipStream_t st);
+template <typename T>
+hipError_t launch_ds_reduce(const int* slot_layers, const int* slot_start, const int64_t* slot_soff,
+                            const int* slot_D, int n_slots, const LayerDev* layers, const T* dsp,
+                            T* ds, hipStream_t st);
+
+// ---- plain engine (k_plain.hip) ----
+template <typename T>
+hipError_t launch_plain_factor(const LayerDev* layers, const Item* items, int n_items,
+                               const T* z, const T* mu, const T* s, T* f, bool caller_off,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_plain_lse_fwd(const LayerDev* layers, const Item* items, int n_items,
+                                int max_kc, const T* f, bool caller_off, const T* u, double* alpha, T* rl,
+                                double* pairM, hipStream_t st);
+template <typename T>
+hipError_t launch_plain_lse_bwd(const LayerDev* layers, const Item* items, int n_items, int vec,
+                                const T* f, bool caller_off, const double* alpha,
+                                const T* rl, const double* pairM, const double* dlogp, T* p,
+                                T* g_out, bool g_caller_off, bool scale_by_dlogp, T* du,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_plain_gmu(const LayerDev* layers, const Item* items, int n_items,
+                            const T* g, const T* z, const T* mu, const T* s, const T* p,
+                            const double* dlogp, T* dz, hipStream_t st);
+template <typename T>
+hipError_t launch_plain_gtz(const LayerDev* layers, const Item* items, int n_items,
+                            const T* g, const T* z, const T* mu, const T* s, const T* p,
+                            const double* dlogp, T* gtz, T* dmu, hipStream_t st);
+template <typename T>
+hipError_t launch_pair_dsp(const LayerDev* layers, const int* pair_ids, int n_pairs,
+                           const T* z, const T* mu, const T* s, const T* p, const T* gtz,
+                           const double* dlogp, T* dsp, hipStream_t st);
+
+// plain tiling constants (host and device agree)
+constexpr int kPlainFactorRows = 32, kPlainFactorCols = 64;
+constexpr int kPlainFwdRowsPerBlock = 16;      // 4 waves x 4 rows
+constexpr int kPlainBwdColsScalar = 64;        // one column per lane
+constexpr int kPlainBwdColsVec = 256;          // four columns per lane (float4 / 2x double2)
+constexpr int kPlainGemmRows = 32, kPlainGemmD = 64;
+
+}  // namespace tmc

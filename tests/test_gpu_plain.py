@@ -1,0 +1,204 @@
+"""GPU parity of the plain engine (materialised factors) against the FP64 oracle,
+through the C ABI.  Tolerances: FP64 log P within 1e-9 relative; FP32 log P within
+1e-4 absolute (both on the same cast inputs); gradients as stated per test."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tmc_oracle as O
+from workloads import Chain, make
+
+from .gpu_helpers import cast_chains, oracle_grads, rel_l2, run_gauss, torch, unpack
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand_chain(rng, Ks, Ds, scale=1.0):
+    L = len(Ks)
+    z = [rng.normal(size=(Ks[l], Ds[l])) for l in range(L)]
+    mu = [np.tanh(rng.normal(size=(Ks[l + 1], Ds[l]))) * scale for l in range(L - 1)]
+    s = [rng.uniform(-1.0, 0.0, size=Ds[l]) for l in range(L - 1)]
+    u = [rng.normal(size=Ks[l]) * 5.0 for l in range(L)]
+    return Chain(z=z, mu=mu, s=s, u=u)
+
+
+def _check_grads(out, chains, tol):
+    ref = oracle_grads(chains)
+    dz = unpack(out["dz"], chains, "z")
+    dmu = unpack(out["dmu"], chains, "mu")
+    ds = unpack(out["ds"], chains, "s")
+    du = unpack(out["du"], chains, "u")
+    for c, (lp, rdz, rdmu, rds, rdu) in enumerate(ref):
+        for l in range(len(rdz)):
+            assert rel_l2(dz[c][l], rdz[l]) < tol, ("dz", c, l, rel_l2(dz[c][l], rdz[l]))
+            assert rel_l2(du[c][l], rdu[l]) < tol, ("du", c, l)
+        for l in range(len(rdmu)):
+            assert rel_l2(dmu[c][l], rdmu[l]) < tol, ("dmu", c, l, rel_l2(dmu[c][l], rdmu[l]))
+            assert rel_l2(ds[c][l], rds[l]) < tol, ("ds", c, l, rel_l2(ds[c][l], rds[l]))
+
+
+def test_c1_fp64_matches_oracle_and_brute_force():
+    w = make("c1")
+    out = run_gauss(w.chains, "fp64", engine="plain")
+    assert out["info"]["engine"] == 2
+    for b, c in enumerate(w.chains):
+        f = O.gauss_chain_factors(c.z, c.mu, c.s)
+        ref = O.brute_force_logp(f, c.u)
+        assert abs(out["logp"][b] - ref) <= 1e-9 * max(1.0, abs(ref))
+    _check_grads(out, w.chains, 1e-8)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ragged_tails_match_oracle(prec):
+    """Shapes that are not multiples of any tile: K in {1,3,17,63,65,130,257}, D in
+    {1,3,33,65,100}, chains of 1..5 layers (one-layer chains are IWAE)."""
+    rng = np.random.default_rng(123)
+    shapes = [((3,), (2,)), ((17, 3), (5, 1)), ((63, 65, 130), (33, 3, 65)),
+              ((1, 1, 1), (4, 4, 4)), ((257, 17, 64, 5, 9), (100, 7, 2, 1, 3)),
+              ((130, 257), (65, 16))]
+    chains = [_rand_chain(rng, Ks, Ds) for Ks, Ds in shapes]
+    chains = cast_chains(chains, prec)
+    out = run_gauss(chains, prec, engine="plain")
+    for b, c in enumerate(chains):
+        ref = O.gauss_chain_logp(c.z, c.mu, c.s, c.u)
+        if prec == "fp64":
+            assert abs(out["logp"][b] - ref) <= 1e-9 * max(1.0, abs(ref)), (b, out["logp"][b], ref)
+        else:
+            assert abs(out["logp"][b] - ref) <= 1e-4, (b, out["logp"][b], ref)
+    _check_grads(out, chains, 1e-8 if prec == "fp64" else 2e-3)
+
+
+def test_c2_fp32_subset_matches_oracle():
+    w = make("c2", B=8)
+    chains = cast_chains(w.chains, "fp32")
+    out = run_gauss(chains, "fp32", engine="plain")
+    errs = []
+    for b, c in enumerate(chains):
+        ref = O.gauss_chain_logp(c.z, c.mu, c.s, c.u)
+        errs.append(abs(out["logp"][b] - ref))
+    assert max(errs) <= 1e-4, errs
+    _check_grads(out, chains, 2e-3)
+
+
+def test_shared_s_gradient_is_summed_over_batch():
+    """Homogeneous layout: s [L-1, D] shared by all chains; ds is the batch sum."""
+    from paper_1806_08593_amd import autograd as A
+    w = make("c1", B=5)
+    B, L, K, D = w.z.shape
+    run = A.GaussChainTMC(B, L, K, D, precision="fp64", engine="plain")
+    t = {k: torch.tensor(getattr(w, k), device="cuda:0", requires_grad=True)
+         for k in ("z", "mu", "s", "u")}
+    logp = run(t["z"], t["mu"], t["s"], t["u"])
+    wts = torch.arange(1, B + 1, dtype=torch.float64, device="cuda:0")
+    (logp * wts).sum().backward()
+    ref = oracle_grads(w.chains)
+    ds_ref = sum((b + 1) * np.stack(r[3]) for b, r in enumerate(ref))
+    np.testing.assert_allclose(t["s"].grad.cpu().numpy(), ds_ref, rtol=1e-9, atol=1e-9)
+    dz_ref = np.stack([(b + 1) * np.stack(r[1]) for b, r in enumerate(ref)])
+    np.testing.assert_allclose(t["z"].grad.cpu().numpy(), dz_ref, rtol=1e-9, atol=1e-9)
+    for b, c in enumerate(w.chains):
+        assert abs(logp[b].item() - O.gauss_chain_logp(c.z, c.mu, c.s, c.u)) < 1e-9 * 1e3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_logfactor_hmm_is_exact(prec):
+    """Exact discrete marginalisation (Appendix): TMC over caller-supplied log-factors
+    equals log P(x) of the HMM; df are the pairwise marginals (sum to 1)."""
+    from paper_1806_08593_amd import tmc as T
+    rng = np.random.default_rng(7)
+    S = [(5, 7, 3, 6), (64, 64, 64), (300, 2), (9,)]
+    shapes, fl, ul, refs, fs_all, us_all = [], [], [], [], [], []
+    for Ss in S:
+        L = len(Ss)
+        prior = rng.dirichlet(np.ones(Ss[-1]))
+        trans = [rng.dirichlet(np.ones(Ss[l]), size=Ss[l + 1]).T for l in range(L - 1)]
+        emit = np.log(rng.uniform(0.05, 1.0, size=Ss[0]))
+        f = [np.log(trans[l]) for l in range(L - 1)]
+        u = [np.full(Ss[l], math.log(Ss[l])) for l in range(L)]
+        u[0] = u[0] + emit
+        u[-1] = u[-1] + np.log(prior)
+        dt = np.float64 if prec == "fp64" else np.float32
+        f = [a.astype(dt).astype(np.float64) for a in f]
+        u = [a.astype(dt).astype(np.float64) for a in u]
+        shapes.append((list(Ss), [1] * L))
+        fl += [a.reshape(-1) for a in f]
+        ul += [a.reshape(-1) for a in u]
+        refs.append(O.chain_logp(f, u))
+        fs_all.append(f)
+        us_all.append(u)
+        if prec == "fp64":
+            assert abs(refs[-1] - O.hmm_log_evidence(prior, trans, emit)) < 1e-10
+    prob, sizes = T.ragged_problem(shapes, prec, "plain")
+    plan = T.Plan(prob)
+    ws = plan.new_workspace()
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    f_d = torch.tensor(np.concatenate(fl), dtype=tdt, device="cuda:0")
+    u_d = torch.tensor(np.concatenate(ul), dtype=tdt, device="cuda:0")
+    logp = torch.empty(len(S), dtype=torch.float64, device="cuda:0")
+    T.tmc_logfactor_fwd(plan.handle, f_d, u_d, logp, ws)
+    df = torch.full_like(f_d, float("nan"))
+    du = torch.full_like(u_d, float("nan"))
+    dl = torch.full((len(S),), 2.0, dtype=torch.float64, device="cuda:0")
+    T.tmc_logfactor_bwd(plan.handle, f_d, u_d, dl, ws, df, du)
+    torch.cuda.synchronize()
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    for b in range(len(S)):
+        assert abs(logp[b].item() - refs[b]) <= tol * (max(1, abs(refs[b])) if prec == "fp64" else 1)
+    df = df.cpu().numpy()
+    du = du.cpu().numpy()
+    o = ou = 0
+    for b in range(len(S)):
+        lp, G, p = O.chain_marginals(fs_all[b], us_all[b])
+        for g in G:
+            got = df[o:o + g.size].reshape(g.shape)
+            np.testing.assert_allclose(got, 2.0 * g, atol=1e-12 if prec == "fp64" else 1e-5)
+            o += g.size
+        for q in p:
+            np.testing.assert_allclose(du[ou:ou + q.size], 2.0 * q, atol=1e-12 if prec == "fp64" else 1e-5)
+            ou += q.size
+
+
+def test_minus_inf_and_nan_inputs():
+    """A chain whose every weight is zero gives log P = -inf (not NaN) and zero
+    gradients; a NaN input gives NaN and raises the device flag."""
+    from paper_1806_08593_amd import tmc as T
+    rng = np.random.default_rng(9)
+    good = _rand_chain(rng, (6, 5, 4), (3, 3, 3))
+    dead = _rand_chain(rng, (6, 5, 4), (3, 3, 3))
+    dead.u[1][:] = -np.inf
+    bad = _rand_chain(rng, (6, 5), (3, 3))
+    bad.u[0][2] = np.nan
+    out = run_gauss([good, dead], "fp64", engine="plain")
+    assert abs(out["logp"][0] - O.gauss_chain_logp(good.z, good.mu, good.s, good.u)) < 1e-9 * 100
+    assert out["logp"][1] == -np.inf
+    n0 = sum(a.size for a in good.z)
+    assert np.all(out["dz"][n0:] == 0.0)
+    with pytest.raises(T.TMCError) as ei:
+        run_gauss([good, bad], "fp64", engine="plain")
+    assert ei.value.status == T.TMC_ERR_NUMERIC
+
+
+def test_graph_replay_equals_eager():
+    from paper_1806_08593_amd import tmc as T
+    from .gpu_helpers import pack_chains, to_dev
+    w = make("c2", B=4)
+    chains = cast_chains(w.chains, "fp32")
+    shapes, flat = pack_chains(chains, "fp32")
+    prob, _ = T.ragged_problem(shapes, "fp32", "plain")
+    plan = T.Plan(prob)
+    ws = plan.new_workspace()
+    d = {k: to_dev(v) for k, v in flat.items()}
+    st = torch.cuda.Stream()
+    logp_e = torch.empty(4, dtype=torch.float64, device="cuda:0")
+    logp_g = torch.empty(4, dtype=torch.float64, device="cuda:0")
+    with torch.cuda.stream(st):
+        T.tmc_gauss_fwd(plan.handle, d["z"], d["mu"], d["s"], d["u"], logp_e, ws, st)
+        torch.cuda.synchronize()
+        T.tmc_plan_graph_capture_gauss(plan.handle, 0, d["z"], d["mu"], d["s"], d["u"], logp_g,
+                                       None, ws, None, None, None, None, st)
+        for rep in range(3):
+            logp_g.fill_(0.0)
+            T.tmc_plan_graph_launch(plan.handle, 0, st)
+            st.synchronize()
+            assert torch.equal(logp_g, logp_e), rep
