@@ -216,6 +216,29 @@ tmc_status tmc_plan_graph_capture_gauss(tmc_plan_t plan, int which, const void* 
                                         void* stream);
 tmc_status tmc_plan_graph_launch(tmc_plan_t plan, int which, void* stream);
 
+/* ---- measurement ---- */
+/* Kernel classes timed by the plan's optional event timer. */
+typedef enum tmc_kernel_class {
+  TMC_KC_PLAIN_FACTOR = 0,   /* plain: materialise f_l */
+  TMC_KC_PLAIN_LSE_FWD = 1,  /* plain: streaming row log-sum-exp (forward messages) */
+  TMC_KC_PLAIN_LSE_BWD = 2,  /* plain: column-strip marginals (backward messages) */
+  TMC_KC_PLAIN_GRAD = 3,     /* plain: Gaussian gradients from the marginals */
+  TMC_KC_FUSED_PREP = 4,     /* fused: operand packing and row/column constants */
+  TMC_KC_FUSED_FWD = 5,      /* fused: factor GEMM + forward message */
+  TMC_KC_FUSED_BWD = 6,      /* fused: factor GEMM + marginals + gradient GEMM */
+  TMC_KC_OTHER = 7,          /* initialisation, log-normaliser, reductions */
+  TMC_KC_COUNT = 8
+} tmc_kernel_class;
+
+/* enable != 0: every later execute call on this plan records a hipEvent pair around
+ * each kernel launch, on the stream the kernel runs on (up to a fixed pool of
+ * events; launches beyond it are not timed).  Clears accumulated times.  Not for use
+ * inside graph capture.  enable == 0 turns it off. */
+tmc_status tmc_plan_set_timing(tmc_plan_t plan, int enable);
+/* Synchronises the recorded events and returns, for kernel class `kc`, the summed
+ * device time of its timed launches (ms) and their count. */
+tmc_status tmc_plan_timing(tmc_plan_t plan, int kc, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,4 +1,5 @@
-// Fused engine interface: factors recomputed on MFMA inside the message kernels.
+// Fused engine interface (host side): schedules and launches of the kernels that
+// recompute the pairwise factors on MFMA inside the message passes.
 #pragma once
 
 #include <vector>
@@ -8,37 +9,50 @@
 
 namespace tmc {
 
-constexpr bool kFusedAvailable = false;
+constexpr bool kFusedAvailable = true;
+
+// Instantiated numbers of 16-wide d chunks (a layer of width D uses the smallest
+// bucket >= ceil(D / 16); padding lanes read zeros).
+constexpr int kNkcBuckets[] = {1, 2, 3, 4, 5, 6, 7, 8, 12, 16};
+constexpr int kNumNkcBuckets = sizeof(kNkcBuckets) / sizeof(int);
+
+struct FusedLaunch {
+  int off = 0, n = 0, nkc = 0;
+};
 
 struct FusedPlan {
   int prec = 0, flags = 0;
+  std::vector<std::vector<FusedLaunch>> fwd, bwd;   // [depth step][nkc group]
+  int n_pairs = 0;
+  int pair_ids_off = 0;                             // into the plan's int table
 };
 
-struct FusedArgs {
-  const void *z, *mu, *s, *u;
-  double* logp;
-  const double* dlogp;
-  void *dz, *dmu, *ds, *du;
-  void* ws;
-  hipStream_t stream;
-  const ChainDev* chains_d;
-  const LayerDev* layers_d;
-  int n_chains;
-  int* flag_d;
-  const WsLayout* ws_layout;
-  const int* ints_d;
-  const int64_t* slot_soff_d;
-  int n_slots, slot_layers_off, slot_start_off, slot_D_off;
-};
+int nkc_bucket(int D);
 
-inline tmc_status fused_build(FusedPlan&, int, int, std::vector<LayerDev>&, const std::vector<ChainDev>&,
-                              const std::vector<int>&, WsLayout&, std::vector<Item>&) {
-  return TMC_ERR_UNSUPPORTED;
-}
-inline tmc_status fused_upload(FusedPlan&) { return TMC_ERR_UNSUPPORTED; }
-inline tmc_status fused_fwd(FusedPlan&, const FusedArgs&) { return TMC_ERR_UNSUPPORTED; }
-inline tmc_status fused_bwd(FusedPlan&, const FusedArgs&) { return TMC_ERR_UNSUPPORTED; }
-inline void fused_release(FusedPlan&) {}
-inline void fused_info(const FusedPlan&, tmc_plan_info*) {}
+// Lays out the fused engine's workspace regions (appending at offset `o`), assigns its
+// per-layer offsets and appends its work items.
+tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>& layers,
+                       const std::vector<ChainDev>& chains, const std::vector<int>& pairs,
+                       WsLayout& W, size_t& o, std::vector<Item>& items);
+void fused_info(const FusedPlan& F, tmc_plan_info* out);
+
+// kernel launchers (k_fused_*.hip)
+template <int PREC>
+hipError_t launch_fused_fwd(int nkc, bool grad, const LayerDev* layers, const Item* items, int n,
+                            const float* z, const float* mu, const float* s, const float* u,
+                            double* alpha, float* rl, float* ev, hipStream_t st);
+template <int PREC>
+hipError_t launch_fused_bwd(int nkc, const LayerDev* layers, const Item* items, int n,
+                            const float* z, const float* mu, const float* s, const double* alpha,
+                            const float* rl, float* lam, const double* dlogp, float* p, float* dmu,
+                            float* du, hipStream_t st);
+hipError_t launch_fused_bwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
+                                 const double* alpha, const double* logp_ws, const double* dlogp,
+                                 const float* rl, float* lam, float* p, float* du, float* dz,
+                                 hipStream_t st);
+hipError_t launch_fused_rowep(const LayerDev* layers, const int* pair_ids, int n_pairs,
+                              const float* z, const float* mu, const float* s, const float* p,
+                              const float* ev, const double* dlogp, float* dz, float* dsp,
+                              hipStream_t st);
 
 }  // namespace tmc

@@ -92,10 +92,18 @@ struct tmc_plan {
   std::string gauss_err, logf_err;
   // graphs
   hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool capturing = false;
+  // optional per-launch event timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;   // (kernel class, index of start event)
+  double kc_ms[TMC_KC_COUNT] = {0};
+  int64_t kc_n[TMC_KC_COUNT] = {0};
   ~tmc_plan() {
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (auto& g : graph)
       if (g) (void)hipGraphExecDestroy(g);
-    fused_release(fused);
     if (chains_d) (void)hipFree(chains_d);
     if (layers_d) (void)hipFree(layers_d);
     if (items_d) (void)hipFree(items_d);
@@ -403,9 +411,8 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   // fused engine layout and schedules
   if (P->engine == TMC_ENGINE_FUSED) {
     tmc_status st = fused_build(P->fused, P->prec, P->flags, P->layers_h, P->chains_h, pairs,
-                                P->ws, items);
-    if (st != TMC_OK) return st;
-    P->ws.total = align_up(P->ws.total, 256);
+                                P->ws, o, items);
+    if (st != TMC_OK) return fail(st, "fused engine: unsupported layer width");
   }
 
   // upload
@@ -427,10 +434,6 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
                  slot_soff.size() * sizeof(int64_t)));
   HIP_TRY(hipMalloc((void**)&P->flag_d, sizeof(int)));
   HIP_TRY(hipMemset(P->flag_d, 0, sizeof(int)));
-  if (P->engine == TMC_ENGINE_FUSED) {
-    tmc_status st = fused_upload(P->fused);
-    if (st != TMC_OK) return st;
-  }
   HIP_TRY(hipDeviceSynchronize());
   return TMC_OK;
 }
@@ -445,12 +448,30 @@ tmc_status check_exec(tmc_plan* P, void* ws) {
   return TMC_OK;
 }
 
-#define LAUNCH(expr)                                                                 \
+// Records an event pair around one launch when the plan's timer is on.
+struct TimedScope {
+  tmc_plan* P;
+  hipStream_t st;
+  bool on = false;
+  TimedScope(tmc_plan* p, int kc, hipStream_t s) : P(p), st(s) {
+    if (!P->timing || P->capturing || P->ev_used + 2 > P->ev_pool.size()) return;
+    P->ev_marks.push_back({kc, P->ev_used});
+    on = hipEventRecord(P->ev_pool[P->ev_used], st) == hipSuccess;
+    P->ev_used += 2;
+  }
+  ~TimedScope() {
+    if (on) (void)hipEventRecord(P->ev_pool[P->ev_marks.back().second + 1], st);
+  }
+};
+
+#define LAUNCH_KC(kc, expr)                                                          \
   do {                                                                               \
+    TimedScope ts_(P, kc, st);                                                       \
     hipError_t e_ = (expr);                                                          \
     if (e_ != hipSuccess)                                                            \
       return fail(TMC_ERR_HIP, "kernel launch %s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+#define LAUNCH(expr) LAUNCH_KC(TMC_KC_OTHER, expr)
 
 // ---- plain engine ----
 template <typename T>
@@ -461,11 +482,11 @@ tmc_status plain_fwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, co
   const bool caller = f_caller != nullptr;
   T* wf = wsp<T>(ws, W.wf);
   const T* f = caller ? f_caller : wf;
-  if (!caller)
-    LAUNCH(launch_plain_factor<T>(P->layers_d, it + P->factor.off, P->factor.n, z, mu, s, wf, false, st));
+  if (!caller && P->factor.n > 0)
+    LAUNCH_KC(TMC_KC_PLAIN_FACTOR, launch_plain_factor<T>(P->layers_d, it + P->factor.off, P->factor.n, z, mu, s, wf, false, st));
   LAUNCH(launch_init_top<T>(P->chains_d, P->n_chains, P->layers_d, u, wsp<double>(ws, W.alpha), st));
   for (size_t t = 0; t < P->fwd.size(); ++t)
-    LAUNCH(launch_plain_lse_fwd<T>(P->layers_d, it + P->fwd[t].off, P->fwd[t].n, P->fwd_maxkc[t], f,
+    LAUNCH_KC(TMC_KC_PLAIN_LSE_FWD, launch_plain_lse_fwd<T>(P->layers_d, it + P->fwd[t].off, P->fwd[t].n, P->fwd_maxkc[t], f,
                                    caller, u, wsp<double>(ws, W.alpha), wsp<T>(ws, W.rl),
                                    wsp<double>(ws, W.pairM), st));
   LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, wsp<double>(ws, W.alpha), logp,
@@ -488,24 +509,81 @@ tmc_status plain_bwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, co
   for (size_t t = 0; t < P->bwd_vec.size(); ++t) {
     for (int pass = 0; pass < 2; ++pass) {
       const Launch& L = pass == 0 ? P->bwd_vec[t] : P->bwd_sca[t];
-      LAUNCH(launch_plain_lse_bwd<T>(P->layers_d, it + L.off, L.n, pass == 0, f, caller,
+      if (L.n > 0) LAUNCH_KC(TMC_KC_PLAIN_LSE_BWD, launch_plain_lse_bwd<T>(P->layers_d, it + L.off, L.n, pass == 0, f, caller,
                                      wsp<double>(ws, W.alpha), wsp<T>(ws, W.rl),
                                      wsp<double>(ws, W.pairM), dlogp, p, g, caller, caller, du, st));
     }
   }
   if (caller) return TMC_OK;
   if (dz)
-    LAUNCH(launch_plain_gmu<T>(P->layers_d, it + P->gmu.off, P->gmu.n, g, z, mu, s, p, dlogp, dz, st));
+    LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_plain_gmu<T>(P->layers_d, it + P->gmu.off, P->gmu.n, g, z, mu, s, p, dlogp, dz, st));
   if (dmu || ds)
-    LAUNCH(launch_plain_gtz<T>(P->layers_d, it + P->gtz.off, P->gtz.n, g, z, mu, s, p, dlogp,
+    LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_plain_gtz<T>(P->layers_d, it + P->gtz.off, P->gtz.n, g, z, mu, s, p, dlogp,
                                wsp<T>(ws, W.gtz), dmu, st));
   if (ds) {
-    LAUNCH(launch_pair_dsp<T>(P->layers_d, P->ints_d + P->pair_ids_off, P->n_pairs, z, mu, s, p,
+    LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_pair_dsp<T>(P->layers_d, P->ints_d + P->pair_ids_off, P->n_pairs, z, mu, s, p,
                               wsp<T>(ws, W.gtz), dlogp, wsp<T>(ws, W.dsp), st));
     LAUNCH(launch_ds_reduce<T>(P->ints_d + P->slot_layers_off, P->ints_d + P->slot_start_off,
                                P->slot_soff_d, P->ints_d + P->slot_D_off, P->n_slots, P->layers_d,
                                wsp<T>(ws, W.dsp), ds, st));
   }
+  return TMC_OK;
+}
+
+// ---- fused engine ----
+tmc_status fused_fwd_impl(tmc_plan* P, const float* z, const float* mu, const float* s,
+                          const float* u, double* logp, void* ws, hipStream_t st) {
+  const WsLayout& W = P->ws;
+  const bool grad = !(P->flags & TMC_FLAG_FORWARD_ONLY);
+  double* alpha = wsp<double>(ws, W.alpha);
+  float* rl = wsp<float>(ws, W.rl);
+  float* ev = wsp<float>(ws, W.ev);
+  LAUNCH(launch_init_top<float>(P->chains_d, P->n_chains, P->layers_d, u, alpha, st));
+  for (auto& step : P->fused.fwd)
+    for (auto& g : step) {
+      const Item* it = P->items_d + g.off;
+      if (P->prec == TMC_FP32)
+        LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_FP32>(g.nkc, grad, P->layers_d, it, g.n, z,
+                                                               mu, s, u, alpha, rl, ev, st));
+      else
+        LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_BF16X3>(g.nkc, grad, P->layers_d, it, g.n,
+                                                                 z, mu, s, u, alpha, rl, ev, st));
+    }
+  LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, alpha, logp,
+                         wsp<double>(ws, W.logp), P->flag_d, st));
+  return TMC_OK;
+}
+
+tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const float* s,
+                          const double* dlogp, void* ws, float* dz, float* dmu, float* ds,
+                          float* du, hipStream_t st) {
+  const WsLayout& W = P->ws;
+  double* alpha = wsp<double>(ws, W.alpha);
+  float* rl = wsp<float>(ws, W.rl);
+  float* lam = wsp<float>(ws, W.lam);
+  float* p = wsp<float>(ws, W.p);
+  LAUNCH(launch_fused_bwd_init(P->chains_d, P->n_chains, P->layers_d, alpha,
+                               wsp<double>(ws, W.logp), dlogp, rl, lam, p, du, dz, st));
+  for (auto& step : P->fused.bwd)
+    for (auto& g : step) {
+      const Item* it = P->items_d + g.off;
+      if (P->prec == TMC_FP32)
+        LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_FP32>(g.nkc, P->layers_d, it, g.n, z, mu,
+                                                               s, alpha, rl, lam, dlogp, p, dmu,
+                                                               du, st));
+      else
+        LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_BF16X3>(g.nkc, P->layers_d, it, g.n, z,
+                                                                 mu, s, alpha, rl, lam, dlogp, p,
+                                                                 dmu, du, st));
+    }
+  if ((dz || ds) && P->n_pairs > 0)
+    LAUNCH(launch_fused_rowep(P->layers_d, P->ints_d + P->pair_ids_off, P->n_pairs, z, mu, s, p,
+                              wsp<float>(ws, W.ev), dlogp, dz, ds ? wsp<float>(ws, W.dsp) : nullptr,
+                              st));
+  if (ds)
+    LAUNCH(launch_ds_reduce<float>(P->ints_d + P->slot_layers_off, P->ints_d + P->slot_start_off,
+                                   P->slot_soff_d, P->ints_d + P->slot_D_off, P->n_slots,
+                                   P->layers_d, wsp<float>(ws, W.dsp), ds, st));
   return TMC_OK;
 }
 
@@ -515,13 +593,9 @@ tmc_status gauss_fwd_impl(tmc_plan* P, const void* z, const void* mu, const void
   if (P->n_chains == 0) return TMC_OK;
   if (!u || !logp || (P->n_pairs > 0 && (!z || !mu || !s)))
     return fail(TMC_ERR_INVALID_ARG, "NULL input or output pointer");
-  if (P->engine == TMC_ENGINE_FUSED) {
-    FusedArgs a{};
-    a.z = z; a.mu = mu; a.s = s; a.u = u; a.logp = logp; a.ws = ws; a.stream = st;
-    a.chains_d = P->chains_d; a.layers_d = P->layers_d; a.n_chains = P->n_chains;
-    a.flag_d = P->flag_d; a.ws_layout = &P->ws;
-    return fused_fwd(P->fused, a);
-  }
+  if (P->engine == TMC_ENGINE_FUSED)
+    return fused_fwd_impl(P, (const float*)z, (const float*)mu, (const float*)s, (const float*)u,
+                          logp, ws, st);
   if (P->prec == TMC_FP64)
     return plain_fwd<double>(P, nullptr, (const double*)z, (const double*)mu, (const double*)s,
                              (const double*)u, logp, ws, st);
@@ -539,15 +613,8 @@ tmc_status gauss_bwd_impl(tmc_plan* P, const void* z, const void* mu, const void
   if (P->engine == TMC_ENGINE_FUSED) {
     if (P->flags & TMC_FLAG_FORWARD_ONLY)
       return fail(TMC_ERR_STATE, "plan was created with TMC_FLAG_FORWARD_ONLY");
-    FusedArgs a{};
-    a.z = z; a.mu = mu; a.s = s; a.u = u; a.dlogp = dlogp; a.ws = ws; a.stream = st;
-    a.dz = dz; a.dmu = dmu; a.ds = ds; a.du = du;
-    a.chains_d = P->chains_d; a.layers_d = P->layers_d; a.n_chains = P->n_chains;
-    a.flag_d = P->flag_d; a.ws_layout = &P->ws;
-    a.ints_d = P->ints_d; a.slot_soff_d = P->slot_soff_d;
-    a.n_slots = P->n_slots; a.slot_layers_off = P->slot_layers_off;
-    a.slot_start_off = P->slot_start_off; a.slot_D_off = P->slot_D_off;
-    return fused_bwd(P->fused, a);
+    return fused_bwd_impl(P, (const float*)z, (const float*)mu, (const float*)s, dlogp, ws,
+                          (float*)dz, (float*)dmu, (float*)ds, (float*)du, st);
   }
   if (P->prec == TMC_FP64)
     return plain_bwd<double>(P, nullptr, (const double*)z, (const double*)mu, (const double*)s,
@@ -705,6 +772,7 @@ tmc_status tmc_gauss_factors(tmc_plan_t plan, const void* z, const void* mu, con
     DeviceGuard g(plan->device);
     const Item* it = plan->items_d + plan->factor.off;
     hipStream_t st = (hipStream_t)stream;
+    tmc_plan* P = plan;
     if (plan->prec == TMC_FP64)
       LAUNCH(launch_plain_factor<double>(plan->layers_d, it, plan->factor.n, (const double*)z,
                                          (const double*)mu, (const double*)s, (double*)f, true, st));
@@ -774,9 +842,11 @@ tmc_status tmc_plan_graph_capture_gauss(tmc_plan_t plan, int which, const void* 
     DeviceGuard g(plan->device);
     hipStream_t hs = (hipStream_t)stream;
     HIP_TRY(hipStreamBeginCapture(hs, hipStreamCaptureModeThreadLocal));
+    plan->capturing = true;
     tmc_status rs = which == 0 ? gauss_fwd_impl(plan, z, mu, s, u, logp, workspace, hs)
                                : gauss_bwd_impl(plan, z, mu, s, u, dlogp, workspace, dz, dmu, ds,
                                                 du, hs);
+    plan->capturing = false;
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(hs, &graph);
     if (rs != TMC_OK) {
@@ -803,6 +873,47 @@ tmc_status tmc_plan_graph_launch(tmc_plan_t plan, int which, void* stream) {
   if (!plan->graph[which]) return fail(TMC_ERR_STATE, "no graph captured for which=%d", which);
   DeviceGuard g(plan->device);
   HIP_TRY(hipGraphLaunch(plan->graph[which], (hipStream_t)stream));
+  return TMC_OK;
+}
+
+tmc_status tmc_plan_set_timing(tmc_plan_t plan, int enable) {
+  if (!plan) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+  try {
+    DeviceGuard g(plan->device);
+    plan->timing = enable != 0;
+    plan->ev_used = 0;
+    plan->ev_marks.clear();
+    for (int k = 0; k < TMC_KC_COUNT; ++k) {
+      plan->kc_ms[k] = 0.0;
+      plan->kc_n[k] = 0;
+    }
+    const size_t kPool = 8192;
+    while (enable && plan->ev_pool.size() < kPool) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      plan->ev_pool.push_back(e);
+    }
+    return TMC_OK;
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_plan_timing(tmc_plan_t plan, int kc, double* total_ms, int64_t* launches) {
+  if (!plan || !total_ms || !launches) return fail(TMC_ERR_INVALID_ARG, "NULL argument");
+  if (kc < 0 || kc >= TMC_KC_COUNT) return fail(TMC_ERR_INVALID_ARG, "unknown kernel class %d", kc);
+  DeviceGuard g(plan->device);
+  for (auto& m : plan->ev_marks) {
+    HIP_TRY(hipEventSynchronize(plan->ev_pool[m.second + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, plan->ev_pool[m.second], plan->ev_pool[m.second + 1]));
+    plan->kc_ms[m.first] += ms;
+    plan->kc_n[m.first] += 1;
+  }
+  plan->ev_marks.clear();
+  plan->ev_used = 0;
+  *total_ms = plan->kc_ms[kc];
+  *launches = plan->kc_n[kc];
   return TMC_OK;
 }
 

@@ -35,16 +35,7 @@ struct LayerDev {
   int64_t wf_off;        // plain: T f/G[K][Kc]
   int64_t gtz_off;       // plain: T (G^T z)[Kc][D]
   int64_t dsp_off;       // T ds partial[D] of this pair
-  // fused engine (element offsets into its regions)
-  int64_t opa_off;       // packed row operand (z side)
-  int64_t opb_off;       // packed column operand (mu side)
-  int64_t opbt_off;      // packed mu^T operand (forward P.mu)
-  int64_t opat_off;      // packed z^T operand (backward G^T z)
-  int64_t rterm_off;     // double row constant [Kpad]
-  int64_t cterm_off;     // double column constant [Kcpad]
-  int64_t ev_off;        // float E_softmax[mu] per row [K][D]
-  int64_t cpart_off;     // fused bwd partial column sums
-  int32_t Kpad, Kcpad, Dpad, pad0;
+  int64_t ev_off;        // fused: float softmax-weighted mean of mu per row [K][D]
 };
 
 struct ChainDev {
@@ -54,10 +45,11 @@ struct ChainDev {
   int32_t pad;
 };
 
+// Byte offsets of the workspace regions.
 struct WsLayout {
-  size_t alpha, p, rl, pairM, logp, flags_unused;
-  size_t wf, wg, gtz, dsp;          // plain engine
-  size_t opa, opb, opbt, opat, rterm, cterm, ev, cpart;   // fused engine
+  size_t alpha, p, rl, pairM, logp;
+  size_t wf, wg, gtz, dsp;          // plain engine (dsp shared)
+  size_t ev, lam;                   // fused engine
   size_t total;
 };
 

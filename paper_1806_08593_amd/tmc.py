@@ -73,6 +73,8 @@ _SIGS = {
     "tmc_plan_graph_capture_gauss": (c_int, [_P, c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
                                              _P, _P]),
     "tmc_plan_graph_launch": (c_int, [_P, c_int, _P]),
+    "tmc_plan_set_timing": (c_int, [_P, c_int]),
+    "tmc_plan_timing": (c_int, [_P, c_int, POINTER(c_double), POINTER(c_int64)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -190,6 +192,21 @@ def tmc_plan_graph_capture_gauss(plan, which, z, mu, s, u, logp, dlogp, workspac
 
 def tmc_plan_graph_launch(plan, which, stream=None):
     _check(_lib.tmc_plan_graph_launch(plan, which, _stream(stream)))
+
+
+KERNEL_CLASSES = ["plain_factor", "plain_lse_fwd", "plain_lse_bwd", "plain_grad", "fused_prep",
+                  "fused_fwd", "fused_bwd", "other"]
+
+
+def tmc_plan_set_timing(plan, enable: bool):
+    _check(_lib.tmc_plan_set_timing(plan, int(bool(enable))))
+
+
+def tmc_plan_timing(plan, kc: int):
+    """(total ms, launches) of kernel class kc since timing was enabled."""
+    ms, n = c_double(), c_int64()
+    _check(_lib.tmc_plan_timing(plan, kc, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 # ---------------------------------------------------------------------------

@@ -72,6 +72,8 @@ def test_validation_errors():
     _expect(T.homogeneous_problem(2, 3, 0, 5), T.TMC_ERR_SHAPE, "K=0")
     _expect(T.homogeneous_problem(2, 3, 4, 0, engine="plain"), T.TMC_ERR_SHAPE, "D=0")
     _expect(T.homogeneous_problem(1, 2, 5000, 4, precision="fp64"), T.TMC_ERR_SHAPE)
+    _expect(T.homogeneous_problem(1, 2, 64, 300, precision="bf16x3"), T.TMC_ERR_SHAPE, "D=300")
+    _expect(T.homogeneous_problem(1, 2, 64, 8, precision="fp64", engine="fused"), T.TMC_ERR_UNSUPPORTED)
     _expect(T.homogeneous_problem(1, 2, 8, 4, precision="bf16x3", engine="plain"),
             T.TMC_ERR_UNSUPPORTED)
     # chains sharing a layer, chain out of range

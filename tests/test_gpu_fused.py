@@ -1,0 +1,161 @@
+"""GPU parity of the fused engine (factors recomputed on MFMA, never stored) against
+the FP64 oracle on the same cast inputs, through the C ABI.
+
+Tolerances on log P per instance: FP32 1e-4 absolute, BF16X3 2e-3 absolute.
+Gradients (relative L2 per layer block against the oracle's closed-form gradients):
+FP32 1e-3, BF16X3 1e-2 -- see the design doc for how these follow from the arithmetic."""
+import numpy as np
+import pytest
+
+from oracle import tmc_oracle as O
+from workloads import Chain, make
+
+from .gpu_helpers import cast_chains, oracle_grads, pack_chains, rel_l2, run_gauss, to_dev, torch, unpack
+
+pytestmark = pytest.mark.gpu
+
+LOGP_TOL = {"fp32": 1e-4, "bf16x3": 2e-3}
+GRAD_TOL = {"fp32": 1e-3, "bf16x3": 1e-2}
+
+
+def _rand_chain(rng, Ks, Ds):
+    L = len(Ks)
+    z = [rng.normal(size=(Ks[l], Ds[l])) for l in range(L)]
+    mu = [np.tanh(rng.normal(size=(Ks[l + 1], Ds[l]))) for l in range(L - 1)]
+    s = [rng.uniform(-1.0, 0.0, size=Ds[l]) for l in range(L - 1)]
+    u = [rng.normal(size=Ks[l]) * 5.0 for l in range(L)]
+    return Chain(z=z, mu=mu, s=s, u=u)
+
+
+def _check(out, chains, prec, grads=True):
+    errs = []
+    for b, c in enumerate(chains):
+        ref = O.gauss_chain_logp(c.z, c.mu, c.s, c.u)
+        errs.append(abs(out["logp"][b] - ref))
+    assert max(errs) <= LOGP_TOL[prec], errs
+    if not grads:
+        return errs
+    ref = oracle_grads(chains)
+    tol = GRAD_TOL[prec]
+    for name, key, idx in (("dz", "z", 1), ("dmu", "mu", 2), ("ds", "s", 3), ("du", "u", 4)):
+        got = unpack(out[name], chains, key)
+        for c, r in enumerate(ref):
+            for l, rb in enumerate(r[idx]):
+                if np.linalg.norm(rb) == 0:
+                    assert np.abs(got[c][l]).max() == 0, (name, c, l)
+                    continue
+                e = rel_l2(got[c][l], rb)
+                assert e < tol, (name, c, l, e)
+    return errs
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fused_ragged_tails(prec):
+    """K and D off every tile boundary (K 1..300, D 1..256), chains of 1-5 layers."""
+    rng = np.random.default_rng(321)
+    shapes = [((3,), (2,)), ((17, 3), (5, 1)), ((63, 65, 130), (33, 3, 65)),
+              ((1, 1, 1), (4, 4, 4)), ((257, 17, 64, 5, 9), (100, 7, 2, 1, 3)),
+              ((130, 257), (200, 16)), ((40, 300, 33), (256, 129, 64)), ((31, 32, 33), (16, 17, 15))]
+    chains = cast_chains([_rand_chain(rng, Ks, Ds) for Ks, Ds in shapes], "fp32")
+    out = run_gauss(chains, prec, engine="fused")
+    assert out["info"]["engine"] == 1
+    _check(out, chains, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fused_c2_subset(prec):
+    w = make("c2", B=8)
+    chains = cast_chains(w.chains, "fp32")
+    out = run_gauss(chains, prec, engine="fused")
+    _check(out, chains, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fused_c3_instances(prec):
+    """Full C3 shape (L=6, K=256, D=100) on 3 instances."""
+    w = make("c3", instances=[0, 101, 255])
+    chains = cast_chains(w.chains, "fp32")
+    out = run_gauss(chains, prec, engine="fused")
+    errs = _check(out, chains, prec)
+    print(prec, "c3 |dlogP|", errs)
+
+
+def test_fused_deterministic_and_graph_replay():
+    from paper_1806_08593_amd import tmc as T
+    w = make("c2", B=6)
+    chains = cast_chains(w.chains, "fp32")
+    shapes, flat = pack_chains(chains, "fp32")
+    prob, _ = T.ragged_problem(shapes, "bf16x3", "fused")
+    plan = T.Plan(prob)
+    ws = plan.new_workspace()
+    d = {k: to_dev(v) for k, v in flat.items()}
+    n = len(chains)
+    dl = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    st = torch.cuda.Stream()
+    res = []
+    with torch.cuda.stream(st):
+        for rep in range(2):
+            lp = torch.empty(n, dtype=torch.float64, device="cuda:0")
+            g = {k: torch.empty_like(v) for k, v in d.items()}
+            T.tmc_gauss_fwd(plan.handle, d["z"], d["mu"], d["s"], d["u"], lp, ws, st)
+            T.tmc_gauss_bwd(plan.handle, d["z"], d["mu"], d["s"], d["u"], dl, ws, g["z"], g["mu"],
+                            g["s"], g["u"], st)
+            st.synchronize()
+            res.append((lp.clone(), {k: v.clone() for k, v in g.items()}))
+        assert torch.equal(res[0][0], res[1][0])
+        for k in res[0][1]:
+            assert torch.equal(res[0][1][k], res[1][1][k]), k
+        lpg = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        gg = {k: torch.empty_like(v) for k, v in d.items()}
+        T.tmc_plan_graph_capture_gauss(plan.handle, 0, d["z"], d["mu"], d["s"], d["u"], lpg, None, ws,
+                                       None, None, None, None, st)
+        T.tmc_plan_graph_capture_gauss(plan.handle, 1, d["z"], d["mu"], d["s"], d["u"], None, dl, ws,
+                                       gg["z"], gg["mu"], gg["s"], gg["u"], st)
+        for rep in range(3):
+            lpg.zero_()
+            for v in gg.values():
+                v.zero_()
+            T.tmc_plan_graph_launch(plan.handle, 0, st)
+            T.tmc_plan_graph_launch(plan.handle, 1, st)
+            st.synchronize()
+            assert torch.equal(lpg, res[0][0]), rep
+            for k in gg:
+                assert torch.equal(gg[k], res[0][1][k]), (rep, k)
+
+
+def test_fused_minus_inf_and_forward_only():
+    from paper_1806_08593_amd import tmc as T
+    rng = np.random.default_rng(5)
+    good = _rand_chain(rng, (40, 33, 20), (10, 10, 10))
+    dead = _rand_chain(rng, (40, 33, 20), (10, 10, 10))
+    dead.u[2][:] = -np.inf
+    chains = cast_chains([good, dead], "fp32")
+    out = run_gauss(chains, "fp32", engine="fused")
+    ref = O.gauss_chain_logp(chains[0].z, chains[0].mu, chains[0].s, chains[0].u)
+    assert abs(out["logp"][0] - ref) < 1e-4
+    assert out["logp"][1] == -np.inf
+    n0 = sum(a.size for a in chains[0].z)
+    assert np.all(out["dz"][n0:] == 0.0)
+    out2 = run_gauss(chains, "bf16x3", engine="fused", flags=T.TMC_FLAG_FORWARD_ONLY, bwd=False)
+    assert abs(out2["logp"][0] - ref) < 2e-3
+    with pytest.raises(T.TMCError) as ei:
+        run_gauss(chains, "bf16x3", engine="fused", flags=T.TMC_FLAG_FORWARD_ONLY, bwd=True)
+    assert ei.value.status == T.TMC_ERR_STATE
+
+
+def test_fused_shared_s_autograd():
+    """Homogeneous batch with s shared: autograd wrapper returns the batch-summed ds."""
+    from paper_1806_08593_amd import autograd as A
+    w = make("c2", B=4)
+    B, L, K, D = w.z.shape
+    run = A.GaussChainTMC(B, L, K, D, precision="fp32", engine="fused")
+    t = {k: torch.tensor(getattr(w, k), dtype=torch.float32, device="cuda:0", requires_grad=True)
+         for k in ("z", "mu", "s", "u")}
+    logp = run(t["z"], t["mu"], t["s"], t["u"])
+    logp.sum().backward()
+    chains = cast_chains(w.chains, "fp32")
+    ref = oracle_grads(chains)
+    ds_ref = sum(np.stack(r[3]) for r in ref)
+    assert rel_l2(t["s"].grad.cpu().numpy(), ds_ref) < 1e-3
+    for b in range(B):
+        assert abs(logp[b].item() - ref[b][0]) < 1e-4
