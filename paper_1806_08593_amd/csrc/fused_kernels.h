@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "../../include/tmc.h"
 #include "dev_util.h"
 #include "tmc_internal.h"
@@ -98,7 +100,7 @@ __device__ __forceinline__ float lam_f(const float* __restrict__ s, int d, int D
 __device__ __forceinline__ void pair_constants(const LayerDev& L, const double* __restrict__ alpha,
                                                const float* __restrict__ s, double& maxa,
                                                double& cs) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
   const double* aup = alpha + L.alpha_up_off;
   double m = -INFINITY;
   for (int j = lane; j < L.Kc; j += kWave) m = nan_max(m, aup[j]);
@@ -110,87 +112,10 @@ __device__ __forceinline__ void pair_constants(const LayerDev& L, const double* 
   cs = -ss - 0.5 * (double)L.D * log(2.0 * M_PI);
 }
 
-// Loads the mu fragments of the 32 columns j0..j0+31 (lane -> column j0 + l%32) and
-// returns, for the lane's own column, gamma_j = log2e (q_j + alpha_{l+1}[j] - maxa)
-// (-inf past Kc).  Identical in forward and backward.
-template <int PREC, int NKC>
-__device__ __forceinline__ float load_cols(const LayerDev& L, const float* __restrict__ mu,
-                                           const float* __restrict__ lamv,
-                                           const double* __restrict__ alpha, double maxa, int j0,
-                                           Frag<PREC> (&B)[NKC]) {
-  const int lane = threadIdx.x, jr = lane % 32, h = lane / 32;
-  const int j = j0 + jr;
-  const int D = L.D;
-  const bool valid = j < L.Kc;
-  const float* row = mu + L.mu_off + (int64_t)(valid ? j : 0) * D;
-  const bool vec = (D % 4 == 0) && (L.mu_off % 4 == 0);
-  double q = 0.0;
-#pragma unroll
-  for (int kc = 0; kc < NKC; ++kc) {
-    float x[8];
-    const int d0 = kc * 16 + 8 * h;
-    if (valid) load8(row, d0, D, vec, x);
-    else
-#pragma unroll
-      for (int t = 0; t < 8; ++t) x[t] = 0.0f;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) q += (double)lamv[kc * 8 + t] * (double)x[t] * (double)x[t];
-    make_frag<PREC>(x, B[kc]);
-  }
-  q = q + __shfl_xor(q, 32, kWave);
-  if (!valid) return -INFINITY;
-  const double g = -0.5 * q + (alpha[L.alpha_up_off + j] - maxa);
-  return (float)(g * (double)kLog2e);
-}
-
-// Row operand fragments a_i = log2e * lam * z_i for rows i0..i0+31 (lane -> row
-// i0 + l%32); optionally r_i = -1/2 sum lam z^2 (FP64) for the lane's row.
-template <int PREC, int NKC, bool WANT_R>
-__device__ __forceinline__ double load_rows(const LayerDev& L, const float* __restrict__ z,
-                                            const float* __restrict__ lamv, int i0,
-                                            Frag<PREC> (&A)[NKC]) {
-  const int lane = threadIdx.x, ir = lane % 32, h = lane / 32;
-  const int i = i0 + ir;
-  const int D = L.D;
-  const bool valid = i < L.K;
-  const float* row = z + L.z_off + (int64_t)(valid ? i : 0) * D;
-  const bool vec = (D % 4 == 0) && (L.z_off % 4 == 0);
-  double r = 0.0;
-#pragma unroll
-  for (int kc = 0; kc < NKC; ++kc) {
-    float x[8];
-    const int d0 = kc * 16 + 8 * h;
-    if (valid) load8(row, d0, D, vec, x);
-    else
-#pragma unroll
-      for (int t = 0; t < 8; ++t) x[t] = 0.0f;
-    if (WANT_R) {
-#pragma unroll
-      for (int t = 0; t < 8; ++t) r += (double)lamv[kc * 8 + t] * (double)x[t] * (double)x[t];
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) x[t] *= lamv[kc * 8 + t] * kLog2e;
-    make_frag<PREC>(x, A[kc]);
-  }
-  if (WANT_R) r = r + __shfl_xor(r, 32, kWave);
-  return -0.5 * r;
-}
-
-// lam_d for the lane's 8 d of every chunk
-template <int NKC>
-__device__ __forceinline__ void lane_lams(const LayerDev& L, const float* __restrict__ s,
-                                          float (&lamv)[NKC * 8]) {
-  const int h = threadIdx.x / 32;
-#pragma unroll
-  for (int kc = 0; kc < NKC; ++kc)
-#pragma unroll
-    for (int t = 0; t < 8; ++t) lamv[kc * 8 + t] = lam_f(s + L.s_off, kc * 16 + 8 * h + t, L.D);
-}
-
-// Transposed operand for a 32x32 block of an [n][D] row-major matrix X whose rows
-// are the k index: lane (d = d0 + l%32, h = l/32) gets, for k-step t (bf16) or step v
-// (fp32), the values X[k0 + kidx][d] where kidx follows the accumulator row order
-// 8(v/4) + 4h + v%4.  BF16X3: one fragment per t in {0,1}, slots s -> v = 8t + s.
+// Transposed operand of a 32-row tile X[k][d] (rows k are the contraction index):
+// lane (d = 32q + l%32, h = l/32) holds, for step v (fp32) or k-step t with slots
+// s -> v = 8t + s (bf16), the value X[8(v/4) + 4h + v%4][d] -- the same k order as
+// the rows of an accumulator tile, so an accumulator column can be the other operand.
 template <int PREC>
 struct TFrag;
 template <>
@@ -201,32 +126,6 @@ template <>
 struct TFrag<TMC_BF16X3> {
   Frag<TMC_BF16X3> f[2];
 };
-
-template <int PREC>
-__device__ __forceinline__ void load_tfrag(const float* __restrict__ X, int64_t off, int nrows,
-                                           int D, int k0, int d0, TFrag<PREC>& T) {
-  const int lane = threadIdx.x, h = lane / 32;
-  const int d = d0 + lane % 32;
-  float x[16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int k = k0 + 8 * (v / 4) + 4 * h + (v % 4);
-    x[v] = (k < nrows && d < D) ? X[off + (int64_t)k * D + d] : 0.0f;
-  }
-  if constexpr (PREC == TMC_FP32) {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) T.x[v] = x[v];
-  } else {
-    float a[8], b[8];
-#pragma unroll
-    for (int s2 = 0; s2 < 8; ++s2) {
-      a[s2] = x[s2];
-      b[s2] = x[8 + s2];
-    }
-    make_frag<TMC_BF16X3>(a, T.f[0]);
-    make_frag<TMC_BF16X3>(b, T.f[1]);
-  }
-}
 
 // acc[d][n] += sum_k T[d][k] P[k][n] where P is this lane's accumulator column
 // (16 values in accumulator row order) used as the B operand.
@@ -248,70 +147,354 @@ __device__ __forceinline__ void mma_t(f32x16& acc, const TFrag<PREC>& T, const f
   }
 }
 
+
 // ---------------------------------------------------------------------------
-// forward: one wave owns 32 rows of one layer pair and sweeps every column tile.
-//   ell_i   = log2 sum_j exp2(S_ij + gamma_j)            (S = log2e <lam z_i, mu_j>)
+// LDS staging of one 32-row operand tile (32 samples of mu or of z), written once
+// per workgroup and read by all four waves:
+//   row-major copy: fragments with the d chunk along k (factor GEMM);
+//   d-major copy:   fragments with the tile rows along k (G^T z, softmax * mu).
+// The d-major copy stores tile row r at column perm(r) (bits 2 and 3 of r swapped),
+// which puts the 8 rows a lane needs for one k-step next to each other, so every
+// fragment is one or two 128-bit LDS reads.  BF16X3 keeps two bf16 planes (hi, lo),
+// FP32 one float plane.
+// ---------------------------------------------------------------------------
+template <int PREC, int NKC>
+struct TileSmem {
+  static constexpr int DP = NKC * 16;               // padded width
+  static constexpr int ND32 = (NKC + 1) / 2;        // 32-wide d blocks
+  static constexpr int DT = ND32 * 32;              // rows of the d-major copy
+  static constexpr bool BF = PREC == TMC_BF16X3;
+  static constexpr int NPL = BF ? 2 : 1;
+  static constexpr int RS = BF ? DP + 8 : DP + 4;   // row stride (elements)
+  static constexpr int CS = BF ? 40 : 36;           // d-major stride (elements)
+  typedef typename std::conditional<BF, __bf16, float>::type E;
+  E row[NPL][32 * RS];
+  E col[NPL][DT * CS];
+  float lamf[DP];        // lam_d = exp(-2 s_d)            (0 past D)
+  float lam2[DP];        // log2(e) * lam_d
+  float gam[32];         // column terms of the staged tile
+  float lamT[32];        // row shifts of the staged tile (backward)
+};
+
+__device__ __forceinline__ int tile_perm(int r) {
+  return (r & 0x13) | ((r & 4) << 1) | ((r & 8) >> 1);
+}
+
+template <int PREC, int NKC>
+__device__ __forceinline__ void tile_init(TileSmem<PREC, NKC>& T, const LayerDev& L,
+                                          const float* __restrict__ s) {
+  using TS = TileSmem<PREC, NKC>;
+  for (int d = threadIdx.x; d < TS::DP; d += blockDim.x) {
+    const float lf = lam_f(s + L.s_off, d, L.D);
+    T.lamf[d] = lf;
+    T.lam2[d] = lf * kLog2e;
+  }
+  for (int e = threadIdx.x; e < TS::NPL * TS::DT * TS::CS; e += blockDim.x)
+    (&T.col[0][0])[e] = (typename TS::E)0.0f;
+}
+
+// Register stage of one 32-row tile (blockDim 256): thread t serves row t / 8 and
+// float4 columns 4 (t % 8 + 8 m).  Rows >= nvalid and d >= D read as zero.
+template <int NKC>
+struct TilePrefetch {
+  static constexpr int NF = (NKC + 1) / 2;
+  float4 v[NF];
+  float4 e[NF];      // backward row owner: softmax-weighted mean of mu (same positions)
+  double a, q;       // forward/backward column tiles: alpha_{l+1}[j] and q_j (thread t%8 == 0)
+  float lam, p;      // backward: row shift (t < 32) and marginal of the thread's row
+};
+
+__device__ __forceinline__ float4 load_f4(const float* __restrict__ rowp, int d, int D, bool valid,
+                                          bool vec) {
+  if (valid && vec && d < D) return *reinterpret_cast<const float4*>(rowp + d);
+  float4 r;
+  r.x = (valid && d + 0 < D) ? rowp[d + 0] : 0.0f;
+  r.y = (valid && d + 1 < D) ? rowp[d + 1] : 0.0f;
+  r.z = (valid && d + 2 < D) ? rowp[d + 2] : 0.0f;
+  r.w = (valid && d + 3 < D) ? rowp[d + 3] : 0.0f;
+  return r;
+}
+
+// Column tile of pair L: mu rows r0.. (samples of layer l+1), their alpha and q.
+template <int NKC>
+__device__ __forceinline__ void fetch_cols(TilePrefetch<NKC>& pf, const LayerDev& L,
+                                           const float* __restrict__ mu,
+                                           const double* __restrict__ alpha,
+                                           const double* __restrict__ qcol, int r0) {
+  const int t = threadIdx.x, r = t >> 3, sub = t & 7;
+  const int gr = r0 + r;
+  const bool valid = gr < L.Kc;
+  const bool vec = (L.D % 4 == 0) && (L.mu_off % 4 == 0);
+  const float* rowp = mu + L.mu_off + (int64_t)(valid ? gr : 0) * L.D;
+#pragma unroll
+  for (int m = 0; m < TilePrefetch<NKC>::NF; ++m) pf.v[m] = load_f4(rowp, 4 * (sub + 8 * m), L.D, valid, vec);
+  if (sub == 0 && valid) {
+    pf.a = alpha[L.alpha_up_off + gr];
+    if (qcol) pf.q = qcol[L.q_off + gr];
+  }
+}
+
+// Row tile of pair L (samples of layer l): z rows r0.., their shifts Lam and, for the
+// row-owning workgroup, e rows and marginals.
+template <int NKC>
+__device__ __forceinline__ void fetch_rows(TilePrefetch<NKC>& pf, const LayerDev& L,
+                                           const float* __restrict__ z,
+                                           const float* __restrict__ lamrow,
+                                           const float* __restrict__ ev,
+                                           const float* __restrict__ prow, bool owner, int r0) {
+  const int t = threadIdx.x, r = t >> 3, sub = t & 7;
+  const int gr = r0 + r;
+  const bool valid = gr < L.K;
+  const bool vec = (L.D % 4 == 0) && (L.z_off % 4 == 0);
+  const float* rowp = z + L.z_off + (int64_t)(valid ? gr : 0) * L.D;
+#pragma unroll
+  for (int m = 0; m < TilePrefetch<NKC>::NF; ++m) pf.v[m] = load_f4(rowp, 4 * (sub + 8 * m), L.D, valid, vec);
+  if (t < 32) pf.lam = (r0 + t < L.K) ? lamrow[r0 + t] : INFINITY;
+  if (owner) {
+    const bool evec = (L.D % 4 == 0) && (L.ev_off % 4 == 0);
+    const float* erow = ev + L.ev_off + (int64_t)(valid ? gr : 0) * L.D;
+#pragma unroll
+    for (int m = 0; m < TilePrefetch<NKC>::NF; ++m) pf.e[m] = load_f4(erow, 4 * (sub + 8 * m), L.D, valid, evec);
+    pf.p = valid ? prow[gr] : 0.0f;
+  }
+}
+
+// Writes a fetched tile to LDS: row-major copy = x * lam2 when `scale`, else x;
+// d-major copy (when `want_col`) = x.
+template <int PREC, int NKC>
+__device__ __forceinline__ void tile_store(TileSmem<PREC, NKC>& T, const TilePrefetch<NKC>& pf,
+                                           bool scale, bool want_col) {
+  using TS = TileSmem<PREC, NKC>;
+  const int t = threadIdx.x, r = t >> 3, sub = t & 7;
+  const int pr = tile_perm(r);
+#pragma unroll
+  for (int m = 0; m < TilePrefetch<NKC>::NF; ++m) {
+    const int k = sub + 8 * m;
+    if (k >= TS::DP / 4) break;
+    const int d = 4 * k;
+    const float x[4] = {pf.v[m].x, pf.v[m].y, pf.v[m].z, pf.v[m].w};
+    if constexpr (TS::BF) {
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      bf16x4 xh, xl;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const __bf16 hb = (__bf16)x[e];
+        xh[e] = hb;
+        xl[e] = (__bf16)(x[e] - (float)hb);
+      }
+      if (want_col) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          T.col[0][(d + e) * TS::CS + pr] = xh[e];
+          T.col[1][(d + e) * TS::CS + pr] = xl[e];
+        }
+      }
+      if (scale) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float y = x[e] * T.lam2[d + e];
+          const __bf16 hb = (__bf16)y;
+          xh[e] = hb;
+          xl[e] = (__bf16)(y - (float)hb);
+        }
+      }
+      *reinterpret_cast<bf16x4*>(&T.row[0][r * TS::RS + d]) = xh;
+      *reinterpret_cast<bf16x4*>(&T.row[1][r * TS::RS + d]) = xl;
+    } else {
+      if (want_col) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T.col[0][(d + e) * TS::CS + pr] = x[e];
+      }
+      float y[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) y[e] = scale ? x[e] * T.lam2[d + e] : x[e];
+      *reinterpret_cast<float4*>(&T.row[0][r * TS::RS + d]) = make_float4(y[0], y[1], y[2], y[3]);
+    }
+  }
+}
+
+// q_j = -1/2 sum_d lam_d mu_jd^2 (FP64) of the fetched column row, complete in all 8
+// threads serving the row (fixed reduction order).
+template <int PREC, int NKC>
+__device__ __forceinline__ double tile_colq(const TileSmem<PREC, NKC>& T,
+                                            const TilePrefetch<NKC>& pf) {
+  using TS = TileSmem<PREC, NKC>;
+  const int sub = threadIdx.x & 7;
+  double q = 0.0;
+#pragma unroll
+  for (int m = 0; m < TilePrefetch<NKC>::NF; ++m) {
+    const int k = sub + 8 * m;
+    if (k >= TS::DP / 4) break;
+    const int d = 4 * k;
+    const float x[4] = {pf.v[m].x, pf.v[m].y, pf.v[m].z, pf.v[m].w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) q += (double)T.lamf[d + e] * (double)x[e] * (double)x[e];
+  }
+  q += __shfl_xor(q, 1, kWave);
+  q += __shfl_xor(q, 2, kWave);
+  q += __shfl_xor(q, 4, kWave);
+  return -0.5 * q;
+}
+
+// gamma_j = log2(e) (q_j + alpha_{l+1}[j] - maxa) of the staged column tile (-inf past Kc).
+template <int PREC, int NKC>
+__device__ __forceinline__ void tile_gamma(TileSmem<PREC, NKC>& T, const TilePrefetch<NKC>& pf,
+                                           double q, const LayerDev& L, int r0, double maxa) {
+  const int t = threadIdx.x, r = t >> 3;
+  if ((t & 7) == 0)
+    T.gam[r] = (r0 + r < L.Kc) ? (float)((q + (pf.a - maxa)) * (double)kLog2e) : -INFINITY;
+}
+
+// Fragment of staged row (lane % 32) for d chunk kc (d = 16 kc + 8 h + s).
+template <int PREC, int NKC>
+__device__ __forceinline__ void tile_row_frag(const TileSmem<PREC, NKC>& T, int kc, Frag<PREC>& f) {
+  using TS = TileSmem<PREC, NKC>;
+  const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+  const int o = r * TS::RS + kc * 16 + 8 * h;
+  if constexpr (TS::BF) {
+    f.hi = *reinterpret_cast<const bf16x8*>(&T.row[0][o]);
+    f.lo = *reinterpret_cast<const bf16x8*>(&T.row[1][o]);
+  } else {
+    const float4 a = *reinterpret_cast<const float4*>(&T.row[0][o]);
+    const float4 b = *reinterpret_cast<const float4*>(&T.row[0][o + 4]);
+    f.x[0] = a.x; f.x[1] = a.y; f.x[2] = a.z; f.x[3] = a.w;
+    f.x[4] = b.x; f.x[5] = b.y; f.x[6] = b.z; f.x[7] = b.w;
+  }
+}
+
+// Transposed fragment of the staged tile for d block q (lane -> d = 32 q + lane % 32).
+template <int PREC, int NKC>
+__device__ __forceinline__ void tile_col_frag(const TileSmem<PREC, NKC>& T, int q, TFrag<PREC>& f) {
+  using TS = TileSmem<PREC, NKC>;
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int o = (32 * q + (lane & 31)) * TS::CS + 8 * h;
+  if constexpr (TS::BF) {
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+      f.f[tt].hi = *reinterpret_cast<const bf16x8*>(&T.col[0][o + 16 * tt]);
+      f.f[tt].lo = *reinterpret_cast<const bf16x8*>(&T.col[1][o + 16 * tt]);
+    }
+  } else {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 a = *reinterpret_cast<const float4*>(&T.col[0][o + 4 * (g & 1) + 16 * (g >> 1)]);
+      f.x[4 * g + 0] = a.x; f.x[4 * g + 1] = a.y; f.x[4 * g + 2] = a.z; f.x[4 * g + 3] = a.w;
+    }
+  }
+}
+
+// Row operand of the wave's rows i0 .. i0+31 straight from global memory:
+// a_i = log2(e) lam z_i as fragments, and r_i = -1/2 sum_d lam_d z_id^2 (FP64).
+template <int PREC, int NKC>
+__device__ __forceinline__ double wave_rows(const TileSmem<PREC, NKC>& T, const LayerDev& L,
+                                            const float* __restrict__ z, int i0,
+                                            Frag<PREC> (&A)[NKC]) {
+  const int lane = threadIdx.x & 63, ir = lane & 31, h = lane >> 5;
+  const int i = i0 + ir;
+  const int D = L.D;
+  const bool valid = i < L.K;
+  const float* row = z + L.z_off + (int64_t)(valid ? i : 0) * D;
+  const bool vec = (D % 4 == 0) && (L.z_off % 4 == 0);
+  double r = 0.0;
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc) {
+    float x[8];
+    const int d0 = kc * 16 + 8 * h;
+    if (valid) load8(row, d0, D, vec, x);
+    else
+#pragma unroll
+      for (int t = 0; t < 8; ++t) x[t] = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      r += (double)T.lamf[d0 + t] * (double)x[t] * (double)x[t];
+      x[t] *= T.lam2[d0 + t];
+    }
+    make_frag<PREC>(x, A[kc]);
+  }
+  r = r + __shfl_xor(r, 32, kWave);
+  return -0.5 * r;
+}
+
+// ---------------------------------------------------------------------------
+// forward: a workgroup of 4 waves owns 128 rows of one layer pair (wave w: rows
+// start + 32 w ..); every 32-sample column tile of the layer above is staged once
+// in LDS (prefetched into registers one tile ahead) and swept by all waves.
+//   ell_i   = log2 sum_j exp2(S_ij + gamma_j)          (S = log2e <lam z_i, mu_j>)
 //   alpha_i = u_i + r_i + c + maxa + ln2 * ell_i - ln K_{l+1}
-//   e_i     = sum_j softmax_j(S_ij + gamma_j) mu_j          (GRAD: used for dz)
+//   e_i     = sum_j softmax_j(S_ij + gamma_j) mu_j        (GRAD: used for dz)
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, bool GRAD>
-__global__ __launch_bounds__(64) void k_fused_fwd(const LayerDev* __restrict__ Ls,
-                                                  const Item* __restrict__ items,
-                                                  const float* __restrict__ z,
-                                                  const float* __restrict__ mu,
-                                                  const float* __restrict__ s,
-                                                  const float* __restrict__ u,
-                                                  double* __restrict__ alpha,
-                                                  float* __restrict__ rl,
-                                                  float* __restrict__ ev) {
-  constexpr int ND32 = (NKC + 1) / 2;
-  __shared__ __align__(16) float gam[32];
+__global__ __launch_bounds__(256) void k_fused_fwd(const LayerDev* __restrict__ Ls,
+                                                   const Item* __restrict__ items,
+                                                   const float* __restrict__ z,
+                                                   const float* __restrict__ mu,
+                                                   const float* __restrict__ s,
+                                                   const float* __restrict__ u,
+                                                   double* __restrict__ qcol,
+                                                   double* __restrict__ alpha,
+                                                   float* __restrict__ rl,
+                                                   float* __restrict__ ev) {
+  using TS = TileSmem<PREC, NKC>;
+  constexpr int ND32 = TS::ND32;
+  __shared__ __align__(16) TS T;
   const Item it = items[blockIdx.x];
   const LayerDev L = Ls[it.layer];
-  const int lane = threadIdx.x, h = lane / 32, ir = lane % 32;
-  const int i0 = it.start;
-
-  float lamv[NKC * 8];
-  lane_lams<NKC>(L, s, lamv);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, ir = lane & 31;
+  tile_init<PREC, NKC>(T, L, s);
   double maxa, cs;
   pair_constants(L, alpha, s, maxa, cs);
+  __syncthreads();
 
+  const int i0 = it.start + 32 * w;
+  const bool active = i0 < L.K;
   Frag<PREC> A[NKC];
-  const double r_i = load_rows<PREC, NKC, true>(L, z, lamv, i0, A);
+  double r_i = 0.0;
+  if (active) r_i = wave_rows<PREC, NKC>(T, L, z, i0, A);
 
   float m = -INFINITY, ssum = 0.0f;
   f32x16 O[GRAD ? ND32 : 1];
-  if (GRAD) {
 #pragma unroll
-    for (int q = 0; q < ND32; ++q)
+  for (int q = 0; q < (GRAD ? ND32 : 1); ++q)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) O[q][v] = 0.0f;
-  }
+    for (int v = 0; v < 16; ++v) O[q][v] = 0.0f;
 
+  // The forward computes the column norms q_j (FP64) of every column tile it stages;
+  // the workgroup that starts at row 0 stores them for the backward.
+  const bool qwriter = GRAD && it.start == 0;
+  TilePrefetch<NKC> pf;
+  fetch_cols<NKC>(pf, L, mu, alpha, nullptr, 0);
   for (int j0 = 0; j0 < L.Kc; j0 += 32) {
-    Frag<PREC> Bf[NKC];
-    const float gj = load_cols<PREC, NKC>(L, mu, lamv, alpha, maxa, j0, Bf);
+    __syncthreads();                       // waits for the prefetch and for readers of T
+    tile_store<PREC, NKC>(T, pf, false, GRAD);
+    const double qj = tile_colq<PREC, NKC>(T, pf);
+    tile_gamma<PREC, NKC>(T, pf, qj, L, j0, maxa);
+    if (qwriter && (tid & 7) == 0 && j0 + (tid >> 3) < L.Kc) qcol[L.q_off + j0 + (tid >> 3)] = qj;
+    __syncthreads();
+    if (j0 + 32 < L.Kc) fetch_cols<NKC>(pf, L, mu, alpha, nullptr, j0 + 32);   // overlaps compute
+    if (!active) continue;
     f32x16 S;
 #pragma unroll
     for (int v = 0; v < 16; ++v) S[v] = 0.0f;
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc) mma_chunk<PREC>(S, Bf[kc], A[kc]);   // S[j][i]
-    __syncthreads();
-    if (h == 0) gam[ir] = gj;
-    __syncthreads();
+    for (int kc = 0; kc < NKC; ++kc) {
+      Frag<PREC> Bf;
+      tile_row_frag<PREC, NKC>(T, kc, Bf);
+      mma_chunk<PREC>(S, Bf, A[kc]);     // S[j][i]
+    }
     float x[16];
     float tmax = -INFINITY;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float4 g4 = *reinterpret_cast<const float4*>(&gam[8 * q + 4 * h]);
+      const float4 g4 = *reinterpret_cast<const float4*>(&T.gam[8 * q + 4 * h]);
       x[4 * q + 0] = S[4 * q + 0] + g4.x;
       x[4 * q + 1] = S[4 * q + 1] + g4.y;
       x[4 * q + 2] = S[4 * q + 2] + g4.z;
       x[4 * q + 3] = S[4 * q + 3] + g4.w;
     }
+    // (a NaN entry is dropped by fmaxf here but reaches ssum through exp2 below)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) tmax = nan_max(tmax, x[v]);
-    tmax = nan_max(tmax, __shfl_xor(tmax, 32, kWave));
+    for (int v = 0; v < 16; ++v) tmax = fmaxf(tmax, x[v]);
+    tmax = fmaxf(tmax, __shfl_xor(tmax, 32, kWave));
     const bool need = tmax > m + kRescale;
     if (__any(need)) {
       const float mn = need ? tmax : m;
@@ -337,12 +520,13 @@ __global__ __launch_bounds__(64) void k_fused_fwd(const LayerDev* __restrict__ L
     if (GRAD) {
 #pragma unroll
       for (int q = 0; q < ND32; ++q) {
-        TFrag<PREC> T;
-        load_tfrag<PREC>(mu, L.mu_off, L.Kc, L.D, j0, 32 * q, T);
-        mma_t<PREC>(O[q], T, p);
+        TFrag<PREC> Tf;
+        tile_col_frag<PREC, NKC>(T, q, Tf);
+        mma_t<PREC>(O[q], Tf, p);
       }
     }
   }
+  if (!active) return;
   const float stot = ssum + __shfl_xor(ssum, 32, kWave);
   float ell;
   if (m != m || stot != stot) ell = NAN;
@@ -356,48 +540,94 @@ __global__ __launch_bounds__(64) void k_fused_fwd(const LayerDev* __restrict__ L
   }
   if (GRAD && i < L.K) {
     const float inv = (stot > 0.0f) ? 1.0f / stot : 0.0f;
+    float* erow = ev + L.ev_off + (int64_t)i * L.D;
+    const bool vec = (L.D % 4 == 0) && (L.ev_off % 4 == 0);
 #pragma unroll
     for (int q = 0; q < ND32; ++q)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int d = 32 * q + 8 * (v / 4) + 4 * h + (v % 4);
-        if (d < L.D) ev[L.ev_off + (int64_t)i * L.D + d] = O[q][v] * inv;
+      for (int g = 0; g < 4; ++g) {
+        const int d = 32 * q + 8 * g + 4 * h;
+        const float4 o4 = make_float4(O[q][4 * g] * inv, O[q][4 * g + 1] * inv,
+                                      O[q][4 * g + 2] * inv, O[q][4 * g + 3] * inv);
+        if (vec && d + 3 < L.D) {
+          *reinterpret_cast<float4*>(erow + d) = o4;
+        } else {
+          if (d + 0 < L.D) erow[d + 0] = o4.x;
+          if (d + 1 < L.D) erow[d + 1] = o4.y;
+          if (d + 2 < L.D) erow[d + 2] = o4.z;
+          if (d + 3 < L.D) erow[d + 3] = o4.w;
+        }
       }
   }
 }
 
 // ---------------------------------------------------------------------------
-// backward: one wave owns 32 columns (samples j of layer l+1) and sweeps every row
-// tile of layer l:
+// backward: a workgroup of 4 waves owns 128 columns (samples j of layer l+1; wave
+// w: columns start + 32 w ..) and sweeps every row tile of layer l, staged once in
+// LDS (scaled row-major copy for the factor, raw d-major copy for G^T z):
 //   G_ij   = exp2(S_ij + gamma_j - Lam_i),   Lam_i = ell_i - log2 p_l[i]
 //   p_{l+1}[j] = sum_i G_ij,  (G^T z)_j = sum_i G_ij z_i
 //   dmu_j  = dlogp * lam * ((G^T z)_j - p_{l+1}[j] mu_j)
+// The workgroup with start 0 of each pair also owns the rows:
+//   dz_i   = -dlogp * lam * p_i (z_i - e_i)
+// and every workgroup writes one partial row of the log-std gradient,
+//   ds = dlogp * [lam * sum_ij G_ij (z_i - mu_j)^2 - sum_i p_i]
+//      = dlogp * [lam * (sum_i p_i z_i^2 - 2 sum_j mu_j (G^T z)_j + sum_j p'_j mu_j^2) - sum p]
+// (row terms from the row owner, column terms from each workgroup's columns).
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC>
-__global__ __launch_bounds__(64) void k_fused_bwd(const LayerDev* __restrict__ Ls,
-                                                  const Item* __restrict__ items,
-                                                  const float* __restrict__ z,
-                                                  const float* __restrict__ mu,
-                                                  const float* __restrict__ s,
-                                                  const double* __restrict__ alpha,
-                                                  const float* __restrict__ rl,
-                                                  float* __restrict__ lam_ws,
-                                                  const double* __restrict__ dlogp,
-                                                  float* __restrict__ p,
-                                                  float* __restrict__ dmu,
-                                                  float* __restrict__ du) {
-  constexpr int ND32 = (NKC + 1) / 2;
+__global__ __launch_bounds__(256) void k_fused_bwd(const LayerDev* __restrict__ Ls,
+                                                   const Item* __restrict__ items,
+                                                   const float* __restrict__ z,
+                                                   const float* __restrict__ mu,
+                                                   const float* __restrict__ s,
+                                                   const double* __restrict__ alpha,
+                                                   const double* __restrict__ qcol,
+                                                   const float* __restrict__ rl,
+                                                   float* __restrict__ lam_ws,
+                                                   const float* __restrict__ ev,
+                                                   const double* __restrict__ dlogp,
+                                                   float* __restrict__ p,
+                                                   float* __restrict__ dz,
+                                                   float* __restrict__ dmu,
+                                                   float* __restrict__ du,
+                                                   float* __restrict__ dsp) {
+  using TS = TileSmem<PREC, NKC>;
+  constexpr int ND32 = TS::ND32;
+  constexpr int NF = TilePrefetch<NKC>::NF;
+  __shared__ __align__(16) TS T;
+  __shared__ float accD[TS::DT];
   const Item it = items[blockIdx.x];
   const LayerDev L = Ls[it.layer];
-  const int lane = threadIdx.x, h = lane / 32, jr = lane % 32;
-  const int j0 = it.start;
-
-  float lamv[NKC * 8];
-  lane_lams<NKC>(L, s, lamv);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, jr = lane & 31;
+  const int sub = tid & 7, rr = tid >> 3;
+  tile_init<PREC, NKC>(T, L, s);
+  for (int d = tid; d < TS::DT; d += blockDim.x) accD[d] = 0.0f;
   double maxa, cs;
   pair_constants(L, alpha, s, maxa, cs);
+  const int jw = it.start + 32 * w;
+  const bool active = jw < L.Kc;
+  const bool owner = it.start == 0;
+  const float g32 = (float)dlogp[L.chain];
+
+  // the waves' column operands and column terms, staged one wave at a time
   Frag<PREC> Bf[NKC];
-  const float gj = load_cols<PREC, NKC>(L, mu, lamv, alpha, maxa, j0, Bf);
+  float gj = -INFINITY;
+  for (int w2 = 0; w2 < 4; ++w2) {
+    const int jt = it.start + 32 * w2;
+    if (jt >= L.Kc) break;
+    TilePrefetch<NKC> pm;
+    fetch_cols<NKC>(pm, L, mu, alpha, qcol, jt);
+    __syncthreads();
+    tile_store<PREC, NKC>(T, pm, false, false);
+    tile_gamma<PREC, NKC>(T, pm, pm.q, L, jt, maxa);
+    __syncthreads();
+    if (w == w2) {
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc) tile_row_frag<PREC, NKC>(T, kc, Bf[kc]);
+      gj = T.gam[jr];
+    }
+  }
 
   f32x16 GT[ND32];
 #pragma unroll
@@ -405,68 +635,174 @@ __global__ __launch_bounds__(64) void k_fused_bwd(const LayerDev* __restrict__ L
 #pragma unroll
     for (int v = 0; v < 16; ++v) GT[q][v] = 0.0f;
   float csum = 0.0f;
+  float accA[NF][4];     // row owner: sum_i p_i z_id^2 for the thread's d
+#pragma unroll
+  for (int mm = 0; mm < NF; ++mm)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) accA[mm][e] = 0.0f;
+  float psum = 0.0f;
   const float* lamrow = lam_ws + L.rl_off;   // Lam shares the per-layer indexing of rl
+  const float* prow = p + L.p_off;
+  const bool zvec = (L.D % 4 == 0) && (L.z_off % 4 == 0);
 
+  TilePrefetch<NKC> pf;
+  fetch_rows<NKC>(pf, L, z, lamrow, ev, prow, owner, 0);
   for (int i0 = 0; i0 < L.K; i0 += 32) {
-    Frag<PREC> A[NKC];
-    (void)load_rows<PREC, NKC, false>(L, z, lamv, i0, A);
+    __syncthreads();                       // waits for the prefetch and for readers of T
+    tile_store<PREC, NKC>(T, pf, true, true);
+    if (tid < 32) T.lamT[tid] = pf.lam;
+    __syncthreads();
+    if (owner) {
+      const int gi = i0 + rr;
+      if (gi < L.K) {
+        const float pi = pf.p;
+        if (sub == 0) psum += pi;
+        float* dzrow = dz ? dz + L.z_off + (int64_t)gi * L.D : nullptr;
+#pragma unroll
+        for (int mm = 0; mm < NF; ++mm) {
+          const int d = 4 * (sub + 8 * mm);
+          if (d >= L.D) break;
+          const float x[4] = {pf.v[mm].x, pf.v[mm].y, pf.v[mm].z, pf.v[mm].w};
+          const float e4[4] = {pf.e[mm].x, pf.e[mm].y, pf.e[mm].z, pf.e[mm].w};
+          float o[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            accA[mm][e] += pi * x[e] * x[e];
+            o[e] = -g32 * T.lamf[d + e] * pi * (x[e] - e4[e]);
+          }
+          if (dzrow) {
+            if (zvec) {
+              *reinterpret_cast<float4*>(dzrow + d) = make_float4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (d + e < L.D) dzrow[d + e] = o[e];
+            }
+          }
+        }
+      }
+    }
+    if (i0 + 32 < L.K) fetch_rows<NKC>(pf, L, z, lamrow, ev, prow, owner, i0 + 32);   // overlaps compute
+    if (!active) continue;
     f32x16 S;
 #pragma unroll
     for (int v = 0; v < 16; ++v) S[v] = 0.0f;
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc) mma_chunk<PREC>(S, A[kc], Bf[kc]);   // S[i][j]
+    for (int kc = 0; kc < NKC; ++kc) {
+      Frag<PREC> Af;
+      tile_row_frag<PREC, NKC>(T, kc, Af);
+      mma_chunk<PREC>(S, Af, Bf[kc]);    // S[i][j]
+    }
     float g[16];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int ib = i0 + 8 * q + 4 * h;
-      float lm[4];
-      if (ib + 3 < L.K && ((L.rl_off + ib) % 4 == 0)) {
-        const float4 t = *reinterpret_cast<const float4*>(lamrow + ib);
-        lm[0] = t.x; lm[1] = t.y; lm[2] = t.z; lm[3] = t.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) lm[e] = (ib + e < L.K) ? lamrow[ib + e] : INFINITY;
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        g[4 * q + e] = __builtin_amdgcn_exp2f(S[4 * q + e] + gj - lm[e]);
-        csum += g[4 * q + e];
-      }
+      const float4 l4 = *reinterpret_cast<const float4*>(&T.lamT[8 * q + 4 * h]);
+      g[4 * q + 0] = __builtin_amdgcn_exp2f(S[4 * q + 0] + gj - l4.x);
+      g[4 * q + 1] = __builtin_amdgcn_exp2f(S[4 * q + 1] + gj - l4.y);
+      g[4 * q + 2] = __builtin_amdgcn_exp2f(S[4 * q + 2] + gj - l4.z);
+      g[4 * q + 3] = __builtin_amdgcn_exp2f(S[4 * q + 3] + gj - l4.w);
     }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) csum += g[v];
 #pragma unroll
     for (int q = 0; q < ND32; ++q) {
-      TFrag<PREC> T;
-      load_tfrag<PREC>(z, L.z_off, L.K, L.D, i0, 32 * q, T);
-      mma_t<PREC>(GT[q], T, g);
+      TFrag<PREC> Tf;
+      tile_col_frag<PREC, NKC>(T, q, Tf);
+      mma_t<PREC>(GT[q], Tf, g);
     }
   }
+
+  // ---- column epilogue: marginals of layer l+1, dmu, column part of ds ----
   const float ctot = csum + __shfl_xor(csum, 32, kWave);
-  const int j = j0 + jr;
+  const int j = jw + jr;
+  const bool jv = active && j < L.Kc;
   const double gl = dlogp[L.chain];
-  if (j < L.Kc) {
-    if (h == 0) {
-      p[L.p_up_off + j] = ctot;
-      if (du) du[L.u_up_off + j] = (float)(gl * (double)ctot);
-      const LayerDev& U = Ls[L.up];
-      if (U.up >= 0) {
-        const float ell = rl[U.rl_off + j];
-        lam_ws[U.rl_off + j] = (ctot == 0.0f) ? INFINITY : ell - log2f(ctot);
-      }
+  if (jv && h == 0) {
+    p[L.p_up_off + j] = ctot;
+    if (du) du[L.u_up_off + j] = (float)(gl * (double)ctot);
+    const LayerDev& U = Ls[L.up];
+    if (U.up >= 0) {
+      const float ell = rl[U.rl_off + j];
+      lam_ws[U.rl_off + j] = (ctot == 0.0f) ? INFINITY : ell - log2f(ctot);
     }
-    if (dmu) {
-      const float g32 = (float)gl;
+  }
+  // per-lane column terms c_j mu_jd^2 - 2 mu_jd (G^T z)_jd, reduced over the wave's
+  // 32 columns through LDS (wave by wave, fixed order)
+  float colt[ND32][16];
+  {
+    const bool mvec = (L.D % 4 == 0) && (L.mu_off % 4 == 0);
+    const float* murow = mu + L.mu_off + (int64_t)(jv ? j : 0) * L.D;
+    float* dmurow = dmu ? dmu + L.mu_off + (int64_t)(jv ? j : 0) * L.D : nullptr;
+#pragma unroll
+    for (int q = 0; q < ND32; ++q)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int d = 32 * q + 8 * g + 4 * h;
+        const float4 m4 = load_f4(murow, d, L.D, jv, mvec);
+        const float mv[4] = {m4.x, m4.y, m4.z, m4.w};
+        float o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float gt = GT[q][4 * g + e];
+          colt[q][4 * g + e] = jv ? (ctot * mv[e] - 2.0f * gt) * mv[e] : 0.0f;
+          o[e] = (d + e < L.D) ? g32 * T.lamf[d + e] * (gt - ctot * mv[e]) : 0.0f;
+        }
+        if (jv && dmurow) {
+          if (mvec && d + 3 < L.D) {
+            *reinterpret_cast<float4*>(dmurow + d) = make_float4(o[0], o[1], o[2], o[3]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (d + e < L.D) dmurow[d + e] = o[e];
+          }
+        }
+      }
+  }
+  if (!dsp) return;
+  float* buf = reinterpret_cast<float*>(&T.col[0][0]);   // >= 32 x DT floats
+  for (int w2 = 0; w2 < 4; ++w2) {
+    __syncthreads();
+    if (w == w2) {
 #pragma unroll
       for (int q = 0; q < ND32; ++q)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int d = 32 * q + 8 * (v / 4) + 4 * h + (v % 4);
-          if (d < L.D) {
-            const int64_t mi = L.mu_off + (int64_t)j * L.D + d;
-            const float lam = expf(-2.0f * s[L.s_off + d]);
-            dmu[mi] = g32 * lam * (GT[q][v] - ctot * mu[mi]);
-          }
-        }
+        for (int v = 0; v < 16; ++v) buf[jr * TS::DT + 32 * q + 8 * (v / 4) + 4 * h + (v % 4)] = colt[q][v];
     }
+    __syncthreads();
+    for (int d = tid; d < TS::DT; d += blockDim.x) {
+      float acc = 0.0f;
+      for (int c = 0; c < 32; ++c) acc += buf[c * TS::DT + d];
+      accD[d] += acc;
+    }
+  }
+  if (owner) {
+    // row part: sum over the 32 row-threads of each d, then -sum p
+    __syncthreads();
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) {
+      const int d = 4 * (sub + 8 * mm);
+      if (d < TS::DP) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) buf[rr * TS::DP + d + e] = accA[mm][e];
+      }
+    }
+    if (sub == 0) T.gam[rr] = psum;
+    __syncthreads();
+    float ptot = 0.0f;
+    for (int c = 0; c < 32; ++c) ptot += T.gam[c];
+    for (int d = tid; d < TS::DP; d += blockDim.x) {
+      float acc = 0.0f;
+      for (int c = 0; c < 32; ++c) acc += buf[c * TS::DP + d];
+      accD[d] += acc;
+    }
+    __syncthreads();
+    for (int d = tid; d < L.D; d += blockDim.x)
+      dsp[L.dsp_off + d] = g32 * (T.lamf[d] * accD[d] - ptot);
+  } else {
+    __syncthreads();
+    const int part = it.start / 128;
+    for (int d = tid; d < L.D; d += blockDim.x)
+      dsp[L.dsp_off + (int64_t)part * L.D + d] = g32 * T.lamf[d] * accD[d];
   }
 }
 

@@ -83,23 +83,29 @@ __global__ __launch_bounds__(256) void k_bwd_init(const ChainDev* __restrict__ c
   }
 }
 
-// ds[s block] = sum over the layers sharing the block (fixed order) of their partials.
+// ds[s block] = sum of the partial rows that belong to the block, in a fixed order:
+// part_off[slot_start[sl] .. slot_start[sl+1]) are element offsets of [D] partial
+// rows in dsp.  Workgroup = (slot, 64 d); 4 groups of 64 threads split the parts.
 template <typename T>
-__global__ __launch_bounds__(256) void k_ds_reduce(const int* __restrict__ slot_layers,
+__global__ __launch_bounds__(256) void k_ds_reduce(const int64_t* __restrict__ part_off,
                                                    const int* __restrict__ slot_start,
                                                    const int64_t* __restrict__ slot_soff,
                                                    const int* __restrict__ slot_D,
-                                                   const LayerDev* __restrict__ layers,
                                                    const T* __restrict__ dsp, T* __restrict__ ds) {
+  __shared__ double red[4][64];
   const int sl = blockIdx.x;
   const int b = slot_start[sl], e = slot_start[sl + 1];
   const int D = slot_D[sl];
-  const int64_t so = slot_soff[sl];
-  for (int d = threadIdx.x; d < D; d += blockDim.x) {
-    double acc = 0.0;
-    for (int q = b; q < e; ++q) acc += (double)dsp[layers[slot_layers[q]].dsp_off + d];
-    ds[so + d] = (T)acc;
+  const int dl = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int d = blockIdx.y * 64 + dl;
+  double acc = 0.0;
+  if (d < D) {
+#pragma unroll 4
+    for (int q = b + g; q < e; q += 4) acc += (double)dsp[part_off[q] + d];
   }
+  red[g][dl] = acc;
+  __syncthreads();
+  if (g == 0 && d < D) ds[slot_soff[sl] + d] = (T)(red[0][dl] + red[1][dl] + red[2][dl] + red[3][dl]);
 }
 
 // ---- launchers ----
@@ -131,12 +137,12 @@ hipError_t launch_bwd_init(const ChainDev* chains, int n_chains, const LayerDev*
 }
 
 template <typename T>
-hipError_t launch_ds_reduce(const int* slot_layers, const int* slot_start, const int64_t* slot_soff,
-                            const int* slot_D, int n_slots, const LayerDev* layers, const T* dsp,
-                            T* ds, hipStream_t st) {
+hipError_t launch_ds_reduce(const int64_t* part_off, const int* slot_start, const int64_t* slot_soff,
+                            const int* slot_D, int n_slots, int max_D, const T* dsp, T* ds,
+                            hipStream_t st) {
   if (n_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ds_reduce<T>, dim3(n_slots), dim3(256), 0, st, slot_layers, slot_start,
-                     slot_soff, slot_D, layers, dsp, ds);
+  hipLaunchKernelGGL(k_ds_reduce<T>, dim3(n_slots, (max_D + 63) / 64), dim3(256), 0, st, part_off,
+                     slot_start, slot_soff, slot_D, dsp, ds);
   return hipGetLastError();
 }
 
@@ -146,8 +152,8 @@ hipError_t launch_ds_reduce(const int* slot_layers, const int* slot_start, const
   template hipError_t launch_bwd_init<T>(const ChainDev*, int, const LayerDev*, const double*, \
                                          const double*, const double*, T*, T*, T*,             \
                                          hipStream_t);                                         \
-  template hipError_t launch_ds_reduce<T>(const int*, const int*, const int64_t*, const int*,  \
-                                          int, const LayerDev*, const T*, T*, hipStream_t);
+  template hipError_t launch_ds_reduce<T>(const int64_t*, const int*, const int64_t*,         \
+                                          const int*, int, int, const T*, T*, hipStream_t);
 TMC_INST(float)
 TMC_INST(double)
 #undef TMC_INST

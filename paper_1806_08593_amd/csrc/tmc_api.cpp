@@ -78,6 +78,8 @@ struct tmc_plan {
   Item* items_d = nullptr;
   int* ints_d = nullptr;         // pair ids, slot layers, slot starts, slot D
   int64_t* slot_soff_d = nullptr;
+  int64_t* part_off_d = nullptr;    // ds partial rows grouped by s block
+  int max_D = 0;
   int* flag_d = nullptr;
   // schedules (offsets into items_d)
   Launch factor;                              // all pairs, factor tiles
@@ -109,6 +111,7 @@ struct tmc_plan {
     if (items_d) (void)hipFree(items_d);
     if (ints_d) (void)hipFree(ints_d);
     if (slot_soff_d) (void)hipFree(slot_soff_d);
+    if (part_off_d) (void)hipFree(part_off_d);
     if (flag_d) (void)hipFree(flag_d);
   }
 };
@@ -272,8 +275,9 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
         sum_pairKK += align_up((size_t)L.K * d.Kc, 4);
         d.gtz_off = sum_pairKcD;
         sum_pairKcD += (int64_t)d.Kc * L.D;
+        d.dsp_parts = P->engine == TMC_ENGINE_FUSED ? (d.Kc + kFusedBwdCols - 1) / kFusedBwdCols : 1;
         d.dsp_off = sum_pairD;
-        sum_pairD += L.D;
+        sum_pairD += (int64_t)L.D * d.dsp_parts;
         P->entries += (int64_t)L.K * d.Kc;
       }
     }
@@ -403,8 +407,24 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   P->n_slots = (int)slot_soff.size();
   P->slot_layers_off = (int)ints.size();
   ints.insert(ints.end(), by_s.begin(), by_s.end());
+  std::vector<int64_t> part_off;
+  std::vector<int> part_start;
+  {
+    size_t slot = 0;
+    for (size_t i = 0; i < by_s.size(); ++i) {
+      while (slot < slot_soff.size() && slot_start[slot] == (int)i) {
+        part_start.push_back((int)part_off.size());
+        ++slot;
+      }
+      const LayerDev& d = P->layers_h[by_s[i]];
+      for (int q = 0; q < d.dsp_parts; ++q) part_off.push_back(d.dsp_off + (int64_t)q * d.D);
+    }
+    part_start.push_back((int)part_off.size());
+  }
+  P->max_D = 0;
+  for (int dd : slot_D) P->max_D = std::max(P->max_D, dd);
   P->slot_start_off = (int)ints.size();
-  ints.insert(ints.end(), slot_start.begin(), slot_start.end());
+  ints.insert(ints.end(), part_start.begin(), part_start.end());
   P->slot_D_off = (int)ints.size();
   ints.insert(ints.end(), slot_D.begin(), slot_D.end());
 
@@ -432,6 +452,8 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   HIP_TRY(upload((void**)&P->ints_d, ints.empty() ? nullptr : ints.data(), ints.size() * sizeof(int)));
   HIP_TRY(upload((void**)&P->slot_soff_d, slot_soff.empty() ? nullptr : slot_soff.data(),
                  slot_soff.size() * sizeof(int64_t)));
+  HIP_TRY(upload((void**)&P->part_off_d, part_off.empty() ? nullptr : part_off.data(),
+                 part_off.size() * sizeof(int64_t)));
   HIP_TRY(hipMalloc((void**)&P->flag_d, sizeof(int)));
   HIP_TRY(hipMemset(P->flag_d, 0, sizeof(int)));
   HIP_TRY(hipDeviceSynchronize());
@@ -523,9 +545,9 @@ tmc_status plain_bwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, co
   if (ds) {
     LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_pair_dsp<T>(P->layers_d, P->ints_d + P->pair_ids_off, P->n_pairs, z, mu, s, p,
                               wsp<T>(ws, W.gtz), dlogp, wsp<T>(ws, W.dsp), st));
-    LAUNCH(launch_ds_reduce<T>(P->ints_d + P->slot_layers_off, P->ints_d + P->slot_start_off,
-                               P->slot_soff_d, P->ints_d + P->slot_D_off, P->n_slots, P->layers_d,
-                               wsp<T>(ws, W.dsp), ds, st));
+    LAUNCH(launch_ds_reduce<T>(P->part_off_d, P->ints_d + P->slot_start_off, P->slot_soff_d,
+                               P->ints_d + P->slot_D_off, P->n_slots, P->max_D, wsp<T>(ws, W.dsp),
+                               ds, st));
   }
   return TMC_OK;
 }
@@ -536,6 +558,7 @@ tmc_status fused_fwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
   const WsLayout& W = P->ws;
   const bool grad = !(P->flags & TMC_FLAG_FORWARD_ONLY);
   double* alpha = wsp<double>(ws, W.alpha);
+  double* qcol = wsp<double>(ws, W.q);
   float* rl = wsp<float>(ws, W.rl);
   float* ev = wsp<float>(ws, W.ev);
   LAUNCH(launch_init_top<float>(P->chains_d, P->n_chains, P->layers_d, u, alpha, st));
@@ -543,11 +566,13 @@ tmc_status fused_fwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
     for (auto& g : step) {
       const Item* it = P->items_d + g.off;
       if (P->prec == TMC_FP32)
-        LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_FP32>(g.nkc, grad, P->layers_d, it, g.n, z,
-                                                               mu, s, u, alpha, rl, ev, st));
+        LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_FP32>(g.nkc, g.waves, grad, P->layers_d, it,
+                                                               g.n, z, mu, s, u, qcol, alpha, rl,
+                                                               ev, st));
       else
-        LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_BF16X3>(g.nkc, grad, P->layers_d, it, g.n,
-                                                                 z, mu, s, u, alpha, rl, ev, st));
+        LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_BF16X3>(g.nkc, g.waves, grad, P->layers_d,
+                                                                 it, g.n, z, mu, s, u, qcol, alpha,
+                                                                 rl, ev, st));
     }
   LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, alpha, logp,
                          wsp<double>(ws, W.logp), P->flag_d, st));
@@ -559,31 +584,30 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
                           float* du, hipStream_t st) {
   const WsLayout& W = P->ws;
   double* alpha = wsp<double>(ws, W.alpha);
+  const double* qcol = wsp<double>(ws, W.q);
   float* rl = wsp<float>(ws, W.rl);
   float* lam = wsp<float>(ws, W.lam);
   float* p = wsp<float>(ws, W.p);
+  const float* ev = wsp<float>(ws, W.ev);
+  float* dsp = ds ? wsp<float>(ws, W.dsp) : nullptr;
   LAUNCH(launch_fused_bwd_init(P->chains_d, P->n_chains, P->layers_d, alpha,
                                wsp<double>(ws, W.logp), dlogp, rl, lam, p, du, dz, st));
   for (auto& step : P->fused.bwd)
     for (auto& g : step) {
       const Item* it = P->items_d + g.off;
       if (P->prec == TMC_FP32)
-        LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_FP32>(g.nkc, P->layers_d, it, g.n, z, mu,
-                                                               s, alpha, rl, lam, dlogp, p, dmu,
-                                                               du, st));
+        LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_FP32>(g.nkc, g.waves, P->layers_d, it, g.n,
+                                                               z, mu, s, alpha, qcol, rl, lam, ev,
+                                                               dlogp, p, dz, dmu, du, dsp, st));
       else
-        LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_BF16X3>(g.nkc, P->layers_d, it, g.n, z,
-                                                                 mu, s, alpha, rl, lam, dlogp, p,
-                                                                 dmu, du, st));
+        LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_BF16X3>(g.nkc, g.waves, P->layers_d, it,
+                                                                 g.n, z, mu, s, alpha, qcol, rl,
+                                                                 lam, ev, dlogp, p, dz, dmu, du,
+                                                                 dsp, st));
     }
-  if ((dz || ds) && P->n_pairs > 0)
-    LAUNCH(launch_fused_rowep(P->layers_d, P->ints_d + P->pair_ids_off, P->n_pairs, z, mu, s, p,
-                              wsp<float>(ws, W.ev), dlogp, dz, ds ? wsp<float>(ws, W.dsp) : nullptr,
-                              st));
   if (ds)
-    LAUNCH(launch_ds_reduce<float>(P->ints_d + P->slot_layers_off, P->ints_d + P->slot_start_off,
-                                   P->slot_soff_d, P->ints_d + P->slot_D_off, P->n_slots,
-                                   P->layers_d, wsp<float>(ws, W.dsp), ds, st));
+    LAUNCH(launch_ds_reduce<float>(P->part_off_d, P->ints_d + P->slot_start_off, P->slot_soff_d,
+                                   P->ints_d + P->slot_D_off, P->n_slots, P->max_D, dsp, ds, st));
   return TMC_OK;
 }
 

@@ -34,8 +34,11 @@ struct LayerDev {
   int64_t p_up_off;      // p of the layer above
   int64_t wf_off;        // plain: T f/G[K][Kc]
   int64_t gtz_off;       // plain: T (G^T z)[Kc][D]
-  int64_t dsp_off;       // T ds partial[D] of this pair
+  int64_t dsp_off;       // T ds partial rows [dsp_parts][D] of this pair
   int64_t ev_off;        // fused: float softmax-weighted mean of mu per row [K][D]
+  int64_t q_off;         // fused: double column norms q_j of this pair [Kc]
+  int32_t dsp_parts;     // partial rows of the log-std gradient of this pair
+  int32_t pad1;
 };
 
 struct ChainDev {
@@ -49,7 +52,7 @@ struct ChainDev {
 struct WsLayout {
   size_t alpha, p, rl, pairM, logp;
   size_t wf, wg, gtz, dsp;          // plain engine (dsp shared)
-  size_t ev, lam;                   // fused engine
+  size_t ev, lam, q;                // fused engine
   size_t total;
 };
 

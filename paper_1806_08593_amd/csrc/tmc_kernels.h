@@ -17,9 +17,9 @@ hipError_t launch_bwd_init(const ChainDev* chains, int n_chains, const LayerDev*
                            const double* alpha, const double* logp_ws, const double* dlogp,
                            T* p, T* du, T* dz, hipStream_t st);
 template <typename T>
-hipError_t launch_ds_reduce(const int* slot_layers, const int* slot_start, const int64_t* slot_soff,
-                            const int* slot_D, int n_slots, const LayerDev* layers, const T* dsp,
-                            T* ds, hipStream_t st);
+hipError_t launch_ds_reduce(const int64_t* part_off, const int* slot_start, const int64_t* slot_soff,
+                            const int* slot_D, int n_slots, int max_D, const T* dsp, T* ds,
+                            hipStream_t st);
 
 // ---- plain engine (k_plain.hip) ----
 template <typename T>
