@@ -42,10 +42,7 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
   W.q = o;
   o = align256(o + (size_t)sq * 8);
   W.total = o;
-  F.colnorm.off = (int)items.size();
-  for (int l : pairs)
-    for (int j = 0; j < layers[l].Kc; j += 32) items.push_back({l, j});
-  F.colnorm.n = (int)items.size() - F.colnorm.off;
+
 
   int max_depth = 0;
   for (auto& c : chains) max_depth = std::max(max_depth, c.L);
@@ -70,16 +67,21 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
         fl.nkc = kv.first.first;
         fl.waves = kv.first.second;
         fl.off = (int)items.size();
+        const int step_rows = dir == 0 ? kFusedFwdRows : kFusedBwdCols;
         for (int l : kv.second) {
           const LayerDev& d = layers[l];
           const int n = dir == 0 ? d.K : d.Kc;
-          for (int x = 0; x < n; x += (dir == 0 ? kFusedFwdRows : kFusedBwdCols)) items.push_back({l, x});
+          for (int x = 0; x < n; x += step_rows) items.push_back({l, x});
         }
         fl.n = (int)items.size() - fl.off;
         (dir == 0 ? F.fwd[t] : F.bwd[t]).push_back(fl);
       }
     }
   }
+  F.dz.off = (int)items.size();
+  for (int l : pairs)
+    for (int r = 0; r < layers[l].K; r += kFusedDzRows) items.push_back({l, r});
+  F.dz.n = (int)items.size() - F.dz.off;
   F.n_pairs = (int)pairs.size();
   return TMC_OK;
 }

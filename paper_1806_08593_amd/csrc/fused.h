@@ -23,7 +23,7 @@ struct FusedLaunch {
 struct FusedPlan {
   int prec = 0, flags = 0;
   std::vector<std::vector<FusedLaunch>> fwd, bwd;   // [depth step][nkc group]
-  FusedLaunch colnorm;                              // all pairs, 32 columns per item
+  FusedLaunch dz;                                   // all pairs, 64 rows per item
   int n_pairs = 0;
   int pair_ids_off = 0;                             // into the plan's int table
 };
@@ -34,6 +34,7 @@ int nkc_bucket(int D);
 // per-layer offsets and appends its work items.  Rows per backward workgroup:
 constexpr int kFusedBwdCols = 128;
 constexpr int kFusedFwdRows = 128;
+constexpr int kFusedDzRows = 64;
 tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>& layers,
                        const std::vector<ChainDev>& chains, const std::vector<int>& pairs,
                        WsLayout& W, size_t& o, std::vector<Item>& items);
@@ -44,15 +45,21 @@ template <int PREC>
 hipError_t launch_fused_fwd(int nkc, int waves, bool grad, const LayerDev* layers,
                             const Item* items, int n, const float* z, const float* mu,
                             const float* s, const float* u, double* qcol, double* alpha,
-                            float* rl, float* ev, hipStream_t st);
+                            double* wmax, const double* pair_c, float* rl, float* ev,
+                            hipStream_t st);
 template <int PREC>
 hipError_t launch_fused_bwd(int nkc, int waves, const LayerDev* layers, const Item* items,
                             int n, const float* z, const float* mu, const float* s,
-                            const double* alpha, const double* qcol, const float* rl, float* lam,
-                            const float* ev, const double* dlogp, float* p, float* dz, float* dmu,
-                            float* du, float* dsp, hipStream_t st);
-hipError_t launch_fused_colnorm(const LayerDev* layers, const Item* items, int n, const float* mu,
-                                const float* s, double* qcol, hipStream_t st);
+                            const double* alpha, const double* wmax, const double* pair_c,
+                            const double* qcol, const float* rl, float* lam,
+                            const double* dlogp, float* p, float* dmu, float* du, float* dsp,
+                            hipStream_t st);
+hipError_t launch_fused_dz(const LayerDev* layers, const Item* items, int n, const float* z,
+                           const float* s, const float* p, const float* ev, const double* dlogp,
+                           float* dz, float* dsp, hipStream_t st);
+hipError_t launch_fused_fwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
+                                 const float* u, const float* s, double* alpha, double* wmax,
+                                 double* pair_c, hipStream_t st);
 hipError_t launch_fused_bwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
                                  const double* alpha, const double* logp_ws, const double* dlogp,
                                  const float* rl, float* lam, float* p, float* du, float* dz,

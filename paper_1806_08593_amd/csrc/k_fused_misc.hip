@@ -1,42 +1,48 @@
-// Fused engine: column norms and the start of the backward pass.
+// Fused engine: the start of the forward and of the backward pass.
 #include <math.h>
 
 #include "dev_util.h"
 #include "fused.h"
 #include "fused_kernels.h"
+#include "tmc_kernels.h"
 
 namespace tmc {
 
-using fused::load_f4;
-
-// q_j = -1/2 sum_d lam_d mu_jd^2 (FP64) for every column sample of every pair; read
-// by both passes so their column terms agree bitwise.  8 threads per row.
-__global__ __launch_bounds__(256) void k_fused_colnorm(const LayerDev* __restrict__ Ls,
-                                                       const Item* __restrict__ items,
-                                                       const float* __restrict__ mu,
-                                                       const float* __restrict__ s,
-                                                       double* __restrict__ qcol) {
-  const Item it = items[blockIdx.x];
-  const LayerDev& L = Ls[it.layer];
-  const int t = threadIdx.x, sub = t & 7;
-  const int j = it.start + (t >> 3);
-  const bool valid = j < L.Kc;
-  const bool vec = (L.D % 4 == 0) && (L.mu_off % 4 == 0);
-  const float* rowp = mu + L.mu_off + (int64_t)(valid ? j : 0) * L.D;
-  double q = 0.0;
-  for (int d = 4 * sub; d < L.D; d += 32) {
-    const float4 v = load_f4(rowp, d, L.D, valid, vec);
-    const float x[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (d + e < L.D) q += (double)expf(-2.0f * s[L.s_off + d + e]) * (double)x[e] * (double)x[e];
+// Start of the fused forward, one workgroup per chain: alpha of the top layer = u;
+// the per-128-row maxima of u_top (the same layout the forward leaves for every
+// other layer); and the per-pair constant c_l = -sum_d s_d - D/2 ln 2 pi.
+__global__ __launch_bounds__(256) void k_fused_fwd_init(const ChainDev* __restrict__ chains,
+                                                        const LayerDev* __restrict__ layers,
+                                                        const float* __restrict__ u,
+                                                        const float* __restrict__ s,
+                                                        double* __restrict__ alpha,
+                                                        double* __restrict__ wmax,
+                                                        double* __restrict__ pair_c) {
+  __shared__ double red[kMaxWaves];
+  const ChainDev ch = chains[blockIdx.x];
+  for (int l = ch.first; l < ch.top; ++l) {
+    const LayerDev& L = layers[l];
+    double ss = 0.0;
+    for (int d = threadIdx.x; d < L.D; d += blockDim.x) ss += (double)s[L.s_off + d];
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) {
+      pair_c[l] = -ss - 0.5 * (double)L.D * log(2.0 * M_PI);
+    }
   }
-  q += __shfl_xor(q, 1, kWave);
-  q += __shfl_xor(q, 2, kWave);
-  q += __shfl_xor(q, 4, kWave);
-  if (sub == 0 && valid) qcol[L.q_off + j] = -0.5 * q;
+  // the top layer's maxima, in the same per-128-row partial layout the forward uses
+  const LayerDev& t = layers[ch.top];
+  const int nparts = (t.K + 127) / 128;
+  for (int q = 0; q < nparts; ++q) {
+    double m = -INFINITY;
+    for (int k = q * 128 + threadIdx.x; k < min(t.K, (q + 1) * 128); k += blockDim.x) {
+      const double v = (double)u[t.u_off + k];
+      alpha[t.alpha_off + k] = v;
+      m = nan_max(m, v);
+    }
+    m = block_max(m, red);
+    if (threadIdx.x == 0) wmax[t.wmax_off + q] = m;
+  }
 }
-
 
 // p_0[i] = exp(alpha_0[i] - ln K_0 - log P), du_0 = dlogp p_0,
 // Lam_0[i] = ell_0[i] - log2 p_0[i] (the row shift the first backward step uses),
@@ -75,6 +81,103 @@ __global__ __launch_bounds__(256) void k_fused_bwd_init(const ChainDev* __restri
   }
 }
 
+// Row part of the backward of one pair, 64 rows of layer l per workgroup, with e_i the
+// softmax-weighted mean of mu left by the forward and p the marginals:
+//   dz_i = -dlogp * lam * p_i (z_i - e_i)
+//   ds row part = dlogp * (lam_d * sum_i p_i z_id^2 - sum_i p_i)
+// (the partial row follows the pair's column parts; fixed summation order).
+__global__ __launch_bounds__(256) void k_fused_dz(const LayerDev* __restrict__ Ls,
+                                                  const Item* __restrict__ items,
+                                                  const float* __restrict__ z,
+                                                  const float* __restrict__ s,
+                                                  const float* __restrict__ p,
+                                                  const float* __restrict__ ev,
+                                                  const double* __restrict__ dlogp,
+                                                  float* __restrict__ dz, float* __restrict__ dsp) {
+  __shared__ float lam[kFusedMaxD];
+  __shared__ float4 red[8][32];
+  __shared__ float redp[kMaxWaves];
+  const Item it = items[blockIdx.x];
+  const LayerDev& L = Ls[it.layer];
+  const int D = L.D, K = L.K, r0 = it.start;
+  const int tid = threadIdx.x, c4 = tid & 31, rg = tid >> 5;
+  for (int d = tid; d < D; d += blockDim.x) lam[d] = expf(-2.0f * s[L.s_off + d]);
+  const float* pr = p + L.p_off;
+  const float g = (float)dlogp[L.chain];
+  float P = 0.0f;
+  if (tid < 64 && r0 + tid < K) P = pr[r0 + tid];
+  P = block_sum(P, redp);     // (contains a barrier: lam is visible after it)
+  const bool vec = (D % 4 == 0) && (L.z_off % 4 == 0) && (L.ev_off % 4 == 0);
+  const int ncol = (L.Kc + kFusedBwdCols - 1) / kFusedBwdCols;
+  float* part = dsp ? dsp + L.dsp_off + (int64_t)(ncol + r0 / kFusedDzRows) * D : nullptr;
+  for (int d0 = 0; d0 < D; d0 += 128) {
+    const int d = d0 + 4 * c4;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (d < D) {
+      for (int r = rg; r < kFusedDzRows; r += 8) {
+        const int i = r0 + r;
+        if (i >= K) break;
+        const float pi = pr[i];
+        const int64_t o = (int64_t)i * D + d;
+        float zv[4], ev4[4];
+        if (vec && d + 3 < D) {
+          const float4 a = *reinterpret_cast<const float4*>(z + L.z_off + o);
+          const float4 b = *reinterpret_cast<const float4*>(ev + L.ev_off + o);
+          zv[0] = a.x; zv[1] = a.y; zv[2] = a.z; zv[3] = a.w;
+          ev4[0] = b.x; ev4[1] = b.y; ev4[2] = b.z; ev4[3] = b.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            zv[e] = (d + e < D) ? z[L.z_off + o + e] : 0.0f;
+            ev4[e] = (d + e < D) ? ev[L.ev_off + o + e] : 0.0f;
+          }
+        }
+        float out[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float lm = (d + e < D) ? lam[d + e] : 0.0f;
+          out[e] = -g * lm * pi * (zv[e] - ev4[e]);
+        }
+        acc.x += pi * zv[0] * zv[0];
+        acc.y += pi * zv[1] * zv[1];
+        acc.z += pi * zv[2] * zv[2];
+        acc.w += pi * zv[3] * zv[3];
+        if (dz) {
+          if (vec && d + 3 < D) {
+            *reinterpret_cast<float4*>(dz + L.z_off + o) = make_float4(out[0], out[1], out[2], out[3]);
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (d + e < D) dz[L.z_off + o + e] = out[e];
+          }
+        }
+      }
+    }
+    red[rg][c4] = acc;
+    __syncthreads();
+    if (rg == 0 && d < D && part) {
+      float4 t = red[0][c4];
+      for (int q = 1; q < 8; ++q) {
+        t.x += red[q][c4].x; t.y += red[q][c4].y; t.z += red[q][c4].z; t.w += red[q][c4].w;
+      }
+      const float tv[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (d + e < D) part[d + e] = g * (lam[d + e] * tv[e] - P);
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_fused_dz(const LayerDev* layers, const Item* items, int n, const float* z,
+                           const float* s, const float* p, const float* ev, const double* dlogp,
+                           float* dz, float* dsp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fused_dz, dim3(n), dim3(256), 0, st, layers, items, z, s, p, ev, dlogp, dz,
+                     dsp);
+  return hipGetLastError();
+}
+
 hipError_t launch_fused_bwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
                                  const double* alpha, const double* logp_ws, const double* dlogp,
                                  const float* rl, float* lam, float* p, float* du, float* dz,
@@ -85,10 +188,12 @@ hipError_t launch_fused_bwd_init(const ChainDev* chains, int n_chains, const Lay
   return hipGetLastError();
 }
 
-hipError_t launch_fused_colnorm(const LayerDev* layers, const Item* items, int n, const float* mu,
-                                const float* s, double* qcol, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_colnorm, dim3(n), dim3(256), 0, st, layers, items, mu, s, qcol);
+hipError_t launch_fused_fwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
+                                 const float* u, const float* s, double* alpha, double* wmax,
+                                 double* pair_c, hipStream_t st) {
+  if (n_chains <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fused_fwd_init, dim3(n_chains), dim3(256), 0, st, chains, layers, u, s,
+                     alpha, wmax, pair_c);
   return hipGetLastError();
 }
 

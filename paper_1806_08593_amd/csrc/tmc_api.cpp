@@ -242,7 +242,7 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   const size_t esz = P->esz;
   P->layers_h.assign(pr->n_layers, LayerDev{});
   P->chains_h.resize(pr->n_chains);
-  int64_t sumK = 0, sum_pairKK = 0, sum_pairKcD = 0, sum_pairD = 0;
+  int64_t sumK = 0, sum_pairKK = 0, sum_pairKcD = 0, sum_pairD = 0, sum_wmax = 0;
   P->max_depth = 0;
   P->entries = 0;
   for (int c = 0; c < pr->n_chains; ++c) {
@@ -267,6 +267,8 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
       d.f_off = top ? 0 : L.f_off;
       d.u_up_off = top ? 0 : pr->layers[l + 1].u_off;
       d.alpha_off = sumK;
+      d.wmax_off = sum_wmax;
+      sum_wmax += (L.K + 127) / 128;
       d.p_off = sumK;
       d.rl_off = sumK;
       sumK += L.K;
@@ -275,7 +277,10 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
         sum_pairKK += align_up((size_t)L.K * d.Kc, 4);
         d.gtz_off = sum_pairKcD;
         sum_pairKcD += (int64_t)d.Kc * L.D;
-        d.dsp_parts = P->engine == TMC_ENGINE_FUSED ? (d.Kc + kFusedBwdCols - 1) / kFusedBwdCols : 1;
+        d.dsp_parts = P->engine == TMC_ENGINE_FUSED
+                          ? (d.Kc + kFusedBwdCols - 1) / kFusedBwdCols +
+                                (L.K + kFusedDzRows - 1) / kFusedDzRows
+                          : 1;
         d.dsp_off = sum_pairD;
         sum_pairD += (int64_t)L.D * d.dsp_parts;
         P->entries += (int64_t)L.K * d.Kc;
@@ -301,6 +306,7 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   W.rl = take(sumK * esz);
   W.pairM = take((size_t)pr->n_layers * 8);
   W.logp = take((size_t)pr->n_chains * 8);
+  W.wmax = take((size_t)sum_wmax * 8);
   W.dsp = take(sum_pairD * esz);
   if (P->engine == TMC_ENGINE_PLAIN) {
     W.wf = take(sum_pairKK * esz);
@@ -561,18 +567,20 @@ tmc_status fused_fwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
   double* qcol = wsp<double>(ws, W.q);
   float* rl = wsp<float>(ws, W.rl);
   float* ev = wsp<float>(ws, W.ev);
-  LAUNCH(launch_init_top<float>(P->chains_d, P->n_chains, P->layers_d, u, alpha, st));
+  double* wmax = wsp<double>(ws, W.wmax);
+  double* pair_c = wsp<double>(ws, W.pairM);
+  LAUNCH(launch_fused_fwd_init(P->chains_d, P->n_chains, P->layers_d, u, s, alpha, wmax, pair_c, st));
   for (auto& step : P->fused.fwd)
     for (auto& g : step) {
       const Item* it = P->items_d + g.off;
       if (P->prec == TMC_FP32)
         LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_FP32>(g.nkc, g.waves, grad, P->layers_d, it,
-                                                               g.n, z, mu, s, u, qcol, alpha, rl,
-                                                               ev, st));
+                                                               g.n, z, mu, s, u, qcol, alpha, wmax,
+                                                               pair_c, rl, ev, st));
       else
         LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_BF16X3>(g.nkc, g.waves, grad, P->layers_d,
                                                                  it, g.n, z, mu, s, u, qcol, alpha,
-                                                                 rl, ev, st));
+                                                                 wmax, pair_c, rl, ev, st));
     }
   LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, alpha, logp,
                          wsp<double>(ws, W.logp), P->flag_d, st));
@@ -585,6 +593,8 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
   const WsLayout& W = P->ws;
   double* alpha = wsp<double>(ws, W.alpha);
   const double* qcol = wsp<double>(ws, W.q);
+  const double* wmax = wsp<double>(ws, W.wmax);
+  const double* pair_c = wsp<double>(ws, W.pairM);
   float* rl = wsp<float>(ws, W.rl);
   float* lam = wsp<float>(ws, W.lam);
   float* p = wsp<float>(ws, W.p);
@@ -597,14 +607,17 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
       const Item* it = P->items_d + g.off;
       if (P->prec == TMC_FP32)
         LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_FP32>(g.nkc, g.waves, P->layers_d, it, g.n,
-                                                               z, mu, s, alpha, qcol, rl, lam, ev,
-                                                               dlogp, p, dz, dmu, du, dsp, st));
+                                                               z, mu, s, alpha, wmax, pair_c, qcol,
+                                                               rl, lam, dlogp, p, dmu, du, dsp, st));
       else
         LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_BF16X3>(g.nkc, g.waves, P->layers_d, it,
-                                                                 g.n, z, mu, s, alpha, qcol, rl,
-                                                                 lam, ev, dlogp, p, dz, dmu, du,
+                                                                 g.n, z, mu, s, alpha, wmax, pair_c,
+                                                                 qcol, rl, lam, dlogp, p, dmu, du,
                                                                  dsp, st));
     }
+  if ((dz || ds) && P->fused.dz.n > 0)
+    LAUNCH(launch_fused_dz(P->layers_d, P->items_d + P->fused.dz.off, P->fused.dz.n, z, s, p, ev,
+                           dlogp, dz, dsp, st));
   if (ds)
     LAUNCH(launch_ds_reduce<float>(P->part_off_d, P->ints_d + P->slot_start_off, P->slot_soff_d,
                                    P->ints_d + P->slot_D_off, P->n_slots, P->max_D, dsp, ds, st));

@@ -37,6 +37,7 @@ struct LayerDev {
   int64_t dsp_off;       // T ds partial rows [dsp_parts][D] of this pair
   int64_t ev_off;        // fused: float softmax-weighted mean of mu per row [K][D]
   int64_t q_off;         // fused: double column norms q_j of this pair [Kc]
+  int64_t wmax_off;      // fused: double maxima of alpha per 128 rows [ceil(K/128)]
   int32_t dsp_parts;     // partial rows of the log-std gradient of this pair
   int32_t pad1;
 };
@@ -50,7 +51,7 @@ struct ChainDev {
 
 // Byte offsets of the workspace regions.
 struct WsLayout {
-  size_t alpha, p, rl, pairM, logp;
+  size_t alpha, p, rl, pairM, logp, wmax;
   size_t wf, wg, gtz, dsp;          // plain engine (dsp shared)
   size_t ev, lam, q;                // fused engine
   size_t total;
