@@ -114,41 +114,43 @@ __global__ __launch_bounds__(256) void k_fused_dz(const LayerDev* __restrict__ L
     const int d = d0 + 4 * c4;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (d < D) {
-      for (int r = rg; r < kFusedDzRows; r += 8) {
-        const int i = r0 + r;
-        if (i >= K) break;
-        const float pi = pr[i];
-        const int64_t o = (int64_t)i * D + d;
-        float zv[4], ev4[4];
-        if (vec && d + 3 < D) {
-          const float4 a = *reinterpret_cast<const float4*>(z + L.z_off + o);
-          const float4 b = *reinterpret_cast<const float4*>(ev + L.ev_off + o);
-          zv[0] = a.x; zv[1] = a.y; zv[2] = a.z; zv[3] = a.w;
-          ev4[0] = b.x; ev4[1] = b.y; ev4[2] = b.z; ev4[3] = b.w;
-        } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            zv[e] = (d + e < D) ? z[L.z_off + o + e] : 0.0f;
-            ev4[e] = (d + e < D) ? ev[L.ev_off + o + e] : 0.0f;
-          }
-        }
-        float out[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float lm = (d + e < D) ? lam[d + e] : 0.0f;
-          out[e] = -g * lm * pi * (zv[e] - ev4[e]);
-        }
-        acc.x += pi * zv[0] * zv[0];
-        acc.y += pi * zv[1] * zv[1];
-        acc.z += pi * zv[2] * zv[2];
-        acc.w += pi * zv[3] * zv[3];
-        if (dz) {
+      for (int rr = 0; rr < kFusedDzRows / 8; ++rr) {
+        const int i = r0 + rg + 8 * rr;
+        if (i < K) {
+          const float pi = pr[i];
+          const int64_t o = (int64_t)i * D + d;
+          float zv[4], ev4[4];
           if (vec && d + 3 < D) {
-            *reinterpret_cast<float4*>(dz + L.z_off + o) = make_float4(out[0], out[1], out[2], out[3]);
+            const float4 a = *reinterpret_cast<const float4*>(z + L.z_off + o);
+            const float4 b = *reinterpret_cast<const float4*>(ev + L.ev_off + o);
+            zv[0] = a.x; zv[1] = a.y; zv[2] = a.z; zv[3] = a.w;
+            ev4[0] = b.x; ev4[1] = b.y; ev4[2] = b.z; ev4[3] = b.w;
           } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (d + e < D) dz[L.z_off + o + e] = out[e];
+            for (int e = 0; e < 4; ++e) {
+              zv[e] = (d + e < D) ? z[L.z_off + o + e] : 0.0f;
+              ev4[e] = (d + e < D) ? ev[L.ev_off + o + e] : 0.0f;
+            }
+          }
+          float out[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float lm = (d + e < D) ? lam[d + e] : 0.0f;
+            out[e] = -g * lm * pi * (zv[e] - ev4[e]);
+          }
+          acc.x += pi * zv[0] * zv[0];
+          acc.y += pi * zv[1] * zv[1];
+          acc.z += pi * zv[2] * zv[2];
+          acc.w += pi * zv[3] * zv[3];
+          if (dz) {
+            if (vec && d + 3 < D) {
+              *reinterpret_cast<float4*>(dz + L.z_off + o) = make_float4(out[0], out[1], out[2], out[3]);
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (d + e < D) dz[L.z_off + o + e] = out[e];
+            }
           }
         }
       }

@@ -22,6 +22,15 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_1806_08593_amd.build_lib`")
+# PyTorch's ROCm wheel ships its own HIP runtime under the same soname
+# (libamdhip64.so.7).  Loading torch first makes libtmc bind to that runtime instead
+# of loading a second HIP/HSA runtime into the process (with two, whichever
+# initialises second sees no GPU, and torch's device pointers would belong to the
+# other runtime).
+try:
+    import torch  # noqa: F401
+except ImportError:  # pure C-ABI use without torch: the system HIP runtime is used
+    pass
 _lib = ctypes.CDLL(_LIB_PATH)
 
 TMC_OK, TMC_ERR_INVALID_ARG, TMC_ERR_SHAPE, TMC_ERR_WORKSPACE = 0, 1, 2, 3
