@@ -1,20 +1,22 @@
 #!/usr/bin/env python
 """Throughput of the TMC chain estimator on one MI355X.
 
-One step = one forward + backward pass of the Gaussian-chain estimator (factor
-construction, top-down log-sum-exp messages, FP64 log-normaliser, marginals and the
-gradients with respect to z, mu, s and u) over one batch of synthetic inputs that
-are already resident in device memory.
+One step = one forward + backward pass of the Gaussian-chain estimator over one batch
+of synthetic inputs already resident in device memory: the pairwise factors on
+MFMA, the top-down log-sum-exp messages, the FP64 log-normaliser, the pairwise
+marginals and the gradients with respect to z, mu, s and u.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
                     [--precision bf16x3|fp32|fp64] [--engine auto|fused|plain]
+                    [--no-compare] [--no-cpu-baseline] [--calibrate-copy MB]
 
-Prints one JSON line.  `value` is factor entries per second, where a step processes
-sum over chains and adjacent layer pairs of K_l * K_{l+1} entries.  The roofline
-object describes the kernel class with the largest device time, timed with HIP
-events recorded by the library around each of its launches in the timed region.
-The cpu_baseline object times the FP64 NumPy oracle on a bounded sample of the same
-workload on the host.
+Prints one JSON line.  `value` is factor entries per second (a step processes the
+sum over chains and adjacent layer pairs of K_l * K_{l+1} entries).  `roofline`
+describes the kernel class with the largest device time in the timed region, timed
+with HIP events that the library records around each of its launches on the stream
+it launches on.  `compare` times the same step in the other precisions / engines
+and gives each one's error against the FP64 oracle; `cpu_baseline` times the FP64
+oracle on a bounded sample of the workload on the host.
 """
 import argparse
 import json
@@ -26,42 +28,105 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# dense peaks (TFLOP/s) of MI355X: matrix cores by dtype, vector ALU without packed FP32
+# dense peaks of MI355X (TFLOP/s): matrix cores by operand type; vector ALU without
+# packed FP32 (256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz)
 MFMA_PEAK = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
-VALU_PEAK = {"fp32": 78.6, "fp64": 78.6, "bf16x3": 78.6}
+VALU_PEAK = 78.6
 
 
-def _algorithmic(kc_name, entries, D, prec, pairs_bytes):
-    """(amount per step, unit, bound, peak) of one kernel class.
-    Fused kernels: the factor GEMM counts 2*D flops per entry; the forward also
-    forms the softmax-weighted mean of mu (2*D), the backward recomputes the
-    factors (2*D) and forms G^T z (2*D).  Plain log-sum-exp passes are HBM-bound:
-    the forward reads f once (esz bytes per entry), the backward reads f and
-    writes G (2*esz)."""
+def algorithmic(kc_name, entries, d_weighted, prec):
+    """(amount per step, unit, bound, peak) of one kernel class; d_weighted is
+    sum over pairs of K_l K_{l+1} D_l.  Fused forward: the factor GEMM (2 D flops per
+    entry) and the softmax-weighted mean of mu (2 D); fused backward: the recomputed
+    factor GEMM (2 D) and G^T z (2 D).  Plain log-sum-exp passes stream the stored
+    factors: the forward reads esz bytes per entry, the backward reads f and writes G."""
     esz = 8 if prec == "fp64" else 4
-    if kc_name == "fused_fwd":
-        return 4.0 * D * entries, "TFLOP/s", "mfma", MFMA_PEAK[prec]
-    if kc_name == "fused_bwd":
-        return 4.0 * D * entries, "TFLOP/s", "mfma", MFMA_PEAK[prec]
+    if kc_name in ("fused_fwd", "fused_bwd"):
+        return 4.0 * d_weighted, "TFLOP/s", "mfma", MFMA_PEAK[prec]
     if kc_name == "plain_lse_fwd":
         return float(esz * entries), "GB/s", "hbm", HBM_PEAK_GBS
     if kc_name == "plain_lse_bwd":
         return float(2 * esz * entries), "GB/s", "hbm", HBM_PEAK_GBS
     if kc_name == "plain_factor":
-        # direct difference: 3 flops per (entry, d)
-        return 3.0 * D * entries, "TFLOP/s", "alu", VALU_PEAK[prec]
+        return 3.0 * d_weighted, "TFLOP/s", "alu", VALU_PEAK
     if kc_name == "plain_grad":
-        # G mu and G^T z: 2 * 2*D flops per entry
-        return 4.0 * D * entries, "TFLOP/s", "alu", VALU_PEAK[prec]
-    if kc_name == "fused_prep":
-        return float(pairs_bytes), "GB/s", "hbm", HBM_PEAK_GBS
+        return 4.0 * d_weighted, "TFLOP/s", "alu", VALU_PEAK
     return None
 
 
-def cpu_baseline(chains, budget_s=15.0):
-    """Time the FP64 oracle (forward + backward) on as many instances as fit in
-    about budget_s seconds of host time; returns (entries/s, sample description,
-    per-instance oracle log P)."""
+def upload(w, prec, engine, flags=0):
+    """Device buffers and the problem for workload w (homogeneous layout with s shared
+    by the batch when w is a stacked batch, packed ragged layout otherwise)."""
+    import numpy as np
+    import torch
+    from paper_1806_08593_amd import tmc as T
+    from workloads import pack
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    npdt = np.float64 if prec == "fp64" else np.float32
+    if w.z is not None:
+        B, L, K, D = w.z.shape
+        prob = T.homogeneous_problem(B, L, K, D, prec, engine, flags)
+        arrs = {k: getattr(w, k) for k in ("z", "mu", "s", "u")}
+    else:
+        shapes, arrs = pack(w.chains, npdt)
+        prob, _ = T.ragged_problem(shapes, prec, engine, flags)
+    dev = {k: torch.tensor(np.ascontiguousarray(v), dtype=tdt, device="cuda:0") for k, v in arrs.items()}
+    return prob, dev
+
+
+def run_mode(w, prec, engine, steps, warmup, timing):
+    import torch
+    from paper_1806_08593_amd import tmc as T
+    prob, d = upload(w, prec, engine)
+    plan = T.Plan(prob)
+    ws = plan.new_workspace()
+    n = prob.n_chains
+    logp = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    dlogp = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    g = {k: torch.empty_like(v) for k, v in d.items()}
+    h = plan.handle
+
+    def step():
+        T.tmc_gauss_fwd(h, d["z"], d["mu"], d["s"], d["u"], logp, ws)
+        T.tmc_gauss_bwd(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"], g["s"],
+                        g["u"])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    T.tmc_plan_check(h)
+    if timing:
+        T.tmc_plan_set_timing(h, True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()                     # (one GPU: the barrier is this sync)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kc = {}
+    if timing:
+        for i, name in enumerate(T.KERNEL_CLASSES):
+            ms, cnt = T.tmc_plan_timing(h, i)
+            if cnt:
+                kc[name] = dict(ms_per_step=ms / steps, launches_per_step=cnt / steps,
+                                avg_launch_us=1e3 * ms / cnt)
+        T.tmc_plan_set_timing(h, False)
+    T.tmc_plan_check(h)
+    out = dict(ms_per_step=(t1 - t0) * 1e3 / steps, event_ms_per_step=e0.elapsed_time(e1) / steps,
+               kernels=kc, logp=logp.cpu().numpy(), info=plan.info)
+    plan.close()
+    del d, g, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(chains, budget_s):
+    """FP64 oracle (forward + backward) on as many instances as fit in about budget_s
+    seconds of host time.  Returns (entries/s, instances done, seconds, log P list)."""
     from oracle import tmc_oracle as O
     t0 = time.perf_counter()
     done, ent, refs = 0, 0, []
@@ -85,6 +150,10 @@ def main():
     ap.add_argument("--engine", default="auto")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0,
+                    help="first copy this many MiB with a plain device copy (a known-size "
+                         "kernel for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -94,90 +163,84 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1806_08593_amd import tmc as T
-    from workloads import CONFIGS, cast_chain, make
+    from workloads import cast_chain, make
 
-    cfg = CONFIGS[args.workload]
+    if args.calibrate_copy > 0:
+        n = int(args.calibrate_copy * 2 ** 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     prec = args.precision or ("fp64" if args.workload == "c1" else "bf16x3")
     print(f"[bench] generating workload {args.workload} ...", file=sys.stderr, flush=True)
     w = make(args.workload)
-    B, L, K, D = w.z.shape
-    tdt = torch.float64 if prec == "fp64" else torch.float32
-    dev = "cuda:0"
-    z = torch.tensor(w.z, dtype=tdt, device=dev)
-    mu = torch.tensor(w.mu, dtype=tdt, device=dev)
-    s = torch.tensor(w.s, dtype=tdt, device=dev)
-    u = torch.tensor(w.u, dtype=tdt, device=dev)
-    prob = T.homogeneous_problem(B, L, K, D, prec, args.engine)
-    plan = T.Plan(prob)
-    ws = plan.new_workspace()
-    logp = torch.empty(B, dtype=torch.float64, device=dev)
-    dlogp = torch.ones(B, dtype=torch.float64, device=dev)
-    dz, dmu, ds, du = (torch.empty_like(t) for t in (z, mu, s, u))
-    entries = plan.info["factor_entries"]
-    h = plan.handle
+    entries = w.entries()
+    d_weighted = float(sum(c.K[l] * c.K[l + 1] * c.D[l] for c in w.chains for l in range(c.L - 1)))
 
-    def step():
-        T.tmc_gauss_fwd(h, z, mu, s, u, logp, ws)
-        T.tmc_gauss_bwd(h, z, mu, s, u, dlogp, ws, dz, dmu, ds, du)
-
-    print(f"[bench] warmup {args.warmup} steps ...", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    T.tmc_plan_check(h)
-
-    T.tmc_plan_set_timing(h, True)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall_ms = (t1 - t0) * 1e3 / args.steps
-    ev_ms = e0.elapsed_time(e1) / args.steps
-    kc = {}
-    for i, name in enumerate(T.KERNEL_CLASSES):
-        ms, n = T.tmc_plan_timing(h, i)
-        if n:
-            kc[name] = dict(ms_per_step=ms / args.steps, launches_per_step=n / args.steps,
-                            avg_launch_us=1e3 * ms / n)
-    T.tmc_plan_set_timing(h, False)
-    T.tmc_plan_check(h)
-    ms_per_step = wall_ms
+    print(f"[bench] {prec}/{args.engine}: warmup {args.warmup}, timed {args.steps} steps",
+          file=sys.stderr, flush=True)
+    main_run = run_mode(w, prec, args.engine, args.steps, args.warmup, timing=True)
+    ms_per_step = main_run["ms_per_step"]
     value = entries / (ms_per_step / 1e3)
-
+    kc = main_run["kernels"]
     dom = max((k for k in kc if k != "other"), key=lambda k: kc[k]["ms_per_step"])
-    alg = _algorithmic(dom, entries, D, prec, 0)
+    alg = algorithmic(dom, entries, d_weighted, prec)
     roofline = None
     if alg is not None:
         amount, unit, bound, peak = alg
         per_launch = amount / kc[dom]["launches_per_step"]
-        secs = kc[dom]["avg_launch_us"] * 1e-6
-        achieved = per_launch / secs / (1e12 if unit == "TFLOP/s" else 1e9)
+        achieved = per_launch / (kc[dom]["avg_launch_us"] * 1e-6) / (1e12 if unit == "TFLOP/s" else 1e9)
         roofline = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
                         frac=round(achieved / peak, 4), traffic=None,
                         algorithmic_per_launch=per_launch,
                         avg_launch_us=round(kc[dom]["avg_launch_us"], 3))
 
-    # accuracy and CPU baseline on the same instances
-    out_logp = logp.cpu().numpy()
+    # comparators: the other arithmetic modes of the same step
+    compare = {}
+    if not args.no_compare and prec != "fp64":
+        for cp, ce in (("fp32", "fused"), ("fp32", "plain")):
+            if (cp, ce) == (prec, args.engine):
+                continue
+            try:
+                print(f"[bench] comparator {cp}/{ce}", file=sys.stderr, flush=True)
+                r = run_mode(w, cp, ce, max(3, args.steps // 3), 2, timing=False)
+                compare[f"{cp}_{ce}"] = dict(ms_per_step=r["ms_per_step"],
+                                             value=entries / (r["ms_per_step"] / 1e3), logp=r["logp"])
+            except Exception as e:   # e.g. a plain-engine workspace that does not fit
+                compare[f"{cp}_{ce}"] = dict(error=str(e)[:200])
+
+    # errors against the FP64 oracle on the CPU-baseline sample, and the baseline itself
     cpu = None
-    err = None
+    errs = {}
     if not args.no_cpu_baseline:
         npdt = np.float64 if prec == "fp64" else np.float32
         sample = [cast_chain(c, npdt) for c in w.chains]
         print(f"[bench] CPU oracle baseline (~{args.cpu_budget:.0f} s) ...", file=sys.stderr, flush=True)
         rate, done, dt, refs = cpu_baseline(sample, args.cpu_budget)
-        err = float(max(abs(out_logp[b] - refs[b]) for b in range(done)))
+        errs[prec] = float(max(abs(main_run["logp"][b] - refs[b]) for b in range(done)))
+        for k, v in compare.items():
+            if "logp" in v:
+                errs[k] = float(max(abs(v["logp"][b] - refs[b]) for b in range(done)))
         cpu = dict(value=rate, unit="factor entries/s", cores=1, kind="oracle",
-                   sample=f"forward+backward of {done} of {B} instances "
-                          f"({done * entries // B} entries) in {dt:.1f} s, FP64 NumPy, one thread")
+                   sample=f"forward+backward of the first {done} of {len(w.chains)} instances "
+                          f"({sum(c.entries() for c in w.chains[:done])} entries) in {dt:.1f} s, "
+                          f"FP64 NumPy, one thread")
+    for v in compare.values():
+        v.pop("logp", None)
+    if compare:
+        base = compare.get("fp32_plain", {}).get("ms_per_step")
+        if base:
+            compare["speedup_over_fp32_plain"] = base / ms_per_step
 
+    cfg = {"workload": args.workload, "chains": len(w.chains), "factor_entries": entries,
+           "precision": prec, "engine": ["auto", "fused", "plain"][main_run["info"]["engine"]],
+           "parallelism": "single GPU"}
+    if w.z is not None:
+        B, L, K, D = w.z.shape
+        cfg.update(B=B, L=L, K=K, D=D)
     line = {
         "metric": "factor entries/s (fwd+bwd)",
         "value": value,
@@ -191,14 +254,13 @@ def main():
         "vs_baseline": None,
         "dtype": {"bf16x3": "bf16", "fp32": "f32", "fp64": "f64"}[prec],
         "data": "synthetic",
-        "config": {"workload": args.workload, "B": B, "L": L, "K": K, "D": D,
-                   "precision": prec, "engine": ["auto", "fused", "plain"][plan.info["engine"]],
-                   "factor_entries": entries, "parallelism": "single GPU"},
+        "config": cfg,
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "max_abs_err_logp_vs_oracle": err,
-        "event_ms_per_step": ev_ms,
+        "max_abs_err_logp_vs_oracle": errs,
+        "event_ms_per_step": main_run["event_ms_per_step"],
         "kernels": kc,
+        "compare": compare,
     }
     print(json.dumps(line))
 

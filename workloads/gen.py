@@ -237,3 +237,16 @@ def cast_chain(c: Chain, dtype) -> Chain:
     f = lambda a: np.asarray(a, dtype=dtype).astype(np.float64)
     return Chain(z=[f(a) for a in c.z], mu=[f(a) for a in c.mu], s=[f(a) for a in c.s],
                  u=[f(a) for a in c.u])
+
+
+def pack(chains: List[Chain], dtype=np.float32):
+    """Flatten chains back to back (the layout of the library's ragged problem
+    descriptor): returns (shapes, dict of flat z, mu, s, u arrays) where shapes is a
+    list of (K_list, D_list) per chain."""
+    shapes = [([int(a.shape[0]) for a in c.z], [int(a.shape[1]) for a in c.z]) for c in chains]
+    cat = lambda arrs: (np.concatenate([a.reshape(-1) for a in arrs]) if arrs
+                        else np.zeros(1)).astype(dtype)
+    return shapes, dict(z=cat([a for c in chains for a in c.z]),
+                        mu=cat([a for c in chains for a in c.mu]),
+                        s=cat([a for c in chains for a in c.s]),
+                        u=cat([a for c in chains for a in c.u]))
