@@ -45,12 +45,11 @@ template <int PREC>
 hipError_t launch_fused_fwd(int nkc, int waves, bool grad, const LayerDev* layers,
                             const Item* items, int n, const float* z, const float* mu,
                             const float* s, const float* u, double* qcol, double* alpha,
-                            double* wmax, const double* pair_c, float* rl, float* ev,
-                            hipStream_t st);
+                            double* wmax, float* rl, float* ev, hipStream_t st);
 template <int PREC>
 hipError_t launch_fused_bwd(int nkc, int waves, const LayerDev* layers, const Item* items,
                             int n, const float* z, const float* mu, const float* s,
-                            const double* alpha, const double* wmax, const double* pair_c,
+                            const double* alpha, const double* wmax,
                             const double* qcol, const float* rl, float* lam,
                             const double* dlogp, float* p, float* dmu, float* du, float* dsp,
                             hipStream_t st);
@@ -58,8 +57,7 @@ hipError_t launch_fused_dz(const LayerDev* layers, const Item* items, int n, con
                            const float* s, const float* p, const float* ev, const double* dlogp,
                            float* dz, float* dsp, hipStream_t st);
 hipError_t launch_fused_fwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
-                                 const float* u, const float* s, double* alpha, double* wmax,
-                                 double* pair_c, hipStream_t st);
+                                 const float* u, double* alpha, double* wmax, hipStream_t st);
 hipError_t launch_fused_bwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
                                  const double* alpha, const double* logp_ws, const double* dlogp,
                                  const float* rl, float* lam, float* p, float* du, float* dz,

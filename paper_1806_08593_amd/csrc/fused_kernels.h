@@ -6,8 +6,9 @@
 // (the diagonal-Gaussian conditional of Sec. "Computational costs for TMC and IWAE")
 // is never stored: the inner product runs on MFMA tile by tile and feeds an online
 // log-sum-exp (forward) or the pairwise marginals (backward).  The per-sample norms
-// r_i, q_j are accumulated in FP64 (O(K D) work) so the large, cancelling terms of the
-// expansion never pass through FP32; the per-entry arithmetic is FP32.
+// r_i, q_j and the constant c are accumulated in FP64 (O(K D) work) so the large,
+// cancelling terms of the expansion never pass through FP32; the per-entry arithmetic
+// is FP32.
 //
 // MFMA layouts (v_mfma_f32_32x32x16_bf16 and v_mfma_f32_32x32x2_f32 on gfx950):
 //   operand fragment: lane l holds vector (l % 32) and a k-slice selected by l / 32;
@@ -16,6 +17,13 @@
 // registers: BF16X3 keeps x = hi + lo (both bf16) and forms hi*hi + hi*lo + lo*hi;
 // FP32 feeds the values directly.  A 16-wide d chunk gives each lane 8 consecutive d
 // (d = 16 kc + 8 (l/32) + s); both operands use that same k order.
+//
+// Pipelining.  Global loads are issued branch-free (clamped addresses, zeros
+// selected afterwards) so that a wave's loads are all in flight together, and the
+// workgroup barriers wait for LDS traffic only (lds_barrier), never for global loads
+// in flight.  Staged operand tiles are double-buffered in LDS when two buffers fit
+// beside a second workgroup (d <= 128): tile t+1 is written and tile t+2 fetched while
+// tile t is consumed, one barrier per tile.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,8 +43,15 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kHalfLn2Pi = 0.91893853320467274178;
 constexpr float kRescale = 8.0f;   // lazy online-max threshold (log2 units)
 constexpr int kFusedRowsPerGroup = 128;   // forward rows per workgroup (4 waves x 32)
+
+// Workgroup barrier that orders LDS traffic only: outstanding global loads stay in
+// flight across it (a fence-based __syncthreads would wait for them).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 template <int PREC>
 struct Frag;
@@ -77,38 +92,69 @@ __device__ __forceinline__ void mma_chunk(f32x16& acc, const Frag<PREC>& a, cons
   }
 }
 
-// Eight consecutive values row[d0 .. d0+7] with zeros past D (vector loads when the
-// row is 16-byte aligned and the chunk is whole).
+// Eight consecutive values row[d0 .. d0+7], zeros past D, without branches: the
+// addresses are clamped into the row (which must be a valid row of D >= 1 values).
+// `vec`: D % 4 == 0 and the row is 16-byte aligned.
 __device__ __forceinline__ void load8(const float* __restrict__ row, int d0, int D, bool vec,
                                       float (&x)[8]) {
-  if (vec && d0 + 8 <= D) {
-    const float4 a = *reinterpret_cast<const float4*>(row + d0);
-    const float4 b = *reinterpret_cast<const float4*>(row + d0 + 4);
-    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-    x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+  if (vec) {
+    const float4 a = *reinterpret_cast<const float4*>(row + min(d0, D - 4));
+    const float4 b = *reinterpret_cast<const float4*>(row + min(d0 + 4, D - 4));
+    const bool va = d0 < D, vb = d0 + 4 < D;
+    x[0] = va ? a.x : 0.0f; x[1] = va ? a.y : 0.0f; x[2] = va ? a.z : 0.0f; x[3] = va ? a.w : 0.0f;
+    x[4] = vb ? b.x : 0.0f; x[5] = vb ? b.y : 0.0f; x[6] = vb ? b.z : 0.0f; x[7] = vb ? b.w : 0.0f;
   } else {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) x[s] = (d0 + s < D) ? row[d0 + s] : 0.0f;
+    for (int s = 0; s < 8; ++s) {
+      const float v = row[min(d0 + s, D - 1)];
+      x[s] = (d0 + s < D) ? v : 0.0f;
+    }
   }
 }
 
-__device__ __forceinline__ float lam_f(const float* __restrict__ s, int d, int D) {
-  return d < D ? expf(-2.0f * s[d]) : 0.0f;
+// Four values row[d .. d+3] (zeros past D, or everywhere when !valid), branch-free.
+__device__ __forceinline__ float4 load_f4(const float* __restrict__ row, int d, int D, bool valid,
+                                          bool vec) {
+  float4 r;
+  if (vec) {
+    r = *reinterpret_cast<const float4*>(row + min(d, D - 4));
+    const bool v = valid && d < D;
+    r.x = v ? r.x : 0.0f; r.y = v ? r.y : 0.0f; r.z = v ? r.z : 0.0f; r.w = v ? r.w : 0.0f;
+  } else {
+    const float a = row[min(d + 0, D - 1)], b = row[min(d + 1, D - 1)];
+    const float c = row[min(d + 2, D - 1)], e = row[min(d + 3, D - 1)];
+    r.x = (valid && d + 0 < D) ? a : 0.0f;
+    r.y = (valid && d + 1 < D) ? b : 0.0f;
+    r.z = (valid && d + 2 < D) ? c : 0.0f;
+    r.w = (valid && d + 3 < D) ? e : 0.0f;
+  }
+  return r;
 }
 
-// Column constant pieces shared by forward and backward (identical in both):
-// maxa = max_j alpha_{l+1}[j], reduced from the per-workgroup maxima the pass that
-// wrote alpha_{l+1} left in wmax (fixed order); cs = -sum_d s_d - D/2 ln 2 pi (per
-// pair, written at the start of the forward).
-__device__ __forceinline__ void pair_constants(const LayerDev& L, const LayerDev& U,
-                                               const double* __restrict__ wmax,
-                                               const double* __restrict__ pair_c, double& maxa,
-                                               double& cs) {
-  const int n = (U.K + kFusedRowsPerGroup - 1) / kFusedRowsPerGroup;
+__device__ __forceinline__ float lam_f(const float* __restrict__ s, int d, int D) {
+  const float v = s[min(d, D - 1)];
+  return d < D ? expf(-2.0f * v) : 0.0f;
+}
+
+// Column shift of pair L: maxa = max_j alpha_{l+1}[j], reduced over the
+// per-workgroup maxima the pass that wrote alpha_{l+1} left in wmax (one lane per
+// partial, then a wave reduction; exact, so the order does not matter).
+__device__ __forceinline__ double pair_maxa(const LayerDev& L, const double* __restrict__ wmax) {
+  const int lane = threadIdx.x & 63;
   double m = -INFINITY;
-  for (int k = 0; k < n; ++k) m = nan_max(m, wmax[U.wmax_off + k]);
-  maxa = (m == -INFINITY) ? 0.0 : m;
-  cs = pair_c[L.up - 1];
+  for (int k = lane; k < L.nwmax_up; k += 64) m = nan_max(m, wmax[L.wmax_up_off + k]);
+  m = wave_max(m);
+  return (m == -INFINITY) ? 0.0 : m;
+}
+
+// c = -sum_d s_d - D/2 ln 2 pi of pair L in FP64 (fixed order: lane-strided partial
+// sums, then a butterfly over the wave), complete in every lane of the calling wave.
+__device__ __forceinline__ double pair_const(const LayerDev& L, const float* __restrict__ s) {
+  const int lane = threadIdx.x & 63;
+  double a = 0.0;
+  for (int d = lane; d < L.D; d += 64) a += (double)s[L.s_off + d];
+  a = wave_sum(a);
+  return -a - (double)L.D * kHalfLn2Pi;
 }
 
 // Transposed operand of a 32-row tile X[k][d] (rows k are the contraction index):
@@ -126,41 +172,61 @@ struct TFrag<TMC_BF16X3> {
   Frag<TMC_BF16X3> f[2];
 };
 
-// acc[d][n] += sum_k T[d][k] P[k][n] where P is this lane's accumulator column
-// (16 values in accumulator row order) used as the B operand.
+// An accumulator column (16 values in accumulator row order) prepared as the B operand
+// of mma_t: FP32 keeps the values, BF16X3 splits them once into hi/lo fragments.
 template <int PREC>
-__device__ __forceinline__ void mma_t(f32x16& acc, const TFrag<PREC>& T, const float (&p)[16]) {
+struct PFrag;
+template <>
+struct PFrag<TMC_FP32> {
+  float x[16];
+};
+template <>
+struct PFrag<TMC_BF16X3> {
+  Frag<TMC_BF16X3> f[2];
+};
+
+template <int PREC>
+__device__ __forceinline__ void make_pfrag(const float (&p)[16], PFrag<PREC>& o) {
   if constexpr (PREC == TMC_FP32) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(T.x[v], p[v], acc, 0, 0, 0);
+    for (int v = 0; v < 16; ++v) o.x[v] = p[v];
   } else {
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       float a[8];
 #pragma unroll
       for (int s2 = 0; s2 < 8; ++s2) a[s2] = p[8 * t + s2];
-      Frag<TMC_BF16X3> pf;
-      make_frag<TMC_BF16X3>(a, pf);
-      mma_chunk<TMC_BF16X3>(acc, T.f[t], pf);
+      make_frag<TMC_BF16X3>(a, o.f[t]);
     }
   }
 }
 
+// acc[d][n] += sum_k T[d][k] P[k][n] where P is this lane's accumulator column.
+template <int PREC>
+__device__ __forceinline__ void mma_t(f32x16& acc, const TFrag<PREC>& T, const PFrag<PREC>& P) {
+  if constexpr (PREC == TMC_FP32) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(T.x[v], P.x[v], acc, 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) mma_chunk<TMC_BF16X3>(acc, T.f[t], P.f[t]);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // LDS staging of NS operand tiles of 32 samples (rows of mu or of z), written once
-// per workgroup and read by all four waves.  Per 32-row subtile:
+// per workgroup and read by all four waves, in NB buffers.  Per 32-row subtile:
 //   row-major copy: fragments with the d chunk along k (factor GEMM);
 //   d-major copy:   fragments with the tile rows along k (G^T z, softmax * mu),
 //                   row r stored at column perm(r) (bits 2 and 3 of r swapped) so the
-//                   8 rows a lane needs for one k-step are adjacent.
+//                   8 rows a lane needs for one k-step are adjacent (only when COL).
 // Every fragment is one or two 128-bit LDS reads.  BF16X3 keeps two bf16 planes
-// (hi, lo), FP32 one float plane.  NS independent subtiles give each wave NS
-// independent MFMA chains per stage.
+// (hi, lo), FP32 one float plane.
 // ---------------------------------------------------------------------------
-template <int PREC, int NKC, int NS_>
+template <int PREC, int NKC, int NS_, int NB_, bool COL_>
 struct TileSmem {
-  static constexpr int NS = NS_;
+  static constexpr int NS = NS_, NB = NB_;
+  static constexpr bool COL = COL_;
   static constexpr int DP = NKC * 16;               // padded width
   static constexpr int ND32 = (NKC + 1) / 2;        // 32-wide d blocks
   static constexpr int DT = ND32 * 32;              // rows of the d-major copy
@@ -169,13 +235,14 @@ struct TileSmem {
   static constexpr int RS = BF ? DP + 8 : DP + 4;   // row stride (elements)
   static constexpr int CS = BF ? 40 : 36;           // d-major stride (elements)
   static constexpr int ROWN = 32 * RS, COLN = DT * CS;
+  static constexpr int COLSZ = COL ? NS * COLN : 2;
   typedef typename std::conditional<BF, __bf16, float>::type E;
-  E row[NPL][NS * ROWN];
-  E col[NPL][NS * COLN];
+  E row[NB][NPL][NS * ROWN];
+  E col[NB][NPL][COLSZ];
   float lamf[DP];        // lam_d = exp(-2 s_d)            (0 past D)
   float lam2[DP];        // log2(e) * lam_d
-  float gam[NS * 32];    // column terms of the staged tiles
-  float lamT[NS * 32];   // row shifts of the staged tiles (backward)
+  float gam[NB][NS * 32];   // column terms of the staged tiles (forward)
+  float lamT[NB][NS * 32];  // row shifts of the staged tiles (backward)
   double wm[4];          // per-wave maxima of alpha (forward)
 };
 
@@ -183,17 +250,17 @@ __device__ __forceinline__ int tile_perm(int r) {
   return (r & 0x13) | ((r & 4) << 1) | ((r & 8) >> 1);
 }
 
-template <int PREC, int NKC, int NS>
-__device__ __forceinline__ void tile_init(TileSmem<PREC, NKC, NS>& T, const LayerDev& L,
-                                          const float* __restrict__ s) {
-  using TS = TileSmem<PREC, NKC, NS>;
+// lam into LDS and zeros over the d-major copies (their rows past DP stay zero).
+template <class TS>
+__device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const float* __restrict__ s) {
   for (int d = threadIdx.x; d < TS::DP; d += blockDim.x) {
     const float lf = lam_f(s + L.s_off, d, L.D);
     T.lamf[d] = lf;
     T.lam2[d] = lf * kLog2e;
   }
-  for (int e = threadIdx.x; e < TS::NPL * TS::NS * TS::COLN; e += blockDim.x)
-    (&T.col[0][0])[e] = (typename TS::E)0.0f;
+  if constexpr (TS::COL)
+    for (int e = threadIdx.x; e < TS::NB * TS::NPL * TS::COLSZ; e += blockDim.x)
+      (&T.col[0][0][0])[e] = (typename TS::E)0.0f;
 }
 
 // Register stage of NS tiles (blockDim 256): thread t serves row t / 8 of every
@@ -203,42 +270,50 @@ struct TilePrefetch {
   static constexpr int NS = NS_;
   static constexpr int NF = (NKC + 1) / 2;
   float4 v[NS][NF];
-  double a[NS], q[NS];   // column tiles: alpha_{l+1}[j] and stored q_j (thread t%8 == 0)
-  float lam;         // backward: row shift of row t (t < 32 NS)
+  double a[NS];      // column tiles: alpha_{l+1}[j]
+  float lam;         // row tiles: row shift of row t % (32 NS)
 };
 
-__device__ __forceinline__ float4 load_f4(const float* __restrict__ rowp, int d, int D, bool valid,
-                                          bool vec) {
-  if (valid && vec && d < D) return *reinterpret_cast<const float4*>(rowp + d);
-  float4 r;
-  r.x = (valid && d + 0 < D) ? rowp[d + 0] : 0.0f;
-  r.y = (valid && d + 1 < D) ? rowp[d + 1] : 0.0f;
-  r.z = (valid && d + 2 < D) ? rowp[d + 2] : 0.0f;
-  r.w = (valid && d + 3 < D) ? rowp[d + 3] : 0.0f;
-  return r;
-}
-
-// Column tiles of pair L: mu rows r0.. (samples of layer l+1), their alpha and
-// (when qcol is given) the stored q.
+// Column tiles of pair L: mu rows r0.. (samples of layer l+1) and their alpha.
 template <int NKC, int NS>
 __device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS>& pf, const LayerDev& L,
                                            const float* __restrict__ mu,
-                                           const double* __restrict__ alpha,
-                                           const double* __restrict__ qcol, int r0) {
+                                           const double* __restrict__ alpha, int r0) {
   const int t = threadIdx.x, sub = t & 7;
   const bool vec = (L.D % 4 == 0) && (L.mu_off % 4 == 0);
+  if (vec) {
+    // all loads of the stage first, then the padding zeros
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb) {
+      const int gc = min(r0 + 32 * sb + (t >> 3), L.Kc - 1);
+      const float* rowp = mu + L.mu_off + (int64_t)gc * L.D;
+#pragma unroll
+      for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
+        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(4 * (sub + 8 * m), L.D - 4));
+      pf.a[sb] = alpha[L.alpha_up_off + gc];
+    }
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb) {
+      const bool valid = r0 + 32 * sb + (t >> 3) < L.Kc;
+#pragma unroll
+      for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m) {
+        const bool v = valid && 4 * (sub + 8 * m) < L.D;
+        float4& r = pf.v[sb][m];
+        r.x = v ? r.x : 0.0f; r.y = v ? r.y : 0.0f; r.z = v ? r.z : 0.0f; r.w = v ? r.w : 0.0f;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int sb = 0; sb < NS; ++sb) {
     const int gr = r0 + 32 * sb + (t >> 3);
     const bool valid = gr < L.Kc;
-    const float* rowp = mu + L.mu_off + (int64_t)(valid ? gr : 0) * L.D;
+    const int gc = valid ? gr : L.Kc - 1;
+    const float* rowp = mu + L.mu_off + (int64_t)gc * L.D;
 #pragma unroll
     for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-      pf.v[sb][m] = load_f4(rowp, 4 * (sub + 8 * m), L.D, valid, vec);
-    if (sub == 0 && valid) {
-      pf.a[sb] = alpha[L.alpha_up_off + gr];
-      if (qcol) pf.q[sb] = qcol[L.q_off + gr];
-    }
+      pf.v[sb][m] = load_f4(rowp, 4 * (sub + 8 * m), L.D, valid, false);
+    pf.a[sb] = alpha[L.alpha_up_off + gc];
   }
 }
 
@@ -249,31 +324,55 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
                                            const float* __restrict__ lamrow, int r0) {
   const int t = threadIdx.x, sub = t & 7;
   const bool vec = (L.D % 4 == 0) && (L.z_off % 4 == 0);
+  const int rr = r0 + (t & (32 * NS - 1));
+  if (vec) {
+    // all loads of the stage first, then the padding zeros
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb) {
+      const int gr = min(r0 + 32 * sb + (t >> 3), L.K - 1);
+      const float* rowp = z + L.z_off + (int64_t)gr * L.D;
+#pragma unroll
+      for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
+        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(4 * (sub + 8 * m), L.D - 4));
+    }
+    const float lv = lamrow[min(rr, L.K - 1)];
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb) {
+      const bool valid = r0 + 32 * sb + (t >> 3) < L.K;
+#pragma unroll
+      for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m) {
+        const bool v = valid && 4 * (sub + 8 * m) < L.D;
+        float4& r = pf.v[sb][m];
+        r.x = v ? r.x : 0.0f; r.y = v ? r.y : 0.0f; r.z = v ? r.z : 0.0f; r.w = v ? r.w : 0.0f;
+      }
+    }
+    pf.lam = (rr < L.K) ? lv : INFINITY;
+    return;
+  }
 #pragma unroll
   for (int sb = 0; sb < NS; ++sb) {
     const int gr = r0 + 32 * sb + (t >> 3);
     const bool valid = gr < L.K;
-    const float* rowp = z + L.z_off + (int64_t)(valid ? gr : 0) * L.D;
+    const float* rowp = z + L.z_off + (int64_t)(valid ? gr : L.K - 1) * L.D;
 #pragma unroll
     for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-      pf.v[sb][m] = load_f4(rowp, 4 * (sub + 8 * m), L.D, valid, vec);
+      pf.v[sb][m] = load_f4(rowp, 4 * (sub + 8 * m), L.D, valid, false);
   }
-  if (t < 32 * NS) pf.lam = (r0 + t < L.K) ? lamrow[r0 + t] : INFINITY;
+  const float lv = lamrow[min(rr, L.K - 1)];
+  pf.lam = (rr < L.K) ? lv : INFINITY;
 }
 
-// Writes fetched tiles to LDS: row-major copy = x * lam2 when `scale`, else x;
-// d-major copy (when `want_col`) = x.
-template <int PREC, int NKC, int NS>
-__device__ __forceinline__ void tile_store(TileSmem<PREC, NKC, NS>& T,
-                                           const TilePrefetch<NKC, NS>& pf, bool scale,
-                                           bool want_col) {
-  using TS = TileSmem<PREC, NKC, NS>;
+// Writes fetched tiles to LDS buffer b: row-major copy = x * lam2 when `scale`, else
+// x; d-major copy (when the layout has one) = x.
+template <class TS, int NKC>
+__device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC, TS::NS>& pf,
+                                           bool scale) {
   const int t = threadIdx.x, r = t >> 3, sub = t & 7;
   const int pr = tile_perm(r);
 #pragma unroll
   for (int sb = 0; sb < TS::NS; ++sb) {
 #pragma unroll
-    for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m) {
+    for (int m = 0; m < TilePrefetch<NKC, TS::NS>::NF; ++m) {
       const int k = sub + 8 * m;
       if (k >= TS::DP / 4) break;
       const int d = 4 * k;
@@ -289,11 +388,11 @@ __device__ __forceinline__ void tile_store(TileSmem<PREC, NKC, NS>& T,
           xh[e] = hb;
           xl[e] = (__bf16)(x[e] - (float)hb);
         }
-        if (want_col) {
+        if constexpr (TS::COL) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            T.col[0][co + e * TS::CS] = xh[e];
-            T.col[1][co + e * TS::CS] = xl[e];
+            T.col[b][0][co + e * TS::CS] = xh[e];
+            T.col[b][1][co + e * TS::CS] = xl[e];
           }
         }
         if (scale) {
@@ -305,17 +404,17 @@ __device__ __forceinline__ void tile_store(TileSmem<PREC, NKC, NS>& T,
             xl[e] = (__bf16)(y - (float)hb);
           }
         }
-        *reinterpret_cast<bf16x4*>(&T.row[0][ro]) = xh;
-        *reinterpret_cast<bf16x4*>(&T.row[1][ro]) = xl;
+        *reinterpret_cast<bf16x4*>(&T.row[b][0][ro]) = xh;
+        *reinterpret_cast<bf16x4*>(&T.row[b][1][ro]) = xl;
       } else {
-        if (want_col) {
+        if constexpr (TS::COL) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) T.col[0][co + e * TS::CS] = x[e];
+          for (int e = 0; e < 4; ++e) T.col[b][0][co + e * TS::CS] = x[e];
         }
         float y[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) y[e] = scale ? x[e] * T.lam2[d + e] : x[e];
-        *reinterpret_cast<float4*>(&T.row[0][ro]) = make_float4(y[0], y[1], y[2], y[3]);
+        *reinterpret_cast<float4*>(&T.row[b][0][ro]) = make_float4(y[0], y[1], y[2], y[3]);
       }
     }
   }
@@ -323,14 +422,13 @@ __device__ __forceinline__ void tile_store(TileSmem<PREC, NKC, NS>& T,
 
 // q_j = -1/2 sum_d lam_d mu_jd^2 (FP64) of the fetched column row of subtile sb,
 // complete in all 8 threads serving the row (fixed reduction order).
-template <int PREC, int NKC, int NS>
-__device__ __forceinline__ double tile_colq(const TileSmem<PREC, NKC, NS>& T,
-                                            const TilePrefetch<NKC, NS>& pf, int sb) {
-  using TS = TileSmem<PREC, NKC, NS>;
+template <class TS, int NKC>
+__device__ __forceinline__ double tile_colq(const TS& T, const TilePrefetch<NKC, TS::NS>& pf,
+                                            int sb) {
   const int sub = threadIdx.x & 7;
   double q = 0.0;
 #pragma unroll
-  for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m) {
+  for (int m = 0; m < TilePrefetch<NKC, TS::NS>::NF; ++m) {
     const int k = sub + 8 * m;
     if (k >= TS::DP / 4) break;
     const int d = 4 * k;
@@ -344,91 +442,83 @@ __device__ __forceinline__ double tile_colq(const TileSmem<PREC, NKC, NS>& T,
   return -0.5 * q;
 }
 
-// gamma_j = log2(e) (q_j + alpha_{l+1}[j] - maxa) of staged column j (-inf past Kc).
-template <int PREC, int NKC, int NS>
-__device__ __forceinline__ void tile_gamma(TileSmem<PREC, NKC, NS>& T, double a, double q,
-                                           const LayerDev& L, int sb, int j, double maxa) {
-  const int t = threadIdx.x, r = t >> 3;
-  if ((t & 7) == 0)
-    T.gam[32 * sb + r] = (j < L.Kc) ? (float)((q + (a - maxa)) * (double)kLog2e) : -INFINITY;
+// gamma_j = log2(e) (q_j + alpha_{l+1}[j] - maxa), -inf past Kc.
+__device__ __forceinline__ float col_gamma(double q, double a, int j, int Kc, double maxa) {
+  return (j < Kc) ? (float)((q + (a - maxa)) * (double)kLog2e) : -INFINITY;
 }
 
 // Fragment of staged row (lane % 32) of subtile sb for d chunk kc (d = 16 kc + 8 h + s).
-template <int PREC, int NKC, int NS>
-__device__ __forceinline__ void tile_row_frag(const TileSmem<PREC, NKC, NS>& T, int sb, int kc,
-                                              Frag<PREC>& f) {
-  using TS = TileSmem<PREC, NKC, NS>;
+template <class TS, int PREC>
+__device__ __forceinline__ void tile_row_frag(const TS& T, int b, int sb, int kc, Frag<PREC>& f) {
   const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
   const int o = sb * TS::ROWN + r * TS::RS + kc * 16 + 8 * h;
   if constexpr (TS::BF) {
-    f.hi = *reinterpret_cast<const bf16x8*>(&T.row[0][o]);
-    f.lo = *reinterpret_cast<const bf16x8*>(&T.row[1][o]);
+    f.hi = *reinterpret_cast<const bf16x8*>(&T.row[b][0][o]);
+    f.lo = *reinterpret_cast<const bf16x8*>(&T.row[b][1][o]);
   } else {
-    const float4 a = *reinterpret_cast<const float4*>(&T.row[0][o]);
-    const float4 b = *reinterpret_cast<const float4*>(&T.row[0][o + 4]);
+    const float4 a = *reinterpret_cast<const float4*>(&T.row[b][0][o]);
+    const float4 c = *reinterpret_cast<const float4*>(&T.row[b][0][o + 4]);
     f.x[0] = a.x; f.x[1] = a.y; f.x[2] = a.z; f.x[3] = a.w;
-    f.x[4] = b.x; f.x[5] = b.y; f.x[6] = b.z; f.x[7] = b.w;
+    f.x[4] = c.x; f.x[5] = c.y; f.x[6] = c.z; f.x[7] = c.w;
   }
 }
 
 // Transposed fragment of subtile sb for d block q (lane -> d = 32 q + lane % 32).
-template <int PREC, int NKC, int NS>
-__device__ __forceinline__ void tile_col_frag(const TileSmem<PREC, NKC, NS>& T, int sb, int q,
-                                              TFrag<PREC>& f) {
-  using TS = TileSmem<PREC, NKC, NS>;
+template <class TS, int PREC>
+__device__ __forceinline__ void tile_col_frag(const TS& T, int b, int sb, int q, TFrag<PREC>& f) {
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int o = sb * TS::COLN + (32 * q + (lane & 31)) * TS::CS + 8 * h;
   if constexpr (TS::BF) {
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt) {
-      f.f[tt].hi = *reinterpret_cast<const bf16x8*>(&T.col[0][o + 16 * tt]);
-      f.f[tt].lo = *reinterpret_cast<const bf16x8*>(&T.col[1][o + 16 * tt]);
+      f.f[tt].hi = *reinterpret_cast<const bf16x8*>(&T.col[b][0][o + 16 * tt]);
+      f.f[tt].lo = *reinterpret_cast<const bf16x8*>(&T.col[b][1][o + 16 * tt]);
     }
   } else {
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      const float4 a = *reinterpret_cast<const float4*>(&T.col[0][o + 4 * (g & 1) + 16 * (g >> 1)]);
+      const float4 a = *reinterpret_cast<const float4*>(&T.col[b][0][o + 4 * (g & 1) + 16 * (g >> 1)]);
       f.x[4 * g + 0] = a.x; f.x[4 * g + 1] = a.y; f.x[4 * g + 2] = a.z; f.x[4 * g + 3] = a.w;
     }
   }
 }
 
-// Row operand of the wave's rows i0 .. i0+31 straight from global memory:
-// a_i = log2(e) lam z_i as fragments, and r_i = -1/2 sum_d lam_d z_id^2 (FP64).
-template <int PREC, int NKC, int NS>
-__device__ __forceinline__ double wave_rows(const TileSmem<PREC, NKC, NS>& T, const LayerDev& L,
-                                            const float* __restrict__ z, int i0,
-                                            Frag<PREC> (&A)[NKC]) {
-  const int lane = threadIdx.x & 63, ir = lane & 31, h = lane >> 5;
-  const int i = i0 + ir;
-  const int D = L.D;
-  const bool valid = i < L.K;
-  const float* row = z + L.z_off + (int64_t)(valid ? i : 0) * D;
-  const bool vec = (D % 4 == 0) && (L.z_off % 4 == 0);
-  double r = 0.0;
+// The wave's own 32 rows of a row-major [n][D] block as raw values: x[kc] holds
+// row (lane % 32), d = 16 kc + 8 (lane / 32) + s.  Rows past n read the last row.
+template <int NKC>
+__device__ __forceinline__ void wave_load(const float* __restrict__ base, int64_t off, int n, int D,
+                                          int r0, float (&x)[NKC][8]) {
+  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int r = min(r0 + (lane & 31), n - 1);
+  const float* row = base + off + (int64_t)r * D;
+  if ((D % 4 == 0) && (off % 4 == 0)) {
+    // all loads first (one round trip), then the padding zeros
+    float4 a[NKC][2];
 #pragma unroll
-  for (int kc = 0; kc < NKC; ++kc) {
-    float x[8];
-    const int d0 = kc * 16 + 8 * h;
-    if (valid) load8(row, d0, D, vec, x);
-    else
+    for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
-      for (int t = 0; t < 8; ++t) x[t] = 0.0f;
+      for (int e = 0; e < 2; ++e)
+        a[kc][e] = *reinterpret_cast<const float4*>(row + min(kc * 16 + 8 * h + 4 * e, D - 4));
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      r += (double)T.lamf[d0 + t] * (double)x[t] * (double)x[t];
-      x[t] *= T.lam2[d0 + t];
-    }
-    make_frag<PREC>(x, A[kc]);
+    for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const bool v = kc * 16 + 8 * h + 4 * e < D;
+        x[kc][4 * e + 0] = v ? a[kc][e].x : 0.0f;
+        x[kc][4 * e + 1] = v ? a[kc][e].y : 0.0f;
+        x[kc][4 * e + 2] = v ? a[kc][e].z : 0.0f;
+        x[kc][4 * e + 3] = v ? a[kc][e].w : 0.0f;
+      }
+    return;
   }
-  r = r + __shfl_xor(r, 32, kWave);
-  return -0.5 * r;
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc) load8(row, kc * 16 + 8 * h, D, false, x[kc]);
 }
 
 // ---------------------------------------------------------------------------
 // forward: a workgroup of 4 waves owns 128 rows of one layer pair (wave w: rows
 // start + 32 w ..); the samples of the layer above are staged NS x 32 at a time in
-// LDS (prefetched into registers one stage ahead) and swept by all waves.
+// LDS and swept by all waves.
 //   ell_i   = log2 sum_j exp2(S_ij + gamma_j)          (S = log2e <lam z_i, mu_j>)
 //   alpha_i = u_i + r_i + c + maxa + ln2 * ell_i - ln K_{l+1}
 //   e_i     = sum_j softmax_j(S_ij + gamma_j) mu_j        (GRAD: used for dz)
@@ -443,27 +533,62 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const Lay
                                                    double* __restrict__ qcol,
                                                    double* __restrict__ alpha,
                                                    double* __restrict__ wmax,
-                                                   const double* __restrict__ pair_c,
                                                    float* __restrict__ rl,
                                                    float* __restrict__ ev) {
-  using TS = TileSmem<PREC, NKC, NS>;
+  constexpr int NB = (NKC <= 8) ? 2 : 1;
+  using TS = TileSmem<PREC, NKC, NS, NB, GRAD>;
   constexpr int ND32 = TS::ND32;
   __shared__ __align__(16) TS T;
   const Item it = items[blockIdx.x];
   const LayerDev L = Ls[it.layer];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, ir = lane & 31;
-  double maxa, cs;
-  pair_constants(L, Ls[L.up], wmax, pair_c, maxa, cs);
-  tile_init<PREC, NKC, NS>(T, L, s);
-  __syncthreads();
-
   const int i0 = it.start + 32 * w;
   const bool active = i0 < L.K;
+  const int i = i0 + ir;
+  const int nt = (L.Kc + 32 * NS - 1) / (32 * NS);
+
+  // every global load of the prologue is issued before the first wait
+  float xz[NKC][8];
+  wave_load<NKC>(z, L.z_off, L.K, L.D, i0, xz);
+  TilePrefetch<NKC, NS> pf;
+  fetch_cols<NKC, NS>(pf, L, mu, alpha, 0);
+  const float u_i = u[L.u_off + min(i, L.K - 1)];
+  const double maxa = pair_maxa(L, wmax);
+  const double cs = pair_const(L, s);
+  tile_init(T, L, s);
+  lds_barrier();
+
+  // row operand a_i = log2(e) lam z_i as fragments, r_i = -1/2 sum_d lam_d z_id^2 (FP64)
   Frag<PREC> A[NKC];
   double r_i = 0.0;
-  if (active) r_i = wave_rows<PREC, NKC, NS>(T, L, z, i0, A);
-  TilePrefetch<NKC, NS> pf;
-  fetch_cols<NKC, NS>(pf, L, mu, alpha, nullptr, 0);
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc) {
+    const int d0 = kc * 16 + 8 * h;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      r_i += (double)T.lamf[d0 + t] * (double)xz[kc][t] * (double)xz[kc][t];
+      xz[kc][t] *= T.lam2[d0 + t];
+    }
+    make_frag<PREC>(xz[kc], A[kc]);
+  }
+  r_i = -0.5 * (r_i + __shfl_xor(r_i, 32, kWave));
+
+  // The forward computes the column norms q_j (FP64) of every column it stages; the
+  // workgroup that starts at row 0 stores them for the backward.
+  const bool qwriter = GRAD && it.start == 0;
+  auto stage = [&](int b, int j0) {
+    tile_store<TS, NKC>(T, b, pf, false);
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb) {
+      const int j = j0 + 32 * sb + (tid >> 3);
+      const double qj = tile_colq<TS, NKC>(T, pf, sb);
+      if ((tid & 7) == 0) T.gam[b][32 * sb + (tid >> 3)] = col_gamma(qj, pf.a[sb], j, L.Kc, maxa);
+      if (qwriter && (tid & 7) == 0 && j < L.Kc) qcol[L.q_off + j] = qj;
+    }
+  };
+  stage(0, 0);
+  if (nt > 1) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS);
+  lds_barrier();
 
   float m = -INFINITY, ssum = 0.0f;
   f32x16 O[GRAD ? ND32 : 1];
@@ -472,86 +597,87 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const Lay
 #pragma unroll
     for (int v = 0; v < 16; ++v) O[q][v] = 0.0f;
 
-  // The forward computes the column norms q_j (FP64) of every column it stages; the
-  // workgroup that starts at row 0 stores them for the backward.
-  const bool qwriter = GRAD && it.start == 0;
-  for (int j0 = 0; j0 < L.Kc; j0 += 32 * NS) {
-    __syncthreads();                       // waits for the prefetch and for readers of T
-    tile_store<PREC, NKC, NS>(T, pf, false, GRAD);
-#pragma unroll
-    for (int sb = 0; sb < NS; ++sb) {
-      const int j = j0 + 32 * sb + (tid >> 3);
-      const double qj = tile_colq<PREC, NKC, NS>(T, pf, sb);
-      tile_gamma<PREC, NKC, NS>(T, pf.a[sb], qj, L, sb, j, maxa);
-      if (qwriter && (tid & 7) == 0 && j < L.Kc) qcol[L.q_off + j] = qj;
+  for (int t = 0; t < nt; ++t) {
+    const int cur = (NB == 2) ? (t & 1) : 0;
+    if (NB == 2 && t + 1 < nt) {
+      stage(cur ^ 1, 32 * NS * (t + 1));
+      if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
     }
-    __syncthreads();
-    if (j0 + 32 * NS < L.Kc) fetch_cols<NKC, NS>(pf, L, mu, alpha, nullptr, j0 + 32 * NS);
-    if (!active) continue;
-    f32x16 S[NS];
+    if (active) {
+      f32x16 S[NS];
 #pragma unroll
-    for (int sb = 0; sb < NS; ++sb)
+      for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) S[sb][v] = 0.0f;
+        for (int v = 0; v < 16; ++v) S[sb][v] = 0.0f;
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc)
+      for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb) {
-        Frag<PREC> Bf;
-        tile_row_frag<PREC, NKC, NS>(T, sb, kc, Bf);
-        mma_chunk<PREC>(S[sb], Bf, A[kc]);     // S[j][i]
+        for (int sb = 0; sb < NS; ++sb) {
+          Frag<PREC> Bf;
+          tile_row_frag<TS, PREC>(T, cur, sb, kc, Bf);
+          mma_chunk<PREC>(S[sb], Bf, A[kc]);     // S[j][i]
+        }
+      float x[NS][16];
+      float tmax = -INFINITY;
+#pragma unroll
+      for (int sb = 0; sb < NS; ++sb)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 g4 = *reinterpret_cast<const float4*>(&T.gam[cur][32 * sb + 8 * q + 4 * h]);
+          x[sb][4 * q + 0] = S[sb][4 * q + 0] + g4.x;
+          x[sb][4 * q + 1] = S[sb][4 * q + 1] + g4.y;
+          x[sb][4 * q + 2] = S[sb][4 * q + 2] + g4.z;
+          x[sb][4 * q + 3] = S[sb][4 * q + 3] + g4.w;
+        }
+      // (a NaN entry is dropped by fmaxf here but reaches ssum through exp2 below)
+#pragma unroll
+      for (int sb = 0; sb < NS; ++sb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) tmax = fmaxf(tmax, x[sb][v]);
+      tmax = fmaxf(tmax, __shfl_xor(tmax, 32, kWave));
+      const bool need = tmax > m + kRescale;
+      if (__any(need)) {
+        const float mn = need ? tmax : m;
+        const float f = need ? ((m == -INFINITY) ? 0.0f : __builtin_amdgcn_exp2f(m - mn)) : 1.0f;
+        ssum *= f;
+        if (GRAD) {
+#pragma unroll
+          for (int q = 0; q < ND32; ++q)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) O[q][v] *= f;
+        }
+        m = mn;
       }
-    float x[NS][16];
-    float tmax = -INFINITY;
+      const float msafe = (m == -INFINITY) ? 0.0f : m;
+      float p[NS][16];
+      float ps = 0.0f;
 #pragma unroll
-    for (int sb = 0; sb < NS; ++sb)
+      for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 g4 = *reinterpret_cast<const float4*>(&T.gam[32 * sb + 8 * q + 4 * h]);
-        x[sb][4 * q + 0] = S[sb][4 * q + 0] + g4.x;
-        x[sb][4 * q + 1] = S[sb][4 * q + 1] + g4.y;
-        x[sb][4 * q + 2] = S[sb][4 * q + 2] + g4.z;
-        x[sb][4 * q + 3] = S[sb][4 * q + 3] + g4.w;
-      }
-    // (a NaN entry is dropped by fmaxf here but reaches ssum through exp2 below)
-#pragma unroll
-    for (int sb = 0; sb < NS; ++sb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) tmax = fmaxf(tmax, x[sb][v]);
-    tmax = fmaxf(tmax, __shfl_xor(tmax, 32, kWave));
-    const bool need = tmax > m + kRescale;
-    if (__any(need)) {
-      const float mn = need ? tmax : m;
-      const float f = need ? ((m == -INFINITY) ? 0.0f : __builtin_amdgcn_exp2f(m - mn)) : 1.0f;
-      ssum *= f;
+        for (int v = 0; v < 16; ++v) {
+          p[sb][v] = __builtin_amdgcn_exp2f(x[sb][v] - msafe);
+          ps += p[sb][v];
+        }
+      ssum += ps;
       if (GRAD) {
+        PFrag<PREC> P[NS];
+#pragma unroll
+        for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(p[sb], P[sb]);
 #pragma unroll
         for (int q = 0; q < ND32; ++q)
 #pragma unroll
-          for (int v = 0; v < 16; ++v) O[q][v] *= f;
+          for (int sb = 0; sb < NS; ++sb) {
+            TFrag<PREC> Tf;
+            tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+            mma_t<PREC>(O[q], Tf, P[sb]);
+          }
       }
-      m = mn;
     }
-    const float msafe = (m == -INFINITY) ? 0.0f : m;
-    float p[NS][16];
-    float ps = 0.0f;
-#pragma unroll
-    for (int sb = 0; sb < NS; ++sb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        p[sb][v] = __builtin_amdgcn_exp2f(x[sb][v] - msafe);
-        ps += p[sb][v];
-      }
-    ssum += ps;
-    if (GRAD) {
-#pragma unroll
-      for (int q = 0; q < ND32; ++q)
-#pragma unroll
-        for (int sb = 0; sb < NS; ++sb) {
-          TFrag<PREC> Tf;
-          tile_col_frag<PREC, NKC, NS>(T, sb, q, Tf);
-          mma_t<PREC>(O[q], Tf, p[sb]);
-        }
+    lds_barrier();
+    if (NB == 1 && t + 1 < nt) {
+      stage(0, 32 * NS * (t + 1));
+      if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
+      lds_barrier();
     }
   }
   const float stot = ssum + __shfl_xor(ssum, 32, kWave);
@@ -559,24 +685,36 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const Lay
   if (m != m || stot != stot) ell = NAN;
   else if (m == -INFINITY || stot == 0.0f) ell = -INFINITY;
   else ell = m + log2f(stot);
-  const int i = active ? i0 + ir : L.K;
-  const double a_i = (double)u[L.u_off + (i < L.K ? i : 0)] + r_i + cs + maxa +
-                     kLn2 * (double)ell - log((double)L.Kc);
-  if (h == 0 && i < L.K) {
+  const bool iv = active && i < L.K;
+  const double a_i = (double)u_i + r_i + cs + maxa + kLn2 * (double)ell - L.lnKc;
+  if (h == 0 && iv) {
     rl[L.rl_off + i] = ell;
     alpha[L.alpha_off + i] = a_i;
   }
-  // this workgroup's max_i alpha_l[i], for the next step's column terms
-  const double wm = wave_max(i < L.K ? a_i : -INFINITY);
+  // this workgroup's max_i alpha_l[i], for the next step's column shift
+  const double wm = wave_max(iv ? a_i : -INFINITY);
   if (lane == 0) T.wm[w] = wm;
-  __syncthreads();
+  lds_barrier();
   if (tid == 0)
     wmax[L.wmax_off + it.start / kFusedRowsPerGroup] =
         nan_max(nan_max(T.wm[0], T.wm[1]), nan_max(T.wm[2], T.wm[3]));
-  if (GRAD && i < L.K) {
+  if (GRAD && iv) {
     const float inv = (stot > 0.0f) ? 1.0f / stot : 0.0f;
     float* erow = ev + L.ev_off + (int64_t)i * L.D;
     const bool vec = (L.D % 4 == 0) && (L.ev_off % 4 == 0);
+    if (vec) {
+      // D % 4 == 0: a float4 at d < D is whole
+#pragma unroll
+      for (int q = 0; q < ND32; ++q)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const int d = 32 * q + 8 * g + 4 * h;
+          if (d < L.D)
+            *reinterpret_cast<float4*>(erow + d) =
+                make_float4(O[q][4 * g] * inv, O[q][4 * g + 1] * inv, O[q][4 * g + 2] * inv,
+                            O[q][4 * g + 3] * inv);
+        }
+    } else {
 #pragma unroll
     for (int q = 0; q < ND32; ++q)
 #pragma unroll
@@ -584,15 +722,14 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const Lay
         const int d = 32 * q + 8 * g + 4 * h;
         const float4 o4 = make_float4(O[q][4 * g] * inv, O[q][4 * g + 1] * inv,
                                       O[q][4 * g + 2] * inv, O[q][4 * g + 3] * inv);
-        if (vec && d + 3 < L.D) {
-          *reinterpret_cast<float4*>(erow + d) = o4;
-        } else {
+        {
           if (d + 0 < L.D) erow[d + 0] = o4.x;
           if (d + 1 < L.D) erow[d + 1] = o4.y;
           if (d + 2 < L.D) erow[d + 2] = o4.z;
           if (d + 3 < L.D) erow[d + 3] = o4.w;
         }
       }
+    }
   }
 }
 
@@ -606,6 +743,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const Lay
 // and writes the column part of the log-std gradient of its columns,
 //   dlogp * lam * sum_j (p_{l+1}[j] mu_j^2 - 2 mu_j (G^T z)_j)
 // (sum_ij G_ij (z_i - mu_j)^2 expanded; the row terms come from k_fused_dz).
+// The constant c cancels between the forward's ell_i and G, so it is not needed here.
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, int NS>
 __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const LayerDev* __restrict__ Ls,
@@ -615,7 +753,6 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const Lay
                                                    const float* __restrict__ s,
                                                    const double* __restrict__ alpha,
                                                    const double* __restrict__ wmax,
-                                                   const double* __restrict__ pair_c,
                                                    const double* __restrict__ qcol,
                                                    const float* __restrict__ rl,
                                                    float* __restrict__ lam_ws,
@@ -624,41 +761,48 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const Lay
                                                    float* __restrict__ dmu,
                                                    float* __restrict__ du,
                                                    float* __restrict__ dsp) {
-  using TS = TileSmem<PREC, NKC, NS>;
+  constexpr int NB = (NKC <= 8) ? 2 : 1;
+  using TS = TileSmem<PREC, NKC, NS, NB, true>;
   constexpr int ND32 = TS::ND32;
   __shared__ __align__(16) TS T;
   __shared__ float accD[TS::DT];
   const Item it = items[blockIdx.x];
   const LayerDev L = Ls[it.layer];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, jr = lane & 31;
-  tile_init<PREC, NKC, NS>(T, L, s);
-  for (int d = tid; d < TS::DT; d += blockDim.x) accD[d] = 0.0f;
-  double maxa, cs;
-  pair_constants(L, Ls[L.up], wmax, pair_c, maxa, cs);
   const int jw = it.start + 32 * w;
   const bool active = jw < L.Kc;
-  const float g32 = (float)dlogp[L.chain];
+  const int j = jw + jr;
+  const int jc = min(j, L.Kc - 1);
+  const int nt = (L.K + 32 * NS - 1) / (32 * NS);
+  const float* lamrow = lam_ws + L.rl_off;   // Lam shares the per-layer indexing of rl
 
-  // the waves' column operands and column terms, staged NS waves at a time
+  // prologue loads: the wave's own column operands (mu rows), their column terms and
+  // the first row tile
+  float xm[NKC][8];
+  wave_load<NKC>(mu, L.mu_off, L.Kc, L.D, jw, xm);
+  const double qj = qcol[L.q_off + jc];
+  const double aj = alpha[L.alpha_up_off + jc];
+  const double gl = dlogp[L.chain];
+  TilePrefetch<NKC, NS> pf;
+  fetch_rows<NKC, NS>(pf, L, z, lamrow, 0);
+  const double maxa = pair_maxa(L, wmax);
+  tile_init(T, L, s);
+  for (int d = tid; d < TS::DT; d += blockDim.x) accD[d] = 0.0f;
+  lds_barrier();
+
   Frag<PREC> Bf[NKC];
-  float gj = -INFINITY;
-  for (int w0 = 0; w0 < 4; w0 += NS) {
-    const int jt = it.start + 32 * w0;
-    if (jt >= L.Kc) break;
-    TilePrefetch<NKC, NS> pm;
-    fetch_cols<NKC, NS>(pm, L, mu, alpha, qcol, jt);
-    __syncthreads();
-    tile_store<PREC, NKC, NS>(T, pm, false, false);
 #pragma unroll
-    for (int sb = 0; sb < NS; ++sb)
-      tile_gamma<PREC, NKC, NS>(T, pm.a[sb], pm.q[sb], L, sb, jt + 32 * sb + (tid >> 3), maxa);
-    __syncthreads();
-    if (w >= w0 && w < w0 + NS) {
-#pragma unroll
-      for (int kc = 0; kc < NKC; ++kc) tile_row_frag<PREC, NKC, NS>(T, w - w0, kc, Bf[kc]);
-      gj = T.gam[32 * (w - w0) + jr];
-    }
-  }
+  for (int kc = 0; kc < NKC; ++kc) make_frag<PREC>(xm[kc], Bf[kc]);
+  const float gj = col_gamma(qj, aj, j, L.Kc, maxa);
+  const float g32 = (float)gl;
+
+  auto stage = [&](int b) {
+    tile_store<TS, NKC>(T, b, pf, true);
+    if (tid < 32 * NS) T.lamT[b][tid] = pf.lam;
+  };
+  stage(0);
+  if (nt > 1) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS);
+  lds_barrier();
 
   f32x16 GT[ND32];
 #pragma unroll
@@ -666,76 +810,110 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const Lay
 #pragma unroll
     for (int v = 0; v < 16; ++v) GT[q][v] = 0.0f;
   float csum = 0.0f;
-  const float* lamrow = lam_ws + L.rl_off;   // Lam shares the per-layer indexing of rl
 
-  TilePrefetch<NKC, NS> pf;
-  fetch_rows<NKC, NS>(pf, L, z, lamrow, 0);
-  for (int i0 = 0; i0 < L.K; i0 += 32 * NS) {
-    __syncthreads();                       // waits for the prefetch and for readers of T
-    tile_store<PREC, NKC, NS>(T, pf, true, true);
-    if (tid < 32 * NS) T.lamT[tid] = pf.lam;
-    __syncthreads();
-    if (i0 + 32 * NS < L.K) fetch_rows<NKC, NS>(pf, L, z, lamrow, i0 + 32 * NS);
-    if (!active) continue;
-    f32x16 S[NS];
+  for (int t = 0; t < nt; ++t) {
+    const int cur = (NB == 2) ? (t & 1) : 0;
+    if (NB == 2 && t + 1 < nt) {
+      stage(cur ^ 1);
+      if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+    }
+    if (active) {
+      f32x16 S[NS];
 #pragma unroll
-    for (int sb = 0; sb < NS; ++sb)
+      for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) S[sb][v] = 0.0f;
+        for (int v = 0; v < 16; ++v) S[sb][v] = 0.0f;
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc)
+      for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb) {
-        Frag<PREC> Af;
-        tile_row_frag<PREC, NKC, NS>(T, sb, kc, Af);
-        mma_chunk<PREC>(S[sb], Af, Bf[kc]);    // S[i][j]
-      }
-    float g[NS][16];
+        for (int sb = 0; sb < NS; ++sb) {
+          Frag<PREC> Af;
+          tile_row_frag<TS, PREC>(T, cur, sb, kc, Af);
+          mma_chunk<PREC>(S[sb], Af, Bf[kc]);    // S[i][j]
+        }
+      float g[NS][16];
 #pragma unroll
-    for (int sb = 0; sb < NS; ++sb)
+      for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float4 l4 = *reinterpret_cast<const float4*>(&T.lamT[32 * sb + 8 * q + 4 * h]);
-        g[sb][4 * q + 0] = __builtin_amdgcn_exp2f(S[sb][4 * q + 0] + gj - l4.x);
-        g[sb][4 * q + 1] = __builtin_amdgcn_exp2f(S[sb][4 * q + 1] + gj - l4.y);
-        g[sb][4 * q + 2] = __builtin_amdgcn_exp2f(S[sb][4 * q + 2] + gj - l4.z);
-        g[sb][4 * q + 3] = __builtin_amdgcn_exp2f(S[sb][4 * q + 3] + gj - l4.w);
-      }
+        for (int q = 0; q < 4; ++q) {
+          const float4 l4 = *reinterpret_cast<const float4*>(&T.lamT[cur][32 * sb + 8 * q + 4 * h]);
+          g[sb][4 * q + 0] = __builtin_amdgcn_exp2f(S[sb][4 * q + 0] + gj - l4.x);
+          g[sb][4 * q + 1] = __builtin_amdgcn_exp2f(S[sb][4 * q + 1] + gj - l4.y);
+          g[sb][4 * q + 2] = __builtin_amdgcn_exp2f(S[sb][4 * q + 2] + gj - l4.z);
+          g[sb][4 * q + 3] = __builtin_amdgcn_exp2f(S[sb][4 * q + 3] + gj - l4.w);
+        }
 #pragma unroll
-    for (int sb = 0; sb < NS; ++sb)
+      for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) csum += g[sb][v];
+        for (int v = 0; v < 16; ++v) csum += g[sb][v];
+      PFrag<PREC> P[NS];
 #pragma unroll
-    for (int q = 0; q < ND32; ++q)
+      for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(g[sb], P[sb]);
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb) {
-        TFrag<PREC> Tf;
-        tile_col_frag<PREC, NKC, NS>(T, sb, q, Tf);
-        mma_t<PREC>(GT[q], Tf, g[sb]);
-      }
+      for (int q = 0; q < ND32; ++q)
+#pragma unroll
+        for (int sb = 0; sb < NS; ++sb) {
+          TFrag<PREC> Tf;
+          tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+          mma_t<PREC>(GT[q], Tf, P[sb]);
+        }
+    }
+    lds_barrier();
+    if (NB == 1 && t + 1 < nt) {
+      stage(0);
+      if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+      lds_barrier();
+    }
   }
 
   // ---- column epilogue: marginals of layer l+1, dmu, column part of ds ----
   const float ctot = csum + __shfl_xor(csum, 32, kWave);
-  const int j = jw + jr;
   const bool jv = active && j < L.Kc;
-  const double gl = dlogp[L.chain];
   if (jv && h == 0) {
     p[L.p_up_off + j] = ctot;
     if (du) du[L.u_up_off + j] = (float)(gl * (double)ctot);
-    const LayerDev& U = Ls[L.up];
-    if (U.up >= 0) {
-      const float ell = rl[U.rl_off + j];
-      lam_ws[U.rl_off + j] = (ctot == 0.0f) ? INFINITY : ell - log2f(ctot);
+    if (!L.up_top) {
+      // row shift of layer l+1 for the next backward step (rl and Lam share indexing)
+      const float ell = rl[L.alpha_up_off + j];
+      lam_ws[L.alpha_up_off + j] = (ctot == 0.0f) ? INFINITY : ell - log2f(ctot);
     }
   }
   // per-lane column terms p'_j mu_jd^2 - 2 mu_jd (G^T z)_jd, reduced over the wave's
   // 32 columns through LDS (wave by wave, fixed order)
   float colt[ND32][16];
-  {
-    const bool mvec = (L.D % 4 == 0) && (L.mu_off % 4 == 0);
-    const float* murow = mu + L.mu_off + (int64_t)(jv ? j : 0) * L.D;
-    float* dmurow = dmu ? dmu + L.mu_off + (int64_t)(jv ? j : 0) * L.D : nullptr;
+  if ((L.D % 4 == 0) && (L.mu_off % 4 == 0)) {
+    // all loads of mu_j first (one round trip), then the column terms and dmu
+    const float* murow = mu + L.mu_off + (int64_t)jc * L.D;
+    float4 mr[ND32][4];
+#pragma unroll
+    for (int q = 0; q < ND32; ++q)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        mr[q][g] = *reinterpret_cast<const float4*>(murow + min(32 * q + 8 * g + 4 * h, L.D - 4));
+    float* dmurow = dmu ? dmu + L.mu_off + (int64_t)jc * L.D : nullptr;
+#pragma unroll
+    for (int q = 0; q < ND32; ++q)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int d = 32 * q + 8 * g + 4 * h;
+        const bool v = jv && d < L.D;
+        const float mv[4] = {v ? mr[q][g].x : 0.0f, v ? mr[q][g].y : 0.0f, v ? mr[q][g].z : 0.0f,
+                             v ? mr[q][g].w : 0.0f};
+        float o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float gt = GT[q][4 * g + e];
+          colt[q][4 * g + e] = jv ? (ctot * mv[e] - 2.0f * gt) * mv[e] : 0.0f;
+          o[e] = (d < L.D) ? g32 * T.lamf[d + e] * (gt - ctot * mv[e]) : 0.0f;
+        }
+        // D % 4 == 0: a float4 at d < D is whole
+        if (v && dmurow)
+          *reinterpret_cast<float4*>(dmurow + d) = make_float4(o[0], o[1], o[2], o[3]);
+      }
+  } else {
+    const bool mvec = false;
+    const float* murow = mu + L.mu_off + (int64_t)jc * L.D;
+    float* dmurow = dmu ? dmu + L.mu_off + (int64_t)jc * L.D : nullptr;
 #pragma unroll
     for (int q = 0; q < ND32; ++q)
 #pragma unroll
@@ -762,23 +940,23 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const Lay
       }
   }
   if (!dsp) return;
-  float* buf = reinterpret_cast<float*>(&T.col[0][0]);   // >= 32 x DT floats
+  float* buf = reinterpret_cast<float*>(&T.col[0][0][0]);   // >= 32 x DT floats
   for (int w2 = 0; w2 < 4; ++w2) {
-    __syncthreads();
+    lds_barrier();
     if (w == w2) {
 #pragma unroll
       for (int q = 0; q < ND32; ++q)
 #pragma unroll
         for (int v = 0; v < 16; ++v) buf[jr * TS::DT + 32 * q + 8 * (v / 4) + 4 * h + (v % 4)] = colt[q][v];
     }
-    __syncthreads();
+    lds_barrier();
     for (int d = tid; d < TS::DT; d += blockDim.x) {
       float acc = 0.0f;
       for (int c = 0; c < 32; ++c) acc += buf[c * TS::DT + d];
       accD[d] += acc;
     }
   }
-  __syncthreads();
+  lds_barrier();
   const int part = it.start / 128;
   for (int d = tid; d < L.D; d += blockDim.x)
     dsp[L.dsp_off + (int64_t)part * L.D + d] = g32 * T.lamf[d] * accD[d];

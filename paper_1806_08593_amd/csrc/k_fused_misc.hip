@@ -8,39 +8,27 @@
 
 namespace tmc {
 
-// Start of the fused forward, one workgroup per chain: alpha of the top layer = u;
-// the per-128-row maxima of u_top (the same layout the forward leaves for every
-// other layer); and the per-pair constant c_l = -sum_d s_d - D/2 ln 2 pi.
+// Start of the fused forward, one workgroup per chain: alpha of the top layer = u,
+// and the per-128-row maxima of u_top (the same layout the forward leaves for every
+// other layer), one wave per 128-row part.
 __global__ __launch_bounds__(256) void k_fused_fwd_init(const ChainDev* __restrict__ chains,
                                                         const LayerDev* __restrict__ layers,
                                                         const float* __restrict__ u,
-                                                        const float* __restrict__ s,
                                                         double* __restrict__ alpha,
-                                                        double* __restrict__ wmax,
-                                                        double* __restrict__ pair_c) {
-  __shared__ double red[kMaxWaves];
+                                                        double* __restrict__ wmax) {
   const ChainDev ch = chains[blockIdx.x];
-  for (int l = ch.first; l < ch.top; ++l) {
-    const LayerDev& L = layers[l];
-    double ss = 0.0;
-    for (int d = threadIdx.x; d < L.D; d += blockDim.x) ss += (double)s[L.s_off + d];
-    ss = block_sum(ss, red);
-    if (threadIdx.x == 0) {
-      pair_c[l] = -ss - 0.5 * (double)L.D * log(2.0 * M_PI);
-    }
-  }
-  // the top layer's maxima, in the same per-128-row partial layout the forward uses
   const LayerDev& t = layers[ch.top];
   const int nparts = (t.K + 127) / 128;
-  for (int q = 0; q < nparts; ++q) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = w; q < nparts; q += blockDim.x >> 6) {
     double m = -INFINITY;
-    for (int k = q * 128 + threadIdx.x; k < min(t.K, (q + 1) * 128); k += blockDim.x) {
+    for (int k = q * 128 + lane; k < min(t.K, (q + 1) * 128); k += 64) {
       const double v = (double)u[t.u_off + k];
       alpha[t.alpha_off + k] = v;
       m = nan_max(m, v);
     }
-    m = block_max(m, red);
-    if (threadIdx.x == 0) wmax[t.wmax_off + q] = m;
+    m = wave_max(m);
+    if (lane == 0) wmax[t.wmax_off + q] = m;
   }
 }
 
@@ -191,11 +179,10 @@ hipError_t launch_fused_bwd_init(const ChainDev* chains, int n_chains, const Lay
 }
 
 hipError_t launch_fused_fwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
-                                 const float* u, const float* s, double* alpha, double* wmax,
-                                 double* pair_c, hipStream_t st) {
+                                 const float* u, double* alpha, double* wmax, hipStream_t st) {
   if (n_chains <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fused_fwd_init, dim3(n_chains), dim3(256), 0, st, chains, layers, u, s,
-                     alpha, wmax, pair_c);
+  hipLaunchKernelGGL(k_fused_fwd_init, dim3(n_chains), dim3(256), 0, st, chains, layers, u,
+                     alpha, wmax);
   return hipGetLastError();
 }
 

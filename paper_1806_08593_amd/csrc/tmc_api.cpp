@@ -289,8 +289,13 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   }
   for (auto& d : P->layers_h)
     if (d.up >= 0) {
-      d.alpha_up_off = P->layers_h[d.up].alpha_off;
-      d.p_up_off = P->layers_h[d.up].p_off;
+      const LayerDev& U = P->layers_h[d.up];
+      d.alpha_up_off = U.alpha_off;
+      d.p_up_off = U.p_off;
+      d.wmax_up_off = U.wmax_off;
+      d.nwmax_up = (U.K + 127) / 128;
+      d.up_top = U.up < 0 ? 1 : 0;
+      d.lnKc = std::log((double)U.K);
     }
 
   // workspace layout
@@ -568,19 +573,18 @@ tmc_status fused_fwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
   float* rl = wsp<float>(ws, W.rl);
   float* ev = wsp<float>(ws, W.ev);
   double* wmax = wsp<double>(ws, W.wmax);
-  double* pair_c = wsp<double>(ws, W.pairM);
-  LAUNCH(launch_fused_fwd_init(P->chains_d, P->n_chains, P->layers_d, u, s, alpha, wmax, pair_c, st));
+  LAUNCH(launch_fused_fwd_init(P->chains_d, P->n_chains, P->layers_d, u, alpha, wmax, st));
   for (auto& step : P->fused.fwd)
     for (auto& g : step) {
       const Item* it = P->items_d + g.off;
       if (P->prec == TMC_FP32)
         LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_FP32>(g.nkc, g.waves, grad, P->layers_d, it,
                                                                g.n, z, mu, s, u, qcol, alpha, wmax,
-                                                               pair_c, rl, ev, st));
+                                                               rl, ev, st));
       else
         LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_BF16X3>(g.nkc, g.waves, grad, P->layers_d,
                                                                  it, g.n, z, mu, s, u, qcol, alpha,
-                                                                 wmax, pair_c, rl, ev, st));
+                                                                 wmax, rl, ev, st));
     }
   LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, alpha, logp,
                          wsp<double>(ws, W.logp), P->flag_d, st));
@@ -594,7 +598,6 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
   double* alpha = wsp<double>(ws, W.alpha);
   const double* qcol = wsp<double>(ws, W.q);
   const double* wmax = wsp<double>(ws, W.wmax);
-  const double* pair_c = wsp<double>(ws, W.pairM);
   float* rl = wsp<float>(ws, W.rl);
   float* lam = wsp<float>(ws, W.lam);
   float* p = wsp<float>(ws, W.p);
@@ -607,11 +610,11 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
       const Item* it = P->items_d + g.off;
       if (P->prec == TMC_FP32)
         LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_FP32>(g.nkc, g.waves, P->layers_d, it, g.n,
-                                                               z, mu, s, alpha, wmax, pair_c, qcol,
+                                                               z, mu, s, alpha, wmax, qcol,
                                                                rl, lam, dlogp, p, dmu, du, dsp, st));
       else
         LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_BF16X3>(g.nkc, g.waves, P->layers_d, it,
-                                                                 g.n, z, mu, s, alpha, wmax, pair_c,
+                                                                 g.n, z, mu, s, alpha, wmax,
                                                                  qcol, rl, lam, dlogp, p, dmu, du,
                                                                  dsp, st));
     }

@@ -39,7 +39,11 @@ struct LayerDev {
   int64_t q_off;         // fused: double column norms q_j of this pair [Kc]
   int64_t wmax_off;      // fused: double maxima of alpha per 128 rows [ceil(K/128)]
   int32_t dsp_parts;     // partial rows of the log-std gradient of this pair
-  int32_t pad1;
+  int32_t up_top;        // 1 if the layer above is the top of its chain
+  int64_t wmax_up_off;   // fused: wmax offset of the layer above
+  int32_t nwmax_up;      // fused: number of wmax partials of the layer above
+  int32_t pad2;
+  double lnKc;           // ln K of the layer above
 };
 
 struct ChainDev {
