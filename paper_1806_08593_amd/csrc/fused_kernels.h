@@ -131,28 +131,44 @@ __device__ __forceinline__ float4 load_f4(const float* __restrict__ row, int d, 
   return r;
 }
 
-__device__ __forceinline__ float lam_f(const float* __restrict__ s, int d, int D) {
-  const float v = s[min(d, D - 1)];
-  return d < D ? expf(-2.0f * v) : 0.0f;
+// The small per-pair inputs of a workgroup's prologue, loaded from clamped addresses
+// before the bulk operand loads so that consuming them waits for them alone: this
+// lane's partial max of alpha_{l+1} (see pair_maxa), this lane's s values for the
+// constant c (d = lane + 64 k, D <= 256), and s_d for d = threadIdx.x (lam into LDS).
+struct PairPre {
+  double wm;
+  float sv[4];
+  float slam;
+};
+
+__device__ __forceinline__ void pair_preload(const LayerDev& L, const double* __restrict__ wmax,
+                                             const float* __restrict__ s, PairPre& P) {
+  const int lane = threadIdx.x & 63;
+  P.wm = wmax[L.wmax_up_off + min(lane, L.nwmax_up - 1)];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) P.sv[k] = s[L.s_off + min(lane + 64 * k, L.D - 1)];
+  P.slam = s[L.s_off + min((int)threadIdx.x, L.D - 1)];
 }
 
 // Column shift of pair L: maxa = max_j alpha_{l+1}[j], reduced over the
 // per-workgroup maxima the pass that wrote alpha_{l+1} left in wmax (one lane per
 // partial, then a wave reduction; exact, so the order does not matter).
-__device__ __forceinline__ double pair_maxa(const LayerDev& L, const double* __restrict__ wmax) {
+__device__ __forceinline__ double pair_maxa(const LayerDev& L, const double* __restrict__ wmax,
+                                            const PairPre& P) {
   const int lane = threadIdx.x & 63;
-  double m = -INFINITY;
-  for (int k = lane; k < L.nwmax_up; k += 64) m = nan_max(m, wmax[L.wmax_up_off + k]);
+  double m = (lane < L.nwmax_up) ? P.wm : -INFINITY;
+  for (int k = lane + 64; k < L.nwmax_up; k += 64) m = nan_max(m, wmax[L.wmax_up_off + k]);
   m = wave_max(m);
   return (m == -INFINITY) ? 0.0 : m;
 }
 
 // c = -sum_d s_d - D/2 ln 2 pi of pair L in FP64 (fixed order: lane-strided partial
 // sums, then a butterfly over the wave), complete in every lane of the calling wave.
-__device__ __forceinline__ double pair_const(const LayerDev& L, const float* __restrict__ s) {
+__device__ __forceinline__ double pair_const(const LayerDev& L, const PairPre& P) {
   const int lane = threadIdx.x & 63;
   double a = 0.0;
-  for (int d = lane; d < L.D; d += 64) a += (double)s[L.s_off + d];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a += (lane + 64 * k < L.D) ? (double)P.sv[k] : 0.0;
   a = wave_sum(a);
   return -a - (double)L.D * kHalfLn2Pi;
 }
@@ -250,11 +266,13 @@ __device__ __forceinline__ int tile_perm(int r) {
   return (r & 0x13) | ((r & 4) << 1) | ((r & 8) >> 1);
 }
 
-// lam into LDS and zeros over the d-major copies (their rows past DP stay zero).
+// lam into LDS (thread d holds s_d, DP <= blockDim) and zeros over the d-major copies
+// (their rows past DP stay zero).
 template <class TS>
-__device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const float* __restrict__ s) {
-  for (int d = threadIdx.x; d < TS::DP; d += blockDim.x) {
-    const float lf = lam_f(s + L.s_off, d, L.D);
+__device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const PairPre& P) {
+  const int d = threadIdx.x;
+  if (d < TS::DP) {
+    const float lf = d < L.D ? expf(-2.0f * P.slam) : 0.0f;
     T.lamf[d] = lf;
     T.lam2[d] = lf * kLog2e;
   }
@@ -547,15 +565,18 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const Lay
   const int i = i0 + ir;
   const int nt = (L.Kc + 32 * NS - 1) / (32 * NS);
 
-  // every global load of the prologue is issued before the first wait
+  // small inputs first, then the bulk operand loads; consuming the small ones waits
+  // for them alone
+  PairPre pre;
+  pair_preload(L, wmax, s, pre);
+  const float u_i = u[L.u_off + min(i, L.K - 1)];
   float xz[NKC][8];
   wave_load<NKC>(z, L.z_off, L.K, L.D, i0, xz);
   TilePrefetch<NKC, NS> pf;
   fetch_cols<NKC, NS>(pf, L, mu, alpha, 0);
-  const float u_i = u[L.u_off + min(i, L.K - 1)];
-  const double maxa = pair_maxa(L, wmax);
-  const double cs = pair_const(L, s);
-  tile_init(T, L, s);
+  const double maxa = pair_maxa(L, wmax, pre);
+  const double cs = pair_const(L, pre);
+  tile_init(T, L, pre);
   lds_barrier();
 
   // row operand a_i = log2(e) lam z_i as fragments, r_i = -1/2 sum_d lam_d z_id^2 (FP64)
@@ -778,15 +799,17 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const Lay
 
   // prologue loads: the wave's own column operands (mu rows), their column terms and
   // the first row tile
-  float xm[NKC][8];
-  wave_load<NKC>(mu, L.mu_off, L.Kc, L.D, jw, xm);
+  PairPre pre;
+  pair_preload(L, wmax, s, pre);
   const double qj = qcol[L.q_off + jc];
   const double aj = alpha[L.alpha_up_off + jc];
   const double gl = dlogp[L.chain];
+  float xm[NKC][8];
+  wave_load<NKC>(mu, L.mu_off, L.Kc, L.D, jw, xm);
   TilePrefetch<NKC, NS> pf;
   fetch_rows<NKC, NS>(pf, L, z, lamrow, 0);
-  const double maxa = pair_maxa(L, wmax);
-  tile_init(T, L, s);
+  const double maxa = pair_maxa(L, wmax, pre);
+  tile_init(T, L, pre);
   for (int d = tid; d < TS::DT; d += blockDim.x) accD[d] = 0.0f;
   lds_barrier();
 
