@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define TMC_ABI_VERSION 1
+#define TMC_ABI_VERSION 2
 
 typedef enum tmc_status {
   TMC_OK = 0,
@@ -104,8 +104,8 @@ typedef enum tmc_engine {
 #define TMC_FLAG_FORWARD_ONLY 1  /* no backward will follow: the fused forward skips
                                     the work it does only for gradients */
 #define TMC_FLAG_PERSISTENT 2    /* fused engine: run each pass as one persistent
-                                    launch over a dependency-ordered work queue instead
-                                    of one launch per chain depth */
+                                    launch per width bucket over a queue of whole
+                                    chains instead of one launch per chain depth */
 
 /* One latent layer of one chain (host struct). */
 typedef struct tmc_layer {
@@ -150,6 +150,8 @@ typedef struct tmc_plan_info {
   int32_t tile_rows;            /* fused engine: rows per workgroup tile */
   int32_t tile_cols;            /* fused engine: columns per inner tile */
   int32_t waves_per_group;
+  int32_t persistent;           /* fused engine: passes run as persistent launches */
+  int32_t tuned;                /* launch shape chosen by tmc_plan_autotune or its cache */
 } tmc_plan_info;
 
 /* ---- library ---- */
@@ -215,6 +217,31 @@ tmc_status tmc_plan_graph_capture_gauss(tmc_plan_t plan, int which, const void* 
                                         void* dz, void* dmu, void* ds, void* du,
                                         void* stream);
 tmc_status tmc_plan_graph_launch(tmc_plan_t plan, int which, void* stream);
+
+/* ---- launch shape ---- */
+/* Batching of many chains of uneven depth and width (fused engine).  By default each
+ * pass launches one kernel per chain depth and width bucket, over all chains at that
+ * depth (a workgroup per block of 128 samples of one layer pair).  With
+ * TMC_FLAG_PERSISTENT (or when the tuner picks it) each pass is one persistent launch
+ * per width bucket: its workgroups take whole chains from a queue in the workspace,
+ * most expensive chain (sum of K_l K_{l+1} D_l) first, and each runs every layer pair
+ * of its chain in order (top-down in the forward, bottom-up in the backward), so no
+ * launch boundary separates the depths and no workgroup waits for another. */
+
+/* Launch-shape tuner: runs every candidate launch shape of a fused plan (per-depth
+ * launches; persistent launches with 1x or 2x the resident workgroup capacity; for
+ * forward-only plans, 1 or 2 staged 32-sample subtiles per LDS stage) `reps` times
+ * (reps >= 1) on the caller's buffers -- a forward, plus a backward unless the plan is
+ * forward-only -- times each with HIP events on `stream`, and keeps the fastest for
+ * later calls.  Output buffers are overwritten; dz, dmu, ds, du, dlogp may be NULL for a
+ * forward-only plan.  Synchronises the stream.  If the environment variable
+ * TMC_TUNE_CACHE names a file, the choice is appended to it as a line
+ * "<shape signature> <persist> <grid factor> <stages>" and plans created later with the
+ * same signature start from it.  Not for use during graph capture.  Plain-engine plans:
+ * returns TMC_OK without doing anything. */
+tmc_status tmc_plan_autotune(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                             const void* u, const double* dlogp, void* workspace, void* dz,
+                             void* dmu, void* ds, void* du, int reps, void* stream);
 
 /* ---- measurement ---- */
 /* Kernel classes timed by the plan's optional event timer. */

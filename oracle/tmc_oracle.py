@@ -191,6 +191,32 @@ def gauss_chain_grads(z, mu, s, u, chunk: int = 128):
     return logp, dz, dmu, ds, [np.asarray(a) for a in p]
 
 
+def gauss_layer0_row_grads(z, mu, s, u, rows):
+    """log P_TMC and, for the listed sample indices i of layer 0 (the layer next to the
+    data), dlogP/dz_0[i] and dlogP/du_0[i], without forming every pairwise marginal:
+    layer 0 is where the bottom-up message starts, beta_0 = -ln K_0, so its marginals
+    need only the top-down messages (see `chain_marginals`):
+        G_0[i, j] = exp(beta_0 + u_0[i] + f_0[i, j] + alpha_1[j] - ln K_1 - log P)
+        dz_0[i]   = sum_j G_0[i, j] * (-lam * (z_0[i] - mu_0[j]))
+        du_0[i]   = exp(beta_0 + alpha_0[i] - log P)
+    For spot checks of large chains.  Returns (log P, dz rows [n, D_0], du rows [n])."""
+    f = gauss_chain_factors(z, mu, s)
+    logp, alpha = chain_messages(f, u)
+    rows = np.asarray(rows, dtype=np.int64)
+    K0, K1 = len(u[0]), len(u[1])
+    beta0 = -log_k(K0)
+    lam = np.exp(-2.0 * np.asarray(s[0], np.float64))
+    z0 = np.asarray(z[0], np.float64)
+    m0 = np.asarray(mu[0], np.float64)
+    e = (beta0 + np.asarray(u[0], np.float64)[rows][:, None] + f[0][rows]
+         + alpha[1][None, :] - log_k(K1) - logp)
+    G = np.exp(e)                                             # [n, K1]
+    diff = z0[rows][:, None, :] - m0[None, :, :]              # [n, K1, D]
+    dz = np.sum(G[:, :, None] * (-lam * diff), axis=1)
+    du = np.exp(beta0 + alpha[0][rows] - logp)
+    return logp, dz, du
+
+
 def finite_difference(fun, x: np.ndarray, h: float = 1e-5, idx=None) -> np.ndarray:
     """Central differences (fun(x + h e) - fun(x - h e)) / 2h at the flat indices
     `idx` (all entries when None)."""

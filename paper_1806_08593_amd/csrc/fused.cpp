@@ -1,9 +1,13 @@
 // Fused engine host side: workspace regions, per-depth schedules grouped by the
-// instantiated d-chunk count, and the forward/backward launch sequences.
+// instantiated d-chunk count, the dependency-ordered queues of the persistent launches,
+// and the shape signature the launch-shape tuner caches its choices under.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <map>
+#include <string>
+#include <tuple>
 
 #include "fused.h"
 #include "tmc_kernels.h"
@@ -21,9 +25,11 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>& layers,
                        const std::vector<ChainDev>& chains, const std::vector<int>& pairs,
-                       WsLayout& W, size_t& o, std::vector<Item>& items) {
+                       WsLayout& W, size_t& o, std::vector<Item>& items, std::vector<int>& ints) {
   F.prec = prec;
   F.flags = flags;
+  F.n_layers = (int)layers.size();
+  F.tune.persist = (flags & TMC_FLAG_PERSISTENT) != 0;
   const bool grad = !(flags & TMC_FLAG_FORWARD_ONLY);
   int64_t ev = 0, sumK = 0, sq = 0;
   for (auto& d : layers) sumK += d.K;
@@ -41,31 +47,26 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
   o = align256(o + (size_t)sumK * 4);
   W.q = o;
   o = align256(o + (size_t)sq * 8);
-  W.total = o;
-
 
   int max_depth = 0;
   for (auto& c : chains) max_depth = std::max(max_depth, c.L);
   const int steps = std::max(max_depth - 1, 0);
+
+  // level-synchronous schedules: one launch per (depth step, chunk bucket)
   F.fwd.assign(steps, {});
   F.bwd.assign(steps, {});
   for (int t = 0; t < steps; ++t) {
     for (int dir = 0; dir < 2; ++dir) {
-      std::map<std::pair<int, int>, std::vector<int>> groups;   // (nkc, waves) -> pairs
+      std::map<int, std::vector<int>> groups;   // nkc -> pairs
       for (int l : pairs) {
         const LayerDev& d = layers[l];
         const int L = chains[d.chain].L;
         const bool in_step = dir == 0 ? d.depth == L - 2 - t : d.depth == t;
-        if (!in_step) continue;
-        const int n = dir == 0 ? d.K : d.Kc;
-        const int waves = 4;   // the staged-tile loader assumes 256 threads
-        (void)n;
-        groups[{nkc_bucket(d.D), waves}].push_back(l);
+        if (in_step) groups[nkc_bucket(d.D)].push_back(l);
       }
       for (auto& kv : groups) {
         FusedLaunch fl;
-        fl.nkc = kv.first.first;
-        fl.waves = kv.first.second;
+        fl.nkc = kv.first;
         fl.off = (int)items.size();
         const int step_rows = dir == 0 ? kFusedFwdRows : kFusedBwdCols;
         for (int l : kv.second) {
@@ -78,6 +79,43 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
       }
     }
   }
+
+  // persistent queues: chains grouped by the largest chunk bucket among their pairs,
+  // each group's chains ordered by decreasing work (sum of K_l K_{l+1} D_l) so that the
+  // longest chains start first
+  std::map<int, std::vector<int>> chain_groups;   // nkc -> chains
+  std::vector<int> chain_nkc(chains.size(), 0);
+  std::vector<double> cost(chains.size(), 0.0);
+  for (int l : pairs) {
+    const LayerDev& d = layers[l];
+    chain_nkc[d.chain] = std::max(chain_nkc[d.chain], nkc_bucket(d.D));
+    cost[d.chain] += (double)d.K * d.Kc * d.D;
+  }
+  for (size_t c = 0; c < chains.size(); ++c)
+    if (chain_nkc[c] > 0) chain_groups[chain_nkc[c]].push_back((int)c);
+  F.pfwd.clear();
+  F.pbwd.clear();
+  int heads = 0;
+  for (auto& kv : chain_groups) {
+    std::vector<int>& cs = kv.second;
+    std::stable_sort(cs.begin(), cs.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    PersistGroup g;
+    g.nkc = kv.first;
+    g.off = (int)ints.size();
+    g.n = (int)cs.size();
+    ints.insert(ints.end(), cs.begin(), cs.end());
+    g.head = heads++;
+    F.pfwd.push_back(g);
+  }
+  for (auto g : F.pfwd) {
+    g.head = heads++;
+    F.pbwd.push_back(g);
+  }
+  // queue head counters (forward groups, then backward groups)
+  W.cnt = o;
+  o = align256(o + (size_t)(heads + 1) * 4);
+  W.total = o;
+
   F.dz.off = (int)items.size();
   for (int l : pairs)
     for (int r = 0; r < layers[l].K; r += kFusedDzRows) items.push_back({l, r});
@@ -86,14 +124,40 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
   return TMC_OK;
 }
 
+void fused_set_grids(FusedPlan& F) {
+  const bool grad = !(F.flags & TMC_FLAG_FORWARD_ONLY);
+  for (int dir = 0; dir < 2; ++dir)
+    for (auto& g : (dir == 0 ? F.pfwd : F.pbwd)) {
+      const int cap = F.prec == TMC_BF16X3 ? fused_capacity<TMC_BF16X3>(dir, g.nkc, grad, F.tune.fwd_ns)
+                                           : fused_capacity<TMC_FP32>(dir, g.nkc, grad, F.tune.fwd_ns);
+      const int want = cap * std::max(F.tune.grid_factor, 1);
+      g.grid = std::max(1, std::min(g.n, want));   // one workgroup per chain at most
+    }
+}
+
 void fused_info(const FusedPlan& F, tmc_plan_info* out) {
   out->tile_rows = 32;
   out->tile_cols = 32;
-  int w = 0;
-  for (auto& st : F.fwd)
-    for (auto& g : st) w = std::max(w, g.waves);
-  out->waves_per_group = w;
-  (void)F;
+  out->waves_per_group = 4;
+  out->persistent = F.tune.persist ? 1 : 0;
+  out->tuned = F.tuned ? 1 : 0;
+}
+
+std::string fused_signature(const FusedPlan& F, const std::vector<LayerDev>& layers,
+                            const std::vector<ChainDev>& chains) {
+  // precision, flags and the multiset of (K, Kc, D bucket) pair shapes, run-length coded
+  std::map<std::tuple<int, int, int>, int> hist;
+  for (auto& d : layers)
+    if (d.up >= 0) hist[{d.K, d.Kc, nkc_bucket(d.D)}]++;
+  std::string s = "p" + std::to_string(F.prec) + "f" + std::to_string(F.flags & ~TMC_FLAG_PERSISTENT) +
+                  "c" + std::to_string(chains.size());
+  for (auto& kv : hist) {
+    char b[64];
+    snprintf(b, sizeof b, "_%dx%dx%d:%d", std::get<0>(kv.first), std::get<1>(kv.first),
+             std::get<2>(kv.first), kv.second);
+    s += b;
+  }
+  return s;
 }
 
 }  // namespace tmc

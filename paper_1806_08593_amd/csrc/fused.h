@@ -2,6 +2,7 @@
 // recompute the pairwise factors on MFMA inside the message passes.
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "../../include/tmc.h"
@@ -20,12 +21,32 @@ struct FusedLaunch {
   int off = 0, n = 0, nkc = 0, waves = 4;
 };
 
+// One persistent launch: the chains ints[off .. off + n) of the plan's int table, most
+// expensive first; a workgroup runs all pairs of a chain it takes.  All chains of the
+// group use the chunk count nkc (the largest bucket among their pairs).
+struct PersistGroup {
+  int nkc = 0, off = 0, n = 0;
+  int head = 0;       // index of its queue head counter
+  int grid = 0;       // workgroups launched
+};
+
+// Launch-shape choices (the autotuner picks among them per plan).
+struct FusedTune {
+  bool persist = false;   // one persistent launch per group instead of one per depth
+  int grid_factor = 1;    // persistent grid = min(items, factor x resident capacity)
+  int fwd_ns = 2;         // forward-only: staged 32-sample subtiles per LDS stage (1, 2)
+};
+
 struct FusedPlan {
   int prec = 0, flags = 0;
   std::vector<std::vector<FusedLaunch>> fwd, bwd;   // [depth step][nkc group]
+  std::vector<PersistGroup> pfwd, pbwd;             // persistent launches
   FusedLaunch dz;                                   // all pairs, 64 rows per item
   int n_pairs = 0;
   int pair_ids_off = 0;                             // into the plan's int table
+  int n_layers = 0;
+  FusedTune tune;
+  bool tuned = false;
 };
 
 int nkc_bucket(int D);
@@ -37,31 +58,56 @@ constexpr int kFusedFwdRows = 128;
 constexpr int kFusedDzRows = 64;
 tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>& layers,
                        const std::vector<ChainDev>& chains, const std::vector<int>& pairs,
-                       WsLayout& W, size_t& o, std::vector<Item>& items);
+                       WsLayout& W, size_t& o, std::vector<Item>& items, std::vector<int>& ints);
+// Sets the persistent grids from the device's resident capacity (device must be current).
+void fused_set_grids(FusedPlan& F);
 void fused_info(const FusedPlan& F, tmc_plan_info* out);
+// Signature of the plan's shapes for the tuning cache.
+std::string fused_signature(const FusedPlan& F, const std::vector<LayerDev>& layers,
+                            const std::vector<ChainDev>& chains);
 
-// kernel launchers (k_fused_*.hip)
+// kernel arguments of the fused launches
+struct FusedFwdPtrs {
+  const LayerDev* layers;
+  const float *z, *mu, *s, *u;
+  double *qcol, *alpha, *wmax;
+  float *rl, *ev;
+};
+struct FusedBwdPtrs {
+  const LayerDev* layers;
+  const float *z, *mu, *s;
+  const double *alpha, *wmax, *qcol;
+  const float* rl;
+  float* lam;
+  const double* dlogp;
+  float *p, *dmu, *du, *dsp;
+};
+struct FusedQueue {
+  const int* chains = nullptr;   // chain ids, most expensive first
+  int n_chains = 0;
+  int* head = nullptr;           // queue head counter (zeroed by the pass's init kernel)
+  const ChainDev* cd = nullptr;
+  int grid = 0;
+};
+
+// kernel launchers (k_fused_*.hip); q == nullptr: one workgroup per item
 template <int PREC>
-hipError_t launch_fused_fwd(int nkc, int waves, bool grad, const LayerDev* layers,
-                            const Item* items, int n, const float* z, const float* mu,
-                            const float* s, const float* u, double* qcol, double* alpha,
-                            double* wmax, float* rl, float* ev, hipStream_t st);
+int fused_capacity(int dir, int nkc, bool grad, int ns);
 template <int PREC>
-hipError_t launch_fused_bwd(int nkc, int waves, const LayerDev* layers, const Item* items,
-                            int n, const float* z, const float* mu, const float* s,
-                            const double* alpha, const double* wmax,
-                            const double* qcol, const float* rl, float* lam,
-                            const double* dlogp, float* p, float* dmu, float* du, float* dsp,
-                            hipStream_t st);
+hipError_t launch_fused_fwd(int nkc, int waves, bool grad, int ns, const FusedFwdPtrs& a,
+                            const Item* items, int n, const FusedQueue* q, hipStream_t st);
+template <int PREC>
+hipError_t launch_fused_bwd(int nkc, int waves, const FusedBwdPtrs& a, const Item* items, int n,
+                            const FusedQueue* q, hipStream_t st);
 hipError_t launch_fused_dz(const LayerDev* layers, const Item* items, int n, const float* z,
                            const float* s, const float* p, const float* ev, const double* dlogp,
                            float* dz, float* dsp, hipStream_t st);
 hipError_t launch_fused_fwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
-                                 const float* u, double* alpha, double* wmax, hipStream_t st);
+                                 const float* u, double* alpha, double* wmax, int* heads,
+                                 int n_heads, hipStream_t st);
 hipError_t launch_fused_bwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
                                  const double* alpha, const double* logp_ws, const double* dlogp,
                                  const float* rl, float* lam, float* p, float* du, float* dz,
-                                 hipStream_t st);
-
+                                 int* heads, int n_heads, hipStream_t st);
 
 }  // namespace tmc

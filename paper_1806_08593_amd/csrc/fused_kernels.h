@@ -46,6 +46,35 @@ constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kHalfLn2Pi = 0.91893853320467274178;
 constexpr float kRescale = 8.0f;   // lazy online-max threshold (log2 units)
 constexpr int kFusedRowsPerGroup = 128;   // forward rows per workgroup (4 waves x 32)
+constexpr int kFusedBwdColsDev = 128;     // backward columns per workgroup (4 waves x 32)
+
+// Kernel arguments (device pointers; see the launchers for their regions).
+struct FwdArgs {
+  const LayerDev* Ls;
+  const Item* items;
+  const float *z, *mu, *s, *u;
+  double *qcol, *alpha, *wmax;
+  float *rl, *ev;
+};
+struct BwdArgs {
+  const LayerDev* Ls;
+  const Item* items;
+  const float *z, *mu, *s;
+  const double *alpha, *wmax, *qcol;
+  const float* rl;
+  float* lam;
+  const double* dlogp;
+  float *p, *dmu, *du, *dsp;
+};
+// Chain queue of a persistent launch: chains[0 .. n) (most expensive first); a
+// workgroup takes the next chain from the head counter and runs all of its layer
+// pairs itself, so no workgroup ever waits for another.
+struct ChainQueue {
+  const int* chains;
+  int n;
+  int* head;
+  const ChainDev* cd;
+};
 
 // Workgroup barrier that orders LDS traffic only: outstanding global loads stay in
 // flight across it (a fence-based __syncthreads would wait for them).
@@ -542,23 +571,23 @@ __device__ __forceinline__ void wave_load(const float* __restrict__ base, int64_
 //   e_i     = sum_j softmax_j(S_ij + gamma_j) mu_j        (GRAD: used for dz)
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, bool GRAD, int NS>
-__global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const LayerDev* __restrict__ Ls,
-                                                   const Item* __restrict__ items,
-                                                   const float* __restrict__ z,
-                                                   const float* __restrict__ mu,
-                                                   const float* __restrict__ s,
-                                                   const float* __restrict__ u,
-                                                   double* __restrict__ qcol,
-                                                   double* __restrict__ alpha,
-                                                   double* __restrict__ wmax,
-                                                   float* __restrict__ rl,
-                                                   float* __restrict__ ev) {
-  constexpr int NB = (NKC <= 8) ? 2 : 1;
-  using TS = TileSmem<PREC, NKC, NS, NB, GRAD>;
+using FwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), GRAD>;
+
+template <int PREC, int NKC, bool GRAD, int NS>
+__device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const Item it,
+                                         const LayerDev& L, const FwdArgs& args) {
+  using TS = FwdSmem<PREC, NKC, GRAD, NS>;
+  constexpr int NB = TS::NB;
   constexpr int ND32 = TS::ND32;
-  __shared__ __align__(16) TS T;
-  const Item it = items[blockIdx.x];
-  const LayerDev L = Ls[it.layer];
+  const float* __restrict__ z = args.z;
+  const float* __restrict__ mu = args.mu;
+  const float* __restrict__ s = args.s;
+  const float* __restrict__ u = args.u;
+  double* __restrict__ qcol = args.qcol;
+  double* __restrict__ alpha = args.alpha;
+  double* __restrict__ wmax = args.wmax;
+  float* __restrict__ rl = args.rl;
+  float* __restrict__ ev = args.ev;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, ir = lane & 31;
   const int i0 = it.start + 32 * w;
   const bool active = i0 < L.K;
@@ -754,6 +783,40 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const Lay
   }
 }
 
+// One workgroup per work item (level-synchronous launch).
+template <int PREC, int NKC, bool GRAD, int NS>
+__global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(FwdArgs args) {
+  __shared__ __align__(16) FwdSmem<PREC, NKC, GRAD, NS> T;
+  const Item it = args.items[blockIdx.x];
+  const LayerDev L = args.Ls[it.layer];
+  fwd_item<PREC, NKC, GRAD, NS>(T, it, L, args);
+}
+
+// Persistent launch: each workgroup takes whole chains from the queue and runs their
+// pairs top-down (pair l reads the alpha_{l+1} and maxima its own earlier pair wrote;
+// the workgroup barrier between pairs orders those global writes and reads).
+template <int PREC, int NKC, bool GRAD, int NS>
+__global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(FwdArgs args,
+                                                                               ChainQueue q) {
+  __shared__ __align__(16) FwdSmem<PREC, NKC, GRAD, NS> T;
+  __shared__ int s_k;
+  for (;;) {
+    if (threadIdx.x == 0) s_k = atomicAdd(q.head, 1);
+    __syncthreads();
+    const int k = s_k;
+    __syncthreads();
+    if (k >= q.n) return;
+    const ChainDev ch = q.cd[q.chains[k]];
+    for (int l = ch.top - 1; l >= ch.first; --l) {
+      const LayerDev L = args.Ls[l];
+      for (int x = 0; x < L.K; x += kFusedRowsPerGroup) {
+        fwd_item<PREC, NKC, GRAD, NS>(T, Item{l, x}, L, args);
+        __syncthreads();
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // backward: a workgroup of 4 waves owns 128 columns (samples j of layer l+1; wave
 // w: columns start + 32 w ..) and sweeps every row of layer l, NS x 32 rows per LDS
@@ -767,28 +830,27 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(const Lay
 // The constant c cancels between the forward's ell_i and G, so it is not needed here.
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, int NS>
-__global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const LayerDev* __restrict__ Ls,
-                                                   const Item* __restrict__ items,
-                                                   const float* __restrict__ z,
-                                                   const float* __restrict__ mu,
-                                                   const float* __restrict__ s,
-                                                   const double* __restrict__ alpha,
-                                                   const double* __restrict__ wmax,
-                                                   const double* __restrict__ qcol,
-                                                   const float* __restrict__ rl,
-                                                   float* __restrict__ lam_ws,
-                                                   const double* __restrict__ dlogp,
-                                                   float* __restrict__ p,
-                                                   float* __restrict__ dmu,
-                                                   float* __restrict__ du,
-                                                   float* __restrict__ dsp) {
-  constexpr int NB = (NKC <= 8) ? 2 : 1;
-  using TS = TileSmem<PREC, NKC, NS, NB, true>;
+using BwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), true>;
+
+template <int PREC, int NKC, int NS>
+__device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD, const Item it,
+                                         const LayerDev& L, const BwdArgs& args) {
+  using TS = BwdSmem<PREC, NKC, NS>;
+  constexpr int NB = TS::NB;
   constexpr int ND32 = TS::ND32;
-  __shared__ __align__(16) TS T;
-  __shared__ float accD[TS::DT];
-  const Item it = items[blockIdx.x];
-  const LayerDev L = Ls[it.layer];
+  const float* __restrict__ z = args.z;
+  const float* __restrict__ mu = args.mu;
+  const float* __restrict__ s = args.s;
+  const double* __restrict__ alpha = args.alpha;
+  const double* __restrict__ wmax = args.wmax;
+  const double* __restrict__ qcol = args.qcol;
+  const float* __restrict__ rl = args.rl;
+  float* __restrict__ lam_ws = args.lam;
+  const double* __restrict__ dlogp = args.dlogp;
+  float* __restrict__ p = args.p;
+  float* __restrict__ dmu = args.dmu;
+  float* __restrict__ du = args.du;
+  float* __restrict__ dsp = args.dsp;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, jr = lane & 31;
   const int jw = it.start + 32 * w;
   const bool active = jw < L.Kc;
@@ -962,7 +1024,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const Lay
         }
       }
   }
-  if (!dsp) return;
+  if (!dsp) return;   // (uniform: ends this item)
   float* buf = reinterpret_cast<float*>(&T.col[0][0][0]);   // >= 32 x DT floats
   for (int w2 = 0; w2 < 4; ++w2) {
     lds_barrier();
@@ -983,6 +1045,40 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(const Lay
   const int part = it.start / 128;
   for (int d = tid; d < L.D; d += blockDim.x)
     dsp[L.dsp_off + (int64_t)part * L.D + d] = g32 * T.lamf[d] * accD[d];
+}
+
+template <int PREC, int NKC, int NS>
+__global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(BwdArgs args) {
+  __shared__ __align__(16) BwdSmem<PREC, NKC, NS> T;
+  __shared__ float accD[BwdSmem<PREC, NKC, NS>::DT];
+  const Item it = args.items[blockIdx.x];
+  const LayerDev L = args.Ls[it.layer];
+  bwd_item<PREC, NKC, NS>(T, accD, it, L, args);
+}
+
+// Persistent backward: each workgroup takes whole chains and runs their pairs
+// bottom-up (pair l reads the row shifts Lam_l its own pair l-1 wrote).
+template <int PREC, int NKC, int NS>
+__global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd_persist(BwdArgs args,
+                                                                               ChainQueue q) {
+  __shared__ __align__(16) BwdSmem<PREC, NKC, NS> T;
+  __shared__ float accD[BwdSmem<PREC, NKC, NS>::DT];
+  __shared__ int s_k;
+  for (;;) {
+    if (threadIdx.x == 0) s_k = atomicAdd(q.head, 1);
+    __syncthreads();
+    const int k = s_k;
+    __syncthreads();
+    if (k >= q.n) return;
+    const ChainDev ch = q.cd[q.chains[k]];
+    for (int l = ch.first; l < ch.top; ++l) {
+      const LayerDev L = args.Ls[l];
+      for (int x = 0; x < L.Kc; x += kFusedBwdColsDev) {
+        bwd_item<PREC, NKC, NS>(T, accD, Item{l, x}, L, args);
+        __syncthreads();
+      }
+    }
+  }
 }
 
 }  // namespace fused

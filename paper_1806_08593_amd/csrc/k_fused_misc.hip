@@ -10,13 +10,17 @@ namespace tmc {
 
 // Start of the fused forward, one workgroup per chain: alpha of the top layer = u,
 // and the per-128-row maxima of u_top (the same layout the forward leaves for every
-// other layer), one wave per 128-row part.
+// other layer), one wave per 128-row part.  Workgroup 0 clears the queue heads of the
+// persistent forward launches.
 __global__ __launch_bounds__(256) void k_fused_fwd_init(const ChainDev* __restrict__ chains,
                                                         const LayerDev* __restrict__ layers,
                                                         const float* __restrict__ u,
                                                         double* __restrict__ alpha,
-                                                        double* __restrict__ wmax) {
+                                                        double* __restrict__ wmax,
+                                                        int* __restrict__ heads, int n_heads) {
   const ChainDev ch = chains[blockIdx.x];
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < n_heads; k += blockDim.x) heads[k] = 0;
   const LayerDev& t = layers[ch.top];
   const int nparts = (t.K + 127) / 128;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -44,9 +48,12 @@ __global__ __launch_bounds__(256) void k_fused_bwd_init(const ChainDev* __restri
                                                         float* __restrict__ lam,
                                                         float* __restrict__ p,
                                                         float* __restrict__ du,
-                                                        float* __restrict__ dz) {
+                                                        float* __restrict__ dz,
+                                                        int* __restrict__ heads, int n_heads) {
   const int c = blockIdx.x;
   const ChainDev ch = chains[c];
+  if (c == 0)
+    for (int k = threadIdx.x; k < n_heads; k += blockDim.x) heads[k] = 0;
   const LayerDev& l0 = layers[ch.first];
   const double lp = logp_ws[c];
   const double g = dlogp[c];
@@ -171,18 +178,19 @@ hipError_t launch_fused_dz(const LayerDev* layers, const Item* items, int n, con
 hipError_t launch_fused_bwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
                                  const double* alpha, const double* logp_ws, const double* dlogp,
                                  const float* rl, float* lam, float* p, float* du, float* dz,
-                                 hipStream_t st) {
+                                 int* heads, int n_heads, hipStream_t st) {
   if (n_chains <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fused_bwd_init, dim3(n_chains), dim3(256), 0, st, chains, layers, alpha,
-                     logp_ws, dlogp, rl, lam, p, du, dz);
+                     logp_ws, dlogp, rl, lam, p, du, dz, heads, n_heads);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_fwd_init(const ChainDev* chains, int n_chains, const LayerDev* layers,
-                                 const float* u, double* alpha, double* wmax, hipStream_t st) {
+                                 const float* u, double* alpha, double* wmax, int* heads,
+                                 int n_heads, hipStream_t st) {
   if (n_chains <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fused_fwd_init, dim3(n_chains), dim3(256), 0, st, chains, layers, u,
-                     alpha, wmax);
+                     alpha, wmax, heads, n_heads);
   return hipGetLastError();
 }
 

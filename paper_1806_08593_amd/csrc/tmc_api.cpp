@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -235,6 +237,40 @@ T* wsp(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
+// ---- launch-shape tuning cache ----
+// A text file named by TMC_TUNE_CACHE holds lines "<signature> <persist> <grid factor>
+// <stages>"; the last line with a plan's signature sets its starting launch shape.
+void tune_cache_lookup(tmc_plan* P) {
+  const char* path = std::getenv("TMC_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  const std::string sig = fused_signature(P->fused, P->layers_h, P->chains_h);
+  char line[8192];
+  while (std::fgets(line, sizeof line, f)) {
+    char key[8000];
+    int persist = 0, gf = 1, ns = 2;
+    if (std::sscanf(line, "%7999s %d %d %d", key, &persist, &gf, &ns) == 4 && sig == key) {
+      P->fused.tune.persist = persist != 0;
+      P->fused.tune.grid_factor = std::max(1, std::min(gf, 8));
+      P->fused.tune.fwd_ns = ns == 1 ? 1 : 2;
+      P->fused.tuned = true;
+    }
+  }
+  std::fclose(f);
+}
+
+void tune_cache_store(const tmc_plan* P) {
+  const char* path = std::getenv("TMC_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  const FusedTune& t = P->fused.tune;
+  std::fprintf(f, "%s %d %d %d\n", fused_signature(P->fused, P->layers_h, P->chains_h).c_str(),
+               t.persist ? 1 : 0, t.grid_factor, t.fwd_ns);
+  std::fclose(f);
+}
+
 tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   P->n_chains = pr->n_chains;
   P->n_layers = pr->n_layers;
@@ -442,8 +478,10 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   // fused engine layout and schedules
   if (P->engine == TMC_ENGINE_FUSED) {
     tmc_status st = fused_build(P->fused, P->prec, P->flags, P->layers_h, P->chains_h, pairs,
-                                P->ws, o, items);
+                                P->ws, o, items, ints);
     if (st != TMC_OK) return fail(st, "fused engine: unsupported layer width");
+    tune_cache_lookup(P);
+    fused_set_grids(P->fused);
   }
 
   // upload
@@ -567,26 +605,32 @@ tmc_status plain_bwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, co
 tmc_status fused_fwd_impl(tmc_plan* P, const float* z, const float* mu, const float* s,
                           const float* u, double* logp, void* ws, hipStream_t st) {
   const WsLayout& W = P->ws;
+  const FusedPlan& F = P->fused;
   const bool grad = !(P->flags & TMC_FLAG_FORWARD_ONLY);
-  double* alpha = wsp<double>(ws, W.alpha);
-  double* qcol = wsp<double>(ws, W.q);
-  float* rl = wsp<float>(ws, W.rl);
-  float* ev = wsp<float>(ws, W.ev);
-  double* wmax = wsp<double>(ws, W.wmax);
-  LAUNCH(launch_fused_fwd_init(P->chains_d, P->n_chains, P->layers_d, u, alpha, wmax, st));
-  for (auto& step : P->fused.fwd)
-    for (auto& g : step) {
-      const Item* it = P->items_d + g.off;
-      if (P->prec == TMC_FP32)
-        LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_FP32>(g.nkc, g.waves, grad, P->layers_d, it,
-                                                               g.n, z, mu, s, u, qcol, alpha, wmax,
-                                                               rl, ev, st));
-      else
-        LAUNCH_KC(TMC_KC_FUSED_FWD, launch_fused_fwd<TMC_BF16X3>(g.nkc, g.waves, grad, P->layers_d,
-                                                                 it, g.n, z, mu, s, u, qcol, alpha,
-                                                                 wmax, rl, ev, st));
+  FusedFwdPtrs a{P->layers_d, z, mu, s, u, wsp<double>(ws, W.q), wsp<double>(ws, W.alpha),
+                 wsp<double>(ws, W.wmax), wsp<float>(ws, W.rl), wsp<float>(ws, W.ev)};
+  int* heads = wsp<int>(ws, W.cnt);
+  LAUNCH(launch_fused_fwd_init(P->chains_d, P->n_chains, P->layers_d, u, a.alpha, a.wmax, heads,
+                               (int)F.pfwd.size(), st));
+  auto go = [&](int nkc, int waves, const Item* it, int n, const FusedQueue* q) -> hipError_t {
+    return P->prec == TMC_FP32 ? launch_fused_fwd<TMC_FP32>(nkc, waves, grad, F.tune.fwd_ns, a, it, n, q, st)
+                               : launch_fused_fwd<TMC_BF16X3>(nkc, waves, grad, F.tune.fwd_ns, a, it, n, q, st);
+  };
+  if (F.tune.persist) {
+    for (auto& g : F.pfwd) {
+      FusedQueue q;
+      q.chains = P->ints_d + g.off;
+      q.n_chains = g.n;
+      q.head = heads + g.head;
+      q.cd = P->chains_d;
+      q.grid = g.grid;
+      LAUNCH_KC(TMC_KC_FUSED_FWD, go(g.nkc, 4, P->items_d, g.n, &q));
     }
-  LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, alpha, logp,
+  } else {
+    for (auto& step : F.fwd)
+      for (auto& g : step) LAUNCH_KC(TMC_KC_FUSED_FWD, go(g.nkc, g.waves, P->items_d + g.off, g.n, nullptr));
+  }
+  LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, a.alpha, logp,
                          wsp<double>(ws, W.logp), P->flag_d, st));
   return TMC_OK;
 }
@@ -595,32 +639,36 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
                           const double* dlogp, void* ws, float* dz, float* dmu, float* ds,
                           float* du, hipStream_t st) {
   const WsLayout& W = P->ws;
-  double* alpha = wsp<double>(ws, W.alpha);
-  const double* qcol = wsp<double>(ws, W.q);
-  const double* wmax = wsp<double>(ws, W.wmax);
-  float* rl = wsp<float>(ws, W.rl);
-  float* lam = wsp<float>(ws, W.lam);
-  float* p = wsp<float>(ws, W.p);
-  const float* ev = wsp<float>(ws, W.ev);
+  const FusedPlan& F = P->fused;
   float* dsp = ds ? wsp<float>(ws, W.dsp) : nullptr;
-  LAUNCH(launch_fused_bwd_init(P->chains_d, P->n_chains, P->layers_d, alpha,
-                               wsp<double>(ws, W.logp), dlogp, rl, lam, p, du, dz, st));
-  for (auto& step : P->fused.bwd)
-    for (auto& g : step) {
-      const Item* it = P->items_d + g.off;
-      if (P->prec == TMC_FP32)
-        LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_FP32>(g.nkc, g.waves, P->layers_d, it, g.n,
-                                                               z, mu, s, alpha, wmax, qcol,
-                                                               rl, lam, dlogp, p, dmu, du, dsp, st));
-      else
-        LAUNCH_KC(TMC_KC_FUSED_BWD, launch_fused_bwd<TMC_BF16X3>(g.nkc, g.waves, P->layers_d, it,
-                                                                 g.n, z, mu, s, alpha, wmax,
-                                                                 qcol, rl, lam, dlogp, p, dmu, du,
-                                                                 dsp, st));
+  FusedBwdPtrs a{P->layers_d, z, mu, s, wsp<double>(ws, W.alpha), wsp<double>(ws, W.wmax),
+                 wsp<double>(ws, W.q), wsp<float>(ws, W.rl), wsp<float>(ws, W.lam), dlogp,
+                 wsp<float>(ws, W.p), dmu, du, dsp};
+  int* heads = wsp<int>(ws, W.cnt);
+  LAUNCH(launch_fused_bwd_init(P->chains_d, P->n_chains, P->layers_d, a.alpha,
+                               wsp<double>(ws, W.logp), dlogp, a.rl, a.lam, a.p, du, dz,
+                               heads + F.pfwd.size(), (int)F.pbwd.size(), st));
+  auto go = [&](int nkc, int waves, const Item* it, int n, const FusedQueue* q) -> hipError_t {
+    return P->prec == TMC_FP32 ? launch_fused_bwd<TMC_FP32>(nkc, waves, a, it, n, q, st)
+                               : launch_fused_bwd<TMC_BF16X3>(nkc, waves, a, it, n, q, st);
+  };
+  if (F.tune.persist) {
+    for (auto& g : F.pbwd) {
+      FusedQueue q;
+      q.chains = P->ints_d + g.off;
+      q.n_chains = g.n;
+      q.head = heads + g.head;
+      q.cd = P->chains_d;
+      q.grid = g.grid;
+      LAUNCH_KC(TMC_KC_FUSED_BWD, go(g.nkc, 4, P->items_d, g.n, &q));
     }
-  if ((dz || ds) && P->fused.dz.n > 0)
-    LAUNCH(launch_fused_dz(P->layers_d, P->items_d + P->fused.dz.off, P->fused.dz.n, z, s, p, ev,
-                           dlogp, dz, dsp, st));
+  } else {
+    for (auto& step : F.bwd)
+      for (auto& g : step) LAUNCH_KC(TMC_KC_FUSED_BWD, go(g.nkc, g.waves, P->items_d + g.off, g.n, nullptr));
+  }
+  if ((dz || ds) && F.dz.n > 0)
+    LAUNCH(launch_fused_dz(P->layers_d, P->items_d + F.dz.off, F.dz.n, z, s, a.p,
+                           wsp<float>(ws, W.ev), dlogp, dz, dsp, st));
   if (ds)
     LAUNCH(launch_ds_reduce<float>(P->part_off_d, P->ints_d + P->slot_start_off, P->slot_soff_d,
                                    P->ints_d + P->slot_D_off, P->n_slots, P->max_D, dsp, ds, st));
@@ -914,6 +962,81 @@ tmc_status tmc_plan_graph_launch(tmc_plan_t plan, int which, void* stream) {
   DeviceGuard g(plan->device);
   HIP_TRY(hipGraphLaunch(plan->graph[which], (hipStream_t)stream));
   return TMC_OK;
+}
+
+tmc_status tmc_plan_autotune(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                             const void* u, const double* dlogp, void* workspace, void* dz,
+                             void* dmu, void* ds, void* du, int reps, void* stream) {
+  try {
+    tmc_status st = check_exec(plan, workspace);
+    if (st != TMC_OK) return st;
+    if (plan->engine != TMC_ENGINE_FUSED) return TMC_OK;
+    if (plan->capturing) return fail(TMC_ERR_STATE, "autotune during graph capture");
+    if (reps < 1) return fail(TMC_ERR_INVALID_ARG, "reps must be >= 1");
+    if (!plan->gauss_err.empty()) return fail(TMC_ERR_SHAPE, "%s", plan->gauss_err.c_str());
+    if (!z || !mu || !s || !u) return fail(TMC_ERR_INVALID_ARG, "z, mu, s and u are required");
+    const bool fwd_only = (plan->flags & TMC_FLAG_FORWARD_ONLY) != 0;
+    if (!fwd_only && !dlogp) return fail(TMC_ERR_INVALID_ARG, "dlogp is required for a backward");
+    DeviceGuard g(plan->device);
+    hipStream_t hs = (hipStream_t)stream;
+    tmc_plan* P = plan;
+    double* logp = wsp<double>(workspace, P->ws.logp);
+    const bool was_timing = P->timing;
+    P->timing = false;
+    std::vector<FusedTune> cands;
+    for (int persist = 0; persist < 2; ++persist)
+      for (int gf = 1; gf <= (persist ? 2 : 1); ++gf)
+        for (int ns = 1; ns <= 2; ++ns) {
+          if (!fwd_only && ns == 1) continue;   // the gradient forward has one stage width
+          FusedTune t;
+          t.persist = persist != 0;
+          t.grid_factor = gf;
+          t.fwd_ns = ns;
+          cands.push_back(t);
+        }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto run = [&]() -> tmc_status {
+      tmc_status r = fused_fwd_impl(P, (const float*)z, (const float*)mu, (const float*)s,
+                                    (const float*)u, logp, workspace, hs);
+      if (r != TMC_OK || fwd_only) return r;
+      return fused_bwd_impl(P, (const float*)z, (const float*)mu, (const float*)s, dlogp,
+                            workspace, (float*)dz, (float*)dmu, (float*)ds, (float*)du, hs);
+    };
+    float best = -1.0f;
+    FusedTune best_t = P->fused.tune;
+    tmc_status rs = TMC_OK;
+    for (const FusedTune& t : cands) {
+      P->fused.tune = t;
+      fused_set_grids(P->fused);
+      if ((rs = run()) != TMC_OK) break;   // warm-up
+      if (hipEventRecord(e0, hs) != hipSuccess) { rs = fail(TMC_ERR_HIP, "event record"); break; }
+      for (int r = 0; r < reps && rs == TMC_OK; ++r) rs = run();
+      if (rs != TMC_OK) break;
+      if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rs = fail(TMC_ERR_HIP, "event synchronise");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        best_t = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P->timing = was_timing;
+    P->fused.tune = best_t;
+    fused_set_grids(P->fused);
+    if (rs != TMC_OK) return rs;
+    P->fused.tuned = true;
+    tune_cache_store(P);
+    return tmc_plan_check(plan, stream);
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
 }
 
 tmc_status tmc_plan_set_timing(tmc_plan_t plan, int enable) {

@@ -57,7 +57,7 @@ struct ChainDev {
 struct WsLayout {
   size_t alpha, p, rl, pairM, logp, wmax;
   size_t wf, wg, gtz, dsp;          // plain engine (dsp shared)
-  size_t ev, lam, q;                // fused engine
+  size_t ev, lam, q, cnt;           // fused engine (cnt: int counters of persistent launches)
   size_t total;
 };
 

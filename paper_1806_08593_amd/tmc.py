@@ -61,7 +61,8 @@ class tmc_problem(ctypes.Structure):
 class tmc_plan_info(ctypes.Structure):
     _fields_ = [("factor_entries", c_int64), ("workspace_bytes", c_int64), ("engine", c_int32),
                 ("precision", c_int32), ("max_depth", c_int32), ("tile_rows", c_int32),
-                ("tile_cols", c_int32), ("waves_per_group", c_int32)]
+                ("tile_cols", c_int32), ("waves_per_group", c_int32), ("persistent", c_int32),
+                ("tuned", c_int32)]
 
 
 _P = c_void_p
@@ -84,6 +85,7 @@ _SIGS = {
     "tmc_plan_graph_launch": (c_int, [_P, c_int, _P]),
     "tmc_plan_set_timing": (c_int, [_P, c_int]),
     "tmc_plan_timing": (c_int, [_P, c_int, POINTER(c_double), POINTER(c_int64)]),
+    "tmc_plan_autotune": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -216,6 +218,13 @@ def tmc_plan_timing(plan, kc: int):
     ms, n = c_double(), c_int64()
     _check(_lib.tmc_plan_timing(plan, kc, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def tmc_plan_autotune(plan, z, mu, s, u, dlogp, workspace, dz=None, dmu=None, ds=None, du=None,
+                      reps: int = 3, stream=None):
+    _check(_lib.tmc_plan_autotune(plan, _ptr(z), _ptr(mu), _ptr(s), _ptr(u), _ptr(dlogp),
+                                  _ptr(workspace), _ptr(dz), _ptr(dmu), _ptr(ds), _ptr(du), reps,
+                                  _stream(stream)))
 
 
 # ---------------------------------------------------------------------------

@@ -40,6 +40,8 @@ MUTATIONS = [
      P.test_gauss_gradients_against_finite_differences),
     ("linear_gauss_log_evidence", "sigma_x ** 2", "sigma_x", P.test_linear_gauss_evidence_against_quadrature),
     ("hmm_log_evidence", "v = T @ v", "v = T.T @ v", P.test_hmm_evidence_by_enumeration),
+    ("gauss_layer0_row_grads", "- log_k(K1) - logp)", "- logp)",
+     P.test_layer0_row_grads_agree_with_full_marginals),
 ]
 
 

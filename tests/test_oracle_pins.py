@@ -310,3 +310,20 @@ def test_gauss_gradients_against_finite_differences():
         fd = O.finite_difference(lambda a: O.gauss_chain_logp(z, mu, with_(s, l, a), u), s[l])
         np.testing.assert_allclose(ds[l], fd, atol=2e-7)
     assert np.all(dz[L - 1] == 0)
+
+
+def test_layer0_row_grads_agree_with_full_marginals():
+    """The spot-check routine for large chains gives the same dz_0 and du_0 rows as the
+    full forward-backward gradients (and the same log P)."""
+    rng = np.random.default_rng(11)
+    Ks, Ds = (9, 7, 5), (4, 3, 2)
+    z = [rng.normal(size=(Ks[l], Ds[l])) for l in range(3)]
+    mu = [rng.normal(size=(Ks[l + 1], Ds[l])) for l in range(2)]
+    s = [rng.uniform(-1, 0, size=Ds[l]) for l in range(2)]
+    u = [rng.normal(size=Ks[l]) for l in range(3)]
+    lp, dz, dmu, ds, du = O.gauss_chain_grads(z, mu, s, u)
+    rows = [0, 3, 8]
+    lp2, dz_r, du_r = O.gauss_layer0_row_grads(z, mu, s, u, rows)
+    assert abs(lp - lp2) < 1e-12
+    assert np.allclose(dz_r, dz[0][rows], rtol=1e-12, atol=1e-14)
+    assert np.allclose(du_r, du[0][rows], rtol=1e-12, atol=1e-14)
