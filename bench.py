@@ -74,10 +74,10 @@ def upload(w, prec, engine, flags=0):
     return prob, dev
 
 
-def run_mode(w, prec, engine, steps, warmup, timing):
+def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0):
     import torch
     from paper_1806_08593_amd import tmc as T
-    prob, d = upload(w, prec, engine)
+    prob, d = upload(w, prec, engine, flags)
     plan = T.Plan(prob)
     ws = plan.new_workspace()
     n = prob.n_chains
@@ -85,6 +85,10 @@ def run_mode(w, prec, engine, steps, warmup, timing):
     dlogp = torch.ones(n, dtype=torch.float64, device="cuda:0")
     g = {k: torch.empty_like(v) for k, v in d.items()}
     h = plan.handle
+    if tune and plan.info["engine"] == T.TMC_ENGINE_FUSED:
+        # the library's launch-shape tuner, outside the timed region
+        T.tmc_plan_autotune(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"], g["s"],
+                            g["u"], reps=3)
 
     def step():
         T.tmc_gauss_fwd(h, d["z"], d["mu"], d["s"], d["u"], logp, ws)
@@ -117,7 +121,7 @@ def run_mode(w, prec, engine, steps, warmup, timing):
         T.tmc_plan_set_timing(h, False)
     T.tmc_plan_check(h)
     out = dict(ms_per_step=(t1 - t0) * 1e3 / steps, event_ms_per_step=e0.elapsed_time(e1) / steps,
-               kernels=kc, logp=logp.cpu().numpy(), info=plan.info)
+               kernels=kc, logp=logp.cpu().numpy(), info=T.tmc_plan_info_get(h))
     plan.close()
     del d, g, ws
     torch.cuda.empty_cache()
@@ -151,6 +155,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the launch-shape tuner (per-depth launches unless --persistent)")
+    ap.add_argument("--persistent", action="store_true", help="persistent launches (with --no-tune)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="first copy this many MiB with a plain device copy (a known-size "
                          "kernel for scaling memory counters)")
@@ -182,7 +189,10 @@ def main():
 
     print(f"[bench] {prec}/{args.engine}: warmup {args.warmup}, timed {args.steps} steps",
           file=sys.stderr, flush=True)
-    main_run = run_mode(w, prec, args.engine, args.steps, args.warmup, timing=True)
+    from paper_1806_08593_amd import tmc as T
+    main_run = run_mode(w, prec, args.engine, args.steps, args.warmup, timing=True,
+                        tune=not args.no_tune,
+                        flags=T.TMC_FLAG_PERSISTENT if args.persistent else 0)
     ms_per_step = main_run["ms_per_step"]
     value = entries / (ms_per_step / 1e3)
     kc = main_run["kernels"]
@@ -206,7 +216,8 @@ def main():
                 continue
             try:
                 print(f"[bench] comparator {cp}/{ce}", file=sys.stderr, flush=True)
-                r = run_mode(w, cp, ce, max(3, args.steps // 3), 2, timing=False)
+                r = run_mode(w, cp, ce, max(3, args.steps // 3), 2, timing=False,
+                             tune=not args.no_tune and ce == "fused")
                 compare[f"{cp}_{ce}"] = dict(ms_per_step=r["ms_per_step"],
                                              value=entries / (r["ms_per_step"] / 1e3), logp=r["logp"])
             except Exception as e:   # e.g. a plain-engine workspace that does not fit
@@ -235,8 +246,11 @@ def main():
         if base:
             compare["speedup_over_fp32_plain"] = base / ms_per_step
 
+    info = main_run["info"]
     cfg = {"workload": args.workload, "chains": len(w.chains), "factor_entries": entries,
-           "precision": prec, "engine": ["auto", "fused", "plain"][main_run["info"]["engine"]],
+           "precision": prec, "engine": ["auto", "fused", "plain"][info["engine"]],
+           "launch": ("persistent" if info["persistent"] else "per-depth") +
+                     (" (tuned)" if info["tuned"] else ""),
            "parallelism": "single GPU"}
     if w.z is not None:
         B, L, K, D = w.z.shape

@@ -316,10 +316,19 @@ template <int NKC, int NS_>
 struct TilePrefetch {
   static constexpr int NS = NS_;
   static constexpr int NF = (NKC + 1) / 2;
-  float4 v[NS][NF];
+  float4 v[NS][NF];  // values; rows past `rem` and d past D are zeroed at the store
   double a[NS];      // column tiles: alpha_{l+1}[j]
-  float lam;         // row tiles: row shift of row t % (32 NS)
+  float lam;         // row tiles: row shift of row t % (32 NS) (+inf applied at the store)
+  int rem;           // rows of the stage that exist, counted from its first row
 };
+
+// (valid and d + e < D) ? v.e : 0 for the four values of a float4 at d
+__device__ __forceinline__ void mask_f4(const float4& v, int d, int D, bool valid, float (&x)[4]) {
+  x[0] = (valid && d + 0 < D) ? v.x : 0.0f;
+  x[1] = (valid && d + 1 < D) ? v.y : 0.0f;
+  x[2] = (valid && d + 2 < D) ? v.z : 0.0f;
+  x[3] = (valid && d + 3 < D) ? v.w : 0.0f;
+}
 
 // Column tiles of pair L: mu rows r0.. (samples of layer l+1) and their alpha.
 template <int NKC, int NS>
@@ -328,8 +337,10 @@ __device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS>& pf, const Laye
                                            const double* __restrict__ alpha, int r0) {
   const int t = threadIdx.x, sub = t & 7;
   const bool vec = (L.D % 4 == 0) && (L.mu_off % 4 == 0);
+  pf.rem = L.Kc - r0;
   if (vec) {
-    // all loads of the stage first, then the padding zeros
+    // loads only (clamped into the block): the values are not used until the stage is
+    // written to LDS, so the loads stay in flight across the compute of the current tile
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) {
       const int gc = min(r0 + 32 * sb + (t >> 3), L.Kc - 1);
@@ -338,16 +349,6 @@ __device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS>& pf, const Laye
       for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
         pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(4 * (sub + 8 * m), L.D - 4));
       pf.a[sb] = alpha[L.alpha_up_off + gc];
-    }
-#pragma unroll
-    for (int sb = 0; sb < NS; ++sb) {
-      const bool valid = r0 + 32 * sb + (t >> 3) < L.Kc;
-#pragma unroll
-      for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m) {
-        const bool v = valid && 4 * (sub + 8 * m) < L.D;
-        float4& r = pf.v[sb][m];
-        r.x = v ? r.x : 0.0f; r.y = v ? r.y : 0.0f; r.z = v ? r.z : 0.0f; r.w = v ? r.w : 0.0f;
-      }
     }
     return;
   }
@@ -372,8 +373,9 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
   const int t = threadIdx.x, sub = t & 7;
   const bool vec = (L.D % 4 == 0) && (L.z_off % 4 == 0);
   const int rr = r0 + (t & (32 * NS - 1));
+  pf.rem = L.K - r0;
   if (vec) {
-    // all loads of the stage first, then the padding zeros
+    // loads only (see fetch_cols)
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) {
       const int gr = min(r0 + 32 * sb + (t >> 3), L.K - 1);
@@ -382,18 +384,7 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
       for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
         pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(4 * (sub + 8 * m), L.D - 4));
     }
-    const float lv = lamrow[min(rr, L.K - 1)];
-#pragma unroll
-    for (int sb = 0; sb < NS; ++sb) {
-      const bool valid = r0 + 32 * sb + (t >> 3) < L.K;
-#pragma unroll
-      for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m) {
-        const bool v = valid && 4 * (sub + 8 * m) < L.D;
-        float4& r = pf.v[sb][m];
-        r.x = v ? r.x : 0.0f; r.y = v ? r.y : 0.0f; r.z = v ? r.z : 0.0f; r.w = v ? r.w : 0.0f;
-      }
-    }
-    pf.lam = (rr < L.K) ? lv : INFINITY;
+    pf.lam = lamrow[min(rr, L.K - 1)];
     return;
   }
 #pragma unroll
@@ -413,17 +404,19 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
 // x; d-major copy (when the layout has one) = x.
 template <class TS, int NKC>
 __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC, TS::NS>& pf,
-                                           bool scale) {
+                                           int D, bool scale) {
   const int t = threadIdx.x, r = t >> 3, sub = t & 7;
   const int pr = tile_perm(r);
 #pragma unroll
   for (int sb = 0; sb < TS::NS; ++sb) {
+    const bool valid = 32 * sb + r < pf.rem;
 #pragma unroll
     for (int m = 0; m < TilePrefetch<NKC, TS::NS>::NF; ++m) {
       const int k = sub + 8 * m;
       if (k >= TS::DP / 4) break;
       const int d = 4 * k;
-      const float x[4] = {pf.v[sb][m].x, pf.v[sb][m].y, pf.v[sb][m].z, pf.v[sb][m].w};
+      float x[4];
+      mask_f4(pf.v[sb][m], d, D, valid, x);
       const int ro = sb * TS::ROWN + r * TS::RS + d;
       const int co = sb * TS::COLN + d * TS::CS + pr;
       if constexpr (TS::BF) {
@@ -471,15 +464,17 @@ __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC,
 // complete in all 8 threads serving the row (fixed reduction order).
 template <class TS, int NKC>
 __device__ __forceinline__ double tile_colq(const TS& T, const TilePrefetch<NKC, TS::NS>& pf,
-                                            int sb) {
+                                            int D, int sb) {
   const int sub = threadIdx.x & 7;
+  const bool valid = 32 * sb + (threadIdx.x >> 3) < pf.rem;
   double q = 0.0;
 #pragma unroll
   for (int m = 0; m < TilePrefetch<NKC, TS::NS>::NF; ++m) {
     const int k = sub + 8 * m;
     if (k >= TS::DP / 4) break;
     const int d = 4 * k;
-    const float x[4] = {pf.v[sb][m].x, pf.v[sb][m].y, pf.v[sb][m].z, pf.v[sb][m].w};
+    float x[4];
+    mask_f4(pf.v[sb][m], d, D, valid, x);
 #pragma unroll
     for (int e = 0; e < 4; ++e) q += (double)T.lamf[d + e] * (double)x[e] * (double)x[e];
   }
@@ -627,11 +622,11 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   // workgroup that starts at row 0 stores them for the backward.
   const bool qwriter = GRAD && it.start == 0;
   auto stage = [&](int b, int j0) {
-    tile_store<TS, NKC>(T, b, pf, false);
+    tile_store<TS, NKC>(T, b, pf, L.D, false);
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) {
       const int j = j0 + 32 * sb + (tid >> 3);
-      const double qj = tile_colq<TS, NKC>(T, pf, sb);
+      const double qj = tile_colq<TS, NKC>(T, pf, L.D, sb);
       if ((tid & 7) == 0) T.gam[b][32 * sb + (tid >> 3)] = col_gamma(qj, pf.a[sb], j, L.Kc, maxa);
       if (qwriter && (tid & 7) == 0 && j < L.Kc) qcol[L.q_off + j] = qj;
     }
@@ -803,7 +798,8 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
   for (;;) {
     if (threadIdx.x == 0) s_k = atomicAdd(q.head, 1);
     __syncthreads();
-    const int k = s_k;
+    // uniform across the workgroup: keep it (and all that derives from it) scalar
+    const int k = __builtin_amdgcn_readfirstlane(s_k);
     __syncthreads();
     if (k >= q.n) return;
     const ChainDev ch = q.cd[q.chains[k]];
@@ -882,8 +878,8 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   const float g32 = (float)gl;
 
   auto stage = [&](int b) {
-    tile_store<TS, NKC>(T, b, pf, true);
-    if (tid < 32 * NS) T.lamT[b][tid] = pf.lam;
+    tile_store<TS, NKC>(T, b, pf, L.D, true);
+    if (tid < 32 * NS) T.lamT[b][tid] = (tid < pf.rem) ? pf.lam : INFINITY;
   };
   stage(0);
   if (nt > 1) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS);
@@ -1067,7 +1063,8 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd_persist(B
   for (;;) {
     if (threadIdx.x == 0) s_k = atomicAdd(q.head, 1);
     __syncthreads();
-    const int k = s_k;
+    // uniform across the workgroup: keep it (and all that derives from it) scalar
+    const int k = __builtin_amdgcn_readfirstlane(s_k);
     __syncthreads();
     if (k >= q.n) return;
     const ChainDev ch = q.cd[q.chains[k]];
