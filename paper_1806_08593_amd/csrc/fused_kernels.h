@@ -39,7 +39,12 @@ namespace tmc {
 namespace fused {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kLn2 = 0.69314718055994530942;
@@ -82,6 +87,49 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Two values split at once: x = hi + lo with hi = bf16(x) (nearest even) and
+// lo = bf16(x - hi); each plane packs the pair (first value in the low half), so one
+// conversion instruction serves two values and hi is widened back by bit operations.
+__device__ __forceinline__ void split2(float a, float b, uint32_t& hi, uint32_t& lo) {
+  const uint32_t hu = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+  const float ha = __uint_as_float(hu << 16), hb = __uint_as_float(hu & 0xffff0000u);
+  hi = hu;
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a - ha, b - hb}, bf16x2));
+}
+
+// v combined with the value of lane (l xor 32): the permlane swap hands every lane
+// the pair {x[l % 32], x[l % 32 + 32]}; sum and max are symmetric in the pair, so
+// both halves of the wave get the identical result.
+__device__ __forceinline__ float xor32_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xor32_max(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+
+// v + (the value of lane l xor m) for m = 1, 2 (quad permutes) and 4 (swizzle), FP64:
+// a butterfly over 8 lanes built from these leaves the same sum in all 8.
+template <int M>
+__device__ __forceinline__ double xor_add_f64(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  int lo2, hi2;
+  if constexpr (M == 1) {
+    lo2 = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    hi2 = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+  } else if constexpr (M == 2) {
+    lo2 = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    hi2 = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+  } else {
+    static_assert(M == 4, "xor 1, 2 or 4");
+    lo2 = __builtin_amdgcn_ds_swizzle(lo, 0x1F | (4 << 10));      // bitmask mode, xor 4
+    hi2 = __builtin_amdgcn_ds_swizzle(hi, 0x1F | (4 << 10));
+  }
+  return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi2 << 32) | (uint32_t)lo2);
+}
+
 template <int PREC>
 struct Frag;
 template <>
@@ -99,12 +147,11 @@ __device__ __forceinline__ void make_frag(const float (&x)[8], Frag<PREC>& f) {
 #pragma unroll
     for (int s = 0; s < 8; ++s) f.x[s] = x[s];
   } else {
+    uint32_t h[4], l[4];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const __bf16 h = (__bf16)x[s];
-      f.hi[s] = h;
-      f.lo[s] = (__bf16)(x[s] - (float)h);
-    }
+    for (int p = 0; p < 4; ++p) split2(x[2 * p], x[2 * p + 1], h[p], l[p]);
+    f.hi = __builtin_bit_cast(bf16x8, (u32x4){h[0], h[1], h[2], h[3]});
+    f.lo = __builtin_bit_cast(bf16x8, (u32x4){l[0], l[1], l[2], l[3]});
   }
 }
 
@@ -284,6 +331,7 @@ struct TileSmem {
   typedef typename std::conditional<BF, __bf16, float>::type E;
   E row[NB][NPL][NS * ROWN];
   E col[NB][NPL][COLSZ];
+  __attribute__((aligned(16))) double lamd[DP];   // lam_d in FP64 (column norms)
   float lamf[DP];        // lam_d = exp(-2 s_d)            (0 past D)
   float lam2[DP];        // log2(e) * lam_d
   float gam[NB][NS * 32];   // column terms of the staged tiles (forward)
@@ -304,6 +352,7 @@ __device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const PairPr
     const float lf = d < L.D ? expf(-2.0f * P.slam) : 0.0f;
     T.lamf[d] = lf;
     T.lam2[d] = lf * kLog2e;
+    T.lamd[d] = (double)lf;
   }
   if constexpr (TS::COL)
     for (int e = threadIdx.x; e < TS::NB * TS::NPL * TS::COLSZ; e += blockDim.x)
@@ -401,15 +450,19 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
 }
 
 // Writes fetched tiles to LDS buffer b: row-major copy = x * lam2 when `scale`, else
-// x; d-major copy (when the layout has one) = x.
-template <class TS, int NKC>
+// x; d-major copy (when the layout has one) = x.  With Q, also the column norms of the
+// staged rows, q[sb] = -1/2 sum_d lam_d x_d^2 (FP64, lane-strided partial sums in
+// increasing d, then a butterfly over the 8 threads of the row: complete and identical
+// in all 8).
+template <class TS, int NKC, bool Q>
 __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC, TS::NS>& pf,
-                                           int D, bool scale) {
+                                           int D, bool scale, double (&q)[TS::NS]) {
   const int t = threadIdx.x, r = t >> 3, sub = t & 7;
   const int pr = tile_perm(r);
 #pragma unroll
   for (int sb = 0; sb < TS::NS; ++sb) {
     const bool valid = 32 * sb + r < pf.rem;
+    double qa = 0.0;
 #pragma unroll
     for (int m = 0; m < TilePrefetch<NKC, TS::NS>::NF; ++m) {
       const int k = sub + 8 * m;
@@ -417,35 +470,36 @@ __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC,
       const int d = 4 * k;
       float x[4];
       mask_f4(pf.v[sb][m], d, D, valid, x);
+      if constexpr (Q) {
+        const double2 la = *reinterpret_cast<const double2*>(&T.lamd[d]);
+        const double2 lb = *reinterpret_cast<const double2*>(&T.lamd[d + 2]);
+        qa += la.x * (double)x[0] * (double)x[0];
+        qa += la.y * (double)x[1] * (double)x[1];
+        qa += lb.x * (double)x[2] * (double)x[2];
+        qa += lb.y * (double)x[3] * (double)x[3];
+      }
       const int ro = sb * TS::ROWN + r * TS::RS + d;
       const int co = sb * TS::COLN + d * TS::CS + pr;
       if constexpr (TS::BF) {
-        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-        bf16x4 xh, xl;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const __bf16 hb = (__bf16)x[e];
-          xh[e] = hb;
-          xl[e] = (__bf16)(x[e] - (float)hb);
-        }
+        uint32_t xh[2], xl[2];
+        split2(x[0], x[1], xh[0], xl[0]);
+        split2(x[2], x[3], xh[1], xl[1]);
         if constexpr (TS::COL) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            T.col[b][0][co + e * TS::CS] = xh[e];
-            T.col[b][1][co + e * TS::CS] = xl[e];
+            T.col[b][0][co + e * TS::CS] =
+                __builtin_bit_cast(__bf16, (uint16_t)(xh[e >> 1] >> (16 * (e & 1))));
+            T.col[b][1][co + e * TS::CS] =
+                __builtin_bit_cast(__bf16, (uint16_t)(xl[e >> 1] >> (16 * (e & 1))));
           }
         }
         if (scale) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float y = x[e] * T.lam2[d + e];
-            const __bf16 hb = (__bf16)y;
-            xh[e] = hb;
-            xl[e] = (__bf16)(y - (float)hb);
-          }
+          const float4 l2 = *reinterpret_cast<const float4*>(&T.lam2[d]);
+          split2(x[0] * l2.x, x[1] * l2.y, xh[0], xl[0]);
+          split2(x[2] * l2.z, x[3] * l2.w, xh[1], xl[1]);
         }
-        *reinterpret_cast<bf16x4*>(&T.row[b][0][ro]) = xh;
-        *reinterpret_cast<bf16x4*>(&T.row[b][1][ro]) = xl;
+        *reinterpret_cast<bf16x4*>(&T.row[b][0][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xh[0], xh[1]});
+        *reinterpret_cast<bf16x4*>(&T.row[b][1][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xl[0], xl[1]});
       } else {
         if constexpr (TS::COL) {
 #pragma unroll
@@ -457,31 +511,13 @@ __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC,
         *reinterpret_cast<float4*>(&T.row[b][0][ro]) = make_float4(y[0], y[1], y[2], y[3]);
       }
     }
+    if constexpr (Q) {
+      qa = xor_add_f64<1>(qa);
+      qa = xor_add_f64<2>(qa);
+      qa = xor_add_f64<4>(qa);
+      q[sb] = -0.5 * qa;
+    }
   }
-}
-
-// q_j = -1/2 sum_d lam_d mu_jd^2 (FP64) of the fetched column row of subtile sb,
-// complete in all 8 threads serving the row (fixed reduction order).
-template <class TS, int NKC>
-__device__ __forceinline__ double tile_colq(const TS& T, const TilePrefetch<NKC, TS::NS>& pf,
-                                            int D, int sb) {
-  const int sub = threadIdx.x & 7;
-  const bool valid = 32 * sb + (threadIdx.x >> 3) < pf.rem;
-  double q = 0.0;
-#pragma unroll
-  for (int m = 0; m < TilePrefetch<NKC, TS::NS>::NF; ++m) {
-    const int k = sub + 8 * m;
-    if (k >= TS::DP / 4) break;
-    const int d = 4 * k;
-    float x[4];
-    mask_f4(pf.v[sb][m], d, D, valid, x);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) q += (double)T.lamf[d + e] * (double)x[e] * (double)x[e];
-  }
-  q += __shfl_xor(q, 1, kWave);
-  q += __shfl_xor(q, 2, kWave);
-  q += __shfl_xor(q, 4, kWave);
-  return -0.5 * q;
 }
 
 // gamma_j = log2(e) (q_j + alpha_{l+1}[j] - maxa), -inf past Kc.
@@ -622,11 +658,12 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   // workgroup that starts at row 0 stores them for the backward.
   const bool qwriter = GRAD && it.start == 0;
   auto stage = [&](int b, int j0) {
-    tile_store<TS, NKC>(T, b, pf, L.D, false);
+    double qs[NS];
+    tile_store<TS, NKC, true>(T, b, pf, L.D, false, qs);
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) {
       const int j = j0 + 32 * sb + (tid >> 3);
-      const double qj = tile_colq<TS, NKC>(T, pf, L.D, sb);
+      const double qj = qs[sb];
       if ((tid & 7) == 0) T.gam[b][32 * sb + (tid >> 3)] = col_gamma(qj, pf.a[sb], j, L.Kc, maxa);
       if (qwriter && (tid & 7) == 0 && j < L.Kc) qcol[L.q_off + j] = qj;
     }
@@ -679,7 +716,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
         for (int v = 0; v < 16; ++v) tmax = fmaxf(tmax, x[sb][v]);
-      tmax = fmaxf(tmax, __shfl_xor(tmax, 32, kWave));
+      tmax = xor32_max(tmax);
       const bool need = tmax > m + kRescale;
       if (__any(need)) {
         const float mn = need ? tmax : m;
@@ -725,7 +762,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       lds_barrier();
     }
   }
-  const float stot = ssum + __shfl_xor(ssum, 32, kWave);
+  const float stot = xor32_sum(ssum);
   float ell;
   if (m != m || stot != stot) ell = NAN;
   else if (m == -INFINITY || stot == 0.0f) ell = -INFINITY;
@@ -878,7 +915,8 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   const float g32 = (float)gl;
 
   auto stage = [&](int b) {
-    tile_store<TS, NKC>(T, b, pf, L.D, true);
+    double qs[NS];
+    tile_store<TS, NKC, false>(T, b, pf, L.D, true, qs);
     if (tid < 32 * NS) T.lamT[b][tid] = (tid < pf.rem) ? pf.lam : INFINITY;
   };
   stage(0);
@@ -948,7 +986,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   }
 
   // ---- column epilogue: marginals of layer l+1, dmu, column part of ds ----
-  const float ctot = csum + __shfl_xor(csum, 32, kWave);
+  const float ctot = xor32_sum(csum);
   const bool jv = active && j < L.Kc;
   if (jv && h == 0) {
     p[L.p_up_off + j] = ctot;
