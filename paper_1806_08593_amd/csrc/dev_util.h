@@ -1,4 +1,4 @@
-// Device helpers: NaN-propagating max and wave64 / workgroup reductions.
+// Device helpers: NaN-propagating max, wave64 / workgroup reductions, an optimizer barrier.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,6 +8,13 @@ namespace tmc {
 
 constexpr int kWave = 64;
 constexpr int kMaxWaves = 16;
+
+// v, hidden from the optimizer: values computed from it are not hoisted out of loops
+// (keeps loop-invariant address arithmetic from occupying registers across a loop).
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
 
 // max that returns NaN if either argument is NaN (fmax would drop it).
 template <typename T>

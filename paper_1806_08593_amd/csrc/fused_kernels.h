@@ -130,6 +130,20 @@ __device__ __forceinline__ double xor_add_f64(double v) {
   return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi2 << 32) | (uint32_t)lo2);
 }
 
+// Scheduling hint for a block that holds a chain of N dependent MFMAs and independent
+// staging work: one MFMA, then an LDS read, a few VALU instructions and LDS writes, N
+// times, so that the staging issues while the matrix core works through the chain.
+template <int N>
+__device__ __forceinline__ void interleave_mfma() {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+    __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);   // VALU
+    __builtin_amdgcn_sched_group_barrier(0x200, 2, 0);   // LDS write
+  }
+}
+
 template <int PREC>
 struct Frag;
 template <>
@@ -321,19 +335,20 @@ struct TileSmem {
   static constexpr bool COL = COL_;
   static constexpr int DP = NKC * 16;               // padded width
   static constexpr int ND32 = (NKC + 1) / 2;        // 32-wide d blocks
-  static constexpr int DT = ND32 * 32;              // rows of the d-major copy
+  static constexpr int DT = ND32 * 32;              // rows of the d-major copy; also the
+                                                    // d span the staging threads cover
   static constexpr bool BF = PREC == TMC_BF16X3;
   static constexpr int NPL = BF ? 2 : 1;
-  static constexpr int RS = BF ? DP + 8 : DP + 4;   // row stride (elements)
+  static constexpr int RS = BF ? DT + 8 : DT + 4;   // row stride (elements)
   static constexpr int CS = BF ? 40 : 36;           // d-major stride (elements)
   static constexpr int ROWN = 32 * RS, COLN = DT * CS;
   static constexpr int COLSZ = COL ? NS * COLN : 2;
   typedef typename std::conditional<BF, __bf16, float>::type E;
   E row[NB][NPL][NS * ROWN];
   E col[NB][NPL][COLSZ];
-  __attribute__((aligned(16))) double lamd[DP];   // lam_d in FP64 (column norms)
-  float lamf[DP];        // lam_d = exp(-2 s_d)            (0 past D)
-  float lam2[DP];        // log2(e) * lam_d
+  __attribute__((aligned(16))) double lamd[DT];   // lam_d in FP64 (column norms)
+  float lamf[DT];        // lam_d = exp(-2 s_d)            (0 past D)
+  float lam2[DT];        // log2(e) * lam_d
   float gam[NB][NS * 32];   // column terms of the staged tiles (forward)
   float lamT[NB][NS * 32];  // row shifts of the staged tiles (backward)
   double wm[4];          // per-wave maxima of alpha (forward)
@@ -343,41 +358,33 @@ __device__ __forceinline__ int tile_perm(int r) {
   return (r & 0x13) | ((r & 4) << 1) | ((r & 8) >> 1);
 }
 
-// lam into LDS (thread d holds s_d, DP <= blockDim) and zeros over the d-major copies
-// (their rows past DP stay zero).
+// lam into LDS (thread d holds s_d, DT <= blockDim; zeros past D).
 template <class TS>
 __device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const PairPre& P) {
   const int d = threadIdx.x;
-  if (d < TS::DP) {
+  if (d < TS::DT) {
     const float lf = d < L.D ? expf(-2.0f * P.slam) : 0.0f;
     T.lamf[d] = lf;
     T.lam2[d] = lf * kLog2e;
     T.lamd[d] = (double)lf;
   }
-  if constexpr (TS::COL)
-    for (int e = threadIdx.x; e < TS::NB * TS::NPL * TS::COLSZ; e += blockDim.x)
-      (&T.col[0][0][0])[e] = (typename TS::E)0.0f;
 }
 
 // Register stage of NS tiles (blockDim 256): thread t serves row t / 8 of every
-// subtile and float4 columns 4 (t % 8 + 8 m).  Rows >= nvalid and d >= D read as zero.
+// subtile and float4 columns 4 (t % 8 + 8 m), d < DT.  Slots past the data -- rows
+// past the block's end, d >= D -- hold zeros (unaligned path) or copies of real values
+// of the block (aligned path: clamped addresses).  Either is harmless: such d meet an
+// exact zero (lam_d = 0, zero padding of the register operand) or land in outputs that
+// are discarded, and such rows get a -inf shift (gamma_j, or Lam_i = +inf).
 template <int NKC, int NS_>
 struct TilePrefetch {
   static constexpr int NS = NS_;
   static constexpr int NF = (NKC + 1) / 2;
-  float4 v[NS][NF];  // values; rows past `rem` and d past D are zeroed at the store
+  float4 v[NS][NF];
   double a[NS];      // column tiles: alpha_{l+1}[j]
   float lam;         // row tiles: row shift of row t % (32 NS) (+inf applied at the store)
   int rem;           // rows of the stage that exist, counted from its first row
 };
-
-// (valid and d + e < D) ? v.e : 0 for the four values of a float4 at d
-__device__ __forceinline__ void mask_f4(const float4& v, int d, int D, bool valid, float (&x)[4]) {
-  x[0] = (valid && d + 0 < D) ? v.x : 0.0f;
-  x[1] = (valid && d + 1 < D) ? v.y : 0.0f;
-  x[2] = (valid && d + 2 < D) ? v.z : 0.0f;
-  x[3] = (valid && d + 3 < D) ? v.w : 0.0f;
-}
 
 // Column tiles of pair L: mu rows r0.. (samples of layer l+1) and their alpha.
 template <int NKC, int NS>
@@ -396,7 +403,7 @@ __device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS>& pf, const Laye
       const float* rowp = mu + L.mu_off + (int64_t)gc * L.D;
 #pragma unroll
       for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(4 * (sub + 8 * m), L.D - 4));
+        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(opaque(4 * (sub + 8 * m)), L.D - 4));
       pf.a[sb] = alpha[L.alpha_up_off + gc];
     }
     return;
@@ -409,7 +416,7 @@ __device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS>& pf, const Laye
     const float* rowp = mu + L.mu_off + (int64_t)gc * L.D;
 #pragma unroll
     for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-      pf.v[sb][m] = load_f4(rowp, 4 * (sub + 8 * m), L.D, valid, false);
+      pf.v[sb][m] = load_f4(rowp, opaque(4 * (sub + 8 * m)), L.D, valid, false);
     pf.a[sb] = alpha[L.alpha_up_off + gc];
   }
 }
@@ -431,7 +438,7 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
       const float* rowp = z + L.z_off + (int64_t)gr * L.D;
 #pragma unroll
       for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(4 * (sub + 8 * m), L.D - 4));
+        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(opaque(4 * (sub + 8 * m)), L.D - 4));
     }
     pf.lam = lamrow[min(rr, L.K - 1)];
     return;
@@ -443,7 +450,7 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
     const float* rowp = z + L.z_off + (int64_t)(valid ? gr : L.K - 1) * L.D;
 #pragma unroll
     for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-      pf.v[sb][m] = load_f4(rowp, 4 * (sub + 8 * m), L.D, valid, false);
+      pf.v[sb][m] = load_f4(rowp, opaque(4 * (sub + 8 * m)), L.D, valid, false);
   }
   const float lv = lamrow[min(rr, L.K - 1)];
   pf.lam = (rr < L.K) ? lv : INFINITY;
@@ -456,20 +463,18 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
 // in all 8).
 template <class TS, int NKC, bool Q>
 __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC, TS::NS>& pf,
-                                           int D, bool scale, double (&q)[TS::NS]) {
+                                           bool scale, double (&q)[TS::NS]) {
   const int t = threadIdx.x, r = t >> 3, sub = t & 7;
   const int pr = tile_perm(r);
 #pragma unroll
   for (int sb = 0; sb < TS::NS; ++sb) {
-    const bool valid = 32 * sb + r < pf.rem;
     double qa = 0.0;
 #pragma unroll
     for (int m = 0; m < TilePrefetch<NKC, TS::NS>::NF; ++m) {
-      const int k = sub + 8 * m;
-      if (k >= TS::DP / 4) break;
-      const int d = 4 * k;
-      float x[4];
-      mask_f4(pf.v[sb][m], d, D, valid, x);
+      // d < DT always (the row stride and the lam tables cover DT, so no thread
+      // branches here); slots past the data are harmless (see TilePrefetch)
+      const int d = 4 * (sub + 8 * m);
+      const float x[4] = {pf.v[sb][m].x, pf.v[sb][m].y, pf.v[sb][m].z, pf.v[sb][m].w};
       if constexpr (Q) {
         const double2 la = *reinterpret_cast<const double2*>(&T.lamd[d]);
         const double2 lb = *reinterpret_cast<const double2*>(&T.lamd[d + 2]);
@@ -601,6 +606,10 @@ __device__ __forceinline__ void wave_load(const float* __restrict__ base, int64_
 //   alpha_i = u_i + r_i + c + maxa + ln2 * ell_i - ln K_{l+1}
 //   e_i     = sum_j softmax_j(S_ij + gamma_j) mu_j        (GRAD: used for dz)
 // ---------------------------------------------------------------------------
+// MFMAs of one 32-column (32-row) tile's factor GEMM per subtile
+template <int PREC, int NKC>
+constexpr int kGemmMfma = NKC * (PREC == TMC_BF16X3 ? 3 : 8);
+
 template <int PREC, int NKC, bool GRAD, int NS>
 using FwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), GRAD>;
 
@@ -657,18 +666,28 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   // The forward computes the column norms q_j (FP64) of every column it stages; the
   // workgroup that starts at row 0 stores them for the backward.
   const bool qwriter = GRAD && it.start == 0;
-  auto stage = [&](int b, int j0) {
-    double qs[NS];
-    tile_store<TS, NKC, true>(T, b, pf, L.D, false, qs);
+  // Stages the fetched columns j0.. into buffer b; the 8 threads of a row hold the same
+  // norm and write the same gamma.  The norms are returned for the q store, which is
+  // kept apart (a divergent store would split the block the stage is scheduled in).
+  auto stage = [&](int b, int j0, double (&qs)[NS]) {
+    tile_store<TS, NKC, true>(T, b, pf, false, qs);
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb)
+      T.gam[b][32 * sb + (tid >> 3)] =
+          col_gamma(qs[sb], pf.a[sb], j0 + 32 * sb + (tid >> 3), L.Kc, maxa);
+  };
+  auto store_q = [&](int j0, const double (&qs)[NS]) {
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) {
       const int j = j0 + 32 * sb + (tid >> 3);
-      const double qj = qs[sb];
-      if ((tid & 7) == 0) T.gam[b][32 * sb + (tid >> 3)] = col_gamma(qj, pf.a[sb], j, L.Kc, maxa);
-      if (qwriter && (tid & 7) == 0 && j < L.Kc) qcol[L.q_off + j] = qj;
+      if (qwriter && (tid & 7) == 0 && j < L.Kc) qcol[L.q_off + j] = qs[sb];
     }
   };
-  stage(0, 0);
+  {
+    double qs[NS];
+    stage(0, 0, qs);
+    store_q(0, qs);
+  }
   if (nt > 1) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS);
   lds_barrier();
 
@@ -679,88 +698,127 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
 #pragma unroll
     for (int v = 0; v < 16; ++v) O[q][v] = 0.0f;
 
-  for (int t = 0; t < nt; ++t) {
-    const int cur = (NB == 2) ? (t & 1) : 0;
-    if (NB == 2 && t + 1 < nt) {
-      stage(cur ^ 1, 32 * NS * (t + 1));
-      if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
-    }
-    if (active) {
-      f32x16 S[NS];
+  // S[j][i] over the staged tile in buffer cur
+  auto s_gemm = [&](auto bc, f32x16 (&S)[NS]) {
+    constexpr int cur = decltype(bc)::value;
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb)
+    for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) S[sb][v] = 0.0f;
+      for (int v = 0; v < 16; ++v) S[sb][v] = 0.0f;
 #pragma unroll
-      for (int kc = 0; kc < NKC; ++kc)
+    for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
-        for (int sb = 0; sb < NS; ++sb) {
-          Frag<PREC> Bf;
-          tile_row_frag<TS, PREC>(T, cur, sb, kc, Bf);
-          mma_chunk<PREC>(S[sb], Bf, A[kc]);     // S[j][i]
-        }
-      float x[NS][16];
-      float tmax = -INFINITY;
-#pragma unroll
-      for (int sb = 0; sb < NS; ++sb)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 g4 = *reinterpret_cast<const float4*>(&T.gam[cur][32 * sb + 8 * q + 4 * h]);
-          x[sb][4 * q + 0] = S[sb][4 * q + 0] + g4.x;
-          x[sb][4 * q + 1] = S[sb][4 * q + 1] + g4.y;
-          x[sb][4 * q + 2] = S[sb][4 * q + 2] + g4.z;
-          x[sb][4 * q + 3] = S[sb][4 * q + 3] + g4.w;
-        }
-      // (a NaN entry is dropped by fmaxf here but reaches ssum through exp2 below)
-#pragma unroll
-      for (int sb = 0; sb < NS; ++sb)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) tmax = fmaxf(tmax, x[sb][v]);
-      tmax = xor32_max(tmax);
-      const bool need = tmax > m + kRescale;
-      if (__any(need)) {
-        const float mn = need ? tmax : m;
-        const float f = need ? ((m == -INFINITY) ? 0.0f : __builtin_amdgcn_exp2f(m - mn)) : 1.0f;
-        ssum *= f;
-        if (GRAD) {
-#pragma unroll
-          for (int q = 0; q < ND32; ++q)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) O[q][v] *= f;
-        }
-        m = mn;
+      for (int sb = 0; sb < NS; ++sb) {
+        Frag<PREC> Bf;
+        tile_row_frag<TS, PREC>(T, cur, sb, kc, Bf);
+        mma_chunk<PREC>(S[sb], Bf, A[kc]);     // S[j][i]
       }
-      const float msafe = (m == -INFINITY) ? 0.0f : m;
-      float p[NS][16];
-      float ps = 0.0f;
+  };
+  // online log-sum-exp over the tile and (GRAD) the softmax-weighted sum of mu
+  auto softmax_e = [&](auto bc, f32x16 (&S)[NS]) {
+    constexpr int cur = decltype(bc)::value;
+    float x[NS][16];
+    float tmax = -INFINITY;
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb)
+    for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          p[sb][v] = __builtin_amdgcn_exp2f(x[sb][v] - msafe);
-          ps += p[sb][v];
-        }
-      ssum += ps;
+      for (int q = 0; q < 4; ++q) {
+        const float4 g4 = *reinterpret_cast<const float4*>(&T.gam[cur][32 * sb + 8 * q + 4 * h]);
+        x[sb][4 * q + 0] = S[sb][4 * q + 0] + g4.x;
+        x[sb][4 * q + 1] = S[sb][4 * q + 1] + g4.y;
+        x[sb][4 * q + 2] = S[sb][4 * q + 2] + g4.z;
+        x[sb][4 * q + 3] = S[sb][4 * q + 3] + g4.w;
+      }
+    // (a NaN entry is dropped by fmaxf here but reaches ssum through exp2 below)
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) tmax = fmaxf(tmax, x[sb][v]);
+    tmax = xor32_max(tmax);
+    const bool need = tmax > m + kRescale;
+    if (__any(need)) {
+      const float mn = need ? tmax : m;
+      const float f = need ? ((m == -INFINITY) ? 0.0f : __builtin_amdgcn_exp2f(m - mn)) : 1.0f;
+      ssum *= f;
       if (GRAD) {
-        PFrag<PREC> P[NS];
-#pragma unroll
-        for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(p[sb], P[sb]);
 #pragma unroll
         for (int q = 0; q < ND32; ++q)
 #pragma unroll
-          for (int sb = 0; sb < NS; ++sb) {
-            TFrag<PREC> Tf;
-            tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
-            mma_t<PREC>(O[q], Tf, P[sb]);
-          }
+          for (int v = 0; v < 16; ++v) O[q][v] *= f;
+      }
+      m = mn;
+    }
+    const float msafe = (m == -INFINITY) ? 0.0f : m;
+    float p[NS][16];
+    float ps = 0.0f;
+#pragma unroll
+    for (int sb = 0; sb < NS; ++sb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        p[sb][v] = __builtin_amdgcn_exp2f(x[sb][v] - msafe);
+        ps += p[sb][v];
+      }
+    ssum += ps;
+    if (GRAD) {
+      PFrag<PREC> P[NS];
+#pragma unroll
+      for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(p[sb], P[sb]);
+#pragma unroll
+      for (int q = 0; q < ND32; ++q)
+#pragma unroll
+        for (int sb = 0; sb < NS; ++sb) {
+          TFrag<PREC> Tf;
+          tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+          mma_t<PREC>(O[q], Tf, P[sb]);
+        }
+    }
+  };
+  // One tile.  Double-buffered: the S MFMAs are issued first, and the next stage is
+  // written to the idle buffer behind them (straight-line code, so the scheduler can
+  // interleave the staging with the MFMAs); past the last tile that stage repeats data
+  // into a buffer that is never read again.
+  auto tile = [&](auto bc, int t) {
+    constexpr int cur = decltype(bc)::value;
+    if constexpr (NB == 2) {
+      double qs[NS];
+      if (active) {
+        f32x16 S[NS];
+        s_gemm(bc, S);
+        stage(cur ^ 1, 32 * NS * (t + 1), qs);
+        interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
+        if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
+        softmax_e(bc, S);
+      } else {
+        stage(cur ^ 1, 32 * NS * (t + 1), qs);
+        if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
+      }
+      store_q(32 * NS * (t + 1), qs);
+      lds_barrier();
+    } else {
+      if (active) {
+        f32x16 S[NS];
+        s_gemm(bc, S);
+        softmax_e(bc, S);
+      }
+      lds_barrier();
+      if (t + 1 < nt) {
+        double qs[NS];
+        stage(0, 32 * NS * (t + 1), qs);
+        store_q(32 * NS * (t + 1), qs);
+        if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
+        lds_barrier();
       }
     }
-    lds_barrier();
-    if (NB == 1 && t + 1 < nt) {
-      stage(0, 32 * NS * (t + 1));
-      if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
-      lds_barrier();
+  };
+  if constexpr (NB == 2) {
+    int t = 0;
+    for (; t + 1 < nt; t += 2) {
+      tile(std::integral_constant<int, 0>{}, t);
+      tile(std::integral_constant<int, 1>{}, t + 1);
     }
+    if (t < nt) tile(std::integral_constant<int, 0>{}, t);
+  } else {
+    for (int t = 0; t < nt; ++t) tile(std::integral_constant<int, 0>{}, t);
   }
   const float stot = xor32_sum(ssum);
   float ell;
@@ -914,10 +972,13 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   const float gj = col_gamma(qj, aj, j, L.Kc, maxa);
   const float g32 = (float)gl;
 
+  // Stages the fetched rows into buffer b.  Threads t and t + 32 NS hold the shift of
+  // the same row, so every thread writes (equal values to equal slots, no branch).
   auto stage = [&](int b) {
     double qs[NS];
-    tile_store<TS, NKC, false>(T, b, pf, L.D, true, qs);
-    if (tid < 32 * NS) T.lamT[b][tid] = (tid < pf.rem) ? pf.lam : INFINITY;
+    tile_store<TS, NKC, false>(T, b, pf, true, qs);
+    const int rr = tid & (32 * NS - 1);
+    T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
   };
   stage(0);
   if (nt > 1) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS);
@@ -930,59 +991,91 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
     for (int v = 0; v < 16; ++v) GT[q][v] = 0.0f;
   float csum = 0.0f;
 
-  for (int t = 0; t < nt; ++t) {
-    const int cur = (NB == 2) ? (t & 1) : 0;
-    if (NB == 2 && t + 1 < nt) {
-      stage(cur ^ 1);
-      if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
-    }
-    if (active) {
-      f32x16 S[NS];
+  // S[i][j] over the staged row tile in buffer cur
+  auto s_gemm = [&](auto bc, f32x16 (&S)[NS]) {
+    constexpr int cur = decltype(bc)::value;
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb)
+    for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) S[sb][v] = 0.0f;
+      for (int v = 0; v < 16; ++v) S[sb][v] = 0.0f;
 #pragma unroll
-      for (int kc = 0; kc < NKC; ++kc)
+    for (int kc = 0; kc < NKC; ++kc)
 #pragma unroll
-        for (int sb = 0; sb < NS; ++sb) {
-          Frag<PREC> Af;
-          tile_row_frag<TS, PREC>(T, cur, sb, kc, Af);
-          mma_chunk<PREC>(S[sb], Af, Bf[kc]);    // S[i][j]
-        }
-      float g[NS][16];
+      for (int sb = 0; sb < NS; ++sb) {
+        Frag<PREC> Af;
+        tile_row_frag<TS, PREC>(T, cur, sb, kc, Af);
+        mma_chunk<PREC>(S[sb], Af, Bf[kc]);    // S[i][j]
+      }
+  };
+  // pairwise marginals of the tile, their column sums and G^T z
+  auto marg = [&](auto bc, f32x16 (&S)[NS]) {
+    constexpr int cur = decltype(bc)::value;
+    float g[NS][16];
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb)
+    for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float4 l4 = *reinterpret_cast<const float4*>(&T.lamT[cur][32 * sb + 8 * q + 4 * h]);
-          g[sb][4 * q + 0] = __builtin_amdgcn_exp2f(S[sb][4 * q + 0] + gj - l4.x);
-          g[sb][4 * q + 1] = __builtin_amdgcn_exp2f(S[sb][4 * q + 1] + gj - l4.y);
-          g[sb][4 * q + 2] = __builtin_amdgcn_exp2f(S[sb][4 * q + 2] + gj - l4.z);
-          g[sb][4 * q + 3] = __builtin_amdgcn_exp2f(S[sb][4 * q + 3] + gj - l4.w);
-        }
+      for (int q = 0; q < 4; ++q) {
+        const float4 l4 = *reinterpret_cast<const float4*>(&T.lamT[cur][32 * sb + 8 * q + 4 * h]);
+        g[sb][4 * q + 0] = __builtin_amdgcn_exp2f(S[sb][4 * q + 0] + gj - l4.x);
+        g[sb][4 * q + 1] = __builtin_amdgcn_exp2f(S[sb][4 * q + 1] + gj - l4.y);
+        g[sb][4 * q + 2] = __builtin_amdgcn_exp2f(S[sb][4 * q + 2] + gj - l4.z);
+        g[sb][4 * q + 3] = __builtin_amdgcn_exp2f(S[sb][4 * q + 3] + gj - l4.w);
+      }
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb)
+    for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) csum += g[sb][v];
-      PFrag<PREC> P[NS];
+      for (int v = 0; v < 16; ++v) csum += g[sb][v];
+    PFrag<PREC> P[NS];
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(g[sb], P[sb]);
+    for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(g[sb], P[sb]);
 #pragma unroll
-      for (int q = 0; q < ND32; ++q)
+    for (int q = 0; q < ND32; ++q)
 #pragma unroll
-        for (int sb = 0; sb < NS; ++sb) {
-          TFrag<PREC> Tf;
-          tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
-          mma_t<PREC>(GT[q], Tf, P[sb]);
-        }
-    }
-    lds_barrier();
-    if (NB == 1 && t + 1 < nt) {
-      stage(0);
-      if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+      for (int sb = 0; sb < NS; ++sb) {
+        TFrag<PREC> Tf;
+        tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+        mma_t<PREC>(GT[q], Tf, P[sb]);
+      }
+  };
+  // One tile (see the forward: S MFMAs first, the next stage behind them).
+  auto tile = [&](auto bc, int t) {
+    constexpr int cur = decltype(bc)::value;
+    if constexpr (NB == 2) {
+      if (active) {
+        f32x16 S[NS];
+        s_gemm(bc, S);
+        stage(cur ^ 1);
+        interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
+        if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+        marg(bc, S);
+      } else {
+        stage(cur ^ 1);
+        if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+      }
       lds_barrier();
+    } else {
+      if (active) {
+        f32x16 S[NS];
+        s_gemm(bc, S);
+        marg(bc, S);
+      }
+      lds_barrier();
+      if (t + 1 < nt) {
+        stage(0);
+        if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+        lds_barrier();
+      }
     }
+  };
+  if constexpr (NB == 2) {
+    int t = 0;
+    for (; t + 1 < nt; t += 2) {
+      tile(std::integral_constant<int, 0>{}, t);
+      tile(std::integral_constant<int, 1>{}, t + 1);
+    }
+    if (t < nt) tile(std::integral_constant<int, 0>{}, t);
+  } else {
+    for (int t = 0; t < nt; ++t) tile(std::integral_constant<int, 0>{}, t);
   }
 
   // ---- column epilogue: marginals of layer l+1, dmu, column part of ds ----
