@@ -11,10 +11,11 @@ marginals and the gradients with respect to z, mu, s and u.
                     [--no-compare] [--no-cpu-baseline] [--calibrate-copy MB]
 
 Prints one JSON line.  `value` is factor entries per second (a step processes the
-sum over chains and adjacent layer pairs of K_l * K_{l+1} entries).  `roofline`
-describes the kernel class with the largest device time in the timed region, timed
-with HIP events that the library records around each of its launches on the stream
-it launches on.  `compare` times the same step in the other precisions / engines
+sum over chains and adjacent layer pairs of K_l * K_{l+1} entries); the timed steps
+replay the forward and backward graphs captured from the library's launches
+(--no-graph: eager launches).  `roofline` describes the kernel class with the largest
+device time in a second region of eager steps, timed with HIP events that the
+library records around each of its launches on the stream it launches on.  `compare` times the same step in the other precisions / engines
 and gives each one's error against the FP64 oracle; `cpu_baseline` times the FP64
 oracle on a bounded sample of the workload on the host.
 """
@@ -74,54 +75,81 @@ def upload(w, prec, engine, flags=0):
     return prob, dev
 
 
-def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0):
+def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=True):
+    """Times `steps` steps of workload w after `warmup` eager steps, all on one stream.
+    graph: the step is a replay of the forward and backward graphs captured from the
+    library's own launches (the same kernels; no host launch gaps).  timing: afterwards,
+    a second region of eager steps with the library's per-kernel HIP events, for the
+    kernel breakdown."""
     import torch
     from paper_1806_08593_amd import tmc as T
     prob, d = upload(w, prec, engine, flags)
     plan = T.Plan(prob)
     ws = plan.new_workspace()
     n = prob.n_chains
-    logp = torch.empty(n, dtype=torch.float64, device="cuda:0")
-    dlogp = torch.ones(n, dtype=torch.float64, device="cuda:0")
-    g = {k: torch.empty_like(v) for k, v in d.items()}
-    h = plan.handle
-    if tune and plan.info["engine"] == T.TMC_ENGINE_FUSED:
-        # the library's launch-shape tuner, outside the timed region
-        T.tmc_plan_autotune(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"], g["s"],
-                            g["u"], reps=3)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        logp = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        dlogp = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        g = {k: torch.empty_like(v) for k, v in d.items()}
+        st.synchronize()
+        h = plan.handle
+        if tune and plan.info["engine"] == T.TMC_ENGINE_FUSED:
+            # the library's launch-shape tuner, outside the timed region
+            T.tmc_plan_autotune(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"],
+                                g["s"], g["u"], reps=3, stream=st)
 
-    def step():
-        T.tmc_gauss_fwd(h, d["z"], d["mu"], d["s"], d["u"], logp, ws)
-        T.tmc_gauss_bwd(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"], g["s"],
-                        g["u"])
+        def eager():
+            T.tmc_gauss_fwd(h, d["z"], d["mu"], d["s"], d["u"], logp, ws, st)
+            T.tmc_gauss_bwd(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"], g["s"],
+                            g["u"], st)
 
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    T.tmc_plan_check(h)
-    if timing:
-        T.tmc_plan_set_timing(h, True)
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()                     # (one GPU: the barrier is this sync)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kc = {}
-    if timing:
-        for i, name in enumerate(T.KERNEL_CLASSES):
-            ms, cnt = T.tmc_plan_timing(h, i)
-            if cnt:
-                kc[name] = dict(ms_per_step=ms / steps, launches_per_step=cnt / steps,
-                                avg_launch_us=1e3 * ms / cnt)
-        T.tmc_plan_set_timing(h, False)
-    T.tmc_plan_check(h)
-    out = dict(ms_per_step=(t1 - t0) * 1e3 / steps, event_ms_per_step=e0.elapsed_time(e1) / steps,
-               kernels=kc, logp=logp.cpu().numpy(), info=T.tmc_plan_info_get(h))
+        for _ in range(warmup):
+            eager()
+        st.synchronize()
+        T.tmc_plan_check(h)
+        step = eager
+        if graph:
+            T.tmc_plan_graph_capture_gauss(h, 0, d["z"], d["mu"], d["s"], d["u"], logp, None, ws,
+                                           None, None, None, None, st)
+            T.tmc_plan_graph_capture_gauss(h, 1, d["z"], d["mu"], d["s"], d["u"], None, dlogp, ws,
+                                           g["z"], g["mu"], g["s"], g["u"], st)
+
+            def step():
+                T.tmc_plan_graph_launch(h, 0, st)
+                T.tmc_plan_graph_launch(h, 1, st)
+
+            step()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()                     # (one GPU: the barrier is this sync)
+        t0 = time.perf_counter()
+        e0.record(st)
+        for _ in range(steps):
+            step()
+        e1.record(st)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        T.tmc_plan_check(h)
+        lp = logp.cpu().numpy()
+        kc, eager_ms = {}, None
+        if timing:
+            ksteps = max(3, steps // 2)
+            T.tmc_plan_set_timing(h, True)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(ksteps):
+                eager()
+            torch.cuda.synchronize()
+            eager_ms = (time.perf_counter() - t2) * 1e3 / ksteps
+            for i, name in enumerate(T.KERNEL_CLASSES):
+                ms, cnt = T.tmc_plan_timing(h, i)
+                if cnt:
+                    kc[name] = dict(ms_per_step=ms / ksteps, launches_per_step=cnt / ksteps,
+                                    avg_launch_us=1e3 * ms / cnt)
+            T.tmc_plan_set_timing(h, False)
+            T.tmc_plan_check(h)
+        out = dict(ms_per_step=(t1 - t0) * 1e3 / steps, event_ms_per_step=e0.elapsed_time(e1) / steps,
+                   eager_ms_per_step=eager_ms, kernels=kc, logp=lp, info=T.tmc_plan_info_get(h))
     plan.close()
     del d, g, ws
     torch.cuda.empty_cache()
@@ -132,15 +160,17 @@ def cpu_baseline(chains, budget_s):
     """FP64 oracle (forward + backward) on as many instances as fit in about budget_s
     seconds of host time.  Returns (entries/s, instances done, seconds, log P list)."""
     from oracle import tmc_oracle as O
-    t0 = time.perf_counter()
-    done, ent, refs = 0, 0, []
-    for c in chains:
-        refs.append(O.gauss_chain_grads(c.z, c.mu, c.s, c.u)[0])
-        done += 1
-        ent += c.entries()
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):        # one host thread, so that `cores` is exact
+        t0 = time.perf_counter()
+        done, ent, refs = 0, 0, []
+        for c in chains:
+            refs.append(O.gauss_chain_grads(c.z, c.mu, c.s, c.u)[0])
+            done += 1
+            ent += c.entries()
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
     return ent / dt, done, dt, refs
 
 
@@ -158,6 +188,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape tuner (per-depth launches unless --persistent)")
     ap.add_argument("--persistent", action="store_true", help="persistent launches (with --no-tune)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of replays of the captured step graphs")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="first copy this many MiB with a plain device copy (a known-size "
                          "kernel for scaling memory counters)")
@@ -192,7 +224,8 @@ def main():
     from paper_1806_08593_amd import tmc as T
     main_run = run_mode(w, prec, args.engine, args.steps, args.warmup, timing=True,
                         tune=not args.no_tune,
-                        flags=T.TMC_FLAG_PERSISTENT if args.persistent else 0)
+                        flags=T.TMC_FLAG_PERSISTENT if args.persistent else 0,
+                        graph=not args.no_graph)
     ms_per_step = main_run["ms_per_step"]
     value = entries / (ms_per_step / 1e3)
     kc = main_run["kernels"]
@@ -217,7 +250,7 @@ def main():
             try:
                 print(f"[bench] comparator {cp}/{ce}", file=sys.stderr, flush=True)
                 r = run_mode(w, cp, ce, max(3, args.steps // 3), 2, timing=False,
-                             tune=not args.no_tune and ce == "fused")
+                             tune=not args.no_tune and ce == "fused", graph=not args.no_graph)
                 compare[f"{cp}_{ce}"] = dict(ms_per_step=r["ms_per_step"],
                                              value=entries / (r["ms_per_step"] / 1e3), logp=r["logp"])
             except Exception as e:   # e.g. a plain-engine workspace that does not fit
@@ -250,7 +283,8 @@ def main():
     cfg = {"workload": args.workload, "chains": len(w.chains), "factor_entries": entries,
            "precision": prec, "engine": ["auto", "fused", "plain"][info["engine"]],
            "launch": ("persistent" if info["persistent"] else "per-depth") +
-                     (" (tuned)" if info["tuned"] else ""),
+                     (" (tuned)" if info["tuned"] else "") +
+                     (", eager" if args.no_graph else ", graph replay"),
            "parallelism": "single GPU"}
     if w.z is not None:
         B, L, K, D = w.z.shape
@@ -273,6 +307,7 @@ def main():
         "cpu_baseline": cpu,
         "max_abs_err_logp_vs_oracle": errs,
         "event_ms_per_step": main_run["event_ms_per_step"],
+        "eager_ms_per_step": main_run["eager_ms_per_step"],
         "kernels": kc,
         "compare": compare,
     }

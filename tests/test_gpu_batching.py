@@ -72,11 +72,22 @@ def test_persistent_equals_per_depth_and_oracle(prec):
             assert rel_l2(gmu[c][l], r[2][l]) < 1e-2
 
 
-def test_persistent_graph_replay():
+def _c3_like(n):
+    # n chains of the homogeneous benchmark shape (L = 6 layers of K = 256, D = 100)
+    return cast_chains(make("c3", B=n).chains, "fp32")
+
+
+@pytest.mark.parametrize("case", ["persistent_fp32_c4", "per_depth_bf16x3_c3"])
+def test_graph_replay(case):
+    """Replays of the captured forward and backward graphs equal the eager launches
+    bitwise, three times over, with eager work and synchronisation between replays."""
     from paper_1806_08593_amd import tmc as T
-    chains = _c4_subset(24)
+    if case == "persistent_fp32_c4":
+        chains, prec, flags = _c4_subset(24), "fp32", T.TMC_FLAG_PERSISTENT
+    else:
+        chains, prec, flags = _c3_like(64), "bf16x3", 0
     n = len(chains)
-    plan, ws, d = _setup(chains, "fp32", T.TMC_FLAG_PERSISTENT)
+    plan, ws, d = _setup(chains, prec, flags)
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
         lp0, g0 = _run(plan, ws, d, n, stream=st)
