@@ -149,7 +149,7 @@ typedef struct tmc_plan_info {
   int32_t max_depth;            /* max chain length L */
   int32_t tile_rows;            /* fused engine: rows per workgroup tile */
   int32_t tile_cols;            /* fused engine: columns per inner tile */
-  int32_t waves_per_group;
+  int32_t waves_per_group;      /* fused engine: waves of the widest per-depth workgroup (4, 8) */
   int32_t persistent;           /* fused engine: passes run as persistent launches */
   int32_t tuned;                /* launch shape chosen by tmc_plan_autotune or its cache */
 } tmc_plan_info;
@@ -221,7 +221,8 @@ tmc_status tmc_plan_graph_launch(tmc_plan_t plan, int which, void* stream);
 /* ---- launch shape ---- */
 /* Batching of many chains of uneven depth and width (fused engine).  By default each
  * pass launches one kernel per chain depth and width bucket, over all chains at that
- * depth (a workgroup per block of 128 samples of one layer pair).  With
+ * depth (a workgroup of 4 waves per block of 128 samples of one layer pair; in the
+ * forward of gradient plans, 8 waves per 256 samples for widths d = 97..128).  With
  * TMC_FLAG_PERSISTENT (or when the tuner picks it) each pass is one persistent launch
  * per width bucket: its workgroups take whole chains from a queue in the workspace,
  * most expensive chain (sum of K_l K_{l+1} D_l) first, and each runs every layer pair
@@ -229,14 +230,17 @@ tmc_status tmc_plan_graph_launch(tmc_plan_t plan, int which, void* stream);
  * launch boundary separates the depths and no workgroup waits for another. */
 
 /* Launch-shape tuner: runs every candidate launch shape of a fused plan (per-depth
- * launches; persistent launches with 1x or 2x the resident workgroup capacity; for
- * forward-only plans, 1 or 2 staged 32-sample subtiles per LDS stage) `reps` times
+ * launches, for gradient plans with or without 8-wave workgroups of 256 rows / columns
+ * in each direction where the width allows; persistent launches with 1x or 2x the
+ * resident workgroup capacity; for forward-only plans, 1 or 2 staged 32-sample subtiles
+ * per LDS stage) `reps` times
  * (reps >= 1) on the caller's buffers -- a forward, plus a backward unless the plan is
  * forward-only -- times each with HIP events on `stream`, and keeps the fastest for
  * later calls.  Output buffers are overwritten; dz, dmu, ds, du, dlogp may be NULL for a
  * forward-only plan.  Synchronises the stream.  If the environment variable
  * TMC_TUNE_CACHE names a file, the choice is appended to it as a line
- * "<shape signature> <persist> <grid factor> <stages>" and plans created later with the
+ * "<shape signature> <persist> <grid factor> <stages> <wide forward> <wide backward>" and
+ * plans created later with the
  * same signature start from it.  Not for use during graph capture.  Plain-engine plans:
  * returns TMC_OK without doing anything. */
 tmc_status tmc_plan_autotune(tmc_plan_t plan, const void* z, const void* mu, const void* s,

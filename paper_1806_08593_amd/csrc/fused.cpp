@@ -52,32 +52,40 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
   for (auto& c : chains) max_depth = std::max(max_depth, c.L);
   const int steps = std::max(max_depth - 1, 0);
 
-  // level-synchronous schedules: one launch per (depth step, chunk bucket)
-  F.fwd.assign(steps, {});
-  F.bwd.assign(steps, {});
+  // level-synchronous schedules: one launch per (depth step, chunk bucket, waves), once
+  // with 4-wave workgroups only and once with 8 waves where eligible
+  for (int wide = 0; wide < 2; ++wide) {
+  F.fwd[wide].assign(steps, {});
+  F.bwd[wide].assign(steps, {});
   for (int t = 0; t < steps; ++t) {
     for (int dir = 0; dir < 2; ++dir) {
-      std::map<int, std::vector<int>> groups;   // nkc -> pairs
+      std::map<std::pair<int, int>, std::vector<int>> groups;   // (nkc, waves) -> pairs
       for (int l : pairs) {
         const LayerDev& d = layers[l];
         const int L = chains[d.chain].L;
         const bool in_step = dir == 0 ? d.depth == L - 2 - t : d.depth == t;
-        if (in_step) groups[nkc_bucket(d.D)].push_back(l);
+        if (!in_step) continue;
+        // 8 waves (256 rows / columns per workgroup) for wide layers of gradient plans
+        const int nkc = nkc_bucket(d.D), n = dir == 0 ? d.K : d.Kc;
+        const int waves = (wide && grad && fused_wide_ok(nkc) && n >= kFusedWideMin) ? 8 : 4;
+        groups[{nkc, waves}].push_back(l);
       }
       for (auto& kv : groups) {
         FusedLaunch fl;
-        fl.nkc = kv.first;
+        fl.nkc = kv.first.first;
+        fl.waves = kv.first.second;
         fl.off = (int)items.size();
-        const int step_rows = dir == 0 ? kFusedFwdRows : kFusedBwdCols;
+        const int step_rows = 32 * fl.waves;
         for (int l : kv.second) {
           const LayerDev& d = layers[l];
           const int n = dir == 0 ? d.K : d.Kc;
           for (int x = 0; x < n; x += step_rows) items.push_back({l, x});
         }
         fl.n = (int)items.size() - fl.off;
-        (dir == 0 ? F.fwd[t] : F.bwd[t]).push_back(fl);
+        (dir == 0 ? F.fwd[wide][t] : F.bwd[wide][t]).push_back(fl);
       }
     }
+  }
   }
 
   // persistent queues: chains grouped by the largest chunk bucket among their pairs,
@@ -138,7 +146,13 @@ void fused_set_grids(FusedPlan& F) {
 void fused_info(const FusedPlan& F, tmc_plan_info* out) {
   out->tile_rows = 32;
   out->tile_cols = 32;
-  out->waves_per_group = 4;
+  int waves = 4;
+  if (!F.tune.persist)
+    for (int dir = 0; dir < 2; ++dir)
+      if (dir == 0 ? F.tune.wide_fwd : F.tune.wide_bwd)
+        for (auto& step : (dir == 0 ? F.fwd[1] : F.bwd[1]))
+          for (auto& g : step) waves = std::max(waves, g.waves);
+  out->waves_per_group = waves;   // the widest launch of the current launch shape
   out->persistent = F.tune.persist ? 1 : 0;
   out->tuned = F.tuned ? 1 : 0;
 }

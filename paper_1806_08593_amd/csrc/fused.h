@@ -21,6 +21,14 @@ struct FusedLaunch {
   int off = 0, n = 0, nkc = 0, waves = 4;
 };
 
+// Chunk counts with an 8-wave kernel (256 rows or columns per workgroup, one workgroup
+// per compute unit): the widest ones with a double-buffered stage (d 97..128), whose
+// 4-wave kernels already run at two waves per SIMD, so the wider workgroup costs no
+// occupancy while it halves each wave's share of the staging.
+inline bool fused_wide_ok(int nkc) { return nkc == 7 || nkc == 8; }
+// Smallest layer width (rows in the forward, columns in the backward) given to 8 waves.
+constexpr int kFusedWideMin = 256;
+
 // One persistent launch: the chains ints[off .. off + n) of the plan's int table, most
 // expensive first; a workgroup runs all pairs of a chain it takes.  All chains of the
 // group use the chunk count nkc (the largest bucket among their pairs).
@@ -35,11 +43,15 @@ struct FusedTune {
   bool persist = false;   // one persistent launch per group instead of one per depth
   int grid_factor = 1;    // persistent grid = min(items, factor x resident capacity)
   int fwd_ns = 2;         // forward-only: staged 32-sample subtiles per LDS stage (1, 2)
+  bool wide_fwd = true;   // per-depth gradient forward: 8-wave workgroups where eligible
+  bool wide_bwd = false;  // per-depth backward: 8-wave workgroups where eligible
 };
 
 struct FusedPlan {
   int prec = 0, flags = 0;
-  std::vector<std::vector<FusedLaunch>> fwd, bwd;   // [depth step][nkc group]
+  // per-depth schedules [wide][depth step][(nkc, waves) group]: wide = 0 all 4-wave,
+  // wide = 1 with 8-wave groups where eligible
+  std::vector<std::vector<FusedLaunch>> fwd[2], bwd[2];
   std::vector<PersistGroup> pfwd, pbwd;             // persistent launches
   FusedLaunch dz;                                   // all pairs, 64 rows per item
   int n_pairs = 0;
@@ -52,7 +64,9 @@ struct FusedPlan {
 int nkc_bucket(int D);
 
 // Lays out the fused engine's workspace regions (appending at offset `o`), assigns its
-// per-layer offsets and appends its work items.  Rows per backward workgroup:
+// per-layer offsets and appends its work items.  Granularity of the per-layer partials
+// (alpha maxima per 128 rows, ds column parts per 128 columns; a 256-wide workgroup
+// writes two of each) and rows per dz item:
 constexpr int kFusedBwdCols = 128;
 constexpr int kFusedFwdRows = 128;
 constexpr int kFusedDzRows = 64;

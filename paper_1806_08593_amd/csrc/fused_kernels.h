@@ -50,8 +50,9 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kHalfLn2Pi = 0.91893853320467274178;
 constexpr float kRescale = 8.0f;   // lazy online-max threshold (log2 units)
-constexpr int kFusedRowsPerGroup = 128;   // forward rows per workgroup (4 waves x 32)
-constexpr int kFusedBwdColsDev = 128;     // backward columns per workgroup (4 waves x 32)
+constexpr int kFusedRowsPerGroup = 128;   // rows per alpha-max partial / ds column part;
+                                          // also the rows (columns) of a 4-wave workgroup
+constexpr int kFusedBwdColsDev = 128;     // backward columns of a 4-wave workgroup
 
 // Kernel arguments (device pointers; see the launchers for their regions).
 struct FwdArgs {
@@ -109,8 +110,8 @@ __device__ __forceinline__ float xor32_max(float v) {
   return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
-// v + (the value of lane l xor m) for m = 1, 2 (quad permutes) and 4 (swizzle), FP64:
-// a butterfly over 8 lanes built from these leaves the same sum in all 8.
+// v + (the value of lane l xor m) for m = 1, 2 (quad permutes), 4 (swizzle) and 8 (row
+// rotation), FP64: a butterfly built from these leaves the same sum in all its lanes.
 template <int M>
 __device__ __forceinline__ double xor_add_f64(double v) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
@@ -122,10 +123,13 @@ __device__ __forceinline__ double xor_add_f64(double v) {
   } else if constexpr (M == 2) {
     lo2 = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
     hi2 = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
-  } else {
-    static_assert(M == 4, "xor 1, 2 or 4");
+  } else if constexpr (M == 4) {
     lo2 = __builtin_amdgcn_ds_swizzle(lo, 0x1F | (4 << 10));      // bitmask mode, xor 4
     hi2 = __builtin_amdgcn_ds_swizzle(hi, 0x1F | (4 << 10));
+  } else {
+    static_assert(M == 8, "xor 1, 2, 4 or 8");
+    lo2 = __builtin_amdgcn_mov_dpp(lo, 0x128, 0xF, 0xF, false);  // row_ror:8 = xor 8 in 16 lanes
+    hi2 = __builtin_amdgcn_mov_dpp(hi, 0x128, 0xF, 0xF, false);
   }
   return v + __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi2 << 32) | (uint32_t)lo2);
 }
@@ -351,7 +355,7 @@ struct TileSmem {
   float lam2[DT];        // log2(e) * lam_d
   float gam[NB][NS * 32];   // column terms of the staged tiles (forward)
   float lamT[NB][NS * 32];  // row shifts of the staged tiles (backward)
-  double wm[4];          // per-wave maxima of alpha (forward)
+  double wm[8];          // per-wave maxima of alpha (forward)
 };
 
 __device__ __forceinline__ int tile_perm(int r) {
@@ -370,28 +374,35 @@ __device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const PairPr
   }
 }
 
-// Register stage of NS tiles (blockDim 256): thread t serves row t / 8 of every
-// subtile and float4 columns 4 (t % 8 + 8 m), d < DT.  Slots past the data -- rows
+// Register stage of NS tiles (blockDim 64 WV): thread t serves row t / TPR of every
+// subtile and float4 columns 4 (t % TPR + TPR m), d < DT, with TPR = 2 WV threads per
+// row.  Slots past the data -- rows
 // past the block's end, d >= D -- hold zeros (unaligned path) or copies of real values
 // of the block (aligned path: clamped addresses).  Either is harmless: such d meet an
 // exact zero (lam_d = 0, zero padding of the register operand) or land in outputs that
 // are discarded, and such rows get a -inf shift (gamma_j, or Lam_i = +inf).
-template <int NKC, int NS_>
+template <int NKC, int NS_, int WV = 4>
 struct TilePrefetch {
   static constexpr int NS = NS_;
-  static constexpr int NF = (NKC + 1) / 2;
-  float4 v[NS][NF];
+  static constexpr int NF = (NKC + 1) / 2;       // float4 columns of a row (4 NF = DT)
+  static constexpr int TPR = 2 * WV;             // threads per row
+  static constexpr int NFT = NF * 8 / TPR;       // float4 columns per thread
+  static_assert(WV == 4 || WV == 8, "4 or 8 waves");
+  static_assert(NKC <= 8 || WV == 4, "8-wave workgroups for d <= 128 only");
+  static_assert(NFT * TPR == NF * 8, "8-wave staging needs an even float4 count");
+  float4 v[NS][NFT];
   double a[NS];      // column tiles: alpha_{l+1}[j]
   float lam;         // row tiles: row shift of row t % (32 NS) (+inf applied at the store)
   int rem;           // rows of the stage that exist, counted from its first row
 };
 
 // Column tiles of pair L: mu rows r0.. (samples of layer l+1) and their alpha.
-template <int NKC, int NS>
-__device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS>& pf, const LayerDev& L,
+template <int NKC, int NS, int WV>
+__device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS, WV>& pf, const LayerDev& L,
                                            const float* __restrict__ mu,
                                            const double* __restrict__ alpha, int r0) {
-  const int t = threadIdx.x, sub = t & 7;
+  constexpr int TPR = TilePrefetch<NKC, NS, WV>::TPR, NFT = TilePrefetch<NKC, NS, WV>::NFT;
+  const int t = threadIdx.x, sub = t % TPR;
   const bool vec = (L.D % 4 == 0) && (L.mu_off % 4 == 0);
   pf.rem = L.Kc - r0;
   if (vec) {
@@ -399,34 +410,35 @@ __device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS>& pf, const Laye
     // written to LDS, so the loads stay in flight across the compute of the current tile
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) {
-      const int gc = min(r0 + 32 * sb + (t >> 3), L.Kc - 1);
+      const int gc = min(r0 + 32 * sb + (t / TPR), L.Kc - 1);
       const float* rowp = mu + L.mu_off + (int64_t)gc * L.D;
 #pragma unroll
-      for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(opaque(4 * (sub + 8 * m)), L.D - 4));
+      for (int m = 0; m < NFT; ++m)
+        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(opaque(4 * (sub + TPR * m)), L.D - 4));
       pf.a[sb] = alpha[L.alpha_up_off + gc];
     }
     return;
   }
 #pragma unroll
   for (int sb = 0; sb < NS; ++sb) {
-    const int gr = r0 + 32 * sb + (t >> 3);
+    const int gr = r0 + 32 * sb + (t / TPR);
     const bool valid = gr < L.Kc;
     const int gc = valid ? gr : L.Kc - 1;
     const float* rowp = mu + L.mu_off + (int64_t)gc * L.D;
 #pragma unroll
-    for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-      pf.v[sb][m] = load_f4(rowp, opaque(4 * (sub + 8 * m)), L.D, valid, false);
+    for (int m = 0; m < NFT; ++m)
+      pf.v[sb][m] = load_f4(rowp, opaque(4 * (sub + TPR * m)), L.D, valid, false);
     pf.a[sb] = alpha[L.alpha_up_off + gc];
   }
 }
 
 // Row tiles of pair L (samples of layer l): z rows r0.. and their shifts Lam.
-template <int NKC, int NS>
-__device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const LayerDev& L,
+template <int NKC, int NS, int WV>
+__device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS, WV>& pf, const LayerDev& L,
                                            const float* __restrict__ z,
                                            const float* __restrict__ lamrow, int r0) {
-  const int t = threadIdx.x, sub = t & 7;
+  constexpr int TPR = TilePrefetch<NKC, NS, WV>::TPR, NFT = TilePrefetch<NKC, NS, WV>::NFT;
+  const int t = threadIdx.x, sub = t % TPR;
   const bool vec = (L.D % 4 == 0) && (L.z_off % 4 == 0);
   const int rr = r0 + (t & (32 * NS - 1));
   pf.rem = L.K - r0;
@@ -434,23 +446,23 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
     // loads only (see fetch_cols)
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) {
-      const int gr = min(r0 + 32 * sb + (t >> 3), L.K - 1);
+      const int gr = min(r0 + 32 * sb + (t / TPR), L.K - 1);
       const float* rowp = z + L.z_off + (int64_t)gr * L.D;
 #pragma unroll
-      for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(opaque(4 * (sub + 8 * m)), L.D - 4));
+      for (int m = 0; m < NFT; ++m)
+        pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(opaque(4 * (sub + TPR * m)), L.D - 4));
     }
     pf.lam = lamrow[min(rr, L.K - 1)];
     return;
   }
 #pragma unroll
   for (int sb = 0; sb < NS; ++sb) {
-    const int gr = r0 + 32 * sb + (t >> 3);
+    const int gr = r0 + 32 * sb + (t / TPR);
     const bool valid = gr < L.K;
     const float* rowp = z + L.z_off + (int64_t)(valid ? gr : L.K - 1) * L.D;
 #pragma unroll
-    for (int m = 0; m < TilePrefetch<NKC, NS>::NF; ++m)
-      pf.v[sb][m] = load_f4(rowp, opaque(4 * (sub + 8 * m)), L.D, valid, false);
+    for (int m = 0; m < NFT; ++m)
+      pf.v[sb][m] = load_f4(rowp, opaque(4 * (sub + TPR * m)), L.D, valid, false);
   }
   const float lv = lamrow[min(rr, L.K - 1)];
   pf.lam = (rr < L.K) ? lv : INFINITY;
@@ -458,30 +470,33 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS>& pf, const Laye
 
 // Writes fetched tiles to LDS buffer b: row-major copy = x * lam2 when `scale`, else
 // x; d-major copy (when the layout has one) = x.  With Q, also the column norms of the
-// staged rows, q[sb] = -1/2 sum_d lam_d x_d^2 (FP64, lane-strided partial sums in
-// increasing d, then a butterfly over the 8 threads of the row: complete and identical
-// in all 8).
-template <class TS, int NKC, bool Q>
-__device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC, TS::NS>& pf,
+// staged rows, q[sb] = -1/2 sum_d lam_d x_d^2 in FP64, in one fixed order for 4 and 8
+// waves: float4 column f of the row goes to partial A if f mod 16 < 8, else to B, each
+// partial summed in increasing f; then A + B, then a butterfly over f mod 8 (so both
+// workgroup sizes give identical norms, complete in every thread of the row).
+template <class TS, int NKC, bool Q, int WV>
+__device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC, TS::NS, WV>& pf,
                                            bool scale, double (&q)[TS::NS]) {
-  const int t = threadIdx.x, r = t >> 3, sub = t & 7;
+  constexpr int TPR = TilePrefetch<NKC, TS::NS, WV>::TPR, NFT = TilePrefetch<NKC, TS::NS, WV>::NFT;
+  const int t = threadIdx.x, r = t / TPR, sub = t % TPR;
   const int pr = tile_perm(r);
 #pragma unroll
   for (int sb = 0; sb < TS::NS; ++sb) {
-    double qa = 0.0;
+    double qa[2] = {0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < TilePrefetch<NKC, TS::NS>::NF; ++m) {
+    for (int m = 0; m < NFT; ++m) {
       // d < DT always (the row stride and the lam tables cover DT, so no thread
       // branches here); slots past the data are harmless (see TilePrefetch)
-      const int d = 4 * (sub + 8 * m);
+      const int d = 4 * (sub + TPR * m);
+      double& qp = qa[WV == 4 ? (m & 1) : 0];
       const float x[4] = {pf.v[sb][m].x, pf.v[sb][m].y, pf.v[sb][m].z, pf.v[sb][m].w};
       if constexpr (Q) {
         const double2 la = *reinterpret_cast<const double2*>(&T.lamd[d]);
         const double2 lb = *reinterpret_cast<const double2*>(&T.lamd[d + 2]);
-        qa += la.x * (double)x[0] * (double)x[0];
-        qa += la.y * (double)x[1] * (double)x[1];
-        qa += lb.x * (double)x[2] * (double)x[2];
-        qa += lb.y * (double)x[3] * (double)x[3];
+        qp += la.x * (double)x[0] * (double)x[0];
+        qp += la.y * (double)x[1] * (double)x[1];
+        qp += lb.x * (double)x[2] * (double)x[2];
+        qp += lb.y * (double)x[3] * (double)x[3];
       }
       const int ro = sb * TS::ROWN + r * TS::RS + d;
       const int co = sb * TS::COLN + d * TS::CS + pr;
@@ -517,10 +532,13 @@ __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC,
       }
     }
     if constexpr (Q) {
-      qa = xor_add_f64<1>(qa);
-      qa = xor_add_f64<2>(qa);
-      qa = xor_add_f64<4>(qa);
-      q[sb] = -0.5 * qa;
+      // 4 waves: this thread holds A (even m) and B (odd m); 8 waves: threads with
+      // sub < 8 hold A, their xor-8 partners B
+      double qs = (WV == 4) ? qa[0] + qa[1] : xor_add_f64<8>(qa[0]);
+      qs = xor_add_f64<1>(qs);
+      qs = xor_add_f64<2>(qs);
+      qs = xor_add_f64<4>(qs);
+      q[sb] = -0.5 * qs;
     }
   }
 }
@@ -613,7 +631,7 @@ constexpr int kGemmMfma = NKC * (PREC == TMC_BF16X3 ? 3 : 8);
 template <int PREC, int NKC, bool GRAD, int NS>
 using FwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), GRAD>;
 
-template <int PREC, int NKC, bool GRAD, int NS>
+template <int PREC, int NKC, bool GRAD, int NS, int WV>
 __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const Item it,
                                          const LayerDev& L, const FwdArgs& args) {
   using TS = FwdSmem<PREC, NKC, GRAD, NS>;
@@ -641,8 +659,8 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   const float u_i = u[L.u_off + min(i, L.K - 1)];
   float xz[NKC][8];
   wave_load<NKC>(z, L.z_off, L.K, L.D, i0, xz);
-  TilePrefetch<NKC, NS> pf;
-  fetch_cols<NKC, NS>(pf, L, mu, alpha, 0);
+  TilePrefetch<NKC, NS, WV> pf;
+  fetch_cols(pf, L, mu, alpha, 0);
   const double maxa = pair_maxa(L, wmax, pre);
   const double cs = pair_const(L, pre);
   tile_init(T, L, pre);
@@ -666,21 +684,22 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   // The forward computes the column norms q_j (FP64) of every column it stages; the
   // workgroup that starts at row 0 stores them for the backward.
   const bool qwriter = GRAD && it.start == 0;
-  // Stages the fetched columns j0.. into buffer b; the 8 threads of a row hold the same
-  // norm and write the same gamma.  The norms are returned for the q store, which is
+  constexpr int TPR = TilePrefetch<NKC, NS, WV>::TPR;
+  const int srow = tid / TPR;   // staged row of this thread
+  // Stages the fetched columns j0.. into buffer b; the TPR threads of a row hold the
+  // same norm and write the same gamma.  The norms are returned for the q store, which is
   // kept apart (a divergent store would split the block the stage is scheduled in).
   auto stage = [&](int b, int j0, double (&qs)[NS]) {
-    tile_store<TS, NKC, true>(T, b, pf, false, qs);
+    tile_store<TS, NKC, true, WV>(T, b, pf, false, qs);
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb)
-      T.gam[b][32 * sb + (tid >> 3)] =
-          col_gamma(qs[sb], pf.a[sb], j0 + 32 * sb + (tid >> 3), L.Kc, maxa);
+      T.gam[b][32 * sb + srow] = col_gamma(qs[sb], pf.a[sb], j0 + 32 * sb + srow, L.Kc, maxa);
   };
   auto store_q = [&](int j0, const double (&qs)[NS]) {
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) {
-      const int j = j0 + 32 * sb + (tid >> 3);
-      if (qwriter && (tid & 7) == 0 && j < L.Kc) qcol[L.q_off + j] = qs[sb];
+      const int j = j0 + 32 * sb + srow;
+      if (qwriter && tid % TPR == 0 && j < L.Kc) qcol[L.q_off + j] = qs[sb];
     }
   };
   {
@@ -688,7 +707,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
     stage(0, 0, qs);
     store_q(0, qs);
   }
-  if (nt > 1) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS);
+  if (nt > 1) fetch_cols(pf, L, mu, alpha, 32 * NS);
   lds_barrier();
 
   float m = -INFINITY, ssum = 0.0f;
@@ -786,11 +805,11 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
         s_gemm(bc, S);
         stage(cur ^ 1, 32 * NS * (t + 1), qs);
         interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
-        if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
+        if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
         softmax_e(bc, S);
       } else {
         stage(cur ^ 1, 32 * NS * (t + 1), qs);
-        if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
+        if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
       }
       store_q(32 * NS * (t + 1), qs);
       lds_barrier();
@@ -805,7 +824,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
         double qs[NS];
         stage(0, 32 * NS * (t + 1), qs);
         store_q(32 * NS * (t + 1), qs);
-        if (t + 2 < nt) fetch_cols<NKC, NS>(pf, L, mu, alpha, 32 * NS * (t + 2));
+        if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
         lds_barrier();
       }
     }
@@ -835,9 +854,12 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   const double wm = wave_max(iv ? a_i : -INFINITY);
   if (lane == 0) T.wm[w] = wm;
   lds_barrier();
-  if (tid == 0)
-    wmax[L.wmax_off + it.start / kFusedRowsPerGroup] =
-        nan_max(nan_max(T.wm[0], T.wm[1]), nan_max(T.wm[2], T.wm[3]));
+  // one partial per 128 rows (waves 4 h .. 4 h + 3), whatever the workgroup size
+  if (tid < WV / 4 && it.start + kFusedRowsPerGroup * tid < L.K) {
+    const double* pw = &T.wm[4 * tid];
+    wmax[L.wmax_off + it.start / kFusedRowsPerGroup + tid] =
+        nan_max(nan_max(pw[0], pw[1]), nan_max(pw[2], pw[3]));
+  }
   if (GRAD && iv) {
     const float inv = (stot > 0.0f) ? 1.0f / stot : 0.0f;
     float* erow = ev + L.ev_off + (int64_t)i * L.D;
@@ -873,13 +895,14 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   }
 }
 
-// One workgroup per work item (level-synchronous launch).
-template <int PREC, int NKC, bool GRAD, int NS>
-__global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd(FwdArgs args) {
+// One workgroup of WV waves (32 WV rows) per work item (level-synchronous launch):
+// 4 waves, two workgroups per compute unit, or 8 waves, one per compute unit.
+template <int PREC, int NKC, bool GRAD, int NS, int WV>
+__global__ __launch_bounds__(64 * WV, (WV == 8 ? 1 : (NKC <= 8 ? 2 : 1))) void k_fused_fwd(FwdArgs args) {
   __shared__ __align__(16) FwdSmem<PREC, NKC, GRAD, NS> T;
   const Item it = args.items[blockIdx.x];
   const LayerDev L = args.Ls[it.layer];
-  fwd_item<PREC, NKC, GRAD, NS>(T, it, L, args);
+  fwd_item<PREC, NKC, GRAD, NS, WV>(T, it, L, args);
 }
 
 // Persistent launch: each workgroup takes whole chains from the queue and runs their
@@ -901,7 +924,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
     for (int l = ch.top - 1; l >= ch.first; --l) {
       const LayerDev L = args.Ls[l];
       for (int x = 0; x < L.K; x += kFusedRowsPerGroup) {
-        fwd_item<PREC, NKC, GRAD, NS>(T, Item{l, x}, L, args);
+        fwd_item<PREC, NKC, GRAD, NS, 4>(T, Item{l, x}, L, args);
         __syncthreads();
       }
     }
@@ -923,7 +946,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
 template <int PREC, int NKC, int NS>
 using BwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), true>;
 
-template <int PREC, int NKC, int NS>
+template <int PREC, int NKC, int NS, int WV>
 __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD, const Item it,
                                          const LayerDev& L, const BwdArgs& args) {
   using TS = BwdSmem<PREC, NKC, NS>;
@@ -959,11 +982,11 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   const double gl = dlogp[L.chain];
   float xm[NKC][8];
   wave_load<NKC>(mu, L.mu_off, L.Kc, L.D, jw, xm);
-  TilePrefetch<NKC, NS> pf;
-  fetch_rows<NKC, NS>(pf, L, z, lamrow, 0);
+  TilePrefetch<NKC, NS, WV> pf;
+  fetch_rows(pf, L, z, lamrow, 0);
   const double maxa = pair_maxa(L, wmax, pre);
   tile_init(T, L, pre);
-  for (int d = tid; d < TS::DT; d += blockDim.x) accD[d] = 0.0f;
+  for (int d = tid; d < (WV / 4) * TS::DT; d += blockDim.x) accD[d] = 0.0f;
   lds_barrier();
 
   Frag<PREC> Bf[NKC];
@@ -976,12 +999,12 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   // the same row, so every thread writes (equal values to equal slots, no branch).
   auto stage = [&](int b) {
     double qs[NS];
-    tile_store<TS, NKC, false>(T, b, pf, true, qs);
+    tile_store<TS, NKC, false, WV>(T, b, pf, true, qs);
     const int rr = tid & (32 * NS - 1);
     T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
   };
   stage(0);
-  if (nt > 1) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS);
+  if (nt > 1) fetch_rows(pf, L, z, lamrow, 32 * NS);
   lds_barrier();
 
   f32x16 GT[ND32];
@@ -1046,11 +1069,11 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
         s_gemm(bc, S);
         stage(cur ^ 1);
         interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
-        if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2));
         marg(bc, S);
       } else {
         stage(cur ^ 1);
-        if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2));
       }
       lds_barrier();
     } else {
@@ -1062,7 +1085,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       lds_barrier();
       if (t + 1 < nt) {
         stage(0);
-        if (t + 2 < nt) fetch_rows<NKC, NS>(pf, L, z, lamrow, 32 * NS * (t + 2));
+        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2));
         lds_barrier();
       }
     }
@@ -1152,35 +1175,45 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       }
   }
   if (!dsp) return;   // (uniform: ends this item)
-  float* buf = reinterpret_cast<float*>(&T.col[0][0][0]);   // >= 32 x DT floats
+  // one column part per 128 columns (waves 4 h .. 4 h + 3), whatever the workgroup size;
+  // the two halves of an 8-wave workgroup are reduced side by side in their own buffers
+  float* buf = reinterpret_cast<float*>(&T.col[0][0][0]);   // >= (WV / 4) x 32 x DT floats
+  static_assert(sizeof(T.col) >= (WV / 4) * 32 * TS::DT * sizeof(float), "reduction buffer");
   for (int w2 = 0; w2 < 4; ++w2) {
     lds_barrier();
-    if (w == w2) {
+    if ((w & 3) == w2) {
+      float* bw = buf + (w >> 2) * 32 * TS::DT;
 #pragma unroll
       for (int q = 0; q < ND32; ++q)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) buf[jr * TS::DT + 32 * q + 8 * (v / 4) + 4 * h + (v % 4)] = colt[q][v];
+        for (int v = 0; v < 16; ++v) bw[jr * TS::DT + 32 * q + 8 * (v / 4) + 4 * h + (v % 4)] = colt[q][v];
     }
     lds_barrier();
-    for (int d = tid; d < TS::DT; d += blockDim.x) {
+    for (int e = tid; e < (WV / 4) * TS::DT; e += blockDim.x) {
+      const float* bh = buf + (e / TS::DT) * 32 * TS::DT;
+      const int d = e % TS::DT;
       float acc = 0.0f;
-      for (int c = 0; c < 32; ++c) acc += buf[c * TS::DT + d];
-      accD[d] += acc;
+      for (int c = 0; c < 32; ++c) acc += bh[c * TS::DT + d];
+      accD[e] += acc;
     }
   }
   lds_barrier();
-  const int part = it.start / 128;
-  for (int d = tid; d < L.D; d += blockDim.x)
-    dsp[L.dsp_off + (int64_t)part * L.D + d] = g32 * T.lamf[d] * accD[d];
+#pragma unroll
+  for (int hh = 0; hh < WV / 4; ++hh) {
+    if (it.start + kFusedBwdColsDev * hh >= L.Kc) break;   // (uniform)
+    const int part = it.start / kFusedBwdColsDev + hh;
+    for (int d = tid; d < L.D; d += blockDim.x)
+      dsp[L.dsp_off + (int64_t)part * L.D + d] = g32 * T.lamf[d] * accD[hh * TS::DT + d];
+  }
 }
 
-template <int PREC, int NKC, int NS>
-__global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd(BwdArgs args) {
+template <int PREC, int NKC, int NS, int WV>
+__global__ __launch_bounds__(64 * WV, (WV == 8 ? 1 : (NKC <= 8 ? 2 : 1))) void k_fused_bwd(BwdArgs args) {
   __shared__ __align__(16) BwdSmem<PREC, NKC, NS> T;
-  __shared__ float accD[BwdSmem<PREC, NKC, NS>::DT];
+  __shared__ float accD[(WV / 4) * BwdSmem<PREC, NKC, NS>::DT];
   const Item it = args.items[blockIdx.x];
   const LayerDev L = args.Ls[it.layer];
-  bwd_item<PREC, NKC, NS>(T, accD, it, L, args);
+  bwd_item<PREC, NKC, NS, WV>(T, accD, it, L, args);
 }
 
 // Persistent backward: each workgroup takes whole chains and runs their pairs
@@ -1202,7 +1235,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd_persist(B
     for (int l = ch.first; l < ch.top; ++l) {
       const LayerDev L = args.Ls[l];
       for (int x = 0; x < L.Kc; x += kFusedBwdColsDev) {
-        bwd_item<PREC, NKC, NS>(T, accD, Item{l, x}, L, args);
+        bwd_item<PREC, NKC, NS, 4>(T, accD, Item{l, x}, L, args);
         __syncthreads();
       }
     }

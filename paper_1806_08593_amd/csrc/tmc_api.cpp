@@ -239,7 +239,8 @@ T* wsp(void* ws, size_t off) {
 
 // ---- launch-shape tuning cache ----
 // A text file named by TMC_TUNE_CACHE holds lines "<signature> <persist> <grid factor>
-// <stages>"; the last line with a plan's signature sets its starting launch shape.
+// <stages> <wide forward> <wide backward>"; the last line with a plan's signature sets
+// its starting launch shape.
 void tune_cache_lookup(tmc_plan* P) {
   const char* path = std::getenv("TMC_TUNE_CACHE");
   if (!path || !*path) return;
@@ -249,11 +250,14 @@ void tune_cache_lookup(tmc_plan* P) {
   char line[8192];
   while (std::fgets(line, sizeof line, f)) {
     char key[8000];
-    int persist = 0, gf = 1, ns = 2;
-    if (std::sscanf(line, "%7999s %d %d %d", key, &persist, &gf, &ns) == 4 && sig == key) {
+    int persist = 0, gf = 1, ns = 2, wf = 1, wb = 0;
+    if (std::sscanf(line, "%7999s %d %d %d %d %d", key, &persist, &gf, &ns, &wf, &wb) == 6 &&
+        sig == key) {
       P->fused.tune.persist = persist != 0;
       P->fused.tune.grid_factor = std::max(1, std::min(gf, 8));
       P->fused.tune.fwd_ns = ns == 1 ? 1 : 2;
+      P->fused.tune.wide_fwd = wf != 0;
+      P->fused.tune.wide_bwd = wb != 0;
       P->fused.tuned = true;
     }
   }
@@ -266,8 +270,8 @@ void tune_cache_store(const tmc_plan* P) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;
   const FusedTune& t = P->fused.tune;
-  std::fprintf(f, "%s %d %d %d\n", fused_signature(P->fused, P->layers_h, P->chains_h).c_str(),
-               t.persist ? 1 : 0, t.grid_factor, t.fwd_ns);
+  std::fprintf(f, "%s %d %d %d %d %d\n", fused_signature(P->fused, P->layers_h, P->chains_h).c_str(),
+               t.persist ? 1 : 0, t.grid_factor, t.fwd_ns, t.wide_fwd ? 1 : 0, t.wide_bwd ? 1 : 0);
   std::fclose(f);
 }
 
@@ -627,7 +631,7 @@ tmc_status fused_fwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
       LAUNCH_KC(TMC_KC_FUSED_FWD, go(g.nkc, 4, P->items_d, g.n, &q));
     }
   } else {
-    for (auto& step : F.fwd)
+    for (auto& step : F.fwd[F.tune.wide_fwd ? 1 : 0])
       for (auto& g : step) LAUNCH_KC(TMC_KC_FUSED_FWD, go(g.nkc, g.waves, P->items_d + g.off, g.n, nullptr));
   }
   LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, a.alpha, logp,
@@ -663,7 +667,7 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
       LAUNCH_KC(TMC_KC_FUSED_BWD, go(g.nkc, 4, P->items_d, g.n, &q));
     }
   } else {
-    for (auto& step : F.bwd)
+    for (auto& step : F.bwd[F.tune.wide_bwd ? 1 : 0])
       for (auto& g : step) LAUNCH_KC(TMC_KC_FUSED_BWD, go(g.nkc, g.waves, P->items_d + g.off, g.n, nullptr));
   }
   if ((dz || ds) && F.dz.n > 0)
@@ -983,17 +987,25 @@ tmc_status tmc_plan_autotune(tmc_plan_t plan, const void* z, const void* mu, con
     double* logp = wsp<double>(workspace, P->ws.logp);
     const bool was_timing = P->timing;
     P->timing = false;
+    // does any per-depth group have an 8-wave form (else the wide flags change nothing)
+    bool has_wide = false;
+    for (int dir = 0; dir < 2; ++dir)
+      for (auto& step : (dir == 0 ? P->fused.fwd[1] : P->fused.bwd[1]))
+        for (auto& g : step) has_wide = has_wide || g.waves == 8;
     std::vector<FusedTune> cands;
     for (int persist = 0; persist < 2; ++persist)
       for (int gf = 1; gf <= (persist ? 2 : 1); ++gf)
-        for (int ns = 1; ns <= 2; ++ns) {
-          if (!fwd_only && ns == 1) continue;   // the gradient forward has one stage width
-          FusedTune t;
-          t.persist = persist != 0;
-          t.grid_factor = gf;
-          t.fwd_ns = ns;
-          cands.push_back(t);
-        }
+        for (int ns = 1; ns <= 2; ++ns)
+          for (int wide = 0; wide < ((!persist && has_wide) ? 4 : 1); ++wide) {
+            if (!fwd_only && ns == 1) continue;   // the gradient forward has one stage width
+            FusedTune t;
+            t.persist = persist != 0;
+            t.grid_factor = gf;
+            t.fwd_ns = ns;
+            t.wide_fwd = (wide & 1) != 0;
+            t.wide_bwd = (wide & 2) != 0;
+            cands.push_back(t);
+          }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -1004,10 +1016,12 @@ tmc_status tmc_plan_autotune(tmc_plan_t plan, const void* z, const void* mu, con
       return fused_bwd_impl(P, (const float*)z, (const float*)mu, (const float*)s, dlogp,
                             workspace, (float*)dz, (float*)dmu, (float*)ds, (float*)du, hs);
     };
-    float best = -1.0f;
-    FusedTune best_t = P->fused.tune;
+    // two rounds over the candidates, each candidate keeping its faster time (a
+    // transient disturbance of one measurement then decides nothing)
+    std::vector<float> best_ms(cands.size(), -1.0f);
     tmc_status rs = TMC_OK;
-    for (const FusedTune& t : cands) {
+    for (size_t k = 0; k < 2 * cands.size() && rs == TMC_OK; ++k) {
+      const FusedTune& t = cands[k % cands.size()];
       P->fused.tune = t;
       fused_set_grids(P->fused);
       if ((rs = run()) != TMC_OK) break;   // warm-up
@@ -1020,11 +1034,16 @@ tmc_status tmc_plan_autotune(tmc_plan_t plan, const void* z, const void* mu, con
       }
       float ms = 0.0f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (best < 0.0f || ms < best) {
-        best = ms;
-        best_t = t;
-      }
+      float& b = best_ms[k % cands.size()];
+      if (b < 0.0f || ms < b) b = ms;
     }
+    FusedTune best_t = P->fused.tune;
+    float best = -1.0f;
+    for (size_t k = 0; k < cands.size(); ++k)
+      if (best_ms[k] >= 0.0f && (best < 0.0f || best_ms[k] < best)) {
+        best = best_ms[k];
+        best_t = cands[k];
+      }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     P->timing = was_timing;

@@ -159,7 +159,7 @@ def test_autotune_picks_a_shape_and_caches_it(tmp_path, monkeypatch):
     info = T.tmc_plan_info_get(plan.handle)
     assert info["tuned"] == 1
     line = cache.read_text().strip().splitlines()[-1].split()
-    assert len(line) == 4 and int(line[1]) == info["persistent"]
+    assert len(line) == 6 and int(line[1]) == info["persistent"]
     # results after tuning are those of the chosen shape, and correct
     lp2, _ = _run(plan, ws, d, n)
     c = chains[5]
