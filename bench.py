@@ -55,6 +55,46 @@ def algorithmic(kc_name, entries, d_weighted, prec):
     return None
 
 
+# Sources whose compiled code the fused kernels are (their hash dates a counter record).
+KERNEL_SOURCES = ["fused_kernels.h", "k_fused_inst.inc", "k_fused_bf16.hip", "k_fused_f32.hip",
+                  "dev_util.h", "tmc_internal.h"]
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fused_c3_bf16x3_pmc.md")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1806_08593_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload, prec):
+    """(read bytes, written bytes) per launch of `kernel` from the committed counter
+    record, or None when there is none for this workload and precision or the kernel
+    sources changed since it was taken.  The record is a block of lines
+        traffic-record sources-sha256 <hex> workload <w> precision <p>
+        traffic-record <kernel class> read-bytes <r> written-bytes <w>
+    in the profile summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)."""
+    try:
+        lines = open(TRAFFIC_RECORD).read().splitlines()
+    except OSError:
+        return None
+    head, rows = None, {}
+    for ln in lines:
+        t = ln.split()
+        if len(t) >= 7 and t[0] == "traffic-record" and t[1] == "sources-sha256":
+            head = dict(sha=t[2], workload=t[4], precision=t[6])
+        elif len(t) == 6 and t[0] == "traffic-record" and t[2] == "read-bytes":
+            rows[t[1]] = (float(t[3]), float(t[5]))
+    if head is None or head["workload"] != workload or head["precision"] != prec:
+        return None
+    if head["sha"] != kernel_sources_sha256():
+        return None
+    return rows.get(kernel)
+
+
 def upload(w, prec, engine, flags=0):
     """Device buffers and the problem for workload w (homogeneous layout with s shared
     by the batch when w is a stacked batch, packed ragged layout otherwise)."""
@@ -240,6 +280,13 @@ def main():
                         frac=round(achieved / peak, 4), traffic=None,
                         algorithmic_per_launch=per_launch,
                         avg_launch_us=round(kc[dom]["avg_launch_us"], 3))
+        rec = recorded_traffic(dom, args.workload, prec)
+        if rec is not None:
+            # HBM bytes per launch (read + written), from the committed counter record
+            roofline["traffic"] = rec[0] + rec[1]
+            roofline["traffic_read"], roofline["traffic_written"] = rec
+            roofline["traffic_unit"] = "bytes per launch"
+            roofline["traffic_source"] = os.path.relpath(TRAFFIC_RECORD, ROOT)
 
     # comparators: the other arithmetic modes of the same step
     compare = {}
