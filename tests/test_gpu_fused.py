@@ -159,3 +159,47 @@ def test_fused_shared_s_autograd():
     assert rel_l2(t["s"].grad.cpu().numpy(), ds_ref) < 1e-3
     for b in range(B):
         assert abs(logp[b].item() - ref[b][0]) < 1e-4
+
+
+def _shape_signature(shapes, prec, flags=0):
+    """The launch-shape signature the library keys its tuning cache on: precision,
+    flags, chain count and the multiset of (K_l, K_{l+1}, chunk bucket of D_l)."""
+    buckets = [1, 2, 3, 4, 5, 6, 7, 8, 12, 16]
+    hist = {}
+    for Ks, Ds in shapes:
+        for l in range(len(Ks) - 1):
+            need = (Ds[l] + 15) // 16
+            key = (Ks[l], Ks[l + 1], next(b for b in buckets if b >= need))
+            hist[key] = hist.get(key, 0) + 1
+    code = {"fp32": 1, "bf16x3": 2}[prec]
+    return f"p{code}f{flags}c{len(shapes)}" + "".join(
+        f"_{k[0]}x{k[1]}x{k[2]}:{v}" for k, v in sorted(hist.items()))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_wide_workgroups_bitwise_equal_narrow(prec, tmp_path, monkeypatch):
+    """8-wave workgroups (256 rows in the forward, 256 columns in the backward), forced in
+    each direction through the tuning cache, on widths d = 97..128 with row counts on and
+    off the 256 boundary: outputs bitwise equal to the 4-wave kernels (the same summation
+    orders), and within tolerance of the oracle."""
+    rng = np.random.default_rng(97)
+    shapes = [((300, 256, 257), (100, 112, 128)), ((257, 300), (128, 97)),
+              ((256, 64, 256), (104, 100, 120))]
+    chains = cast_chains([_rand_chain(rng, Ks, Ds) for Ks, Ds in shapes], "fp32")
+    sig = _shape_signature(shapes, prec)
+    outs = {}
+    for wf in (0, 1):
+        for wb in (0, 1):
+            cache = tmp_path / f"tune_{wf}{wb}.txt"
+            cache.write_text(f"{sig} 0 1 2 {wf} {wb}\n")
+            monkeypatch.setenv("TMC_TUNE_CACHE", str(cache))
+            out = run_gauss(chains, prec, engine="fused")
+            assert out["info"]["tuned"] == 1, "cache line not matched"
+            assert out["info"]["waves_per_group"] == (8 if (wf or wb) else 4)
+            outs[(wf, wb)] = out
+    ref = outs[(0, 0)]
+    for key, out in outs.items():
+        assert np.array_equal(out["logp"], ref["logp"]), key
+        for g in ("dz", "dmu", "ds", "du"):
+            assert np.array_equal(out[g], ref[g]), (key, g)
+    _check(outs[(1, 1)], chains, prec)
