@@ -331,7 +331,8 @@ __device__ __forceinline__ void mma_t(f32x16& acc, const TFrag<PREC>& T, const P
 //                   row r stored at column perm(r) (bits 2 and 3 of r swapped) so the
 //                   8 rows a lane needs for one k-step are adjacent (only when COL).
 // Every fragment is one or two 128-bit LDS reads.  BF16X3 keeps two bf16 planes
-// (hi, lo), FP32 one float plane.
+// (hi, lo), FP32 one float plane.  The BF16X3 forward has no d-major copy: its second
+// GEMM reads the row-major copy through LDS transpose reads (tile_rowT_frag).
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, int NS_, int NB_, bool COL_>
 struct TileSmem {
@@ -584,6 +585,36 @@ __device__ __forceinline__ void tile_col_frag(const TS& T, int b, int sb, int q,
   }
 }
 
+// LDS transpose read (ds_read_b64_tr_b16): in each group of 16 lanes, output lane i
+// receives element i % 4 of the 4-element (64-bit) chunks addressed by lanes i / 4 + 4 e
+// of its group, e = 0..3 (one column gathered from four rows).
+__device__ __forceinline__ bf16x4 lds_read_tr16(const __bf16* p) {
+  typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+  return __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)(p));
+}
+
+// Transposed BF16 fragment of subtile sb for d block q read from the row-major copy
+// (no d-major copy needed).  Lane l addresses row 16 t + 8 half + 4 (l / 32) + (l % 16) / 4
+// at column 32 q + 16 ((l / 16) % 2) + 4 (l % 4), so that it receives rows
+// 16 t + 8 half + 4 (l / 32) + e, e = 0..3, of column d = 32 q + l % 32: for k-step t,
+// slots 4 half + e, the k order of an accumulator column (see TFrag).
+template <class TS>
+__device__ __forceinline__ void tile_rowT_frag(const TS& T, int b, int sb, int q,
+                                               TFrag<TMC_BF16X3>& f) {
+  const int lane = threadIdx.x & 63;
+  const int rb = 4 * (lane >> 5) + ((lane & 15) >> 2);
+  const int cb = 32 * q + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const int o0 = sb * TS::ROWN + (16 * tt + rb) * TS::RS + cb;
+    const int o1 = o0 + 8 * TS::RS;
+    const bf16x4 h0 = lds_read_tr16(&T.row[b][0][o0]), h1 = lds_read_tr16(&T.row[b][0][o1]);
+    const bf16x4 l0 = lds_read_tr16(&T.row[b][1][o0]), l1 = lds_read_tr16(&T.row[b][1][o1]);
+    f.f[tt].hi = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+    f.f[tt].lo = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+  }
+}
+
 // The wave's own 32 rows of a row-major [n][D] block as raw values: x[kc] holds
 // row (lane % 32), d = 16 kc + 8 (lane / 32) + s.  Rows past n read the last row.
 template <int NKC>
@@ -629,7 +660,7 @@ template <int PREC, int NKC>
 constexpr int kGemmMfma = NKC * (PREC == TMC_BF16X3 ? 3 : 8);
 
 template <int PREC, int NKC, bool GRAD, int NS>
-using FwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), GRAD>;
+using FwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), GRAD && PREC != TMC_BF16X3>;
 
 template <int PREC, int NKC, bool GRAD, int NS, int WV>
 __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const Item it,
@@ -787,7 +818,10 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
 #pragma unroll
         for (int sb = 0; sb < NS; ++sb) {
           TFrag<PREC> Tf;
-          tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+          if constexpr (PREC == TMC_BF16X3)
+            tile_rowT_frag<TS>(T, cur, sb, q, Tf);   // transpose reads of the row copy
+          else
+            tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
           mma_t<PREC>(O[q], Tf, P[sb]);
         }
     }
