@@ -331,13 +331,16 @@ __device__ __forceinline__ void mma_t(f32x16& acc, const TFrag<PREC>& T, const P
 //                   row r stored at column perm(r) (bits 2 and 3 of r swapped) so the
 //                   8 rows a lane needs for one k-step are adjacent (only when COL).
 // Every fragment is one or two 128-bit LDS reads.  BF16X3 keeps two bf16 planes
-// (hi, lo), FP32 one float plane.  The BF16X3 forward has no d-major copy: its second
-// GEMM reads the row-major copy through LDS transpose reads (tile_rowT_frag).
+// (hi, lo), FP32 one float plane.  BF16X3 has no d-major copies: the second GEMM reads
+// a row-major copy through LDS transpose reads (tile_rowT_frag) -- the forward its
+// only copy, the backward a second, unscaled one.
 // ---------------------------------------------------------------------------
-template <int PREC, int NKC, int NS_, int NB_, bool COL_>
+template <int PREC, int NKC, int NS_, int NB_, bool COL_, bool RAW_ = false>
 struct TileSmem {
   static constexpr int NS = NS_, NB = NB_;
-  static constexpr bool COL = COL_;
+  static constexpr bool COL = COL_;   // d-major copy of the raw values
+  static constexpr bool RAW = RAW_;   // second row-major copy holding the raw values (the
+                                      // first one scaled), read through transpose reads
   static constexpr int DP = NKC * 16;               // padded width
   static constexpr int ND32 = (NKC + 1) / 2;        // 32-wide d blocks
   static constexpr int DT = ND32 * 32;              // rows of the d-major copy; also the
@@ -351,6 +354,7 @@ struct TileSmem {
   typedef typename std::conditional<BF, __bf16, float>::type E;
   E row[NB][NPL][NS * ROWN];
   E col[NB][NPL][COLSZ];
+  E raw[NB][NPL][RAW ? NS * ROWN : 2];
   __attribute__((aligned(16))) double lamd[DT];   // lam_d in FP64 (column norms)
   float lamf[DT];        // lam_d = exp(-2 s_d)            (0 past D)
   float lam2[DT];        // log2(e) * lam_d
@@ -470,7 +474,8 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS, WV>& pf, const 
 }
 
 // Writes fetched tiles to LDS buffer b: row-major copy = x * lam2 when `scale`, else
-// x; d-major copy (when the layout has one) = x.  With Q, also the column norms of the
+// x; d-major copy and second row-major copy (when the layout has them) = x.  With Q,
+// also the column norms of the
 // staged rows, q[sb] = -1/2 sum_d lam_d x_d^2 in FP64, in one fixed order for 4 and 8
 // waves: float4 column f of the row goes to partial A if f mod 16 < 8, else to B, each
 // partial summed in increasing f; then A + B, then a butterfly over f mod 8 (so both
@@ -505,6 +510,10 @@ __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC,
         uint32_t xh[2], xl[2];
         split2(x[0], x[1], xh[0], xl[0]);
         split2(x[2], x[3], xh[1], xl[1]);
+        if constexpr (TS::RAW) {
+          *reinterpret_cast<bf16x4*>(&T.raw[b][0][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xh[0], xh[1]});
+          *reinterpret_cast<bf16x4*>(&T.raw[b][1][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xl[0], xl[1]});
+        }
         if constexpr (TS::COL) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -598,9 +607,11 @@ __device__ __forceinline__ bf16x4 lds_read_tr16(const __bf16* p) {
 // at column 32 q + 16 ((l / 16) % 2) + 4 (l % 4), so that it receives rows
 // 16 t + 8 half + 4 (l / 32) + e, e = 0..3, of column d = 32 q + l % 32: for k-step t,
 // slots 4 half + e, the k order of an accumulator column (see TFrag).
-template <class TS>
+template <class TS, bool FROM_RAW = false>
 __device__ __forceinline__ void tile_rowT_frag(const TS& T, int b, int sb, int q,
                                                TFrag<TMC_BF16X3>& f) {
+  const __bf16* hi = FROM_RAW ? &T.raw[b][0][0] : &T.row[b][0][0];
+  const __bf16* lo = FROM_RAW ? &T.raw[b][1][0] : &T.row[b][1][0];
   const int lane = threadIdx.x & 63;
   const int rb = 4 * (lane >> 5) + ((lane & 15) >> 2);
   const int cb = 32 * q + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
@@ -608,8 +619,8 @@ __device__ __forceinline__ void tile_rowT_frag(const TS& T, int b, int sb, int q
   for (int tt = 0; tt < 2; ++tt) {
     const int o0 = sb * TS::ROWN + (16 * tt + rb) * TS::RS + cb;
     const int o1 = o0 + 8 * TS::RS;
-    const bf16x4 h0 = lds_read_tr16(&T.row[b][0][o0]), h1 = lds_read_tr16(&T.row[b][0][o1]);
-    const bf16x4 l0 = lds_read_tr16(&T.row[b][1][o0]), l1 = lds_read_tr16(&T.row[b][1][o1]);
+    const bf16x4 h0 = lds_read_tr16(hi + o0), h1 = lds_read_tr16(hi + o1);
+    const bf16x4 l0 = lds_read_tr16(lo + o0), l1 = lds_read_tr16(lo + o1);
     f.f[tt].hi = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
     f.f[tt].lo = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
   }
@@ -968,7 +979,8 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
 // ---------------------------------------------------------------------------
 // backward: a workgroup of 4 waves owns 128 columns (samples j of layer l+1; wave
 // w: columns start + 32 w ..) and sweeps every row of layer l, NS x 32 rows per LDS
-// stage (scaled row-major copy for the factor, raw d-major copy for G^T z):
+// stage (scaled row-major copy for the factor; raw values for G^T z in a second
+// row-major copy read through transpose reads (BF16X3) or in a d-major copy (FP32)):
 //   G_ij   = exp2(S_ij + gamma_j - Lam_i),   Lam_i = ell_i - log2 p_l[i]
 //   p_{l+1}[j] = sum_i G_ij,  (G^T z)_j = sum_i G_ij z_i
 //   dmu_j  = dlogp * lam * ((G^T z)_j - p_{l+1}[j] mu_j)
@@ -978,7 +990,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
 // The constant c cancels between the forward's ell_i and G, so it is not needed here.
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, int NS>
-using BwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), true>;
+using BwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), PREC != TMC_BF16X3, PREC == TMC_BF16X3>;
 
 template <int PREC, int NKC, int NS, int WV>
 __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD, const Item it,
@@ -1090,7 +1102,10 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
 #pragma unroll
       for (int sb = 0; sb < NS; ++sb) {
         TFrag<PREC> Tf;
-        tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+        if constexpr (PREC == TMC_BF16X3)
+          tile_rowT_frag<TS, true>(T, cur, sb, q, Tf);   // raw z^T through transpose reads
+        else
+          tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
         mma_t<PREC>(GT[q], Tf, P[sb]);
       }
   };
@@ -1211,8 +1226,10 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   if (!dsp) return;   // (uniform: ends this item)
   // one column part per 128 columns (waves 4 h .. 4 h + 3), whatever the workgroup size;
   // the two halves of an 8-wave workgroup are reduced side by side in their own buffers
-  float* buf = reinterpret_cast<float*>(&T.col[0][0][0]);   // >= (WV / 4) x 32 x DT floats
-  static_assert(sizeof(T.col) >= (WV / 4) * 32 * TS::DT * sizeof(float), "reduction buffer");
+  // (the tile copies are free once the sweep is done)
+  float* buf = reinterpret_cast<float*>(TS::COL ? (void*)&T.col[0][0][0] : (void*)&T.raw[0][0][0]);
+  static_assert((TS::COL ? sizeof(T.col) : sizeof(T.raw)) >= (WV / 4) * 32 * TS::DT * sizeof(float),
+                "reduction buffer");
   for (int w2 = 0; w2 < 4; ++w2) {
     lds_barrier();
     if ((w & 3) == w2) {
