@@ -70,12 +70,13 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, workload, prec):
-    """(read bytes, written bytes) per launch of `kernel` from the committed counter
-    record, or None when there is none for this workload and precision or the kernel
-    sources changed since it was taken.  The record is a block of lines
+def recorded_traffic(kernel, workload, prec, waves=4):
+    """(read bytes, written bytes) per launch of `kernel` in its `waves`-wave form from the
+    committed counter record, or None when there is none for this workload, precision
+    and form or the kernel sources changed since it was taken.  The record is a block of
+    lines
         traffic-record sources-sha256 <hex> workload <w> precision <p>
-        traffic-record <kernel class> read-bytes <r> written-bytes <w>
+        traffic-record <kernel class> waves <n> read-bytes <r> written-bytes <w>
     in the profile summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)."""
     try:
         lines = open(TRAFFIC_RECORD).read().splitlines()
@@ -86,13 +87,13 @@ def recorded_traffic(kernel, workload, prec):
         t = ln.split()
         if len(t) >= 7 and t[0] == "traffic-record" and t[1] == "sources-sha256":
             head = dict(sha=t[2], workload=t[4], precision=t[6])
-        elif len(t) == 6 and t[0] == "traffic-record" and t[2] == "read-bytes":
-            rows[t[1]] = (float(t[3]), float(t[5]))
+        elif len(t) == 8 and t[0] == "traffic-record" and t[2] == "waves":
+            rows[(t[1], int(t[3]))] = (float(t[5]), float(t[7]))
     if head is None or head["workload"] != workload or head["precision"] != prec:
         return None
     if head["sha"] != kernel_sources_sha256():
         return None
-    return rows.get(kernel)
+    return rows.get((kernel, waves))
 
 
 def upload(w, prec, engine, flags=0):
@@ -280,13 +281,18 @@ def main():
                         frac=round(achieved / peak, 4), traffic=None,
                         algorithmic_per_launch=per_launch,
                         avg_launch_us=round(kc[dom]["avg_launch_us"], 3))
-        rec = recorded_traffic(dom, args.workload, prec)
+        # the form (workgroup width) the plan used for that kernel class (every layer of
+        # the homogeneous workloads the record covers is eligible for the wide form)
+        info = main_run["info"]
+        waves = 8 if info.get("wide_fwd" if dom == "fused_fwd" else "wide_bwd") else 4
+        rec = recorded_traffic(dom, args.workload, prec, waves)
         if rec is not None:
             # HBM bytes per launch (read + written), from the committed counter record
             roofline["traffic"] = rec[0] + rec[1]
             roofline["traffic_read"], roofline["traffic_written"] = rec
             roofline["traffic_unit"] = "bytes per launch"
             roofline["traffic_source"] = os.path.relpath(TRAFFIC_RECORD, ROOT)
+            roofline["waves"] = waves
 
     # comparators: the other arithmetic modes of the same step
     compare = {}
@@ -331,6 +337,9 @@ def main():
            "precision": prec, "engine": ["auto", "fused", "plain"][info["engine"]],
            "launch": ("persistent" if info["persistent"] else "per-depth") +
                      (" (tuned)" if info["tuned"] else "") +
+                     ("" if info["persistent"] else
+                      f", forward {8 if info['wide_fwd'] else 4} / backward "
+                      f"{8 if info['wide_bwd'] else 4} waves where eligible") +
                      (", eager" if args.no_graph else ", graph replay"),
            "parallelism": "single GPU"}
     if w.z is not None:

@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define TMC_ABI_VERSION 2
+#define TMC_ABI_VERSION 3
 
 typedef enum tmc_status {
   TMC_OK = 0,
@@ -152,6 +152,8 @@ typedef struct tmc_plan_info {
   int32_t waves_per_group;      /* fused engine: waves of the widest per-depth workgroup (4, 8) */
   int32_t persistent;           /* fused engine: passes run as persistent launches */
   int32_t tuned;                /* launch shape chosen by tmc_plan_autotune or its cache */
+  int32_t wide_fwd;             /* fused per-depth forward: 8-wave groups where eligible */
+  int32_t wide_bwd;             /* fused per-depth backward: 8-wave groups where eligible */
 } tmc_plan_info;
 
 /* ---- library ---- */

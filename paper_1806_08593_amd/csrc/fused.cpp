@@ -155,6 +155,8 @@ void fused_info(const FusedPlan& F, tmc_plan_info* out) {
   out->waves_per_group = waves;   // the widest launch of the current launch shape
   out->persistent = F.tune.persist ? 1 : 0;
   out->tuned = F.tuned ? 1 : 0;
+  out->wide_fwd = (!F.tune.persist && F.tune.wide_fwd) ? 1 : 0;
+  out->wide_bwd = (!F.tune.persist && F.tune.wide_bwd) ? 1 : 0;
 }
 
 std::string fused_signature(const FusedPlan& F, const std::vector<LayerDev>& layers,

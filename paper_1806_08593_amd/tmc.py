@@ -62,7 +62,7 @@ class tmc_plan_info(ctypes.Structure):
     _fields_ = [("factor_entries", c_int64), ("workspace_bytes", c_int64), ("engine", c_int32),
                 ("precision", c_int32), ("max_depth", c_int32), ("tile_rows", c_int32),
                 ("tile_cols", c_int32), ("waves_per_group", c_int32), ("persistent", c_int32),
-                ("tuned", c_int32)]
+                ("tuned", c_int32), ("wide_fwd", c_int32), ("wide_bwd", c_int32)]
 
 
 _P = c_void_p

@@ -19,7 +19,7 @@ def test_exports_every_declared_function():
     lib = ctypes.CDLL(T._LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert T.tmc_abi_version() == 2
+    assert T.tmc_abi_version() == 3
 
 
 def test_struct_layout_matches_header():

@@ -11,8 +11,8 @@ def _write(path, sha, workload="c3", prec="bf16x3"):
     path.write_text(
         "# summary\n\n"
         f"traffic-record sources-sha256 {sha} workload {workload} precision {prec}\n"
-        "traffic-record fused_fwd read-bytes 8.0e7 written-bytes 2.7e7\n"
-        "traffic-record fused_bwd read-bytes 1.1e8 written-bytes 4.4e7\n")
+        "traffic-record fused_fwd waves 8 read-bytes 8.0e7 written-bytes 2.7e7\n"
+        "traffic-record fused_bwd waves 4 read-bytes 1.1e8 written-bytes 4.4e7\n")
 
 
 def test_record_used_only_for_matching_sources(tmp_path, monkeypatch):
@@ -21,7 +21,8 @@ def test_record_used_only_for_matching_sources(tmp_path, monkeypatch):
     assert bench.recorded_traffic("fused_bwd", "c3", "bf16x3") is None     # no record
     _write(rec, bench.kernel_sources_sha256())
     assert bench.recorded_traffic("fused_bwd", "c3", "bf16x3") == (1.1e8, 4.4e7)
-    assert bench.recorded_traffic("fused_fwd", "c3", "bf16x3") == (8.0e7, 2.7e7)
+    assert bench.recorded_traffic("fused_fwd", "c3", "bf16x3", 8) == (8.0e7, 2.7e7)
+    assert bench.recorded_traffic("fused_fwd", "c3", "bf16x3", 4) is None   # other form
     assert bench.recorded_traffic("fused_dz", "c3", "bf16x3") is None      # not recorded
     assert bench.recorded_traffic("fused_bwd", "c5", "bf16x3") is None     # other workload
     assert bench.recorded_traffic("fused_bwd", "c3", "fp32") is None       # other precision
