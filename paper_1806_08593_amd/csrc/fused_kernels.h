@@ -332,8 +332,7 @@ __device__ __forceinline__ void mma_t(f32x16& acc, const TFrag<PREC>& T, const P
 //                   8 rows a lane needs for one k-step are adjacent (only when COL).
 // Every fragment is one or two 128-bit LDS reads.  BF16X3 keeps two bf16 planes
 // (hi, lo), FP32 one float plane.  BF16X3 has no d-major copies: the second GEMM reads
-// a row-major copy through LDS transpose reads (tile_rowT_frag) -- the forward its
-// only copy, the backward a second, unscaled one.
+// the row-major copy through LDS transpose reads (tile_rowT_frag).
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, int NS_, int NB_, bool COL_, bool RAW_ = false>
 struct TileSmem {
@@ -358,6 +357,7 @@ struct TileSmem {
   __attribute__((aligned(16))) double lamd[DT];   // lam_d in FP64 (column norms)
   float lamf[DT];        // lam_d = exp(-2 s_d)            (0 past D)
   float lam2[DT];        // log2(e) * lam_d
+  float rlam2[DT];       // 1 / (log2(e) lam_d)             (0 past D)
   float gam[NB][NS * 32];   // column terms of the staged tiles (forward)
   float lamT[NB][NS * 32];  // row shifts of the staged tiles (backward)
   double wm[8];          // per-wave maxima of alpha (forward)
@@ -375,6 +375,7 @@ __device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const PairPr
     const float lf = d < L.D ? expf(-2.0f * P.slam) : 0.0f;
     T.lamf[d] = lf;
     T.lam2[d] = lf * kLog2e;
+    T.rlam2[d] = lf > 0.0f ? 1.0f / (lf * kLog2e) : 0.0f;
     T.lamd[d] = (double)lf;
   }
 }
@@ -979,8 +980,9 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
 // ---------------------------------------------------------------------------
 // backward: a workgroup of 4 waves owns 128 columns (samples j of layer l+1; wave
 // w: columns start + 32 w ..) and sweeps every row of layer l, NS x 32 rows per LDS
-// stage (scaled row-major copy for the factor; raw values for G^T z in a second
-// row-major copy read through transpose reads (BF16X3) or in a d-major copy (FP32)):
+// stage (a log2(e) lam-scaled row-major copy for the factor; for G^T z, BF16X3 reads
+// the same copy through transpose reads and divides the sums by log2(e) lam_d, FP32
+// keeps a raw d-major copy):
 //   G_ij   = exp2(S_ij + gamma_j - Lam_i),   Lam_i = ell_i - log2 p_l[i]
 //   p_{l+1}[j] = sum_i G_ij,  (G^T z)_j = sum_i G_ij z_i
 //   dmu_j  = dlogp * lam * ((G^T z)_j - p_{l+1}[j] mu_j)
@@ -990,7 +992,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
 // The constant c cancels between the forward's ell_i and G, so it is not needed here.
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, int NS>
-using BwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), PREC != TMC_BF16X3, PREC == TMC_BF16X3>;
+using BwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), PREC != TMC_BF16X3>;
 
 template <int PREC, int NKC, int NS, int WV>
 __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD, const Item it,
@@ -1103,7 +1105,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       for (int sb = 0; sb < NS; ++sb) {
         TFrag<PREC> Tf;
         if constexpr (PREC == TMC_BF16X3)
-          tile_rowT_frag<TS, true>(T, cur, sb, q, Tf);   // raw z^T through transpose reads
+          tile_rowT_frag<TS>(T, cur, sb, q, Tf);   // (log2e lam z)^T: transpose reads
         else
           tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
         mma_t<PREC>(GT[q], Tf, P[sb]);
@@ -1151,6 +1153,13 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   }
 
   // ---- column epilogue: marginals of layer l+1, dmu, column part of ds ----
+  if constexpr (PREC == TMC_BF16X3) {
+    // the BF16X3 sweep formed sum_i G_ij log2(e) lam_d z_id from the scaled row copy
+#pragma unroll
+    for (int q = 0; q < ND32; ++q)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) GT[q][v] *= T.rlam2[32 * q + 8 * (v / 4) + 4 * h + (v % 4)];
+  }
   const float ctot = xor32_sum(csum);
   const bool jv = active && j < L.Kc;
   if (jv && h == 0) {
@@ -1227,8 +1236,8 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   // one column part per 128 columns (waves 4 h .. 4 h + 3), whatever the workgroup size;
   // the two halves of an 8-wave workgroup are reduced side by side in their own buffers
   // (the tile copies are free once the sweep is done)
-  float* buf = reinterpret_cast<float*>(TS::COL ? (void*)&T.col[0][0][0] : (void*)&T.raw[0][0][0]);
-  static_assert((TS::COL ? sizeof(T.col) : sizeof(T.raw)) >= (WV / 4) * 32 * TS::DT * sizeof(float),
+  float* buf = reinterpret_cast<float*>(TS::COL ? (void*)&T.col[0][0][0] : (void*)&T.row[0][0][0]);
+  static_assert((TS::COL ? sizeof(T.col) : sizeof(T.row)) >= (WV / 4) * 32 * TS::DT * sizeof(float),
                 "reduction buffer");
   for (int w2 = 0; w2 < 4; ++w2) {
     lds_barrier();
