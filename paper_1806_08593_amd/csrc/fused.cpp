@@ -37,6 +37,7 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
     LayerDev& d = layers[l];
     if (nkc_bucket(d.D) < 0) return TMC_ERR_SHAPE;
     d.ev_off = ev;
+    d.dz_fused = (d.D % 4 == 0) && (d.z_off % 4 == 0) && (ev % 4 == 0) ? 1 : 0;
     if (grad) ev += (int64_t)d.K * d.D;
     d.q_off = sq;
     sq += d.Kc;
@@ -124,10 +125,25 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
   o = align256(o + (size_t)(heads + 1) * 4);
   W.total = o;
 
-  F.dz.off = (int)items.size();
-  for (int l : pairs)
-    for (int r = 0; r < layers[l].K; r += kFusedDzRows) items.push_back({l, r});
-  F.dz.n = (int)items.size() - F.dz.off;
+  // row terms: every pair, and (wide schedule) the pairs an 8-wave backward does not cover
+  std::vector<char> covered(layers.size(), 0);
+  for (auto& step : F.bwd[1])
+    for (auto& g : step)
+      if (g.waves == 8)
+        for (int x = g.off; x < g.off + g.n; ++x)
+          if (layers[items[x].layer].dz_fused) {
+            // one row partial per workgroup of the pair, within the pair's row partials
+            const LayerDev& d = layers[items[x].layer];
+            if ((d.Kc + 255) / 256 <= (d.K + kFusedDzRows - 1) / kFusedDzRows) covered[items[x].layer] = 1;
+          }
+  for (int wide = 0; wide < 2; ++wide) {
+    F.dz[wide].off = (int)items.size();
+    for (int l : pairs)
+      if (!(wide && covered[l]))
+        for (int r = 0; r < layers[l].K; r += kFusedDzRows) items.push_back({l, r});
+    F.dz[wide].n = (int)items.size() - F.dz[wide].off;
+  }
+  for (size_t l = 0; l < layers.size(); ++l) layers[l].dz_fused = covered[l];
   F.n_pairs = (int)pairs.size();
   return TMC_OK;
 }

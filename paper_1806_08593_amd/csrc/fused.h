@@ -53,7 +53,9 @@ struct FusedPlan {
   // wide = 1 with 8-wave groups where eligible
   std::vector<std::vector<FusedLaunch>> fwd[2], bwd[2];
   std::vector<PersistGroup> pfwd, pbwd;             // persistent launches
-  FusedLaunch dz;                                   // all pairs, 64 rows per item
+  // row-term launches (dz and the ds row part), 64 rows per item, [wide]: wide = 0 all
+  // pairs, wide = 1 only the pairs whose 8-wave backward does not write them itself
+  FusedLaunch dz[2];
   int n_pairs = 0;
   int pair_ids_off = 0;                             // into the plan's int table
   int n_layers = 0;
@@ -95,6 +97,9 @@ struct FusedBwdPtrs {
   float* lam;
   const double* dlogp;
   float *p, *dmu, *du, *dsp;
+  const float* ev;   // forward's softmax-weighted means (row terms of 8-wave backwards)
+  float* dz;
+  int rows;          // 1: 8-wave backwards of pairs flagged dz_fused write the row terms
 };
 struct FusedQueue {
   const int* chains = nullptr;   // chain ids, most expensive first

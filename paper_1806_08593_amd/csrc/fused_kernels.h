@@ -53,6 +53,7 @@ constexpr float kRescale = 8.0f;   // lazy online-max threshold (log2 units)
 constexpr int kFusedRowsPerGroup = 128;   // rows per alpha-max partial / ds column part;
                                           // also the rows (columns) of a 4-wave workgroup
 constexpr int kFusedBwdColsDev = 128;     // backward columns of a 4-wave workgroup
+constexpr int kFusedDzRowsDev = 64;       // rows per row-term item (one ds row partial)
 
 // Kernel arguments (device pointers; see the launchers for their regions).
 struct FwdArgs {
@@ -71,6 +72,9 @@ struct BwdArgs {
   float* lam;
   const double* dlogp;
   float *p, *dmu, *du, *dsp;
+  const float* ev;   // softmax-weighted means left by the forward (dz of the row layer)
+  float* dz;
+  int rows;          // 1: 8-wave items of dz_fused pairs at column 0 write the row terms
 };
 // Chain queue of a persistent launch: chains[0 .. n) (most expensive first); a
 // workgroup takes the next chain from the head counter and runs all of its layer
@@ -400,6 +404,9 @@ struct TilePrefetch {
   double a[NS];      // column tiles: alpha_{l+1}[j]
   float lam;         // row tiles: row shift of row t % (32 NS) (+inf applied at the store)
   int rem;           // rows of the stage that exist, counted from its first row
+  int r0;            // row tiles: first row of the stage
+  float4 e[NS][NFT]; // row tiles with dz: e of the thread's row (same columns as v)
+  float prow[NS];    // row tiles with dz: marginal p of the thread's row (0 past K)
 };
 
 // Column tiles of pair L: mu rows r0.. (samples of layer l+1) and their alpha.
@@ -442,12 +449,16 @@ __device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS, WV>& pf, const 
 template <int NKC, int NS, int WV>
 __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS, WV>& pf, const LayerDev& L,
                                            const float* __restrict__ z,
-                                           const float* __restrict__ lamrow, int r0) {
+                                           const float* __restrict__ lamrow, int r0,
+                                           const float* __restrict__ ev = nullptr,
+                                           const float* __restrict__ pl = nullptr,
+                                           bool dzw = false) {
   constexpr int TPR = TilePrefetch<NKC, NS, WV>::TPR, NFT = TilePrefetch<NKC, NS, WV>::NFT;
   const int t = threadIdx.x, sub = t % TPR;
   const bool vec = (L.D % 4 == 0) && (L.z_off % 4 == 0);
   const int rr = r0 + (t & (32 * NS - 1));
   pf.rem = L.K - r0;
+  pf.r0 = r0;
   if (vec) {
     // loads only (see fetch_cols)
 #pragma unroll
@@ -457,6 +468,14 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS, WV>& pf, const 
 #pragma unroll
       for (int m = 0; m < NFT; ++m)
         pf.v[sb][m] = *reinterpret_cast<const float4*>(rowp + min(opaque(4 * (sub + TPR * m)), L.D - 4));
+      if (dzw) {   // (uniform)
+        const float* erow = ev + L.ev_off + (int64_t)gr * L.D;
+#pragma unroll
+        for (int m = 0; m < NFT; ++m)
+          pf.e[sb][m] = *reinterpret_cast<const float4*>(erow + min(opaque(4 * (sub + TPR * m)), L.D - 4));
+        const float pv = pl[L.p_off + gr];
+        pf.prow[sb] = (r0 + 32 * sb + (t / TPR) < L.K) ? pv : 0.0f;
+      }
     }
     pf.lam = lamrow[min(rr, L.K - 1)];
     return;
@@ -1020,6 +1039,23 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   const int jc = min(j, L.Kc - 1);
   const int nt = (L.K + 32 * NS - 1) / (32 * NS);
   const float* lamrow = lam_ws + L.rl_off;   // Lam shares the per-layer indexing of rl
+  // Every workgroup of a pair sweeps all rows of layer l, so the 8-wave workgroups of a
+  // flagged pair also write the row terms (dz and the ds row part) from the rows they
+  // stage: workgroup c of nwg takes the row tiles t with t % nwg == c and writes the
+  // pair's row partial c (uniform; the host leaves those pairs out of the row-term
+  // launch and flags them only when nwg <= ceil(K / 64)).
+  const bool dzw = WV == 8 && args.rows && L.dz_fused;
+  const int wg_c = it.start / (32 * WV), nwg = (L.Kc + 32 * WV - 1) / (32 * WV);
+  auto own = [&](int tt) { return dzw && (tt % nwg) == wg_c; };
+  const float* __restrict__ evp = args.ev;
+  float* __restrict__ dzp = args.dz;
+  constexpr int NFT = TilePrefetch<NKC, NS, WV>::NFT, TPR = TilePrefetch<NKC, NS, WV>::TPR;
+  float rsum[NFT][4];   // sum over the thread's rows of p_i z_id^2, its column slots
+#pragma unroll
+  for (int m = 0; m < NFT; ++m)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rsum[m][e] = 0.0f;
+  float psum = 0.0f;    // sum of p_i over the thread's rows
 
   // prologue loads: the wave's own column operands (mu rows), their column terms and
   // the first row tile
@@ -1031,7 +1067,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   float xm[NKC][8];
   wave_load<NKC>(mu, L.mu_off, L.Kc, L.D, jw, xm);
   TilePrefetch<NKC, NS, WV> pf;
-  fetch_rows(pf, L, z, lamrow, 0);
+  fetch_rows(pf, L, z, lamrow, 0, evp, p, own(0));
   const double maxa = pair_maxa(L, wmax, pre);
   tile_init(T, L, pre);
   for (int d = tid; d < (WV / 4) * TS::DT; d += blockDim.x) accD[d] = 0.0f;
@@ -1045,14 +1081,45 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
 
   // Stages the fetched rows into buffer b.  Threads t and t + 32 NS hold the shift of
   // the same row, so every thread writes (equal values to equal slots, no branch).
-  auto stage = [&](int b) {
+  // Row terms of the staged rows when the workgroup owns them (fresh; a 2-buffer sweep
+  // also re-stages its last tile, which is never fresh),
+  //   dz_i = -dlogp lam p_i (z_i - e_i),  sums of p_i z_id^2 and of p_i;
+  // thread t serves the rows and column slots it staged.
+  auto stage = [&](int b, bool fresh) {
     double qs[NS];
     tile_store<TS, NKC, false, WV>(T, b, pf, true, qs);
     const int rr = tid & (32 * NS - 1);
     T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
+    if (fresh) {
+      const int sub = tid % TPR;
+#pragma unroll
+      for (int sb = 0; sb < NS; ++sb) {
+        const int row = pf.r0 + 32 * sb + tid / TPR;
+        const float pr = pf.prow[sb];   // 0 past K
+        psum += pr;
+        float* drow = dzp ? dzp + L.z_off + (int64_t)row * L.D : nullptr;
+#pragma unroll
+        for (int m = 0; m < NFT; ++m) {
+          const int c = 4 * (sub + TPR * m);   // < DT; lamf is 0 past D
+          const float4 l4 = *reinterpret_cast<const float4*>(&T.lamf[c]);
+          const float zv[4] = {pf.v[sb][m].x, pf.v[sb][m].y, pf.v[sb][m].z, pf.v[sb][m].w};
+          const float ev[4] = {pf.e[sb][m].x, pf.e[sb][m].y, pf.e[sb][m].z, pf.e[sb][m].w};
+          const float lv[4] = {l4.x, l4.y, l4.z, l4.w};
+          float o[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            o[e] = -g32 * lv[e] * pr * (zv[e] - ev[e]);
+            rsum[m][e] += pr * zv[e] * zv[e];
+          }
+          // D % 4 == 0: a float4 at c < D is whole
+          if (drow && row < L.K && c < L.D)
+            *reinterpret_cast<float4*>(drow + c) = make_float4(o[0], o[1], o[2], o[3]);
+        }
+      }
+    }
   };
-  stage(0);
-  if (nt > 1) fetch_rows(pf, L, z, lamrow, 32 * NS);
+  stage(0, own(0));
+  if (nt > 1) fetch_rows(pf, L, z, lamrow, 32 * NS, evp, p, own(1));
   lds_barrier();
 
   f32x16 GT[ND32];
@@ -1118,13 +1185,13 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       if (active) {
         f32x16 S[NS];
         s_gemm(bc, S);
-        stage(cur ^ 1);
+        stage(cur ^ 1, t + 1 < nt && own(t + 1));
         interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
-        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2));
+        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
         marg(bc, S);
       } else {
-        stage(cur ^ 1);
-        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2));
+        stage(cur ^ 1, t + 1 < nt && own(t + 1));
+        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
       }
       lds_barrier();
     } else {
@@ -1135,8 +1202,8 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       }
       lds_barrier();
       if (t + 1 < nt) {
-        stage(0);
-        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2));
+        stage(0, own(t + 1));
+        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
         lds_barrier();
       }
     }
@@ -1239,6 +1306,33 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   float* buf = reinterpret_cast<float*>(TS::COL ? (void*)&T.col[0][0][0] : (void*)&T.row[0][0][0]);
   static_assert((TS::COL ? sizeof(T.col) : sizeof(T.row)) >= (WV / 4) * 32 * TS::DT * sizeof(float),
                 "reduction buffer");
+  if constexpr (WV == 8) {
+    if (dzw) {
+      // row part of ds over the workgroup's rows: the 32 row slots' sums, reduced in a
+      // fixed order, into row partial wg_c (workgroup 0 zeroes partials nwg .. nrow - 1)
+      static_assert((WV / 4) * 32 * TS::DT >= 32 * TS::DT + 32, "row reduction buffer");
+      lds_barrier();
+      const int r = tid / TPR, sub = tid % TPR;
+#pragma unroll
+      for (int m = 0; m < NFT; ++m)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) buf[r * TS::DT + 4 * (sub + TPR * m) + e] = rsum[m][e];
+      if (sub == 0) buf[32 * TS::DT + r] = psum;
+      lds_barrier();
+      float P = 0.0f;
+      for (int c = 0; c < 32; ++c) P += buf[32 * TS::DT + c];
+      const int ncol = (L.Kc + kFusedBwdColsDev - 1) / kFusedBwdColsDev;
+      const int nrow = (L.K + kFusedDzRowsDev - 1) / kFusedDzRowsDev;
+      float* part = dsp + L.dsp_off + (int64_t)(ncol + wg_c) * L.D;
+      for (int d = tid; d < L.D; d += blockDim.x) {
+        float acc = 0.0f;
+        for (int c = 0; c < 32; ++c) acc += buf[c * TS::DT + d];
+        part[d] = g32 * (T.lamf[d] * acc - P);
+      }
+      if (wg_c == 0)
+        for (int e = tid; e < (nrow - nwg) * L.D; e += blockDim.x) part[(int64_t)nwg * L.D + e] = 0.0f;
+    }
+  }
   for (int w2 = 0; w2 < 4; ++w2) {
     lds_barrier();
     if ((w & 3) == w2) {

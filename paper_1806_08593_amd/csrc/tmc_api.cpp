@@ -647,7 +647,7 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
   float* dsp = ds ? wsp<float>(ws, W.dsp) : nullptr;
   FusedBwdPtrs a{P->layers_d, z, mu, s, wsp<double>(ws, W.alpha), wsp<double>(ws, W.wmax),
                  wsp<double>(ws, W.q), wsp<float>(ws, W.rl), wsp<float>(ws, W.lam), dlogp,
-                 wsp<float>(ws, W.p), dmu, du, dsp};
+                 wsp<float>(ws, W.p), dmu, du, dsp, wsp<float>(ws, W.ev), dz, (dz || ds) ? 1 : 0};
   int* heads = wsp<int>(ws, W.cnt);
   LAUNCH(launch_fused_bwd_init(P->chains_d, P->n_chains, P->layers_d, a.alpha,
                                wsp<double>(ws, W.logp), dlogp, a.rl, a.lam, a.p, du, dz,
@@ -670,8 +670,9 @@ tmc_status fused_bwd_impl(tmc_plan* P, const float* z, const float* mu, const fl
     for (auto& step : F.bwd[F.tune.wide_bwd ? 1 : 0])
       for (auto& g : step) LAUNCH_KC(TMC_KC_FUSED_BWD, go(g.nkc, g.waves, P->items_d + g.off, g.n, nullptr));
   }
-  if ((dz || ds) && F.dz.n > 0)
-    LAUNCH(launch_fused_dz(P->layers_d, P->items_d + F.dz.off, F.dz.n, z, s, a.p,
+  const FusedLaunch& rows = F.dz[(!F.tune.persist && F.tune.wide_bwd) ? 1 : 0];
+  if ((dz || ds) && rows.n > 0)
+    LAUNCH(launch_fused_dz(P->layers_d, P->items_d + rows.off, rows.n, z, s, a.p,
                            wsp<float>(ws, W.ev), dlogp, dz, dsp, st));
   if (ds)
     LAUNCH(launch_ds_reduce<float>(P->part_off_d, P->ints_d + P->slot_start_off, P->slot_soff_d,

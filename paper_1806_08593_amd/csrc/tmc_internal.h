@@ -42,7 +42,8 @@ struct LayerDev {
   int32_t up_top;        // 1 if the layer above is the top of its chain
   int64_t wmax_up_off;   // fused: wmax offset of the layer above
   int32_t nwmax_up;      // fused: number of wmax partials of the layer above
-  int32_t pad2;
+  int32_t dz_fused;      // fused: an 8-wave backward of this pair may write dz and the
+                         // ds row part itself (aligned rows of z and e)
   double lnKc;           // ln K of the layer above
 };
 

@@ -181,10 +181,12 @@ def test_wide_workgroups_bitwise_equal_narrow(prec, tmp_path, monkeypatch):
     """8-wave workgroups (256 rows in the forward, 256 columns in the backward), forced in
     each direction through the tuning cache, on widths d = 97..128 with row counts on and
     off the 256 boundary: outputs bitwise equal to the 4-wave kernels (the same summation
-    orders), and within tolerance of the oracle."""
+    orders), and within tolerance of the oracle.  The one exception is ds with the
+    8-wave backward: it also sums the row terms of its pairs (over all rows in one
+    workgroup instead of per 64 rows), so ds matches to rounding."""
     rng = np.random.default_rng(97)
     shapes = [((300, 256, 257), (100, 112, 128)), ((257, 300), (128, 97)),
-              ((256, 64, 256), (104, 100, 120))]
+              ((256, 64, 256), (104, 100, 120)), ((129, 520), (128, 100))]
     chains = cast_chains([_rand_chain(rng, Ks, Ds) for Ks, Ds in shapes], "fp32")
     sig = _shape_signature(shapes, prec)
     outs = {}
@@ -201,5 +203,9 @@ def test_wide_workgroups_bitwise_equal_narrow(prec, tmp_path, monkeypatch):
     for key, out in outs.items():
         assert np.array_equal(out["logp"], ref["logp"]), key
         for g in ("dz", "dmu", "ds", "du"):
-            assert np.array_equal(out[g], ref[g]), (key, g)
+            if g == "ds" and key[1] == 1:
+                scale = float(np.abs(ref[g]).max())
+                assert np.allclose(out[g], ref[g], rtol=1e-5, atol=1e-6 * scale), (key, g)
+            else:
+                assert np.array_equal(out[g], ref[g]), (key, g)
     _check(outs[(1, 1)], chains, prec)
