@@ -1007,7 +1007,9 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
 //   dmu_j  = dlogp * lam * ((G^T z)_j - p_{l+1}[j] mu_j)
 // and writes the column part of the log-std gradient of its columns,
 //   dlogp * lam * sum_j (p_{l+1}[j] mu_j^2 - 2 mu_j (G^T z)_j)
-// (sum_ij G_ij (z_i - mu_j)^2 expanded; the row terms come from k_fused_dz).
+// (sum_ij G_ij (z_i - mu_j)^2 expanded).  The row terms, dz and the ds row part, come
+// from k_fused_dz, or for aligned pairs from the 8-wave workgroups themselves (below).
+// With 8 waves a workgroup owns 256 columns.
 // The constant c cancels between the forward's ell_i and G, so it is not needed here.
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, int NS>
