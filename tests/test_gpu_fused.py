@@ -183,10 +183,13 @@ def test_wide_workgroups_bitwise_equal_narrow(prec, tmp_path, monkeypatch):
     off the 256 boundary: outputs bitwise equal to the 4-wave kernels (the same summation
     orders), and within tolerance of the oracle.  The one exception is ds with the
     8-wave backward: it also sums the row terms of its pairs (over all rows in one
-    workgroup instead of per 64 rows), so ds matches to rounding."""
+    workgroup instead of per 64 rows), so ds matches to rounding.  The last two chains
+    keep the row-term launch under 8-wave backwards: d = 99 (rows not 16-byte aligned)
+    and 3 column workgroups for a single 64-row partial."""
     rng = np.random.default_rng(97)
     shapes = [((300, 256, 257), (100, 112, 128)), ((257, 300), (128, 97)),
-              ((256, 64, 256), (104, 100, 120)), ((129, 520), (128, 100))]
+              ((256, 64, 256), (104, 100, 120)), ((129, 520), (128, 100)),
+              ((300, 256), (99, 64)), ((64, 600), (128, 64))]
     chains = cast_chains([_rand_chain(rng, Ks, Ds) for Ks, Ds in shapes], "fp32")
     sig = _shape_signature(shapes, prec)
     outs = {}
