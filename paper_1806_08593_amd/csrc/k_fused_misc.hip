@@ -70,9 +70,18 @@ __global__ __launch_bounds__(256) void k_fused_bwd_init(const ChainDev* __restri
     if (has_pair) lam[l0.rl_off + k] = (pv == 0.0f) ? INFINITY : rl[l0.rl_off + k] - log2f(pv);
   }
   if (dz) {
+    // dz of the top layer is 0: a scalar head up to 16-byte alignment, float4 stores,
+    // a scalar tail
     const LayerDev& t = layers[ch.top];
     const int64_t n = (int64_t)t.K * t.D;
-    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) dz[t.z_off + e] = 0.0f;
+    float* o = dz + t.z_off;
+    int64_t head = (4 - (int64_t)(((uintptr_t)o / sizeof(float)) % 4)) % 4;
+    if (head > n) head = n;
+    const int64_t n4 = (n - head) / 4;
+    float4* o4 = reinterpret_cast<float4*>(o + head);
+    for (int64_t e = threadIdx.x; e < head; e += blockDim.x) o[e] = 0.0f;
+    for (int64_t e = threadIdx.x; e < n4; e += blockDim.x) o4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t e = head + 4 * n4 + threadIdx.x; e < n; e += blockDim.x) o[e] = 0.0f;
   }
 }
 
