@@ -148,6 +148,56 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
   return TMC_OK;
 }
 
+// ---- dispatch of the runtime chunk count to the per-bucket launchers ----
+#define TMC_NKC_SWITCH(nkc, CALL)                                                          \
+  switch (nkc) {                                                                           \
+    case 1: return CALL(1); case 2: return CALL(2); case 3: return CALL(3);                 \
+    case 4: return CALL(4); case 5: return CALL(5); case 6: return CALL(6);                 \
+    case 7: return CALL(7); case 8: return CALL(8); case 12: return CALL(12);               \
+    case 16: return CALL(16);                                                              \
+    default: break;                                                                        \
+  }
+static_assert(kNumNkcBuckets == 10 && kNkcBuckets[8] == 12 && kNkcBuckets[9] == 16,
+              "the dispatch below lists every chunk bucket");
+
+template <int PREC>
+int fused_capacity(int dir, int nkc, bool grad, int ns) {
+#define TMC_CALL(N) fused_capacity_n<PREC, N>(dir, grad, ns)
+  TMC_NKC_SWITCH(nkc, TMC_CALL)
+#undef TMC_CALL
+  return 1;
+}
+
+template <int PREC>
+hipError_t launch_fused_fwd(int nkc, int waves, bool grad, int ns, const FusedFwdPtrs& a,
+                            const Item* items, int n, const FusedQueue* q, hipStream_t st) {
+#define TMC_CALL(N) launch_fused_fwd_n<PREC, N>(waves, grad, ns, a, items, n, q, st)
+  TMC_NKC_SWITCH(nkc, TMC_CALL)
+#undef TMC_CALL
+  return hipErrorInvalidValue;
+}
+
+template <int PREC>
+hipError_t launch_fused_bwd(int nkc, int waves, const FusedBwdPtrs& a, const Item* items, int n,
+                            const FusedQueue* q, hipStream_t st) {
+#define TMC_CALL(N) launch_fused_bwd_n<PREC, N>(waves, a, items, n, q, st)
+  TMC_NKC_SWITCH(nkc, TMC_CALL)
+#undef TMC_CALL
+  return hipErrorInvalidValue;
+}
+#undef TMC_NKC_SWITCH
+
+template int fused_capacity<TMC_FP32>(int, int, bool, int);
+template int fused_capacity<TMC_BF16X3>(int, int, bool, int);
+template hipError_t launch_fused_fwd<TMC_FP32>(int, int, bool, int, const FusedFwdPtrs&,
+                                               const Item*, int, const FusedQueue*, hipStream_t);
+template hipError_t launch_fused_fwd<TMC_BF16X3>(int, int, bool, int, const FusedFwdPtrs&,
+                                                 const Item*, int, const FusedQueue*, hipStream_t);
+template hipError_t launch_fused_bwd<TMC_FP32>(int, int, const FusedBwdPtrs&, const Item*, int,
+                                               const FusedQueue*, hipStream_t);
+template hipError_t launch_fused_bwd<TMC_BF16X3>(int, int, const FusedBwdPtrs&, const Item*, int,
+                                                 const FusedQueue*, hipStream_t);
+
 void fused_set_grids(FusedPlan& F) {
   const bool grad = !(F.flags & TMC_FLAG_FORWARD_ONLY);
   for (int dir = 0; dir < 2; ++dir)

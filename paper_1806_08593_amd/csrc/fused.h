@@ -25,7 +25,7 @@ struct FusedLaunch {
 // per compute unit): the widest ones with a double-buffered stage (d 97..128), whose
 // 4-wave kernels already run at two waves per SIMD, so the wider workgroup costs no
 // occupancy while it halves each wave's share of the staging.
-inline bool fused_wide_ok(int nkc) { return nkc == 7 || nkc == 8; }
+constexpr bool fused_wide_ok(int nkc) { return nkc == 7 || nkc == 8; }
 // Smallest layer width (rows in the forward, columns in the backward) given to 8 waves.
 constexpr int kFusedWideMin = 256;
 
@@ -109,7 +109,17 @@ struct FusedQueue {
   int grid = 0;
 };
 
-// kernel launchers (k_fused_*.hip); q == nullptr: one workgroup per item
+// kernel launchers of one precision and chunk count (k_fused_bf16.hip, k_fused_f32.hip,
+// compiled once per bucket of kNkcBuckets); q == nullptr: one workgroup per item
+template <int PREC, int NKC>
+int fused_capacity_n(int dir, bool grad, int ns);
+template <int PREC, int NKC>
+hipError_t launch_fused_fwd_n(int waves, bool grad, int ns, const FusedFwdPtrs& a,
+                              const Item* items, int n, const FusedQueue* q, hipStream_t st);
+template <int PREC, int NKC>
+hipError_t launch_fused_bwd_n(int waves, const FusedBwdPtrs& a, const Item* items, int n,
+                              const FusedQueue* q, hipStream_t st);
+// dispatch over the runtime chunk count (fused.cpp)
 template <int PREC>
 int fused_capacity(int dir, int nkc, bool grad, int ns);
 template <int PREC>
