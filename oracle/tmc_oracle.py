@@ -217,6 +217,55 @@ def gauss_layer0_row_grads(z, mu, s, u, rows):
     return logp, dz, du
 
 
+def gauss_pair_logfactor_expanded(z: np.ndarray, mu: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """The same f[i, j] as `gauss_pair_logfactor`, with the square written out,
+        sum_d lam_d (z_id - mu_jd)^2 = sum_d lam_d z_id^2 - 2 sum_d lam_d z_id mu_jd
+                                       + sum_d lam_d mu_jd^2,
+    so that the cross term is one matrix product.  For the large configurations only
+    (K in the thousands), where the direct difference would take minutes; FP64 keeps
+    the cancellation of the three terms (each at most a few thousand) near 1e-12."""
+    z = np.asarray(z, np.float64)
+    mu = np.asarray(mu, np.float64)
+    s = np.asarray(s, np.float64)
+    lam = np.exp(-2.0 * s)
+    const = -np.sum(s) - z.shape[1] * HALF_LOG_2PI
+    zz = np.sum(lam * z * z, axis=1)
+    mm = np.sum(lam * mu * mu, axis=1)
+    cross = (z * lam) @ mu.T
+    return -0.5 * (zz[:, None] - 2.0 * cross + mm[None, :]) + const
+
+
+def gauss_chain_grads_expanded(z, mu, s, u):
+    """`gauss_chain_grads` with the factors of `gauss_pair_logfactor_expanded` and the
+    G-weighted sums over (z_i - mu_j) written as matrix products (same quantities,
+    the differences expanded):
+        dz_l[i]  = -lam * (rG_i z_l[i] - (G mu_l)_i),          rG = G 1 (row sums)
+        dmu_l[j] =  lam * ((G^T z_l)_j - cG_j mu_l[j]),         cG = G^T 1 (column sums)
+        ds_l     =  lam * (sum_i rG_i z_i^2 - 2 sum_j (G^T z_l)_j mu_j + sum_j cG_j mu_j^2)
+                    - sum_ij G_ij
+    For the large configurations.  Returns (log P, dz, dmu, ds, du) like
+    `gauss_chain_grads`."""
+    f = [gauss_pair_logfactor_expanded(z[l], mu[l], s[l]) for l in range(len(mu))]
+    logp, G, p = chain_marginals(f, u)
+    L = len(u)
+    dz = [np.zeros_like(np.asarray(a, np.float64)) for a in z]
+    dmu, ds = [], []
+    for l in range(L - 1):
+        lam = np.exp(-2.0 * np.asarray(s[l], np.float64))
+        zl = np.asarray(z[l], np.float64)
+        ml = np.asarray(mu[l], np.float64)
+        g = G[l]
+        rG = g.sum(axis=1)
+        cG = g.sum(axis=0)
+        gmu = g @ ml
+        gtz = g.T @ zl
+        dz[l] = -lam * (rG[:, None] * zl - gmu)
+        dmu.append(lam * (gtz - cG[:, None] * ml))
+        ds.append(lam * (rG @ (zl * zl) - 2.0 * np.sum(gtz * ml, axis=0) + cG @ (ml * ml))
+                  - g.sum())
+    return logp, dz, dmu, ds, [np.asarray(a) for a in p]
+
+
 def finite_difference(fun, x: np.ndarray, h: float = 1e-5, idx=None) -> np.ndarray:
     """Central differences (fun(x + h e) - fun(x - h e)) / 2h at the flat indices
     `idx` (all entries when None)."""

@@ -42,6 +42,16 @@ MUTATIONS = [
     ("hmm_log_evidence", "v = T @ v", "v = T.T @ v", P.test_hmm_evidence_by_enumeration),
     ("gauss_layer0_row_grads", "- log_k(K1) - logp)", "- logp)",
      P.test_layer0_row_grads_agree_with_full_marginals),
+    ("gauss_pair_logfactor_expanded", "- 2.0 * cross", "- cross",
+     P.test_expanded_factor_equals_direct_difference),
+    ("gauss_pair_logfactor_expanded", "mm = np.sum(lam * mu * mu, axis=1)", "mm = np.sum(mu * mu, axis=1)",
+     P.test_expanded_factor_equals_direct_difference),
+    ("gauss_chain_grads_expanded", "rG[:, None] * zl - gmu", "cG[:, None] * zl - gmu",
+     P.test_expanded_gradients_equal_direct_difference),
+    ("gauss_chain_grads_expanded", "gtz = g.T @ zl", "gtz = g @ zl",
+     P.test_expanded_gradients_equal_direct_difference),
+    ("gauss_chain_grads_expanded", "\n                  - g.sum())", ")",
+     P.test_expanded_gradients_equal_direct_difference),
 ]
 
 

@@ -327,3 +327,36 @@ def test_layer0_row_grads_agree_with_full_marginals():
     assert abs(lp - lp2) < 1e-12
     assert np.allclose(dz_r, dz[0][rows], rtol=1e-12, atol=1e-14)
     assert np.allclose(du_r, du[0][rows], rtol=1e-12, atol=1e-14)
+
+
+def test_expanded_factor_equals_direct_difference():
+    """The matrix-product form of the factor (large configurations) against the direct
+    difference and scipy's normal log-density, at the scale of the 128-wide layers
+    (|f| in the hundreds, cancelling terms in the thousands)."""
+    rng = np.random.default_rng(21)
+    z = rng.normal(0.0, 1.0, size=(48, 128)) + rng.normal(0.0, 1.0, size=128)
+    mu = np.tanh(rng.normal(size=(40, 128)))
+    s = rng.uniform(-1.0, 0.0, size=128)
+    f_dir = O.gauss_pair_logfactor(z, mu, s, chunk=7)
+    f_exp = O.gauss_pair_logfactor_expanded(z, mu, s)
+    assert np.abs(f_dir).max() > 100.0
+    np.testing.assert_allclose(f_exp, f_dir, rtol=0, atol=1e-10 * np.abs(f_dir).max())
+    zs, ms, ss = z[:3, :5], mu[:4, :5], s[:5]
+    ref = np.array([[stats.norm.logpdf(zs[i], loc=ms[j], scale=np.exp(ss)).sum()
+                     for j in range(4)] for i in range(3)])
+    np.testing.assert_allclose(O.gauss_pair_logfactor_expanded(zs, ms, ss), ref, rtol=1e-13, atol=1e-12)
+
+
+def test_expanded_gradients_equal_direct_difference():
+    """The matrix-product gradients (large configurations) equal the G-weighted
+    direct-difference sums element by element, on a chain with equal K in every layer
+    (so that a transposed marginal still has the right shape and must fail on values)."""
+    rng = np.random.default_rng(22)
+    K, D = (6, 6, 6, 6), (5, 3, 4, 2)
+    z, mu, s, u = _rand_chain(rng, K, D, scale=0.8)
+    a = O.gauss_chain_grads(z, mu, s, u, chunk=4)
+    b = O.gauss_chain_grads_expanded(z, mu, s, u)
+    assert abs(a[0] - b[0]) < 1e-12
+    for k in range(1, 5):
+        for x, y in zip(a[k], b[k]):
+            np.testing.assert_allclose(y, x, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(x).max()))
