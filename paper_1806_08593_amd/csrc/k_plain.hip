@@ -57,7 +57,15 @@ __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&x)[V]) {
 
 // ---------------------------------------------------------------------------
 // f_l[i,j] = sum_d -1/2 exp(-2 s_d) (z_id - mu_jd)^2 - sum_d s_d - D/2 ln 2 pi
-// (direct difference; tile of 32 rows x 64 columns per workgroup)
+// (direct difference; tile of 32 rows x 64 columns per workgroup).  Each term is
+// formed in the element type and summed in FP64, so the sum over d (hundreds at
+// D = 100) carries no FP32 accumulation error.  For the message pass (anchor != 0) row
+// i is stored relative to its own FP64 value at column 0,
+//   f~[i,j] = f[i,j] - a_i,   a_i = f[i,0]   (a_i written to anchor[] by the
+// workgroups of column tile 0),
+// so the element type holds differences of O(the spread of a row) instead of values
+// of O(|f|): an FP32 row near -480 keeps ~1e-6 absolute precision instead of ~3e-5.
+// With anchor == 0 (tmc_gauss_factors) f itself is written.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict__ Ls,
@@ -65,12 +73,15 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
                                                       const T* __restrict__ z,
                                                       const T* __restrict__ mu,
                                                       const T* __restrict__ s,
-                                                      T* __restrict__ f, int caller_off) {
+                                                      T* __restrict__ f, int caller_off,
+                                                      double* __restrict__ anchor) {
   constexpr int TR = kPlainFactorRows, TC = kPlainFactorCols, DC = 32;
   __shared__ T zt[TR][DC + 1];
   __shared__ T mt[TC][DC + 1];
+  __shared__ T m0[DC];
   __shared__ T lam[DC];
   __shared__ double red[kMaxWaves];
+  __shared__ double arow[TR];
   const Item it = items[blockIdx.x];
   const LayerDev& L = Ls[it.layer];
   const int K = L.K, Kc = L.Kc, D = L.D;
@@ -78,16 +89,18 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
   const int tiles_c = (Kc + TC - 1) / TC;
   const int i0 = (it.start / tiles_c) * TR, j0 = (it.start % tiles_c) * TC;
   const int tid = threadIdx.x;
+  const bool anchored = anchor != nullptr;
 
   double ssum = 0.0;
   for (int d = tid; d < D; d += blockDim.x) ssum += (double)s[so + d];
   ssum = block_sum(ssum, red);
-  const T c0 = (T)(-ssum - 0.5 * (double)D * log(2.0 * M_PI));
+  const double c0 = -ssum - 0.5 * (double)D * log(2.0 * M_PI);
 
   const int col = tid % TC, rsub = tid / TC;
-  T acc[TR / 4];
+  double acc[TR / 4];
 #pragma unroll
-  for (int q = 0; q < TR / 4; ++q) acc[q] = (T)0;
+  for (int q = 0; q < TR / 4; ++q) acc[q] = 0.0;
+  double aacc = 0.0;   // threads tid < TR: FP64 sum of row tid against column 0
 
   for (int d0 = 0; d0 < D; d0 += DC) {
     __syncthreads();
@@ -99,7 +112,10 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
       const int c = e / DC, dd = e % DC;
       mt[c][dd] = (j0 + c < Kc && d0 + dd < D) ? mu[mo + (int64_t)(j0 + c) * D + d0 + dd] : (T)0;
     }
-    if (tid < DC) lam[tid] = (d0 + tid < D) ? (T)exp(-2.0 * (double)s[so + d0 + tid]) : (T)0;
+    if (tid < DC) {
+      lam[tid] = (d0 + tid < D) ? (T)exp(-2.0 * (double)s[so + d0 + tid]) : (T)0;
+      m0[tid] = (d0 + tid < D) ? mu[mo + d0 + tid] : (T)0;
+    }
     __syncthreads();
 #pragma unroll 4
     for (int dd = 0; dd < DC; ++dd) {
@@ -107,9 +123,21 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
 #pragma unroll
       for (int q = 0; q < TR / 4; ++q) {
         const T t = zt[rsub + 4 * q][dd] - m;
-        acc[q] += l * t * t;
+        acc[q] += (double)(l * t * t);
       }
     }
+    if (anchored && tid < TR) {
+      // the same terms, in the same order, as the column-0 entry of row tid
+      for (int dd = 0; dd < DC; ++dd) {
+        const T t = zt[tid][dd] - m0[dd];
+        aacc += (double)(lam[dd] * t * t);
+      }
+    }
+  }
+  if (anchored) {
+    if (tid < TR) arow[tid] = aacc;
+    __syncthreads();
+    if (j0 == 0 && tid < TR && i0 + tid < K) anchor[L.rl_off + i0 + tid] = -0.5 * aacc + c0;
   }
   T* fb = f + (caller_off ? L.f_off : L.wf_off);
   const int j = j0 + col;
@@ -117,62 +145,77 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
 #pragma unroll
     for (int q = 0; q < TR / 4; ++q) {
       const int i = i0 + rsub + 4 * q;
-      if (i < K) fb[(int64_t)i * Kc + j] = (T)(-0.5) * acc[q] + c0;
+      if (i < K)
+        fb[(int64_t)i * Kc + j] = anchored ? (T)(-0.5 * (acc[q] - arow[rsub + 4 * q]))
+                                           : (T)(-0.5 * acc[q] + c0);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// forward message: one wave per row, 4 rows per wave, 16 rows per workgroup
+// forward message: a wave owns kPlainFwdRowsPerWave rows and streams them together,
+// one vector of V elements per lane and row per step, so that every lane has that many
+// loads in flight; each lane keeps an online (max, sum) per row over the columns it
+// reads (no cross-lane work inside the loop), merged across the wave at the end.
 // ---------------------------------------------------------------------------
-template <typename T, int V, int NCH>
-__device__ __forceinline__ T row_lse(const T* __restrict__ row, const T* __restrict__ gam, int Kc,
-                                     int lane) {
+template <typename T, int V, int R>
+__device__ __forceinline__ void rows_lse(const T* __restrict__ fb, int64_t row0, int nrow,
+                                         const T* __restrict__ gam, int Kc, int lane,
+                                         T (&lse)[R]) {
   const T NEG = (T)(-INFINITY);
-  T mrow = NEG, srow = (T)0;
-  for (int base = 0; base < Kc; base += kWave * V * NCH) {
-    T x[NCH][V];
-    T cm = NEG;
+  T m[R], sm[R];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int j = base + (c * kWave + lane) * V;
-      if (j < Kc) {
-        load_vec<T, V>(row + j, x[c]);
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          x[c][v] += gam[j + v];
-          cm = nan_max(cm, x[c][v]);
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[c][v] = NEG;
-      }
-    }
-    cm = wave_max(cm);
-    const T nm = nan_max(mrow, cm);
-    const T sh = (nm == NEG) ? (T)0 : nm;
-    T acc = (T)0;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-#pragma unroll
-      for (int v = 0; v < V; ++v) acc += fast_exp(x[c][v] - sh);
-    srow = srow * fast_exp(mrow - sh) + acc;
-    mrow = nm;
+  for (int r = 0; r < R; ++r) {
+    m[r] = NEG;
+    sm[r] = (T)0;
   }
-  srow = wave_sum(srow);
-  if (mrow != mrow) return mrow;
-  if (mrow == NEG) return NEG;
-  return mrow + fast_log(srow);
+  for (int base = 0; base < Kc; base += kWave * V) {
+    const int j = base + lane * V;
+    const bool ok = j < Kc;   // Kc % V == 0 when V > 1, so a vector is whole or absent
+    T x[R][V];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int rr = min(r, nrow - 1);   // rows past the block repeat its last row
+      if (ok) load_vec<T, V>(fb + (row0 + rr) * (int64_t)Kc + j, x[r]);
+    }
+    T g[V];
+    if (ok) load_vec<T, V>(gam + j, g);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      T cm = NEG;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        x[r][v] = ok ? x[r][v] + g[v] : NEG;
+        cm = nan_max(cm, x[r][v]);
+      }
+      const T nm = nan_max(m[r], cm);
+      const T sh = (nm == NEG) ? (T)0 : nm;
+      T acc = (T)0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc += fast_exp(x[r][v] - sh);
+      sm[r] = sm[r] * fast_exp(m[r] - sh) + acc;
+      m[r] = nm;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const T M = wave_max(m[r]);
+    const T sh = (M == NEG || M != M) ? (T)0 : M;
+    const T S = wave_sum(sm[r] * fast_exp(m[r] - sh));
+    lse[r] = (M != M) ? M : (M == NEG ? NEG : M + fast_log(S));
+  }
 }
 
-template <typename T>
+template <typename T, int V>
 __global__ __launch_bounds__(256) void k_plain_lse_fwd(const LayerDev* __restrict__ Ls,
                                                        const Item* __restrict__ items,
                                                        const T* __restrict__ f, int caller_off,
                                                        const T* __restrict__ u,
                                                        double* __restrict__ alpha,
                                                        T* __restrict__ rl,
-                                                       double* __restrict__ pairM) {
+                                                       double* __restrict__ pairM,
+                                                       const double* __restrict__ anchor) {
+  constexpr int R = kPlainFwdRowsPerWave;
   extern __shared__ unsigned char smem_raw[];
   T* gam = reinterpret_cast<T*>(smem_raw);
   __shared__ double red[kMaxWaves];
@@ -191,36 +234,39 @@ __global__ __launch_bounds__(256) void k_plain_lse_fwd(const LayerDev* __restric
   __syncthreads();
 
   const int w = tid / kWave, lane = tid % kWave;
-  const int64_t fo = caller_off ? L.f_off : L.wf_off;
-  const T* fb = f + fo;
+  const int i0 = it.start + w * R;
+  if (i0 >= K) return;
+  const int nrow = min(R, K - i0);
+  const T* fb = f + (caller_off ? L.f_off : L.wf_off);
+  T lse[R];
+  rows_lse<T, V, R>(fb, i0, nrow, gam, Kc, lane, lse);
   const double lkc = log((double)Kc);
-  constexpr int VV = sizeof(T) == 4 ? 4 : 2;
-  const bool vec_ok = (Kc % VV == 0) && (fo % VV == 0);
-  for (int r = 0; r < 4; ++r) {
-    const int i = it.start + w * 4 + r;
-    if (i >= K) break;
-    const T* row = fb + (int64_t)i * Kc;
-    T lse;
-    if (vec_ok) lse = row_lse<T, VV, 8>(row, gam, Kc, lane);
-    else lse = row_lse<T, 1, 16>(row, gam, Kc, lane);
-    if (lane == 0) {
-      rl[L.rl_off + i] = lse;
-      alpha[L.alpha_off + i] = (double)u[L.u_off + i] + M + (double)lse - lkc;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = i0 + r;
+    if (lane == r && r < nrow) {
+      rl[L.rl_off + i] = lse[r];
+      const double a = anchor ? anchor[L.rl_off + i] : 0.0;
+      alpha[L.alpha_off + i] = (double)u[L.u_off + i] + M + a + (double)lse[r] - lkc;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// backward message: a workgroup owns a strip of columns and walks every row, so the
-// column sums p_{l+1}[j] are complete inside it (no atomics, fixed order).
+// backward message: a workgroup of kPlainBwdWaves waves owns a strip of 64 V columns
+// and walks every row (wave w: rows w, w + kPlainBwdWaves, ..., kPlainBwdRowsPerStep of
+// them per step with all their loads issued first), so the column sums p_{l+1}[j] are
+// complete inside it: per-wave partial sums, then a fixed-order sum over the waves (no
+// atomics).  Reads f and writes G once per entry.
 // ---------------------------------------------------------------------------
 template <typename T, int V>
-__global__ __launch_bounds__(256) void k_plain_lse_bwd(
+__global__ __launch_bounds__(64 * kPlainBwdWaves) void k_plain_lse_bwd(
     const LayerDev* __restrict__ Ls, const Item* __restrict__ items, const T* __restrict__ f,
     int caller_off, const double* __restrict__ alpha, const T* __restrict__ rl,
     const double* __restrict__ pairM, const double* __restrict__ dlogp, T* __restrict__ p,
     T* __restrict__ gout, int g_caller_off, int scale, T* __restrict__ du) {
-  __shared__ T red[4][kWave * V];
+  constexpr int NW = kPlainBwdWaves, RS = kPlainBwdRowsPerStep;
+  __shared__ T red[NW][kWave * V];
   const Item it = items[blockIdx.x];
   const LayerDev& L = Ls[it.layer];
   const int Kc = L.Kc, K = L.K;
@@ -241,24 +287,29 @@ __global__ __launch_bounds__(256) void k_plain_lse_bwd(
   T* gb = gout + (g_caller_off ? L.f_off : L.wf_off);
   const T* pr = p + L.p_off;
   const T* rr = rl + L.rl_off;
-  for (int i = w; i < K; i += 4) {
-    const T pi = pr[i];
-    const T li = rr[i];
-    if (!active) continue;
-    T x[V];
-    if (pi == (T)0) {
+  const int jc = active ? j : 0;   // inactive lanes read column 0 of a valid row
+  for (int i0 = w; i0 < K; i0 += NW * RS) {
+    T x[RS][V], pi[RS], li[RS];
 #pragma unroll
-      for (int v = 0; v < V; ++v) x[v] = (T)0;
-    } else {
-      load_vec<T, V>(fb + (int64_t)i * Kc + j, x);
+    for (int r = 0; r < RS; ++r) {
+      const int i = min(i0 + NW * r, K - 1);   // rows past K repeat row K-1 (not stored)
+      pi[r] = pr[i];
+      li[r] = rr[i];
+      load_vec<T, V>(fb + (int64_t)i * Kc + jc, x[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      const int i = i0 + NW * r;
+      const bool live = i < K && active;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        x[v] = pi * fast_exp(x[v] + gam[v] - li);
-        cs[v] += x[v];
-        x[v] *= gs;
+        // p_i == 0 (a row outside the support) gives G = 0 even where exp overflows
+        const T gv = (pi[r] == (T)0) ? (T)0 : pi[r] * fast_exp(x[r][v] + gam[v] - li[r]);
+        cs[v] += live ? gv : (T)0;
+        x[r][v] = gv * gs;
       }
+      if (gout && live) store_vec<T, V>(gb + (int64_t)i * Kc + j, x[r]);
     }
-    if (gout) store_vec<T, V>(gb + (int64_t)i * Kc + j, x);
   }
 #pragma unroll
   for (int v = 0; v < V; ++v) red[w][lane * V + v] = cs[v];
@@ -266,8 +317,9 @@ __global__ __launch_bounds__(256) void k_plain_lse_bwd(
   if (w == 0 && active) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      const T t = red[0][lane * V + v] + red[1][lane * V + v] + red[2][lane * V + v] +
-                  red[3][lane * V + v];
+      T t = red[0][lane * V + v];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) t += red[q][lane * V + v];
       p[L.p_up_off + j + v] = t;
       if (du) du[L.u_up_off + j + v] = (T)(g * (double)t);
     }
@@ -436,21 +488,26 @@ __global__ __launch_bounds__(256) void k_pair_dsp(const LayerDev* __restrict__ L
 template <typename T>
 hipError_t launch_plain_factor(const LayerDev* layers, const Item* items, int n_items,
                                const T* z, const T* mu, const T* s, T* f, bool caller_off,
-                               hipStream_t st) {
+                               double* anchor, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_plain_factor<T>, dim3(n_items), dim3(256), 0, st, layers, items, z, mu, s,
-                     f, (int)caller_off);
+                     f, (int)caller_off, anchor);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_plain_lse_fwd(const LayerDev* layers, const Item* items, int n_items, int max_kc,
-                                const T* f, bool caller_off, const T* u, double* alpha, T* rl,
-                                double* pairM, hipStream_t st) {
+                                int vec, const T* f, bool caller_off, const T* u, double* alpha,
+                                T* rl, double* pairM, const double* anchor, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
+  constexpr int VV = sizeof(T) == 4 ? 4 : 2;
   const size_t smem = (size_t)max_kc * sizeof(T);
-  hipLaunchKernelGGL(k_plain_lse_fwd<T>, dim3(n_items), dim3(256), smem, st, layers, items, f,
-                     (int)caller_off, u, alpha, rl, pairM);
+  if (vec)
+    hipLaunchKernelGGL((k_plain_lse_fwd<T, VV>), dim3(n_items), dim3(256), smem, st, layers, items,
+                       f, (int)caller_off, u, alpha, rl, pairM, anchor);
+  else
+    hipLaunchKernelGGL((k_plain_lse_fwd<T, 1>), dim3(n_items), dim3(256), smem, st, layers, items,
+                       f, (int)caller_off, u, alpha, rl, pairM, anchor);
   return hipGetLastError();
 }
 
@@ -462,11 +519,11 @@ hipError_t launch_plain_lse_bwd(const LayerDev* layers, const Item* items, int n
   if (n_items <= 0) return hipSuccess;
   constexpr int VV = sizeof(T) == 4 ? 4 : 2;
   if (vec)
-    hipLaunchKernelGGL((k_plain_lse_bwd<T, VV>), dim3(n_items), dim3(256), 0, st, layers, items, f,
+    hipLaunchKernelGGL((k_plain_lse_bwd<T, VV>), dim3(n_items), dim3(64 * kPlainBwdWaves), 0, st, layers, items, f,
                        (int)caller_off, alpha, rl, pairM, dlogp, p, g_out, (int)g_caller_off,
                        (int)scale_by_dlogp, du);
   else
-    hipLaunchKernelGGL((k_plain_lse_bwd<T, 1>), dim3(n_items), dim3(256), 0, st, layers, items, f,
+    hipLaunchKernelGGL((k_plain_lse_bwd<T, 1>), dim3(n_items), dim3(64 * kPlainBwdWaves), 0, st, layers, items, f,
                        (int)caller_off, alpha, rl, pairM, dlogp, p, g_out, (int)g_caller_off,
                        (int)scale_by_dlogp, du);
   return hipGetLastError();
@@ -504,10 +561,10 @@ hipError_t launch_pair_dsp(const LayerDev* layers, const int* pair_ids, int n_pa
 
 #define TMC_INST(T)                                                                              \
   template hipError_t launch_plain_factor<T>(const LayerDev*, const Item*, int, const T*,        \
-                                             const T*, const T*, T*, bool, hipStream_t);         \
-  template hipError_t launch_plain_lse_fwd<T>(const LayerDev*, const Item*, int, int, const T*,  \
-                                              bool, const T*, double*, T*, double*,              \
-                                              hipStream_t);                                      \
+                                             const T*, const T*, T*, bool, double*, hipStream_t); \
+  template hipError_t launch_plain_lse_fwd<T>(const LayerDev*, const Item*, int, int, int,       \
+                                              const T*, bool, const T*, double*, T*, double*,    \
+                                              const double*, hipStream_t);                       \
   template hipError_t launch_plain_lse_bwd<T>(const LayerDev*, const Item*, int, int, const T*,  \
                                               bool, const double*, const T*, const double*,      \
                                               const double*, T*, T*, bool, bool, T*,             \

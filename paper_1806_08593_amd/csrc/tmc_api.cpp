@@ -87,6 +87,7 @@ struct tmc_plan {
   Launch factor;                              // all pairs, factor tiles
   std::vector<Launch> fwd, bwd_vec, bwd_sca;  // per depth step
   std::vector<int> fwd_maxkc;
+  std::vector<char> fwd_vec_ws, fwd_vec_caller;   // plain forward: vector loads allowed
   Launch gmu, gtz;
   int n_pairs = 0, pair_ids_off = 0;
   int n_slots = 0, slot_layers_off = 0, slot_start_off = 0, slot_D_off = 0;
@@ -357,6 +358,7 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
     W.wf = take(sum_pairKK * esz);
     W.wg = take(sum_pairKK * esz);
     W.gtz = take(sum_pairKcD * esz);
+    W.anchor = take(sumK * 8);
   }
   W.total = o;
 
@@ -367,6 +369,8 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   const int D1 = P->max_depth - 1;
   P->fwd.assign(std::max(D1, 0), Launch{});
   P->fwd_maxkc.assign(std::max(D1, 0), 0);
+  P->fwd_vec_ws.assign(std::max(D1, 0), 1);
+  P->fwd_vec_caller.assign(std::max(D1, 0), 1);
   P->bwd_vec.assign(std::max(D1, 0), Launch{});
   P->bwd_sca.assign(std::max(D1, 0), Launch{});
   std::vector<int> pairs;
@@ -398,6 +402,9 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
         const int L = P->chains_h[d.chain].L;
         if (d.depth != L - 2 - t) continue;
         P->fwd_maxkc[t] = std::max(P->fwd_maxkc[t], d.Kc);
+        const int VVf = esz == 4 ? 4 : 2;
+        if (d.Kc % VVf != 0 || d.wf_off % VVf != 0) P->fwd_vec_ws[t] = 0;
+        if (d.Kc % VVf != 0 || d.f_off % VVf != 0) P->fwd_vec_caller[t] = 0;
         for (int r = 0; r < d.K; r += kPlainFwdRowsPerBlock) items.push_back({l, r});
       }
       end(P->fwd[t]);
@@ -557,13 +564,18 @@ tmc_status plain_fwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, co
   const bool caller = f_caller != nullptr;
   T* wf = wsp<T>(ws, W.wf);
   const T* f = caller ? f_caller : wf;
+  // stored factors are anchored per row (FP64 anchors in the workspace); a caller's
+  // factors are read as given
+  double* anchor = caller ? nullptr : wsp<double>(ws, W.anchor);
   if (!caller && P->factor.n > 0)
-    LAUNCH_KC(TMC_KC_PLAIN_FACTOR, launch_plain_factor<T>(P->layers_d, it + P->factor.off, P->factor.n, z, mu, s, wf, false, st));
+    LAUNCH_KC(TMC_KC_PLAIN_FACTOR, launch_plain_factor<T>(P->layers_d, it + P->factor.off, P->factor.n, z, mu, s, wf, false,
+                                                          anchor, st));
   LAUNCH(launch_init_top<T>(P->chains_d, P->n_chains, P->layers_d, u, wsp<double>(ws, W.alpha), st));
   for (size_t t = 0; t < P->fwd.size(); ++t)
-    LAUNCH_KC(TMC_KC_PLAIN_LSE_FWD, launch_plain_lse_fwd<T>(P->layers_d, it + P->fwd[t].off, P->fwd[t].n, P->fwd_maxkc[t], f,
+    LAUNCH_KC(TMC_KC_PLAIN_LSE_FWD, launch_plain_lse_fwd<T>(P->layers_d, it + P->fwd[t].off, P->fwd[t].n, P->fwd_maxkc[t],
+                                   caller ? P->fwd_vec_caller[t] : P->fwd_vec_ws[t], f,
                                    caller, u, wsp<double>(ws, W.alpha), wsp<T>(ws, W.rl),
-                                   wsp<double>(ws, W.pairM), st));
+                                   wsp<double>(ws, W.pairM), anchor, st));
   LAUNCH(launch_finalize(P->chains_d, P->n_chains, P->layers_d, wsp<double>(ws, W.alpha), logp,
                          wsp<double>(ws, W.logp), P->flag_d, st));
   return TMC_OK;
@@ -868,10 +880,10 @@ tmc_status tmc_gauss_factors(tmc_plan_t plan, const void* z, const void* mu, con
     tmc_plan* P = plan;
     if (plan->prec == TMC_FP64)
       LAUNCH(launch_plain_factor<double>(plan->layers_d, it, plan->factor.n, (const double*)z,
-                                         (const double*)mu, (const double*)s, (double*)f, true, st));
+                                         (const double*)mu, (const double*)s, (double*)f, true, nullptr, st));
     else
       LAUNCH(launch_plain_factor<float>(plan->layers_d, it, plan->factor.n, (const float*)z,
-                                        (const float*)mu, (const float*)s, (float*)f, true, st));
+                                        (const float*)mu, (const float*)s, (float*)f, true, nullptr, st));
     return TMC_OK;
   } catch (...) {
     return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");

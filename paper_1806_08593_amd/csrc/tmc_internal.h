@@ -58,6 +58,7 @@ struct ChainDev {
 struct WsLayout {
   size_t alpha, p, rl, pairM, logp, wmax;
   size_t wf, wg, gtz, dsp;          // plain engine (dsp shared)
+  size_t anchor;                    // plain engine: FP64 row anchors of the stored factors
   size_t ev, lam, q, cnt;           // fused engine (cnt: int counters of persistent launches)
   size_t total;
 };

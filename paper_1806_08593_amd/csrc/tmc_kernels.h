@@ -25,11 +25,12 @@ hipError_t launch_ds_reduce(const int64_t* part_off, const int* slot_start, cons
 template <typename T>
 hipError_t launch_plain_factor(const LayerDev* layers, const Item* items, int n_items,
                                const T* z, const T* mu, const T* s, T* f, bool caller_off,
-                               hipStream_t st);
+                               double* anchor, hipStream_t st);
 template <typename T>
 hipError_t launch_plain_lse_fwd(const LayerDev* layers, const Item* items, int n_items,
-                                int max_kc, const T* f, bool caller_off, const T* u, double* alpha, T* rl,
-                                double* pairM, hipStream_t st);
+                                int max_kc, int vec, const T* f, bool caller_off, const T* u,
+                                double* alpha, T* rl, double* pairM, const double* anchor,
+                                hipStream_t st);
 template <typename T>
 hipError_t launch_plain_lse_bwd(const LayerDev* layers, const Item* items, int n_items, int vec,
                                 const T* f, bool caller_off, const double* alpha,
@@ -51,7 +52,10 @@ hipError_t launch_pair_dsp(const LayerDev* layers, const int* pair_ids, int n_pa
 
 // plain tiling constants (host and device agree)
 constexpr int kPlainFactorRows = 32, kPlainFactorCols = 64;
-constexpr int kPlainFwdRowsPerBlock = 16;      // 4 waves x 4 rows
+constexpr int kPlainFwdRowsPerWave = 8;        // rows a forward wave streams together
+constexpr int kPlainFwdRowsPerBlock = 32;      // 4 waves x 8 rows
+constexpr int kPlainBwdWaves = 16;             // waves of a backward workgroup (one column strip)
+constexpr int kPlainBwdRowsPerStep = 4;        // rows a backward wave loads before using them
 constexpr int kPlainBwdColsScalar = 64;        // one column per lane
 constexpr int kPlainBwdColsVec = 256;          // four columns per lane (float4 / 2x double2)
 constexpr int kPlainGemmRows = 32, kPlainGemmD = 64;
