@@ -58,6 +58,44 @@ def oracle_grads(chains):
     return res
 
 
+def elem_err(got, ref):
+    """max_k |got_k - ref_k| / max_k |ref_k| over one block (0 for an all-zero block that
+    is matched exactly)."""
+    got = np.asarray(got, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    d = np.abs(got - ref).max() if ref.size else 0.0
+    scale = np.abs(ref).max() if ref.size else 0.0
+    return float(d / scale) if scale > 0 else float(d)
+
+
+def assert_elem(got, ref, atol_frac, rtol, label):
+    """Element-wise parity of one block: |got - ref| <= atol_frac * max|ref| + rtol * |ref|
+    for every element (NaN fails).  Prints the block-scaled maximum error on a line
+    starting with ERRREC, so a run with -s records the measured errors."""
+    got = np.asarray(got, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    assert got.shape == ref.shape, (label, got.shape, ref.shape)
+    scale = np.abs(ref).max() if ref.size else 0.0
+    bound = atol_frac * scale + rtol * np.abs(ref)
+    err = np.abs(got - ref)
+    e = elem_err(got, ref)
+    print(f"ERRREC {label} {e:.3e}")
+    bad = ~(err <= bound)
+    if bad.any():
+        k = int(np.argmax(np.where(bad, err - bound, -np.inf)))
+        raise AssertionError(f"{label}: element {k} got {got[k]!r} ref {ref[k]!r} "
+                             f"(|d| {err[k]:.3e} > bound {bound[k]:.3e}; block max|ref| {scale:.3e}; "
+                             f"{int(bad.sum())} of {bad.size} outside)")
+    return e
+
+
+# Element-wise gradient tolerances (atol as a fraction of the block's max |ref|, rtol),
+# per arithmetic mode: about five times the largest block-scaled error measured over
+# every gradient block of the GPU parity tests (FP64 2.5e-13, FP32 fused 8.0e-6, FP32
+# plain 3.5e-6, BF16X3 9.5e-5), rounded up.
+GRAD_ELEM_TOL = {"fp64": (1e-11, 1e-10), "fp32": (5e-5, 1e-4), "bf16x3": (5e-4, 5e-3)}
+
+
 def rel_l2(a, b):
     a = np.asarray(a, np.float64).reshape(-1)
     b = np.asarray(b, np.float64).reshape(-1)
