@@ -152,6 +152,30 @@ __device__ __forceinline__ void interleave_mfma() {
   }
 }
 
+// Scheduling hints of the pipelined sweep.  Phase A: the factor-GEMM MFMAs of the next
+// tile (two LDS fragment reads ahead of every three MFMAs) with the exponentials and
+// operand splits of the current tile between them.  Phase B: the second-GEMM MFMAs
+// with the staging of a later tile (VALU and LDS writes) between them.
+template <int NMFMA, int NVALU>
+__device__ __forceinline__ void interleave_phase_a() {
+#pragma unroll
+  for (int i = 0; i < NMFMA; ++i) {
+    if (i % 3 == 0) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // LDS read
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                   // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x002, NVALU, 0);               // VALU
+  }
+}
+template <int NMFMA>
+__device__ __forceinline__ void interleave_phase_b() {
+#pragma unroll
+  for (int i = 0; i < NMFMA; ++i) {
+    if (i % 6 == 0) __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);   // LDS read
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                   // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);                   // VALU
+    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);                   // LDS write
+  }
+}
+
 template <int PREC>
 struct Frag;
 template <>
@@ -690,8 +714,13 @@ __device__ __forceinline__ void wave_load(const float* __restrict__ base, int64_
 template <int PREC, int NKC>
 constexpr int kGemmMfma = NKC * (PREC == TMC_BF16X3 ? 3 : 8);
 
+// LDS stages of a sweep: three for BF16X3 at d <= 128 with one subtile per stage (the
+// pipelined sweep, below), two otherwise at d <= 128, one for wider layers.
+template <int PREC, int NKC, int NS>
+constexpr int kStages = NKC <= 8 ? ((PREC == TMC_BF16X3 && NS == 1) ? 3 : 2) : 1;
+
 template <int PREC, int NKC, bool GRAD, int NS>
-using FwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), GRAD && PREC != TMC_BF16X3>;
+using FwdSmem = TileSmem<PREC, NKC, NS, kStages<PREC, NKC, NS>, GRAD && PREC != TMC_BF16X3>;
 
 template <int PREC, int NKC, bool GRAD, int NS, int WV>
 __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const Item it,
@@ -764,14 +793,6 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       if (qwriter && tid % TPR == 0 && j < L.Kc) qcol[L.q_off + j] = qs[sb];
     }
   };
-  {
-    double qs[NS];
-    stage(0, 0, qs);
-    store_q(0, qs);
-  }
-  if (nt > 1) fetch_cols(pf, L, mu, alpha, 32 * NS);
-  lds_barrier();
-
   float m = -INFINITY, ssum = 0.0f;
   f32x16 O[GRAD ? ND32 : 1];
 #pragma unroll
@@ -780,8 +801,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
     for (int v = 0; v < 16; ++v) O[q][v] = 0.0f;
 
   // S[j][i] over the staged tile in buffer cur
-  auto s_gemm = [&](auto bc, f32x16 (&S)[NS]) {
-    constexpr int cur = decltype(bc)::value;
+  auto s_gemm = [&](int cur, f32x16 (&S)[NS]) {
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
@@ -795,10 +815,9 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
         mma_chunk<PREC>(S[sb], Bf, A[kc]);     // S[j][i]
       }
   };
-  // online log-sum-exp over the tile and (GRAD) the softmax-weighted sum of mu
-  auto softmax_e = [&](auto bc, f32x16 (&S)[NS]) {
-    constexpr int cur = decltype(bc)::value;
-    float x[NS][16];
+  // online log-sum-exp, first half: x = S + gamma and the running max of the tile (a
+  // rescale of the running sums when it grows by more than kRescale, rare)
+  auto soft_max = [&](int cur, const f32x16 (&S)[NS], float (&x)[NS][16]) {
     float tmax = -INFINITY;
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb)
@@ -829,80 +848,151 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       }
       m = mn;
     }
+  };
+  // second half: the exponentials, their sum and (GRAD) the split operand of the
+  // softmax-weighted sum of mu
+  auto soft_exp = [&](float (&x)[NS][16], PFrag<PREC> (&P)[NS]) {
     const float msafe = (m == -INFINITY) ? 0.0f : m;
-    float p[NS][16];
     float ps = 0.0f;
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        p[sb][v] = __builtin_amdgcn_exp2f(x[sb][v] - msafe);
-        ps += p[sb][v];
+        x[sb][v] = __builtin_amdgcn_exp2f(x[sb][v] - msafe);
+        ps += x[sb][v];
       }
     ssum += ps;
     if (GRAD) {
-      PFrag<PREC> P[NS];
 #pragma unroll
-      for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(p[sb], P[sb]);
-#pragma unroll
-      for (int q = 0; q < ND32; ++q)
-#pragma unroll
-        for (int sb = 0; sb < NS; ++sb) {
-          TFrag<PREC> Tf;
-          if constexpr (PREC == TMC_BF16X3)
-            tile_rowT_frag<TS>(T, cur, sb, q, Tf);   // transpose reads of the row copy
-          else
-            tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
-          mma_t<PREC>(O[q], Tf, P[sb]);
-        }
+      for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(x[sb], P[sb]);
     }
   };
-  // One tile.  Double-buffered: the S MFMAs are issued first, and the next stage is
-  // written to the idle buffer behind them (straight-line code, so the scheduler can
-  // interleave the staging with the MFMAs); past the last tile that stage repeats data
-  // into a buffer that is never read again.
-  auto tile = [&](auto bc, int t) {
-    constexpr int cur = decltype(bc)::value;
-    if constexpr (NB == 2) {
+  // O[d][i] += sum_j mu_j[d] P[j][i] over the staged tile in buffer cur
+  auto o_gemm = [&](int cur, const PFrag<PREC> (&P)[NS]) {
+#pragma unroll
+    for (int q = 0; q < ND32; ++q)
+#pragma unroll
+      for (int sb = 0; sb < NS; ++sb) {
+        TFrag<PREC> Tf;
+        if constexpr (PREC == TMC_BF16X3)
+          tile_rowT_frag<TS>(T, cur, sb, q, Tf);   // transpose reads of the row copy
+        else
+          tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+        mma_t<PREC>(O[q], Tf, P[sb]);
+      }
+  };
+  auto softmax_e = [&](int cur, const f32x16 (&S)[NS]) {
+    float x[NS][16];
+    PFrag<PREC> P[NS];
+    soft_max(cur, S, x);
+    soft_exp(x, P);
+    if (GRAD) o_gemm(cur, P);
+  };
+
+  if constexpr (NB == 3) {
+    // Pipelined sweep over three LDS stages.  While the wave works on tile t, tile t+1
+    // is already staged and tile t+2 is being staged: phase A issues the factor-GEMM
+    // MFMAs of tile t+1 and, between them, the exponentials of tile t; phase B issues
+    // the second-GEMM MFMAs of tile t and, between them, the staging of tile t+2 (and
+    // the fetch of tile t+3).  So the matrix cores and the vector ALU of a wave work
+    // at the same time instead of in turns.  Stage b of tile t is t mod 3; every
+    // access past the last tile is in bounds (clamped fetches) and its results are
+    // never read.  Rows past K compute on clamped rows and are discarded at the end.
+    {
       double qs[NS];
-      if (active) {
-        f32x16 S[NS];
-        s_gemm(bc, S);
-        stage(cur ^ 1, 32 * NS * (t + 1), qs);
-        interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
-        if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
-        softmax_e(bc, S);
-      } else {
-        stage(cur ^ 1, 32 * NS * (t + 1), qs);
-        if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
-      }
-      store_q(32 * NS * (t + 1), qs);
-      lds_barrier();
-    } else {
-      if (active) {
-        f32x16 S[NS];
-        s_gemm(bc, S);
-        softmax_e(bc, S);
-      }
-      lds_barrier();
-      if (t + 1 < nt) {
-        double qs[NS];
-        stage(0, 32 * NS * (t + 1), qs);
-        store_q(32 * NS * (t + 1), qs);
-        if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
-        lds_barrier();
-      }
+      stage(0, 0, qs);
+      store_q(0, qs);
     }
-  };
-  if constexpr (NB == 2) {
-    int t = 0;
-    for (; t + 1 < nt; t += 2) {
-      tile(std::integral_constant<int, 0>{}, t);
-      tile(std::integral_constant<int, 1>{}, t + 1);
+    fetch_cols(pf, L, mu, alpha, 32 * NS);
+    lds_barrier();                                   // tile 0 visible
+    {
+      double qs[NS];
+      stage(1, 32 * NS, qs);
+      store_q(32 * NS, qs);
     }
-    if (t < nt) tile(std::integral_constant<int, 0>{}, t);
+    fetch_cols(pf, L, mu, alpha, 64 * NS);
+    f32x16 S[NS];
+    s_gemm(0, S);
+    lds_barrier();                                   // tile 1 visible
+    int cur = 0;
+    for (int t = 0; t < nt; ++t) {
+      const int nxt = cur == 2 ? 0 : cur + 1;
+      const int stg = nxt == 2 ? 0 : nxt + 1;
+      float x[NS][16];
+      soft_max(cur, S, x);
+      // phase A
+      f32x16 Sn[NS];
+      PFrag<PREC> P[NS];
+      s_gemm(nxt, Sn);
+      soft_exp(x, P);
+      interleave_phase_a<kGemmMfma<PREC, NKC> * NS, 8>();
+      // phase B
+      double qs[NS];
+      if (GRAD) o_gemm(cur, P);
+      stage(stg, 32 * NS * (t + 2), qs);
+      fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 3));
+      if (GRAD) interleave_phase_b<ND32 * NS * 2 * (PREC == TMC_BF16X3 ? 3 : 8)>();
+      store_q(32 * NS * (t + 2), qs);
+      lds_barrier();
+#pragma unroll
+      for (int sb = 0; sb < NS; ++sb) S[sb] = Sn[sb];
+      cur = nxt;
+    }
   } else {
-    for (int t = 0; t < nt; ++t) tile(std::integral_constant<int, 0>{}, t);
+    {
+      double qs[NS];
+      stage(0, 0, qs);
+      store_q(0, qs);
+    }
+    if (nt > 1) fetch_cols(pf, L, mu, alpha, 32 * NS);
+    lds_barrier();
+    // One tile.  Double-buffered: the S MFMAs are issued first, and the next stage is
+    // written to the idle buffer behind them (straight-line code, so the scheduler can
+    // interleave the staging with the MFMAs); past the last tile that stage repeats
+    // data into a buffer that is never read again.
+    auto tile = [&](auto bc, int t) {
+      constexpr int cur = decltype(bc)::value;
+      if constexpr (NB == 2) {
+        double qs[NS];
+        if (active) {
+          f32x16 S[NS];
+          s_gemm(cur, S);
+          stage(cur ^ 1, 32 * NS * (t + 1), qs);
+          interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
+          if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
+          softmax_e(cur, S);
+        } else {
+          stage(cur ^ 1, 32 * NS * (t + 1), qs);
+          if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
+        }
+        store_q(32 * NS * (t + 1), qs);
+        lds_barrier();
+      } else {
+        if (active) {
+          f32x16 S[NS];
+          s_gemm(cur, S);
+          softmax_e(cur, S);
+        }
+        lds_barrier();
+        if (t + 1 < nt) {
+          double qs[NS];
+          stage(0, 32 * NS * (t + 1), qs);
+          store_q(32 * NS * (t + 1), qs);
+          if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
+          lds_barrier();
+        }
+      }
+    };
+    if constexpr (NB == 2) {
+      int t = 0;
+      for (; t + 1 < nt; t += 2) {
+        tile(std::integral_constant<int, 0>{}, t);
+        tile(std::integral_constant<int, 1>{}, t + 1);
+      }
+      if (t < nt) tile(std::integral_constant<int, 0>{}, t);
+    } else {
+      for (int t = 0; t < nt; ++t) tile(std::integral_constant<int, 0>{}, t);
+    }
   }
   const float stot = xor32_sum(ssum);
   float ell;
@@ -1013,7 +1103,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
 // The constant c cancels between the forward's ell_i and G, so it is not needed here.
 // ---------------------------------------------------------------------------
 template <int PREC, int NKC, int NS>
-using BwdSmem = TileSmem<PREC, NKC, NS, (NKC <= 8 ? 2 : 1), PREC != TMC_BF16X3>;
+using BwdSmem = TileSmem<PREC, NKC, NS, kStages<PREC, NKC, NS>, PREC != TMC_BF16X3>;
 
 template <int PREC, int NKC, int NS, int WV>
 __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD, const Item it,
@@ -1120,10 +1210,6 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       }
     }
   };
-  stage(0, own(0));
-  if (nt > 1) fetch_rows(pf, L, z, lamrow, 32 * NS, evp, p, own(1));
-  lds_barrier();
-
   f32x16 GT[ND32];
 #pragma unroll
   for (int q = 0; q < ND32; ++q)
@@ -1132,8 +1218,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   float csum = 0.0f;
 
   // S[i][j] over the staged row tile in buffer cur
-  auto s_gemm = [&](auto bc, f32x16 (&S)[NS]) {
-    constexpr int cur = decltype(bc)::value;
+  auto s_gemm = [&](int cur, f32x16 (&S)[NS]) {
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
@@ -1147,9 +1232,8 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
         mma_chunk<PREC>(S[sb], Af, Bf[kc]);    // S[i][j]
       }
   };
-  // pairwise marginals of the tile, their column sums and G^T z
-  auto marg = [&](auto bc, f32x16 (&S)[NS]) {
-    constexpr int cur = decltype(bc)::value;
+  // pairwise marginals of the tile, their column sums, and the split G operand
+  auto marg_exp = [&](int cur, const f32x16 (&S)[NS], PFrag<PREC> (&P)[NS]) {
     float g[NS][16];
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb)
@@ -1165,9 +1249,11 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
     for (int sb = 0; sb < NS; ++sb)
 #pragma unroll
       for (int v = 0; v < 16; ++v) csum += g[sb][v];
-    PFrag<PREC> P[NS];
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb) make_pfrag<PREC>(g[sb], P[sb]);
+  };
+  // G^T z over the staged row tile in buffer cur
+  auto gt_gemm = [&](int cur, const PFrag<PREC> (&P)[NS]) {
 #pragma unroll
     for (int q = 0; q < ND32; ++q)
 #pragma unroll
@@ -1180,45 +1266,90 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
         mma_t<PREC>(GT[q], Tf, P[sb]);
       }
   };
-  // One tile (see the forward: S MFMAs first, the next stage behind them).
-  auto tile = [&](auto bc, int t) {
-    constexpr int cur = decltype(bc)::value;
-    if constexpr (NB == 2) {
-      if (active) {
-        f32x16 S[NS];
-        s_gemm(bc, S);
-        stage(cur ^ 1, t + 1 < nt && own(t + 1));
-        interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
-        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
-        marg(bc, S);
-      } else {
-        stage(cur ^ 1, t + 1 < nt && own(t + 1));
-        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
-      }
-      lds_barrier();
-    } else {
-      if (active) {
-        f32x16 S[NS];
-        s_gemm(bc, S);
-        marg(bc, S);
-      }
-      lds_barrier();
-      if (t + 1 < nt) {
-        stage(0, own(t + 1));
-        if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
-        lds_barrier();
-      }
-    }
+  auto marg = [&](int cur, const f32x16 (&S)[NS]) {
+    PFrag<PREC> P[NS];
+    marg_exp(cur, S, P);
+    gt_gemm(cur, P);
   };
-  if constexpr (NB == 2) {
-    int t = 0;
-    for (; t + 1 < nt; t += 2) {
-      tile(std::integral_constant<int, 0>{}, t);
-      tile(std::integral_constant<int, 1>{}, t + 1);
+
+  if constexpr (NB == 3) {
+    // Pipelined sweep over three LDS stages (see the forward): phase A issues the
+    // factor-GEMM MFMAs of tile t+1 with the marginals of tile t between them, phase B
+    // the G^T z MFMAs of tile t with the staging of tile t+2 (row terms included) and
+    // the fetch of tile t+3 between them.  Columns past Kc compute on clamped columns
+    // with gamma = -inf (zero marginals) and are discarded in the epilogue.
+    stage(0, own(0));
+    fetch_rows(pf, L, z, lamrow, 32 * NS, evp, p, nt > 1 && own(1));
+    lds_barrier();                                   // tile 0 visible
+    stage(1, nt > 1 && own(1));
+    fetch_rows(pf, L, z, lamrow, 64 * NS, evp, p, nt > 2 && own(2));
+    f32x16 S[NS];
+    s_gemm(0, S);
+    lds_barrier();                                   // tile 1 visible
+    int cur = 0;
+    for (int t = 0; t < nt; ++t) {
+      const int nxt = cur == 2 ? 0 : cur + 1;
+      const int stg = nxt == 2 ? 0 : nxt + 1;
+      // phase A
+      f32x16 Sn[NS];
+      PFrag<PREC> P[NS];
+      s_gemm(nxt, Sn);
+      marg_exp(cur, S, P);
+      interleave_phase_a<kGemmMfma<PREC, NKC> * NS, 8>();
+      // phase B
+      gt_gemm(cur, P);
+      stage(stg, t + 2 < nt && own(t + 2));
+      fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 3), evp, p, t + 3 < nt && own(t + 3));
+      interleave_phase_b<ND32 * NS * 2 * (PREC == TMC_BF16X3 ? 3 : 8)>();
+      lds_barrier();
+#pragma unroll
+      for (int sb = 0; sb < NS; ++sb) S[sb] = Sn[sb];
+      cur = nxt;
     }
-    if (t < nt) tile(std::integral_constant<int, 0>{}, t);
   } else {
-    for (int t = 0; t < nt; ++t) tile(std::integral_constant<int, 0>{}, t);
+    stage(0, own(0));
+    if (nt > 1) fetch_rows(pf, L, z, lamrow, 32 * NS, evp, p, own(1));
+    lds_barrier();
+    // One tile (see the forward: S MFMAs first, the next stage behind them).
+    auto tile = [&](auto bc, int t) {
+      constexpr int cur = decltype(bc)::value;
+      if constexpr (NB == 2) {
+        if (active) {
+          f32x16 S[NS];
+          s_gemm(cur, S);
+          stage(cur ^ 1, t + 1 < nt && own(t + 1));
+          interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
+          if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
+          marg(cur, S);
+        } else {
+          stage(cur ^ 1, t + 1 < nt && own(t + 1));
+          if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
+        }
+        lds_barrier();
+      } else {
+        if (active) {
+          f32x16 S[NS];
+          s_gemm(cur, S);
+          marg(cur, S);
+        }
+        lds_barrier();
+        if (t + 1 < nt) {
+          stage(0, own(t + 1));
+          if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
+          lds_barrier();
+        }
+      }
+    };
+    if constexpr (NB == 2) {
+      int t = 0;
+      for (; t + 1 < nt; t += 2) {
+        tile(std::integral_constant<int, 0>{}, t);
+        tile(std::integral_constant<int, 1>{}, t + 1);
+      }
+      if (t < nt) tile(std::integral_constant<int, 0>{}, t);
+    } else {
+      for (int t = 0; t < nt; ++t) tile(std::integral_constant<int, 0>{}, t);
+    }
   }
 
   // ---- column epilogue: marginals of layer l+1, dmu, column part of ds ----
