@@ -6,18 +6,23 @@ of synthetic inputs already resident in device memory: the pairwise factors on
 MFMA, the top-down log-sum-exp messages, the FP64 log-normaliser, the pairwise
 marginals and the gradients with respect to z, mu, s and u.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5]
                     [--precision bf16x3|fp32|fp64] [--engine auto|fused|plain]
                     [--no-compare] [--no-cpu-baseline] [--calibrate-copy MB]
 
-Prints one JSON line.  `value` is factor entries per second (a step processes the
-sum over chains and adjacent layer pairs of K_l * K_{l+1} entries); the timed steps
-replay the forward and backward graphs captured from the library's launches
-(--no-graph: eager launches).  `roofline` describes the kernel class with the largest
-device time in a second region of eager steps, timed with HIP events that the
-library records around each of its launches on the stream it launches on.  `compare` times the same step in the other precisions / engines
-and gives each one's error against the FP64 oracle; `cpu_baseline` times the FP64
-oracle on a bounded sample of the workload on the host.
+Prints one JSON line.  The default workload is the large-K chain (B=32, L=8, K=2048,
+D=128, BF16X3 factor products): the largest configuration, on one GPU.  `value` is
+factor entries per second (a step processes the sum over chains and adjacent layer
+pairs of K_l * K_{l+1} entries); the timed steps replay the forward and backward graphs
+captured from the library's launches (--no-graph: eager launches).  `roofline`
+describes the kernel class with the largest device time in a second region of eager
+steps, timed with HIP events that the library records around each of its launches on
+the stream it launches on.  `compare` times the same step in the FP32 forms (fused, and
+plain with stored factors, whose log-sum-exp passes stream more than a gigabyte of
+factors: their HBM rates are reported), and the mixed-precision configuration
+(B=256, L=6, K=256, D=100); every form's log P is compared with the FP64 oracle on
+every instance.  `cpu_baseline` times the FP64 oracle, as it is, on a bounded sample of
+the workload across the host's cores.
 """
 import argparse
 import json
@@ -29,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LOGP_TOL = {"fp64": None, "fp32": 1e-4, "bf16x3": 2e-3}   # absolute, per instance
 # dense peaks of MI355X (TFLOP/s): matrix cores by operand type; vector ALU without
 # packed FP32 (256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz)
 MFMA_PEAK = {"bf16x3": 2500.0, "fp32": 157.3, "fp64": 78.6}
@@ -58,7 +64,8 @@ def algorithmic(kc_name, entries, d_weighted, prec):
 # Sources whose compiled code the fused kernels are (their hash dates a counter record).
 KERNEL_SOURCES = ["fused_kernels.h", "k_fused_inst.inc", "k_fused_bf16.hip", "k_fused_f32.hip",
                   "dev_util.h", "tmc_internal.h"]
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "fused_c3_bf16x3_pmc.md")
+def traffic_record_path(workload, prec):
+    return os.path.join(ROOT, "profiles", f"fused_{workload}_{prec}_pmc.md")
 
 
 def kernel_sources_sha256():
@@ -70,30 +77,41 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, workload, prec, waves=4):
-    """(read bytes, written bytes) per launch of `kernel` in its `waves`-wave form from the
-    committed counter record, or None when there is none for this workload, precision
-    and form or the kernel sources changed since it was taken.  The record is a block of
-    lines
+def recorded_counters(kernel, workload, prec, waves=4):
+    """Counter record of `kernel` in its `waves`-wave form from the committed profile
+    summary of this workload and precision: dict with read/written bytes per launch (and
+    the BF16 MFMA ops per launch when recorded), or None when there is none or the
+    kernel sources changed since it was taken.  The record is a block of lines
         traffic-record sources-sha256 <hex> workload <w> precision <p>
         traffic-record <kernel class> waves <n> read-bytes <r> written-bytes <w>
-    in the profile summary (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration)."""
+        mfma-record <kernel class> waves <n> mops-bf16 <m>
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration; SQ_INSTS_VALU_MFMA_MOPS_BF16,
+    units of 512 flops)."""
+    path = traffic_record_path(workload, prec)
     try:
-        lines = open(TRAFFIC_RECORD).read().splitlines()
+        lines = open(path).read().splitlines()
     except OSError:
         return None
-    head, rows = None, {}
+    head, rows, mops = None, {}, {}
     for ln in lines:
         t = ln.split()
         if len(t) >= 7 and t[0] == "traffic-record" and t[1] == "sources-sha256":
             head = dict(sha=t[2], workload=t[4], precision=t[6])
         elif len(t) == 8 and t[0] == "traffic-record" and t[2] == "waves":
             rows[(t[1], int(t[3]))] = (float(t[5]), float(t[7]))
+        elif len(t) == 6 and t[0] == "mfma-record" and t[2] == "waves":
+            mops[(t[1], int(t[3]))] = float(t[5])
     if head is None or head["workload"] != workload or head["precision"] != prec:
         return None
     if head["sha"] != kernel_sources_sha256():
         return None
-    return rows.get((kernel, waves))
+    if (kernel, waves) not in rows:
+        return None
+    r, wr = rows[(kernel, waves)]
+    out = dict(read=r, written=wr, source=os.path.relpath(path, ROOT))
+    if (kernel, waves) in mops:
+        out["mops_bf16"] = mops[(kernel, waves)]
+    return out
 
 
 def upload(w, prec, engine, flags=0):
@@ -121,9 +139,12 @@ def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=
     graph: the step is a replay of the forward and backward graphs captured from the
     library's own launches (the same kernels; no host launch gaps).  timing: afterwards,
     a second region of eager steps with the library's per-kernel HIP events, for the
-    kernel breakdown."""
+    kernel breakdown.  Also returns the device-memory high-water mark of the run (inputs,
+    gradients, log P and the workspace; torch's allocator statistics, reset first)."""
     import torch
     from paper_1806_08593_amd import tmc as T
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
     prob, d = upload(w, prec, engine, flags)
     plan = T.Plan(prob)
     ws = plan.new_workspace()
@@ -190,29 +211,80 @@ def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=
             T.tmc_plan_set_timing(h, False)
             T.tmc_plan_check(h)
         out = dict(ms_per_step=(t1 - t0) * 1e3 / steps, event_ms_per_step=e0.elapsed_time(e1) / steps,
-                   eager_ms_per_step=eager_ms, kernels=kc, logp=lp, info=T.tmc_plan_info_get(h))
+                   eager_ms_per_step=eager_ms, kernels=kc, logp=lp, info=T.tmc_plan_info_get(h),
+                   mem_high_water_bytes=int(torch.cuda.max_memory_allocated()),
+                   workspace_bytes=int(plan.workspace_bytes),
+                   input_bytes=int(sum(v.numel() * v.element_size() for v in d.values())))
     plan.close()
     del d, g, ws
     torch.cuda.empty_cache()
     return out
 
 
+def host_cores():
+    """Host threads the CPU legs use: the process's CPU affinity, at most 16 (the host
+    share of one GPU on the benchmark machines)."""
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def oracle_logps(chains):
+    """FP64 oracle log P of every chain (matrix-product factor form, pinned against the
+    direct difference in the oracle's tests), threaded over chains."""
+    import concurrent.futures as cf
+    from oracle import tmc_oracle as O
+
+    def one(c):
+        f = [O.gauss_pair_logfactor_expanded(c.z[l], c.mu[l], c.s[l]) for l in range(len(c.mu))]
+        return O.chain_logp(f, c.u)
+
+    with cf.ThreadPoolExecutor(host_cores()) as ex:
+        return list(ex.map(one, chains))
+
+
 def cpu_baseline(chains, budget_s):
-    """FP64 oracle (forward + backward) on as many instances as fit in about budget_s
-    seconds of host time.  Returns (entries/s, instances done, seconds, log P list)."""
+    """The FP64 oracle as it stands (direct-difference factors, forward + backward:
+    gauss_chain_grads) on a bounded sample of the workload, spread over the host's
+    cores (one chain per thread at a time, BLAS pinned to one thread per caller).  A
+    sample unit is a whole chain, or, for chains of more than 8M factor entries (one such
+    chain alone takes minutes), its first layer pair as a two-layer chain (the same
+    per-entry work).  Units are started until budget_s has passed (at least one).
+    Returns (entries/s, threads, description)."""
+    import threading
+    import concurrent.futures as cf
     from oracle import tmc_oracle as O
     from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):        # one host thread, so that `cores` is exact
-        t0 = time.perf_counter()
-        done, ent, refs = 0, 0, []
-        for c in chains:
-            refs.append(O.gauss_chain_grads(c.z, c.mu, c.s, c.u)[0])
-            done += 1
-            ent += c.entries()
-            if time.perf_counter() - t0 > budget_s:
-                break
-        dt = time.perf_counter() - t0
-    return ent / dt, done, dt, refs
+    from workloads import Chain
+
+    big = max(c.entries() for c in chains) > 8_000_000
+    units = [Chain(z=c.z[:2], mu=c.mu[:1], s=c.s[:1], u=c.u[:2]) if big else c for c in chains]
+    n_thr = host_cores()
+    lock = threading.Lock()
+    state = dict(next=0, done=0, entries=0)
+    t0 = time.perf_counter()
+
+    def worker():
+        while True:
+            with lock:
+                k = state["next"]
+                if k >= len(units) or (k > 0 and time.perf_counter() - t0 > budget_s):
+                    return
+                state["next"] += 1
+            c = units[k]
+            O.gauss_chain_grads(c.z, c.mu, c.s, c.u)
+            with lock:
+                state["done"] += 1
+                state["entries"] += c.entries()
+
+    with threadpool_limits(limits=1):
+        with cf.ThreadPoolExecutor(n_thr) as ex:
+            for f in [ex.submit(worker) for _ in range(n_thr)]:
+                f.result()
+    dt = time.perf_counter() - t0
+    what = ("the first layer pair (as a two-layer chain) of each of" if big else "whole chains:")
+    desc = (f"FP64 oracle forward+backward (direct-difference factors) of {what} "
+            f"{state['done']} instances ({state['entries']} factor entries) in {dt:.1f} s "
+            f"on {n_thr} threads, one chain per thread")
+    return state["entries"] / dt, n_thr, desc
 
 
 def main():
@@ -220,12 +292,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--engine", default="auto")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the log P errors against the oracle")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-shape tuner (per-depth launches unless --persistent)")
     ap.add_argument("--persistent", action="store_true", help="persistent launches (with --no-tune)")
@@ -254,14 +327,18 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    prec = args.precision or ("fp64" if args.workload == "c1" else "bf16x3")
-    print(f"[bench] generating workload {args.workload} ...", file=sys.stderr, flush=True)
-    w = make(args.workload)
-    entries = w.entries()
-    d_weighted = float(sum(c.K[l] * c.K[l + 1] * c.D[l] for c in w.chains for l in range(c.L - 1)))
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    print(f"[bench] {prec}/{args.engine}: warmup {args.warmup}, timed {args.steps} steps",
-          file=sys.stderr, flush=True)
+    prec = args.precision or ("fp64" if args.workload == "c1" else "bf16x3")
+    log(f"generating workload {args.workload} ...")
+    w = make(args.workload)
+
+    def d_weighted(wl):
+        return float(sum(c.K[l] * c.K[l + 1] * c.D[l] for c in wl.chains for l in range(c.L - 1)))
+
+    entries = w.entries()
+    log(f"{prec}/{args.engine}: warmup {args.warmup}, timed {args.steps} steps")
     from paper_1806_08593_amd import tmc as T
     main_run = run_mode(w, prec, args.engine, args.steps, args.warmup, timing=True,
                         tune=not args.no_tune,
@@ -270,69 +347,125 @@ def main():
     ms_per_step = main_run["ms_per_step"]
     value = entries / (ms_per_step / 1e3)
     kc = main_run["kernels"]
-    dom = max((k for k in kc if k != "other"), key=lambda k: kc[k]["ms_per_step"])
-    alg = algorithmic(dom, entries, d_weighted, prec)
-    roofline = None
-    if alg is not None:
-        amount, unit, bound, peak = alg
-        per_launch = amount / kc[dom]["launches_per_step"]
-        achieved = per_launch / (kc[dom]["avg_launch_us"] * 1e-6) / (1e12 if unit == "TFLOP/s" else 1e9)
-        roofline = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
-                        frac=round(achieved / peak, 4), traffic=None,
-                        algorithmic_per_launch=per_launch,
-                        avg_launch_us=round(kc[dom]["avg_launch_us"], 3))
-        # the form (workgroup width) the plan used for that kernel class (every layer of
-        # the homogeneous workloads the record covers is eligible for the wide form)
-        info = main_run["info"]
-        waves = 8 if info.get("wide_fwd" if dom == "fused_fwd" else "wide_bwd") else 4
-        rec = recorded_traffic(dom, args.workload, prec, waves)
-        if rec is not None:
-            # HBM bytes per launch (read + written), from the committed counter record
-            roofline["traffic"] = rec[0] + rec[1]
-            roofline["traffic_read"], roofline["traffic_written"] = rec
-            roofline["traffic_unit"] = "bytes per launch"
-            roofline["traffic_source"] = os.path.relpath(TRAFFIC_RECORD, ROOT)
-            roofline["waves"] = waves
+    info = main_run["info"]
 
-    # comparators: the other arithmetic modes of the same step
+    def roofline_of(kcs, wl, pr, inf, dom):
+        alg = algorithmic(dom, wl.entries(), d_weighted(wl), pr)
+        if alg is None:
+            return None
+        amount, unit, bound, peak = alg
+        per_launch = amount / kcs[dom]["launches_per_step"]
+        achieved = per_launch / (kcs[dom]["avg_launch_us"] * 1e-6) / (1e12 if unit == "TFLOP/s" else 1e9)
+        r = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
+                 frac=round(achieved / peak, 4), traffic=None, algorithmic_per_launch=per_launch,
+                 avg_launch_us=round(kcs[dom]["avg_launch_us"], 3))
+        if dom in ("fused_fwd", "fused_bwd"):
+            # the form (workgroup width) the plan used for that kernel class (every layer of
+            # the homogeneous workloads the record covers is eligible for the wide form)
+            waves = 8 if inf.get("wide_fwd" if dom == "fused_fwd" else "wide_bwd") else 4
+            rec = recorded_counters(dom, wl.name, pr, waves)
+            if rec is not None:
+                # HBM bytes per launch (read + written) from the committed counter record
+                r["traffic"] = rec["read"] + rec["written"]
+                r["traffic_read"], r["traffic_written"] = rec["read"], rec["written"]
+                r["traffic_unit"] = "bytes per launch"
+                r["traffic_source"] = rec["source"]
+                r["waves"] = waves
+                if "mops_bf16" in rec and pr == "bf16x3":
+                    # issued matrix-core work (hi/lo products, padding included) per launch
+                    issued = rec["mops_bf16"] * 512.0 / (kcs[dom]["avg_launch_us"] * 1e-6) / 1e12
+                    r["issued_tflops"] = round(issued, 3)
+                    r["issued_frac"] = round(issued / peak, 4)
+        return r
+
+    dom = max((k for k in kc if k != "other"), key=lambda k: kc[k]["ms_per_step"])
+    roofline = roofline_of(kc, w, prec, info, dom)
+    # the other kernel classes of the step, same measure
+    kernel_roofline = {k: roofline_of(kc, w, prec, info, k) for k in kc if k not in ("other", dom)}
+
+    # comparators: the FP32 forms of the same step, and the mixed-precision configuration
     compare = {}
+    runs = {}
     if not args.no_compare and prec != "fp64":
-        for cp, ce in (("fp32", "fused"), ("fp32", "plain")):
-            if (cp, ce) == (prec, args.engine):
+        cands = [("fp32_fused", w, "fp32", "fused"), ("fp32_plain", w, "fp32", "plain")]
+        if args.workload != "c3":
+            wc3 = make("c3")
+            cands += [("c3_bf16x3", wc3, "bf16x3", "auto"), ("c3_fp32_fused", wc3, "fp32", "fused"),
+                      ("c3_fp32_plain", wc3, "fp32", "plain")]
+        for name, wl, cp, ce in cands:
+            if (wl is w) and (cp, ce) == (prec, args.engine):
                 continue
             try:
-                print(f"[bench] comparator {cp}/{ce}", file=sys.stderr, flush=True)
-                r = run_mode(w, cp, ce, max(3, args.steps // 3), 2, timing=False,
-                             tune=not args.no_tune and ce == "fused", graph=not args.no_graph)
-                compare[f"{cp}_{ce}"] = dict(ms_per_step=r["ms_per_step"],
-                                             value=entries / (r["ms_per_step"] / 1e3), logp=r["logp"])
-            except Exception as e:   # e.g. a plain-engine workspace that does not fit
-                compare[f"{cp}_{ce}"] = dict(error=str(e)[:200])
+                log(f"comparator {name}")
+                r = run_mode(wl, cp, ce, max(3, args.steps // 3), 2, timing=True,
+                             tune=not args.no_tune and ce != "plain", graph=not args.no_graph)
+                ent = wl.entries()
+                e = dict(workload=wl.name, precision=cp, engine=ce, ms_per_step=r["ms_per_step"],
+                         value=ent / (r["ms_per_step"] / 1e3),
+                         mem_high_water_bytes=r["mem_high_water_bytes"])
+                # HBM rate of the plain engine's log-sum-exp passes over the stored factors
+                for kk in ("plain_lse_fwd", "plain_lse_bwd"):
+                    if kk in r["kernels"]:
+                        rf = roofline_of(r["kernels"], wl, cp, r["info"], kk)
+                        e[kk] = dict(achieved_gbs=rf["achieved"], frac=rf["frac"],
+                                     avg_launch_us=rf["avg_launch_us"],
+                                     bytes_per_launch=rf["algorithmic_per_launch"])
+                compare[name] = e
+                runs[name] = (wl, r["logp"])
+            except Exception as ex:   # e.g. a plain-engine workspace that does not fit
+                compare[name] = dict(error=str(ex)[:200])
 
-    # errors against the FP64 oracle on the CPU-baseline sample, and the baseline itself
-    cpu = None
+    # log P errors against the FP64 oracle on every instance
     errs = {}
+    if not args.no_oracle:
+        npdt = np.float64 if prec == "fp64" else np.float32
+        refs_by = {}
+
+        def refs_for(wl):
+            if wl.name not in refs_by:
+                log(f"oracle log P of every {wl.name} instance ...")
+                refs_by[wl.name] = np.array(oracle_logps([cast_chain(c, npdt) for c in wl.chains]))
+            return refs_by[wl.name]
+
+        errs[prec] = float(np.max(np.abs(main_run["logp"] - refs_for(w))))
+        for name, (wl, lp) in runs.items():
+            errs[name] = float(np.max(np.abs(lp - refs_for(wl))))
+            compare[name]["max_abs_err_logp"] = errs[name]
+            tol = LOGP_TOL[compare[name]["precision"]]
+            compare[name]["within_tolerance"] = tol is not None and errs[name] <= tol
+
+    cpu = None
     if not args.no_cpu_baseline:
         npdt = np.float64 if prec == "fp64" else np.float32
-        sample = [cast_chain(c, npdt) for c in w.chains]
-        print(f"[bench] CPU oracle baseline (~{args.cpu_budget:.0f} s) ...", file=sys.stderr, flush=True)
-        rate, done, dt, refs = cpu_baseline(sample, args.cpu_budget)
-        errs[prec] = float(max(abs(main_run["logp"][b] - refs[b]) for b in range(done)))
-        for k, v in compare.items():
-            if "logp" in v:
-                errs[k] = float(max(abs(v["logp"][b] - refs[b]) for b in range(done)))
-        cpu = dict(value=rate, unit="factor entries/s", cores=1, kind="oracle",
-                   sample=f"forward+backward of the first {done} of {len(w.chains)} instances "
-                          f"({sum(c.entries() for c in w.chains[:done])} entries) in {dt:.1f} s, "
-                          f"FP64 NumPy, one thread")
-    for v in compare.values():
-        v.pop("logp", None)
-    if compare:
-        base = compare.get("fp32_plain", {}).get("ms_per_step")
-        if base:
-            compare["speedup_over_fp32_plain"] = base / ms_per_step
+        log(f"CPU oracle baseline (~{args.cpu_budget:.0f} s) ...")
+        rate, n_thr, desc = cpu_baseline([cast_chain(c, npdt) for c in w.chains], args.cpu_budget)
+        cpu = dict(value=rate, unit="factor entries/s", cores=n_thr, kind="oracle", sample=desc,
+                   host_cpus_visible=os.cpu_count())
 
-    info = main_run["info"]
+    # speedups, each with both sides' errors and the tolerance band both meet
+    if compare and prec in LOGP_TOL and LOGP_TOL[prec]:
+        def band(e1, p1, e2, p2):
+            b = [t for t in sorted({LOGP_TOL[p1], LOGP_TOL[p2]}) if e1 <= t and e2 <= t]
+            return b[0] if b else None
+
+        sp = {}
+        for name in ("fp32_plain", "fp32_fused"):
+            c = compare.get(name, {})
+            if "ms_per_step" in c:
+                ent = dict(speedup=c["ms_per_step"] / ms_per_step,
+                           err=errs.get(prec), other_err=c.get("max_abs_err_logp"))
+                if ent["err"] is not None and ent["other_err"] is not None:
+                    ent["band_both_meet"] = band(ent["err"], prec, ent["other_err"], "fp32")
+                sp[f"{prec}_over_{name}"] = ent
+        a, b = compare.get("fp32_fused", {}), compare.get("fp32_plain", {})
+        if "ms_per_step" in a and "ms_per_step" in b:
+            ent = dict(speedup=b["ms_per_step"] / a["ms_per_step"], err=a.get("max_abs_err_logp"),
+                       other_err=b.get("max_abs_err_logp"))
+            if ent["err"] is not None and ent["other_err"] is not None:
+                ent["band_both_meet"] = band(ent["err"], "fp32", ent["other_err"], "fp32")
+            sp["fp32_fused_over_fp32_plain"] = ent
+        compare["speedups"] = sp
+
     cfg = {"workload": args.workload, "chains": len(w.chains), "factor_entries": entries,
            "precision": prec, "engine": ["auto", "fused", "plain"][info["engine"]],
            "launch": ("persistent" if info["persistent"] else "per-depth") +
@@ -362,9 +495,14 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "max_abs_err_logp_vs_oracle": errs,
+        "memory": dict(high_water_bytes=main_run["mem_high_water_bytes"],
+                       workspace_bytes=main_run["workspace_bytes"],
+                       input_bytes=main_run["input_bytes"],
+                       stored_factor_bytes_avoided=4 * entries),
         "event_ms_per_step": main_run["event_ms_per_step"],
         "eager_ms_per_step": main_run["eager_ms_per_step"],
         "kernels": kc,
+        "kernel_roofline": kernel_roofline,
         "compare": compare,
     }
     print(json.dumps(line))
