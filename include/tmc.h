@@ -194,6 +194,23 @@ tmc_status tmc_gauss_fwd(tmc_plan_t plan, const void* z, const void* mu, const v
 tmc_status tmc_gauss_bwd(tmc_plan_t plan, const void* z, const void* mu, const void* s,
                          const void* u, const double* dlogp, void* workspace,
                          void* dz, void* dmu, void* ds, void* du, void* stream);
+/* Allocation-free forward, for callers that cannot allocate device memory (code
+ * under hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tmc_gauss_fwd with the workspace taken from a device array the library holds for
+ * the life of the process, TMC_NOALLOC_WORKSPACE_MAX bytes on each GPU it runs on
+ * (looked up once per device when the first plan on that device is created).  The
+ * caller still passes inputs and the logp output; the call allocates and frees
+ * nothing and does not synchronise.  Same results as tmc_gauss_fwd (the same
+ * kernels).  Errors: TMC_ERR_WORKSPACE if the plan needs a larger workspace than
+ * TMC_NOALLOC_WORKSPACE_MAX (tmc_plan_workspace_size; forward-only plans need the
+ * least), TMC_ERR_HIP if the array's address could not be obtained, otherwise as
+ * tmc_gauss_fwd.  Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents (nothing in it has to start at zero: the forward initialises what it
+ * reads): calls that overlap on one GPU -- on different streams or from different
+ * threads -- race, and a tmc_gauss_bwd cannot use the state this call leaves. */
+#define TMC_NOALLOC_WORKSPACE_MAX ((size_t)64 << 20)
+tmc_status tmc_gauss_fwd_noalloc(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                                 const void* u, double* logp, void* stream);
 /* Writes the pairwise log-factors f_l [K_l][K_{l+1}] (at layers[l].f_off of `f`) by
  * direct difference in the plan's precision (FP64 or FP32).  For inspection and for
  * feeding tmc_logfactor_*; the fused engine never materialises them. */

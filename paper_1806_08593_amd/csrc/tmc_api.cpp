@@ -17,8 +17,12 @@
 #include "fused.h"
 #include "tmc_internal.h"
 #include "tmc_kernels.h"
+#include "tmc_scratch.h"
 
 using namespace tmc;
+
+static_assert(kNoallocWorkspaceBytes == TMC_NOALLOC_WORKSPACE_MAX,
+              "static workspace size and its ABI constant");
 
 namespace {
 
@@ -95,6 +99,10 @@ struct tmc_plan {
   FusedPlan fused;
   // problems that make one family of entry points unusable (empty = usable)
   std::string gauss_err, logf_err;
+  // address of the library's static device workspace on this plan's device (set up at
+  // plan creation; null with the reason in scratch_err if it could not be found)
+  void* scratch = nullptr;
+  std::string scratch_err;
   // graphs
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   bool capturing = false;
@@ -782,6 +790,11 @@ tmc_status tmc_plan_create(const tmc_problem* problem, int device, tmc_plan_t* o
       delete P;
       return st;
     }
+    // the static device workspace of tmc_gauss_fwd_noalloc: its address on this device
+    // (looked up once per device; a failure disables only that entry point)
+    const hipError_t se = scratch_init(device);
+    if (se == hipSuccess) P->scratch = scratch_device_ptr(device);
+    else P->scratch_err = std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(se);
     *out = P;
     g_err.clear();
     return TMC_OK;
@@ -859,6 +872,23 @@ tmc_status tmc_gauss_bwd(tmc_plan_t plan, const void* z, const void* mu, const v
     DeviceGuard g(plan->device);
     return gauss_bwd_impl(plan, z, mu, s, u, dlogp, workspace, dz, dmu, ds, du,
                           (hipStream_t)stream);
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_gauss_fwd_noalloc(tmc_plan_t plan, const void* z, const void* mu, const void* s,
+                                 const void* u, double* logp, void* stream) {
+  try {
+    if (!plan) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+    if (!plan->scratch)
+      return fail(TMC_ERR_HIP, "static device workspace unavailable (%s)", plan->scratch_err.c_str());
+    if (plan->ws.total > kNoallocWorkspaceBytes)
+      return fail(TMC_ERR_WORKSPACE,
+                  "plan needs %zu workspace bytes, the allocation-free forward has %zu "
+                  "(a forward-only plan needs less)", plan->ws.total, kNoallocWorkspaceBytes);
+    DeviceGuard g(plan->device);
+    return gauss_fwd_impl(plan, z, mu, s, u, logp, plan->scratch, (hipStream_t)stream);
   } catch (...) {
     return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
   }

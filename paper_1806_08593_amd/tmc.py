@@ -78,6 +78,7 @@ _SIGS = {
     "tmc_gauss_fwd": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "tmc_gauss_bwd": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "tmc_gauss_factors": (c_int, [_P, _P, _P, _P, _P, _P]),
+    "tmc_gauss_fwd_noalloc": (c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "tmc_logfactor_fwd": (c_int, [_P, _P, _P, _P, _P, _P]),
     "tmc_logfactor_bwd": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "tmc_plan_graph_capture_gauss": (c_int, [_P, c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -178,6 +179,14 @@ def tmc_gauss_bwd(plan, z, mu, s, u, dlogp, workspace, dz, dmu, ds, du, stream=N
     _check(_lib.tmc_gauss_bwd(plan, _ptr(z), _ptr(mu), _ptr(s), _ptr(u), _ptr(dlogp),
                               _ptr(workspace), _ptr(dz), _ptr(dmu), _ptr(ds), _ptr(du),
                               _stream(stream)))
+
+
+def tmc_gauss_fwd_noalloc(plan, z, mu, s, u, logp, stream=None):
+    _check(_lib.tmc_gauss_fwd_noalloc(plan, _ptr(z), _ptr(mu), _ptr(s), _ptr(u), _ptr(logp),
+                                      _stream(stream)))
+
+
+TMC_NOALLOC_WORKSPACE_MAX = 64 << 20
 
 
 def tmc_gauss_factors(plan, z, mu, s, f, stream=None):
