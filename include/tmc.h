@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define TMC_ABI_VERSION 3
+#define TMC_ABI_VERSION 4
 
 typedef enum tmc_status {
   TMC_OK = 0,
@@ -136,6 +136,13 @@ typedef struct tmc_problem {
   int32_t engine;               /* tmc_engine */
   int32_t flags;                /* TMC_FLAG_* */
   int32_t reserved;             /* must be 0 */
+  double exponent;              /* kappa: every importance weight enters raised to the power
+                                   kappa, i.e. log P = log [1/prod_l K_l sum exp(kappa (sum u +
+                                   sum f))] and its gradients; 2 gives the squared weights of
+                                   the DReGs surrogate (Appendix "Combining DReGs and TMC").
+                                   0 (a zero-initialised struct) means 1; otherwise finite
+                                   and > 0.  Applies to every execute call of the plan
+                                   (tmc_gauss_factors writes the unscaled factors). */
 } tmc_problem;
 
 typedef struct tmc_plan* tmc_plan_t;

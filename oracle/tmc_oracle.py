@@ -266,6 +266,165 @@ def gauss_chain_grads_expanded(z, mu, s, u):
     return logp, dz, dmu, ds, [np.asarray(a) for a in p]
 
 
+def tempered_chain_logp(f: Sequence[np.ndarray], u: Sequence[np.ndarray], kappa: float) -> float:
+    """log of the average over all index tuples of w_t**kappa, w_t the importance weight of
+    tuple t (eq. (is) with every weight raised to the power kappa): the chain evaluation
+    with every log-factor and unary multiplied by kappa.  kappa = 2 gives the sum of
+    squared weights that Appendix "Combining DReGs and TMC" obtains by running TMC again
+    with squared weights."""
+    return chain_logp([kappa * np.asarray(a, np.float64) for a in f],
+                      [kappa * np.asarray(a, np.float64) for a in u])
+
+
+def gauss_chain_grads_tempered(z, mu, s, u, kappa: float):
+    """log of the kappa-tempered estimator (`tempered_chain_logp` of the Gaussian chain) and
+    its gradients.  Each tuple's weight enters as exp(kappa log w_t), so with G the
+    pairwise marginals of the tempered chain and lam = exp(-2 s):
+        dz_l[i]  = kappa sum_j G_l[i,j] (-lam (z_l[i] - mu_l[j]))
+        dmu_l[j] = kappa sum_i G_l[i,j] ( lam (z_l[i] - mu_l[j]))
+        ds_l     = kappa sum_ij G_l[i,j] (lam (z_l[i] - mu_l[j])^2 - 1)
+        du_l     = kappa p_l
+    Returns (log P_kappa, dz, dmu, ds, du)."""
+    f = gauss_chain_factors(z, mu, s)
+    logp, G, p = chain_marginals([kappa * a for a in f], [kappa * np.asarray(a, np.float64) for a in u])
+    L = len(u)
+    dz = [np.zeros_like(np.asarray(a, np.float64)) for a in z]
+    dmu, ds = [], []
+    for l in range(L - 1):
+        lam = np.exp(-2.0 * np.asarray(s[l], np.float64))
+        diff = np.asarray(z[l], np.float64)[:, None, :] - np.asarray(mu[l], np.float64)[None, :, :]
+        g = G[l][:, :, None]
+        dz[l] = kappa * np.sum(g * (-lam * diff), axis=1)
+        dmu.append(kappa * np.sum(g * (lam * diff), axis=0))
+        ds.append(kappa * np.sum(g * (lam * diff * diff - 1.0), axis=(0, 1)))
+    return logp, dz, dmu, ds, [kappa * np.asarray(a) for a in p]
+
+
+def dregs_gradients(z, mu, s, u):
+    """Gradients of the DReGs surrogate of Appendix "Combining DReGs and TMC",
+        1/2 * stopgrad(sum_t w_t^2 / (sum_t w_t)^2) * log sum_t w_t^2,
+    with respect to the inputs through which the weights' gradients flow (the caller
+    stops the direct dependence on the proposal parameters in u): the coefficient is
+    exp(logP_2 - 2 logP_1 - sum_l ln K_l) with logP_kappa the kappa-tempered estimator,
+    and d log sum_t w_t^2 = d logP_2.  By the paper's derivation this equals
+    sum_t w_t^2 / (sum_t w_t)^2 * d log w_t.  Returns (coefficient, dz, dmu, ds, du)."""
+    lp1 = gauss_chain_logp(z, mu, s, u)
+    lp2, dz, dmu, ds, du = gauss_chain_grads_tempered(z, mu, s, u, 2.0)
+    c = math.exp(lp2 - 2.0 * lp1 - sum(log_k(len(a)) for a in u))
+    h = 0.5 * c
+    return c, [h * a for a in dz], [h * a for a in dmu], [h * a for a in ds], [h * a for a in du]
+
+
+def brute_force_weighted_grads(z, mu, s, u, weight):
+    """sum over every index tuple t of weight(log w) [t] * d log w_t, with d log w_t written
+    out per tuple (the factors' and unaries' own derivatives); `weight` maps the vector of
+    log weights of all tuples to per-tuple coefficients.  Exponential in L: tiny chains.
+    Returns (dz, dmu, ds, du)."""
+    L = len(u)
+    K = [len(a) for a in u]
+    f = gauss_chain_factors(z, mu, s)
+    tuples = list(itertools.product(*[range(k) for k in K]))
+    logw = np.array([sum(u[l][t[l]] for l in range(L)) + sum(f[l][t[l], t[l + 1]] for l in range(L - 1))
+                     for t in tuples])
+    wt = weight(logw)
+    dz = [np.zeros_like(np.asarray(a, np.float64)) for a in z]
+    dmu = [np.zeros_like(np.asarray(a, np.float64)) for a in mu]
+    ds = [np.zeros_like(np.asarray(a, np.float64)) for a in s]
+    du = [np.zeros(k) for k in K]
+    for c, t in zip(wt, tuples):
+        for l in range(L):
+            du[l][t[l]] += c
+        for l in range(L - 1):
+            lam = np.exp(-2.0 * np.asarray(s[l], np.float64))
+            d = np.asarray(z[l][t[l]], np.float64) - np.asarray(mu[l][t[l + 1]], np.float64)
+            dz[l][t[l]] += c * (-lam * d)
+            dmu[l][t[l + 1]] += c * (lam * d)
+            ds[l] += c * (lam * d * d - 1.0)
+    return dz, dmu, ds, du
+
+
+# ---------------------------------------------------------------------------
+# star-shaped model: one global latent, N local latents (Sec. "Efficient averaging",
+# the latent-variable model with unknown parameters theta)
+# ---------------------------------------------------------------------------
+
+def star_logp(uth: np.ndarray, f: Sequence[np.ndarray], u: Sequence[np.ndarray]) -> float:
+    """TMC estimate of the star model: K_theta samples of the global latent theta (unary
+    log-terms uth[kt]) and, for each data point i, K_i samples of its local latent
+    (unaries u[i][k]) joined to theta by the log-factor f[i][kt, k].  Summing the local
+    indices out first, then theta:
+        log P = logsumexp_kt( uth[kt] + sum_i [logsumexp_k(f[i][kt, k] + u[i][k]) - ln K_i] )
+                - ln K_theta."""
+    uth = np.asarray(uth, np.float64)
+    a = uth.copy()
+    for fi, ui in zip(f, u):
+        a = a + logsumexp(np.asarray(fi, np.float64) + np.asarray(ui, np.float64)[None, :], axis=1) \
+            - log_k(len(ui))
+    return float(logsumexp(a, axis=0) - log_k(len(uth)))
+
+
+def star_brute_force(uth, f, u) -> float:
+    """eq. (is) for the star model written out: log of the average over every tuple
+    (kt, k_1 .. k_N) of exp(uth[kt] + sum_i (f[i][kt, k_i] + u[i][k_i])).  Tiny cases only."""
+    Ks = [len(a) for a in u]
+    terms = []
+    for kt in range(len(uth)):
+        for ks in itertools.product(*[range(k) for k in Ks]):
+            terms.append(uth[kt] + sum(f[i][kt, ks[i]] + u[i][ks[i]] for i in range(len(u))))
+    return float(logsumexp(np.array(terms), axis=0) - log_k(len(uth)) - sum(log_k(k) for k in Ks))
+
+
+def star_marginals(uth, f, u):
+    """d log P / d uth[kt] = w[kt] (the weight of global sample kt) and
+    d log P / d f[i][kt, k] = G_i[kt, k] = w[kt] * softmax_k(f[i][kt, k] + u[i][k]) (= d / d u[i][k]
+    summed over kt).  Returns (log P, w, [G_i])."""
+    uth = np.asarray(uth, np.float64)
+    msg = [logsumexp(np.asarray(fi, np.float64) + np.asarray(ui, np.float64)[None, :], axis=1)
+           - log_k(len(ui)) for fi, ui in zip(f, u)]
+    a = uth + sum(msg) if msg else uth.copy()
+    logp = float(logsumexp(a, axis=0) - log_k(len(uth)))
+    w = np.exp(a - log_k(len(uth)) - logp)
+    G = []
+    for fi, ui, mi in zip(f, u, msg):
+        G.append(w[:, None] * np.exp(np.asarray(fi, np.float64) + np.asarray(ui, np.float64)[None, :]
+                                     - (mi + log_k(len(ui)))[:, None]))
+    return logp, w, G
+
+
+def gauss_star_grads(mth, s, z, u, uth):
+    """Star model with Gaussian local conditionals z_i | theta^kt ~ N(mth[kt], diag exp(2 s))
+    (mth[kt] the mean produced from global sample kt): f[i][kt, k] = log N(z[i][k]; mth[kt], .)
+    by direct difference.  Returns (log P, d mth [Kt, D], d s [D], d z [N][K, D], d u [N][K],
+    d uth [Kt]); with G_i the marginals of `star_marginals` and lam = exp(-2 s):
+        d mth[kt] = sum_i sum_k G_i[kt, k] lam (z_ik - mth[kt])
+        d z_ik    = sum_kt G_i[kt, k] (-lam (z_ik - mth[kt]))
+        d s       = sum_i sum_{kt, k} G_i[kt, k] (lam (z_ik - mth[kt])^2 - 1)."""
+    mth = np.asarray(mth, np.float64)
+    lam = np.exp(-2.0 * np.asarray(s, np.float64))
+    f = [gauss_pair_logfactor(mth, zi, s) for zi in z]   # [Kt, K] (the density is symmetric)
+    logp, w, G = star_marginals(uth, f, u)
+    dm = np.zeros_like(mth)
+    ds = np.zeros_like(lam)
+    dz, du = [], []
+    for zi, gi in zip(z, G):
+        diff = np.asarray(zi, np.float64)[None, :, :] - mth[:, None, :]      # [Kt, K, D]
+        g = gi[:, :, None]
+        dm += np.sum(g * (lam * diff), axis=1)
+        dz.append(np.sum(g * (-lam * diff), axis=0))
+        ds += np.sum(g * (lam * diff * diff - 1.0), axis=(0, 1))
+        du.append(gi.sum(axis=0))
+    return logp, dm, ds, dz, du, w
+
+
+def gauss_star_log_evidence(x: np.ndarray) -> float:
+    """Exact log P(x) of the Gaussian model of Sec. "Comparing TMC, SMC and IWAE":
+    theta ~ N(0, 1), z_i | theta ~ N(theta, 1), x_i | z_i ~ N(z_i, 1), so x is Gaussian
+    with mean 0 and covariance 1 1^T + 2 I."""
+    from scipy.stats import multivariate_normal
+    n = len(x)
+    return float(multivariate_normal(mean=np.zeros(n), cov=np.ones((n, n)) + 2.0 * np.eye(n)).logpdf(x))
+
+
 def finite_difference(fun, x: np.ndarray, h: float = 1e-5, idx=None) -> np.ndarray:
     """Central differences (fun(x + h e) - fun(x - h e)) / 2h at the flat indices
     `idx` (all entries when None)."""

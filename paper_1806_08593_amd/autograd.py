@@ -42,6 +42,29 @@ class GaussChainTMC:
         return _GaussChainFn.apply(z, mu, s, u, self)
 
 
+class RaggedGaussChainTMC:
+    """Chains of uneven depth, sample counts and widths, given as a list of
+    (K_list, D_list) per chain, with z, mu, s, u packed back to back in flat tensors (the
+    layout of tmc.ragged_problem: each chain's layers in order, each layer's block
+    row-major) -> log P_TMC [n_chains] (float64), differentiable in the four flat
+    tensors.  Every chain has its own s blocks."""
+
+    def __init__(self, shapes, precision="fp32", engine="auto", device=0, flags=0):
+        self.problem, self.sizes = T.ragged_problem(shapes, precision, engine, flags)
+        self.plan = T.Plan(self.problem, device)
+        self.shape = (len(shapes),)
+        self.dtype = _DT[self.problem.c.precision]
+        self.device = torch.device(f"cuda:{device}")
+
+    def __call__(self, z, mu, s, u):
+        for name, t in (("z", z), ("mu", mu), ("s", s), ("u", u)):
+            if t.dim() != 1 or t.numel() < max(self.sizes[name], 1):
+                raise ValueError(f"{name}: needs a flat tensor of {self.sizes[name]} elements")
+            if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
+                raise ValueError(f"{name}: needs a contiguous {self.dtype} tensor on {self.device}")
+        return _GaussChainFn.apply(z, mu, s, u, self)
+
+
 class _GaussChainFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, z, mu, s, u, runner: GaussChainTMC):

@@ -402,8 +402,9 @@ __device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const PairPr
   if (d < TS::DT) {
     const float lf = d < L.D ? expf(-2.0f * P.slam) : 0.0f;
     T.lamf[d] = lf;
-    T.lam2[d] = lf * kLog2e;
-    T.rlam2[d] = lf > 0.0f ? 1.0f / (lf * kLog2e) : 0.0f;
+    const float k2 = (float)L.kappa * kLog2e;   // weights raised to the power kappa
+    T.lam2[d] = lf * k2;
+    T.rlam2[d] = lf > 0.0f ? 1.0f / (lf * k2) : 0.0f;
     T.lamd[d] = (double)lf;
   }
 }
@@ -597,9 +598,10 @@ __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC,
   }
 }
 
-// gamma_j = log2(e) (q_j + alpha_{l+1}[j] - maxa), -inf past Kc.
-__device__ __forceinline__ float col_gamma(double q, double a, int j, int Kc, double maxa) {
-  return (j < Kc) ? (float)((q + (a - maxa)) * (double)kLog2e) : -INFINITY;
+// gamma_j = log2(e) (kappa q_j + alpha_{l+1}[j] - maxa), -inf past Kc.
+__device__ __forceinline__ float col_gamma(double q, double a, int j, int Kc, double maxa,
+                                           double kappa) {
+  return (j < Kc) ? (float)((kappa * q + (a - maxa)) * (double)kLog2e) : -INFINITY;
 }
 
 // Fragment of staged row (lane % 32) of subtile sb for d chunk kc (d = 16 kc + 8 h + s).
@@ -706,8 +708,9 @@ __device__ __forceinline__ void wave_load(const float* __restrict__ base, int64_
 // forward: a workgroup of 4 waves owns 128 rows of one layer pair (wave w: rows
 // start + 32 w ..); the samples of the layer above are staged NS x 32 at a time in
 // LDS and swept by all waves.
-//   ell_i   = log2 sum_j exp2(S_ij + gamma_j)          (S = log2e <lam z_i, mu_j>)
-//   alpha_i = u_i + r_i + c + maxa + ln2 * ell_i - ln K_{l+1}
+//   ell_i   = log2 sum_j exp2(S_ij + gamma_j)          (S = kappa log2e <lam z_i, mu_j>)
+//   alpha_i = kappa (u_i + r_i + c) + maxa + ln2 * ell_i - ln K_{l+1}
+// (kappa: the weight exponent of the plan, 1 for the estimator itself)
 //   e_i     = sum_j softmax_j(S_ij + gamma_j) mu_j        (GRAD: used for dz)
 // ---------------------------------------------------------------------------
 // MFMAs of one 32-column (32-row) tile's factor GEMM per subtile
@@ -784,7 +787,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
     tile_store<TS, NKC, true, WV>(T, b, pf, false, qs);
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb)
-      T.gam[b][32 * sb + srow] = col_gamma(qs[sb], pf.a[sb], j0 + 32 * sb + srow, L.Kc, maxa);
+      T.gam[b][32 * sb + srow] = col_gamma(qs[sb], pf.a[sb], j0 + 32 * sb + srow, L.Kc, maxa, L.kappa);
   };
   auto store_q = [&](int j0, const double (&qs)[NS]) {
 #pragma unroll
@@ -1000,7 +1003,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   else if (m == -INFINITY || stot == 0.0f) ell = -INFINITY;
   else ell = m + log2f(stot);
   const bool iv = active && i < L.K;
-  const double a_i = (double)u_i + r_i + cs + maxa + kLn2 * (double)ell - L.lnKc;
+  const double a_i = L.kappa * ((double)u_i + r_i + cs) + maxa + kLn2 * (double)ell - L.lnKc;
   if (h == 0 && iv) {
     rl[L.rl_off + i] = ell;
     alpha[L.alpha_off + i] = a_i;
@@ -1155,7 +1158,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   pair_preload(L, wmax, s, pre);
   const double qj = qcol[L.q_off + jc];
   const double aj = alpha[L.alpha_up_off + jc];
-  const double gl = dlogp[L.chain];
+  const double gl = dlogp[L.chain] * L.kappa;   // d/d(kappa log w) -> d/d(log w)
   float xm[NKC][8];
   wave_load<NKC>(mu, L.mu_off, L.Kc, L.D, jw, xm);
   TilePrefetch<NKC, NS, WV> pf;
@@ -1168,7 +1171,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   Frag<PREC> Bf[NKC];
 #pragma unroll
   for (int kc = 0; kc < NKC; ++kc) make_frag<PREC>(xm[kc], Bf[kc]);
-  const float gj = col_gamma(qj, aj, j, L.Kc, maxa);
+  const float gj = col_gamma(qj, aj, j, L.Kc, maxa, L.kappa);
   const float g32 = (float)gl;
 
   // Stages the fetched rows into buffer b.  Threads t and t + 32 NS hold the shift of

@@ -8,7 +8,8 @@
 
 namespace tmc {
 
-// alpha of the top layer is its unary term (nothing left to sum above it).
+// alpha of the top layer is its unary term (nothing left to sum above it), times the
+// exponent of the weights.
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_top(const ChainDev* __restrict__ chains,
                                                   const LayerDev* __restrict__ layers,
@@ -18,7 +19,7 @@ __global__ __launch_bounds__(256) void k_init_top(const ChainDev* __restrict__ c
   const LayerDev& t = layers[c.top];
   const int K = t.K;
   const int64_t uo = t.u_off, ao = t.alpha_off;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) alpha[ao + k] = (double)u[uo + k];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) alpha[ao + k] = t.kappa * (double)u[uo + k];
 }
 
 // log P_TMC = logsumexp_i alpha_0[i] - ln K_0 (eq. (is)), in double.
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(256) void k_bwd_init(const ChainDev* __restrict__ c
   const ChainDev ch = chains[c];
   const LayerDev& l0 = layers[ch.first];
   const double lp = logp_ws[c];
-  const double g = dlogp[c];
+  const double g = dlogp[c] * l0.kappa;   // d/d(kappa u) -> d/du
   const double lk = log((double)l0.K);
   for (int k = threadIdx.x; k < l0.K; k += blockDim.x) {
     double v;

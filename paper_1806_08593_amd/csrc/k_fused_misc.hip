@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_fused_fwd_init(const ChainDev* __restri
   for (int q = w; q < nparts; q += blockDim.x >> 6) {
     double m = -INFINITY;
     for (int k = q * 128 + lane; k < min(t.K, (q + 1) * 128); k += 64) {
-      const double v = (double)u[t.u_off + k];
+      const double v = t.kappa * (double)u[t.u_off + k];
       alpha[t.alpha_off + k] = v;
       m = nan_max(m, v);
     }
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_fused_bwd_init(const ChainDev* __restri
     for (int k = threadIdx.x; k < n_heads; k += blockDim.x) heads[k] = 0;
   const LayerDev& l0 = layers[ch.first];
   const double lp = logp_ws[c];
-  const double g = dlogp[c];
+  const double g = dlogp[c] * l0.kappa;   // d/d(kappa u) -> d/du
   const double lk = log((double)l0.K);
   const bool has_pair = l0.up >= 0;
   for (int k = threadIdx.x; k < l0.K; k += blockDim.x) {
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_fused_dz(const LayerDev* __restrict__ L
   const int tid = threadIdx.x, c4 = tid & 31, rg = tid >> 5;
   for (int d = tid; d < D; d += blockDim.x) lam[d] = expf(-2.0f * s[L.s_off + d]);
   const float* pr = p + L.p_off;
-  const float g = (float)dlogp[L.chain];
+  const float g = (float)(dlogp[L.chain] * L.kappa);
   float P = 0.0f;
   if (tid < 64 && r0 + tid < K) P = pr[r0 + tid];
   P = block_sum(P, redp);     // (contains a barrier: lam is visible after it)

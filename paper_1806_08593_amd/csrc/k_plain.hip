@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
 // ---------------------------------------------------------------------------
 template <typename T, int V, int R>
 __device__ __forceinline__ void rows_lse(const T* __restrict__ fb, int64_t row0, int nrow,
-                                         const T* __restrict__ gam, int Kc, int lane,
+                                         const T* __restrict__ gam, int Kc, int lane, T kap,
                                          T (&lse)[R]) {
   const T NEG = (T)(-INFINITY);
   T m[R], sm[R];
@@ -185,7 +185,7 @@ __device__ __forceinline__ void rows_lse(const T* __restrict__ fb, int64_t row0,
       T cm = NEG;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        x[r][v] = ok ? x[r][v] + g[v] : NEG;
+        x[r][v] = ok ? kap * x[r][v] + g[v] : NEG;
         cm = nan_max(cm, x[r][v]);
       }
       const T nm = nan_max(m[r], cm);
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_plain_lse_fwd(const LayerDev* __restric
   const int nrow = min(R, K - i0);
   const T* fb = f + (caller_off ? L.f_off : L.wf_off);
   T lse[R];
-  rows_lse<T, V, R>(fb, i0, nrow, gam, Kc, lane, lse);
+  rows_lse<T, V, R>(fb, i0, nrow, gam, Kc, lane, (T)L.kappa, lse);
   const double lkc = log((double)Kc);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_plain_lse_fwd(const LayerDev* __restric
     if (lane == r && r < nrow) {
       rl[L.rl_off + i] = lse[r];
       const double a = anchor ? anchor[L.rl_off + i] : 0.0;
-      alpha[L.alpha_off + i] = (double)u[L.u_off + i] + M + a + (double)lse[r] - lkc;
+      alpha[L.alpha_off + i] = L.kappa * ((double)u[L.u_off + i] + a) + M + (double)lse[r] - lkc;
     }
   }
 }
@@ -275,8 +275,9 @@ __global__ __launch_bounds__(64 * kPlainBwdWaves) void k_plain_lse_bwd(
   const bool active = j < Kc;
   const double M = pairM[it.layer];
   const double* aup = alpha + L.alpha_up_off;
-  const double g = dlogp[L.chain];
+  const double g = dlogp[L.chain] * L.kappa;   // d/d(kappa f) -> d/df
   const T gs = scale ? (T)g : (T)1;
+  const T kap = (T)L.kappa;
   T gam[V], cs[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(64 * kPlainBwdWaves) void k_plain_lse_bwd(
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         // p_i == 0 (a row outside the support) gives G = 0 even where exp overflows
-        const T gv = (pi[r] == (T)0) ? (T)0 : pi[r] * fast_exp(x[r][v] + gam[v] - li[r]);
+        const T gv = (pi[r] == (T)0) ? (T)0 : pi[r] * fast_exp(kap * x[r][v] + gam[v] - li[r]);
         cs[v] += live ? gv : (T)0;
         x[r][v] = gv * gs;
       }
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(256) void k_plain_gmu(const LayerDev* __restrict__ 
   const int d = d0 + dl;
   if (d >= D) return;
   const T lam = (T)exp(-2.0 * (double)s[L.s_off + d]);
-  const T g = (T)dlogp[L.chain];
+  const T g = (T)(dlogp[L.chain] * L.kappa);
 #pragma unroll
   for (int q = 0; q < TR / 4; ++q) {
     const int i = i0 + rs + 4 * q;
@@ -432,7 +433,7 @@ __global__ __launch_bounds__(256) void k_plain_gtz(const LayerDev* __restrict__ 
   const int d = d0 + dl;
   if (d >= D) return;
   const T lam = (T)exp(-2.0 * (double)s[L.s_off + d]);
-  const T g = (T)dlogp[L.chain];
+  const T g = (T)(dlogp[L.chain] * L.kappa);
 #pragma unroll
   for (int q = 0; q < TC / 4; ++q) {
     const int j = j0 + cs + 4 * q;
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(256) void k_pair_dsp(const LayerDev* __restrict__ L
   const int K = L.K, Kc = L.Kc, D = L.D;
   const T* pr = p + L.p_off;
   const T* pc = p + L.p_up_off;
-  const T g = (T)dlogp[L.chain];
+  const T g = (T)(dlogp[L.chain] * L.kappa);
   T P = (T)0;
   for (int i = 0; i < K; ++i) P += pr[i];
   for (int d = threadIdx.x; d < D; d += blockDim.x) {

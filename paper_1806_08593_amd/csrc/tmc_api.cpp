@@ -156,6 +156,8 @@ tmc_status validate(const tmc_problem* pr, int* engine_out, std::string* gauss_e
   if ((pr->n_chains > 0 && !pr->chains) || (pr->n_layers > 0 && !pr->layers))
     return fail(TMC_ERR_INVALID_ARG, "chains or layers array is NULL");
   if (pr->reserved != 0) return fail(TMC_ERR_INVALID_ARG, "reserved field must be 0");
+  if (!(pr->exponent == 0.0 || (std::isfinite(pr->exponent) && pr->exponent > 0.0)))
+    return fail(TMC_ERR_INVALID_ARG, "exponent must be 0 (meaning 1) or finite and > 0");
   if (pr->precision < TMC_FP64 || pr->precision > TMC_BF16X3)
     return fail(TMC_ERR_INVALID_ARG, "unknown precision %d", pr->precision);
   if (pr->engine < TMC_ENGINE_AUTO || pr->engine > TMC_ENGINE_PLAIN)
@@ -307,6 +309,7 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
       d.D = L.D;
       d.chain = c;
       d.depth = q;
+      d.kappa = pr->exponent == 0.0 ? 1.0 : pr->exponent;
       d.up = top ? -1 : l + 1;
       d.Kc = top ? 0 : pr->layers[l + 1].K;
       d.z_off = L.z_off;

@@ -45,6 +45,7 @@ struct LayerDev {
   int32_t dz_fused;      // fused: an 8-wave backward of this pair may write dz and the
                          // ds row part itself (aligned rows of z and e)
   double lnKc;           // ln K of the layer above
+  double kappa;          // exponent of the weights (1: the estimator of eq. (is))
 };
 
 struct ChainDev {

@@ -55,7 +55,7 @@ class tmc_chain(ctypes.Structure):
 class tmc_problem(ctypes.Structure):
     _fields_ = [("n_chains", c_int32), ("n_layers", c_int32), ("chains", POINTER(tmc_chain)),
                 ("layers", POINTER(tmc_layer)), ("precision", c_int32), ("engine", c_int32),
-                ("flags", c_int32), ("reserved", c_int32)]
+                ("flags", c_int32), ("reserved", c_int32), ("exponent", c_double)]
 
 
 class tmc_plan_info(ctypes.Structure):
@@ -248,7 +248,7 @@ class Problem:
     """
 
     def __init__(self, chains: Sequence, layers: Sequence[dict], precision="fp32",
-                 engine="auto", flags=0):
+                 engine="auto", flags=0, exponent=1.0):
         self.n_chains, self.n_layers = len(chains), len(layers)
         self._chains = (tmc_chain * max(1, len(chains)))()
         for i, (first, n) in enumerate(chains):
@@ -260,12 +260,13 @@ class Problem:
         prec = PRECISIONS[precision] if isinstance(precision, str) else precision
         eng = ENGINES[engine] if isinstance(engine, str) else engine
         self.c = tmc_problem(len(chains), len(layers), self._chains, self._layers, prec, eng,
-                             flags, 0)
+                             flags, 0, float(exponent))
         self.chains = list(chains)
         self.layers = [dict(d) for d in layers]
 
 
-def homogeneous_problem(B, L, K, D, precision="fp32", engine="auto", flags=0) -> Problem:
+def homogeneous_problem(B, L, K, D, precision="fp32", engine="auto", flags=0,
+                        exponent=1.0) -> Problem:
     """B chains of L layers, K samples and width D each, laid out as
     z [B, L, K, D], mu [B, L-1, K, D], s [L-1, D] (shared by the batch),
     u [B, L, K] and f [B, L-1, K, K]."""
@@ -278,10 +279,10 @@ def homogeneous_problem(B, L, K, D, precision="fp32", engine="auto", flags=0) ->
                                mu_off=0 if top else ((b * (L - 1) + l) * K) * D,
                                s_off=0 if top else l * D,
                                f_off=0 if top else ((b * (L - 1) + l) * K) * K))
-    return Problem(chains, layers, precision, engine, flags)
+    return Problem(chains, layers, precision, engine, flags, exponent)
 
 
-def ragged_problem(shapes, precision="fp32", engine="auto", flags=0, share_s=False):
+def ragged_problem(shapes, precision="fp32", engine="auto", flags=0, share_s=False, exponent=1.0):
     """Chains given as a list of (K_list, D_list) (one entry per layer), packed
     back to back in flat z, mu, s, u and f buffers.  Returns (problem, sizes) with
     sizes the element counts of the flat buffers."""
@@ -301,7 +302,8 @@ def ragged_problem(shapes, precision="fp32", engine="auto", flags=0, share_s=Fal
                 so += Ds[l]
                 fo += Ks[l] * Ks[l + 1]
             layers.append(d)
-    return Problem(chains, layers, precision, engine, flags), dict(z=zo, u=uo, mu=mo, s=so, f=fo)
+    return (Problem(chains, layers, precision, engine, flags, exponent),
+            dict(z=zo, u=uo, mu=mo, s=so, f=fo))
 
 
 class Plan:

@@ -19,7 +19,7 @@ def test_exports_every_declared_function():
     lib = ctypes.CDLL(T._LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert T.tmc_abi_version() == 3
+    assert T.tmc_abi_version() == 4
 
 
 def test_struct_layout_matches_header():
@@ -29,8 +29,9 @@ def test_struct_layout_matches_header():
 #include "tmc.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(tmc_layer), sizeof(tmc_chain), sizeof(tmc_problem), sizeof(tmc_plan_info));
-  printf("%zu %zu %zu %zu\n", offsetof(tmc_layer, f_off), offsetof(tmc_problem, layers),
-         offsetof(tmc_problem, flags), offsetof(tmc_plan_info, waves_per_group));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(tmc_layer, f_off), offsetof(tmc_problem, layers),
+         offsetof(tmc_problem, flags), offsetof(tmc_plan_info, waves_per_group),
+         offsetof(tmc_problem, exponent));
   return 0;
 }
 '''
@@ -43,7 +44,8 @@ int main(void) {
     got = list(map(int, out))
     want = [ctypes.sizeof(T.tmc_layer), ctypes.sizeof(T.tmc_chain), ctypes.sizeof(T.tmc_problem),
             ctypes.sizeof(T.tmc_plan_info), T.tmc_layer.f_off.offset, T.tmc_problem.layers.offset,
-            T.tmc_problem.flags.offset, T.tmc_plan_info.waves_per_group.offset]
+            T.tmc_problem.flags.offset, T.tmc_plan_info.waves_per_group.offset,
+            T.tmc_problem.exponent.offset]
     assert got == want
 
 
@@ -87,6 +89,8 @@ def test_validation_errors():
     p = T.homogeneous_problem(2, 3, 4, 5)
     p.c.flags = 64
     _expect(p, T.TMC_ERR_INVALID_ARG, "flag")
+    for bad in (-1.0, float("inf"), float("nan")):
+        _expect(T.homogeneous_problem(2, 3, 4, 5, exponent=bad), T.TMC_ERR_INVALID_ARG, "exponent")
 
 
 def test_valid_problem_needs_a_device():

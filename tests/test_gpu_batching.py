@@ -1,6 +1,5 @@
-"""Ragged batching through the C ABI: persistent launches over a dependency-ordered
-work queue, their graph capture, the bounded dependency wait and the launch-shape
-tuner.  The persistent launch runs the same per-item arithmetic as the per-depth
+"""Ragged batching through the C ABI: persistent launches over a queue of whole chains
+(most expensive first), their graph capture and the launch-shape tuner.  The persistent launch runs the same per-item arithmetic as the per-depth
 launches, so its outputs must be bit-identical to them; both are also checked against
 the FP64 oracle on the same FP32-cast inputs."""
 import os

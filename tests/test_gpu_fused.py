@@ -216,3 +216,30 @@ def test_wide_workgroups_bitwise_equal_narrow(prec, tmp_path, monkeypatch):
             else:
                 assert np.array_equal(out[g], ref[g]), (key, g)
     _check(outs[(1, 1)], chains, prec)
+
+
+def test_ragged_autograd_wrapper():
+    """torch.autograd over a ragged batch: the weighted sum of log P differentiates to the
+    weighted oracle gradients of every chain (weights 1..n through dlogp)."""
+    from paper_1806_08593_amd import autograd as A
+    rng = np.random.default_rng(44)
+    shapes = [((37, 64, 9), (16, 33, 5)), ((130, 70), (64, 7)), ((12,), (3,))]
+    chains = cast_chains([_rand_chain(rng, Ks, Ds) for Ks, Ds in shapes], "fp32")
+    shp, flat = pack_chains(chains, "fp32")
+    run = A.RaggedGaussChainTMC(shp, precision="fp32", engine="fused")
+    t = {k: torch.tensor(v, device="cuda:0", requires_grad=True) for k, v in flat.items()}
+    logp = run(t["z"], t["mu"], t["s"], t["u"])
+    wts = torch.arange(1, len(chains) + 1, dtype=torch.float64, device="cuda:0")
+    (logp * wts).sum().backward()
+    ref = oracle_grads(chains)
+    ea, er = GRAD_ELEM_TOL["fp32"]
+    for k, idx in (("z", 1), ("mu", 2), ("s", 3), ("u", 4)):
+        got = unpack(t[k].grad.cpu().numpy().astype(np.float64), chains, k)
+        for c, r in enumerate(ref):
+            assert abs(logp[c].item() - r[0]) <= 1e-4
+            for l, rb in enumerate(r[idx]):
+                want = (c + 1) * np.asarray(rb)
+                if np.abs(want).max() == 0:
+                    assert np.abs(got[c][l]).max() == 0
+                else:
+                    assert_elem(got[c][l], want, ea, er, f"ragged-autograd/d{k}/chain{c}/layer{l}")

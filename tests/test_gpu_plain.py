@@ -248,3 +248,43 @@ def test_graph_replay_equals_eager():
             T.tmc_plan_graph_launch(plan.handle, 0, st)
             st.synchronize()
             assert torch.equal(logp_g, logp_e), rep
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_logfactor_calls_capture_into_a_graph(prec):
+    """The execute calls neither allocate nor synchronise, so a caller's own stream
+    capture around tmc_logfactor_fwd/bwd records them: each replay (outputs cleared
+    eagerly in between) equals the eager results bit for bit."""
+    from paper_1806_08593_amd import tmc as T
+    rng = np.random.default_rng(12)
+    Ks = [(70, 33, 128), (5, 300)]
+    shapes = [(list(k), [1] * len(k)) for k in Ks]
+    prob, sizes = T.ragged_problem(shapes, prec, "plain")
+    plan = T.Plan(prob)
+    ws = plan.new_workspace()
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    f_d = torch.tensor(rng.normal(size=sizes["f"]) * 3.0, dtype=tdt, device="cuda:0")
+    u_d = torch.tensor(rng.normal(size=sizes["u"]) * 2.0, dtype=tdt, device="cuda:0")
+    n = len(Ks)
+    dl = torch.full((n,), 0.5, dtype=torch.float64, device="cuda:0")
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        lp_e = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        df_e, du_e = torch.empty_like(f_d), torch.empty_like(u_d)
+        T.tmc_logfactor_fwd(plan.handle, f_d, u_d, lp_e, ws, st)
+        T.tmc_logfactor_bwd(plan.handle, f_d, u_d, dl, ws, df_e, du_e, st)
+        st.synchronize()
+        lp, df, du = torch.empty_like(lp_e), torch.empty_like(df_e), torch.empty_like(du_e)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            T.tmc_logfactor_fwd(plan.handle, f_d, u_d, lp, ws, st)
+            T.tmc_logfactor_bwd(plan.handle, f_d, u_d, dl, ws, df, du, st)
+        for rep in range(3):
+            for t in (lp, df, du):
+                t.fill_(float("nan"))
+            st.synchronize()
+            g.replay()
+            st.synchronize()
+            assert torch.equal(lp, lp_e), rep
+            assert torch.equal(df, df_e) and torch.equal(du, du_e), rep
+    T.tmc_plan_check(plan.handle)

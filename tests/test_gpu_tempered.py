@@ -1,0 +1,105 @@
+"""Weights raised to a power kappa (the problem's exponent) and the DReGs surrogate of
+Appendix "Combining DReGs and TMC", through the C ABI, against the oracle's tempered
+estimator and its gradients (pinned on the CPU by enumeration of every index tuple)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import tmc_oracle as O
+from workloads import Chain, make
+
+from .gpu_helpers import GRAD_ELEM_TOL, assert_elem, cast_chains, pack_chains, to_dev, torch, unpack
+
+pytestmark = pytest.mark.gpu
+
+LOGP_TOL = {"fp64": None, "fp32": 1e-4, "bf16x3": 2e-3}
+
+
+def _rand_chain(rng, Ks, Ds):
+    L = len(Ks)
+    z = [rng.normal(size=(Ks[l], Ds[l])) for l in range(L)]
+    mu = [np.tanh(rng.normal(size=(Ks[l + 1], Ds[l]))) for l in range(L - 1)]
+    s = [rng.uniform(-1.0, 0.0, size=Ds[l]) for l in range(L - 1)]
+    u = [rng.normal(size=Ks[l]) * 5.0 for l in range(L)]
+    return Chain(z=z, mu=mu, s=s, u=u)
+
+
+def _run(chains, prec, engine, kappa, dlogp=None):
+    from paper_1806_08593_amd import tmc as T
+    shapes, flat = pack_chains(chains, prec)
+    prob, _ = T.ragged_problem(shapes, prec, engine, exponent=kappa)
+    plan = T.Plan(prob)
+    ws = plan.new_workspace()
+    d = {k: to_dev(v) for k, v in flat.items()}
+    n = len(chains)
+    lp = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    dl = torch.ones(n, dtype=torch.float64, device="cuda:0") if dlogp is None else \
+        torch.tensor(dlogp, dtype=torch.float64, device="cuda:0")
+    g = {k: torch.full_like(v, float("nan")) for k, v in d.items()}
+    T.tmc_gauss_fwd(plan.handle, d["z"], d["mu"], d["s"], d["u"], lp, ws)
+    T.tmc_gauss_bwd(plan.handle, d["z"], d["mu"], d["s"], d["u"], dl, ws, g["z"], g["mu"], g["s"], g["u"])
+    torch.cuda.synchronize()
+    T.tmc_plan_check(plan.handle)
+    out = lp.cpu().numpy(), {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    plan.close()
+    return out
+
+
+def _check(lp, g, chains, prec, kappa, label, scale=None):
+    ea, er = GRAD_ELEM_TOL[prec]
+    for c, ch in enumerate(chains):
+        ref = O.gauss_chain_grads_tempered(ch.z, ch.mu, ch.s, ch.u, kappa)
+        tol = 1e-9 * max(1.0, abs(ref[0])) if prec == "fp64" else LOGP_TOL[prec]
+        assert abs(lp[c] - ref[0]) <= tol, (label, c, lp[c], ref[0])
+        for k, idx in (("z", 1), ("mu", 2), ("s", 3), ("u", 4)):
+            got = unpack(g[k], chains, k)[c]
+            for l, rb in enumerate(ref[idx]):
+                rb = np.asarray(rb) * (1.0 if scale is None else scale[c])
+                if np.abs(rb).max() == 0:
+                    assert np.abs(got[l]).max() == 0
+                else:
+                    assert_elem(got[l], rb, ea, er, f"{label}/d{k}/chain{c}/layer{l}")
+
+
+@pytest.mark.parametrize("prec,engine", [("fp64", "plain"), ("fp32", "plain"), ("fp32", "fused"),
+                                         ("bf16x3", "fused")])
+@pytest.mark.parametrize("kappa", [2.0, 0.5])
+def test_tempered_chain_matches_oracle(prec, engine, kappa):
+    """Ragged chains (tile tails in K and D) with every weight raised to kappa."""
+    rng = np.random.default_rng(61)
+    shapes = [((37, 64, 9), (16, 33, 5)), ((130, 70, 33), (64, 7, 100)), ((12,), (3,)),
+              ((257, 40), (128, 12))]
+    chains = cast_chains([_rand_chain(rng, Ks, Ds) for Ks, Ds in shapes], prec)
+    lp, g = _run(chains, prec, engine, kappa)
+    _check(lp, g, chains, prec, kappa, f"tempered-{prec}-{engine}-k{kappa}")
+
+
+@pytest.mark.parametrize("prec,engine", [("fp64", "plain"), ("bf16x3", "fused")])
+def test_dregs_surrogate_from_two_tempered_passes(prec, engine):
+    """The DReGs surrogate's gradient: a kappa = 1 forward gives log P_1, a kappa = 2
+    forward gives log P_2, and the kappa = 2 backward with upstream gradient
+    1/2 exp(log P_2 - 2 log P_1 - sum_l ln K_l) gives the gradients: against the oracle's
+    DReGs gradients (themselves pinned against the enumerated DReGs estimator)."""
+    w = make("c2", B=3)
+    chains = cast_chains(w.chains, prec)
+    from paper_1806_08593_amd import tmc as T
+    lp1, _ = _run(chains, prec, engine, 1.0)
+    lp2, _ = _run(chains, prec, engine, 2.0)
+    lnK = np.array([sum(math.log(k) for k in c.K) for c in chains])
+    coef = np.exp(lp2 - 2.0 * lp1 - lnK)
+    _, g = _run(chains, prec, engine, 2.0, dlogp=0.5 * coef)
+    ea, er = GRAD_ELEM_TOL[prec]
+    for c, ch in enumerate(chains):
+        rc, dz, dmu, ds, du = O.dregs_gradients(ch.z, ch.mu, ch.s, ch.u)
+        assert abs(coef[c] - rc) <= (1e-9 if prec == "fp64" else 5e-3) * rc, (c, coef[c], rc)
+        # the gradients against the oracle's, with the coefficient taken from this side
+        # (its error is the one checked above)
+        for k, blocks in (("z", dz), ("mu", dmu), ("s", ds), ("u", du)):
+            got = unpack(g[k], chains, k)[c]
+            for l, rb in enumerate(blocks):
+                rb = np.asarray(rb) * (coef[c] / rc)
+                if np.abs(rb).max() == 0:
+                    assert np.abs(got[l]).max() == 0
+                else:
+                    assert_elem(got[l], rb, ea, er, f"dregs-{prec}/d{k}/chain{c}/layer{l}")

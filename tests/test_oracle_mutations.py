@@ -52,6 +52,26 @@ MUTATIONS = [
      P.test_expanded_gradients_equal_direct_difference),
     ("gauss_chain_grads_expanded", "\n                  - g.sum())", ")",
      P.test_expanded_gradients_equal_direct_difference),
+    ("tempered_chain_logp", "[kappa * np.asarray(a, np.float64) for a in u]",
+     "[np.asarray(a, np.float64) for a in u]",
+     P.test_tempered_estimator_equals_enumeration_of_powered_weights),
+    ("gauss_chain_grads_tempered", "dz[l] = kappa * np.sum", "dz[l] = np.sum",
+     P.test_tempered_gradients_against_enumeration_and_differences),
+    ("gauss_chain_grads_tempered", "(lam * diff * diff - 1.0)", "(lam * diff * diff)",
+     P.test_tempered_gradients_against_enumeration_and_differences),
+    ("dregs_gradients", "h = 0.5 * c", "h = c",
+     P.test_dregs_surrogate_gradient_is_the_dregs_estimator),
+    ("dregs_gradients", "- 2.0 * lp1 - sum(log_k(len(a)) for a in u))", "- 2.0 * lp1)",
+     P.test_dregs_surrogate_gradient_is_the_dregs_estimator),
+    ("star_logp", "\\\n            - log_k(len(ui))", "",
+     P.test_star_equals_enumeration_and_one_point_chain),
+    ("star_logp", "axis=1)", "axis=0)", P.test_star_equals_enumeration_and_one_point_chain),
+    ("star_marginals", "- (mi + log_k(len(ui)))[:, None]", "- mi[:, None]",
+     P.test_star_marginals_and_gradients_against_differences),
+    ("gauss_star_grads", "dz.append(np.sum(g * (-lam * diff), axis=0))", "dz.append(np.sum(g * (lam * diff), axis=0))",
+     P.test_star_marginals_and_gradients_against_differences),
+    ("gauss_star_log_evidence", "+ 2.0 * np.eye(n)", "+ np.eye(n)",
+     P.test_star_evidence_closed_form_against_quadrature),
 ]
 
 

@@ -360,3 +360,123 @@ def test_expanded_gradients_equal_direct_difference():
     for k in range(1, 5):
         for x, y in zip(a[k], b[k]):
             np.testing.assert_allclose(y, x, rtol=1e-10, atol=1e-12 * max(1.0, np.abs(x).max()))
+
+
+# --- tempered weights and the DReGs surrogate (Appendix "Combining DReGs and TMC") ---
+
+def test_tempered_estimator_equals_enumeration_of_powered_weights():
+    rng = np.random.default_rng(31)
+    K, D = (3, 4, 2), (2, 3, 2)
+    z, mu, s, u = _rand_chain(rng, K, D, scale=0.6)
+    f = O.gauss_chain_factors(z, mu, s)
+    logw = [sum(u[l][t[l]] for l in range(3)) + sum(f[l][t[l], t[l + 1]] for l in range(2))
+            for t in itertools.product(*[range(k) for k in K])]
+    for kappa in (1.0, 2.0, 0.5):
+        ref = special.logsumexp(kappa * np.array(logw)) - sum(math.log(k) for k in K)
+        assert abs(O.tempered_chain_logp(f, u, kappa) - ref) < 1e-11
+    assert abs(O.tempered_chain_logp(f, u, 1.0) - O.chain_logp(f, u)) < 1e-12
+
+
+def test_tempered_gradients_against_enumeration_and_differences():
+    """Tempered gradients: the enumeration of kappa * softmax(kappa log w)_t * d log w_t over
+    tuples, and central finite differences of the tempered log P."""
+    rng = np.random.default_rng(32)
+    K, D = (3, 2, 3), (2, 2, 3)
+    z, mu, s, u = _rand_chain(rng, K, D, scale=0.6)
+    kappa = 2.0
+    lp, dz, dmu, ds, du = O.gauss_chain_grads_tempered(z, mu, s, u, kappa)
+    bz, bmu, bs, bu = O.brute_force_weighted_grads(
+        z, mu, s, u, lambda lw: kappa * np.exp(kappa * lw - special.logsumexp(kappa * lw)))
+    for a, b in zip(dz + dmu + ds + du, bz + bmu + bs + bu):
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
+    tl = lambda zz, mm, ss, uu: O.tempered_chain_logp(O.gauss_chain_factors(zz, mm, ss), uu, kappa)
+    fd = O.finite_difference(lambda a: tl([a, z[1], z[2]], mu, s, u), z[0])
+    np.testing.assert_allclose(dz[0].reshape(-1), fd, atol=2e-7)
+    fd = O.finite_difference(lambda a: tl(z, [mu[0], a], s, u), mu[1])
+    np.testing.assert_allclose(dmu[1].reshape(-1), fd, atol=2e-7)
+    fd = O.finite_difference(lambda a: tl(z, mu, [a, s[1]], u), s[0])
+    np.testing.assert_allclose(ds[0], fd, atol=2e-7)
+
+
+def test_dregs_surrogate_gradient_is_the_dregs_estimator():
+    """The surrogate's gradient, from two tempered passes, equals the DReGs recognition
+    update sum_t w_t^2 / (sum_t w_t)^2 * d log w_t summed over every tuple."""
+    rng = np.random.default_rng(33)
+    K, D = (2, 3, 2), (2, 2, 2)
+    z, mu, s, u = _rand_chain(rng, K, D, scale=0.6)
+    c, dz, dmu, ds, du = O.dregs_gradients(z, mu, s, u)
+    bz, bmu, bs, bu = O.brute_force_weighted_grads(
+        z, mu, s, u, lambda lw: np.exp(2.0 * lw - 2.0 * special.logsumexp(lw)))
+    for a, b in zip(dz + dmu + ds + du, bz + bmu + bs + bu):
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-13)
+    # coefficient = sum w^2 / (sum w)^2, in (0, 1]
+    f = O.gauss_chain_factors(z, mu, s)
+    lw = np.array([sum(u[l][t[l]] for l in range(3)) + sum(f[l][t[l], t[l + 1]] for l in range(2))
+                   for t in itertools.product(*[range(k) for k in K])])
+    assert abs(c - np.exp(special.logsumexp(2 * lw) - 2 * special.logsumexp(lw))) < 1e-12
+
+
+# --- star model: one global latent, N local latents (Sec. "Efficient averaging") ---
+
+def _rand_star(rng, N, Kt, K, D):
+    mth = rng.normal(size=(Kt, D))
+    s = rng.uniform(-1.0, 0.0, size=D)
+    z = [rng.normal(size=(K, D)) for _ in range(N)]
+    u = [rng.normal(size=K) * 2.0 for _ in range(N)]
+    uth = rng.normal(size=Kt)
+    return mth, s, z, u, uth
+
+
+def test_star_equals_enumeration_and_one_point_chain():
+    rng = np.random.default_rng(41)
+    mth, s, z, u, uth = _rand_star(rng, 3, 3, 2, 2)
+    f = [O.gauss_pair_logfactor(mth, zi, s) for zi in z]
+    assert abs(O.star_logp(uth, f, u) - O.star_brute_force(uth, f, u)) < 1e-11
+    # one data point: a chain of two layers (local latent next to the data, theta on top)
+    assert abs(O.star_logp(uth, f[:1], u[:1]) - O.chain_logp([f[0].T], [u[0], uth])) < 1e-11
+    # permuting the data points leaves the estimate unchanged
+    assert abs(O.star_logp(uth, f[::-1], u[::-1]) - O.star_logp(uth, f, u)) < 1e-11
+
+
+def test_star_marginals_and_gradients_against_differences():
+    rng = np.random.default_rng(42)
+    mth, s, z, u, uth = _rand_star(rng, 3, 4, 3, 2)
+    lp, dm, ds, dz, du, w = O.gauss_star_grads(mth, s, z, u, uth)
+    fl = lambda mm, ss, zz, uu, tt: O.star_logp(tt, [O.gauss_pair_logfactor(mm, zi, ss) for zi in zz], uu)
+    np.testing.assert_allclose(dm.reshape(-1), O.finite_difference(lambda a: fl(a, s, z, u, uth), mth), atol=2e-7)
+    np.testing.assert_allclose(ds, O.finite_difference(lambda a: fl(mth, a, z, u, uth), s), atol=2e-7)
+    np.testing.assert_allclose(dz[1].reshape(-1),
+                               O.finite_difference(lambda a: fl(mth, s, [z[0], a, z[2]], u, uth), z[1]), atol=2e-7)
+    np.testing.assert_allclose(du[2], O.finite_difference(lambda a: fl(mth, s, z, [u[0], u[1], a], uth), u[2]), atol=2e-7)
+    np.testing.assert_allclose(w, O.finite_difference(lambda a: fl(mth, s, z, u, a), uth), atol=2e-7)
+    assert abs(w.sum() - 1.0) < 1e-12 and all(abs(d.sum() - 1.0) < 1e-12 for d in du)
+
+
+@pytest.mark.slow
+def test_star_estimate_unbiased_for_the_gaussian_model():
+    """The paper's Gaussian star model (theta ~ N(0,1), z_i | theta ~ N(theta, 1),
+    x_i | z_i ~ N(z_i, 1); proposals N(0, 1) for theta and N(0, 2) for z_i): the mean of
+    exp(log P_TMC - log P(x)) over independent replicates is 1 within 4 standard errors."""
+    rng = np.random.default_rng(43)
+    N, K, Kt, R = 4, 16, 16, 3000
+    x = rng.normal(size=N) * np.sqrt(3.0)
+    lpx = O.gauss_star_log_evidence(x)
+    ratios = []
+    for _ in range(R):
+        th = rng.normal(size=Kt)
+        zs = [rng.normal(size=K) * np.sqrt(2.0) for _ in range(N)]
+        uth = stats.norm.logpdf(th) - stats.norm.logpdf(th)                  # P(theta)/Q(theta)
+        u = [stats.norm.logpdf(x[i], loc=zs[i]) - stats.norm.logpdf(zs[i], scale=np.sqrt(2.0))
+             for i in range(N)]
+        f = [O.gauss_pair_logfactor(th[:, None], zs[i][:, None], np.zeros(1)) for i in range(N)]
+        ratios.append(np.exp(O.star_logp(uth, f, u) - lpx))
+    ratios = np.array(ratios)
+    assert abs(ratios.mean() - 1.0) < 4.0 * ratios.std() / np.sqrt(R), (ratios.mean(), ratios.std())
+
+
+def test_star_evidence_closed_form_against_quadrature():
+    x = np.array([0.3, -1.2, 0.8])
+    # integrate theta out numerically: x_i | theta ~ N(theta, 2) independently
+    val, _ = integrate.quad(lambda t: stats.norm.pdf(t) * np.prod(stats.norm.pdf(x, loc=t, scale=np.sqrt(2.0))),
+                            -12, 12)
+    assert abs(O.gauss_star_log_evidence(x) - np.log(val)) < 1e-9
