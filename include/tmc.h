@@ -23,7 +23,7 @@
  * averaging"), each step a log-domain matrix-vector product (Appendix "Numerically
  * stable matrix (tensor) products in the log-domain").
  *
- * Two families of entry points:
+ * Three families of entry points:
  *   tmc_gauss_*      the chained diagonal-Gaussian model of Sec. "Computational costs
  *                    for TMC and IWAE": f_l[i,j] = log N(z_l^i; mu_l^j, diag exp(2 s_l)),
  *                    where mu_l^j (the conditional mean produced by the caller's network
@@ -32,6 +32,8 @@
  *                    to z, mu, s and u are returned for reparameterised training.
  *   tmc_logfactor_*  any chain whose log-factors f_l are supplied as dense matrices
  *                    (e.g. the exact discrete marginalisation of the Appendix).
+ *   tmc_star_*       not a chain: one global latent shared by many local latents (the
+ *                    latent-variable model of Sec. "Efficient averaging"), below.
  *
  * Memory.  Every data pointer is DEVICE memory on the plan's device unless marked
  * (host).  The caller allocates and owns every buffer, including the workspace; the
@@ -69,7 +71,7 @@
 extern "C" {
 #endif
 
-#define TMC_ABI_VERSION 4
+#define TMC_ABI_VERSION 5
 
 typedef enum tmc_status {
   TMC_OK = 0,
@@ -233,6 +235,56 @@ tmc_status tmc_logfactor_bwd(tmc_plan_t plan, const void* f, const void* u,
                              const double* dlogp, void* workspace, void* df, void* du,
                              void* stream);
 
+/* ---- Star model: a global latent shared by N local latents ---- */
+/* The latent-variable model of Sec. "Efficient averaging" (its factor graph figure):
+ * a global latent theta with K_theta samples and, for each of N data points, a local
+ * latent z_i with K samples whose conditional depends on theta,
+ *
+ *   log P_TMC = log [ 1/(K_theta K^N) sum_{kt, k_1..k_N}
+ *                     exp( uth[kt] + sum_i (u_i[k_i] + f_i[kt, k_i]) ) ]
+ *             = logsumexp_kt( uth[kt] + sum_i m_i[kt] ) - ln K_theta,
+ *   m_i[kt]   = logsumexp_k( u_i[k] + f_i[kt, k] ) - ln K,
+ *
+ * with f_i[kt, k] = log N(z_i^k; mth^kt, diag exp(2 s)): mth^kt is the mean of every
+ * local latent given global sample kt (produced by the caller from theta^kt), s the log
+ * standard deviation.  uth[kt] holds log P(theta^kt) - log Q(theta^kt); u_i[k] holds
+ * log P(x_i | z_i^k) - log Q(z_i^k).  The Gaussian example of Sec. "Comparing TMC, SMC
+ * and IWAE" is D = 1, mth^kt = theta^kt, s = 0.
+ * n_instances independent models of the same shape are evaluated together.
+ * Layout (row-major, element type double for TMC_FP64 and float for TMC_FP32):
+ *   mth [S][K_theta][D], s [S][D], z [S][N][K][D], u [S][N][K], uth [S][K_theta],
+ * S = n_instances; logp and dlogp are double [S].  The plan is a tmc_plan_t: destroy,
+ * workspace size, info (factor_entries = S N K_theta K), check and timing calls apply;
+ * the chain entry points reject it, and the star entry points reject chain plans. */
+typedef struct tmc_star_problem {
+  int32_t n_instances;  /* S >= 1 */
+  int32_t N;            /* data points (local latents) per instance, >= 1 */
+  int32_t K_theta;      /* samples of the global latent, 1 .. 4194304 */
+  int32_t K;            /* samples of each local latent, 1 .. 4194304 */
+  int32_t D;            /* dimension of each local latent, 1 .. 32 */
+  int32_t precision;    /* TMC_FP64 or TMC_FP32 (per-entry arithmetic; sums over rows,
+                           messages and log P are double) */
+  int32_t flags;        /* 0 or TMC_FLAG_FORWARD_ONLY (smaller workspace, no backward) */
+  int32_t reserved;     /* must be 0 */
+} tmc_star_problem;
+
+/* Errors: TMC_ERR_INVALID_ARG (null, bad flags or precision, S N or S K_theta D too
+ * large for one launch grid), TMC_ERR_SHAPE (N, K, K_theta or D out of range),
+ * TMC_ERR_UNSUPPORTED (TMC_BF16X3: the factors of such low-dimensional latents are not
+ * a contraction worth the matrix cores), TMC_ERR_HIP. */
+tmc_status tmc_star_plan_create(const tmc_star_problem* problem, int device, tmc_plan_t* out);
+/* Forward: logp[S].  The workspace receives the messages and weights the backward reads. */
+tmc_status tmc_star_gauss_fwd(tmc_plan_t plan, const void* mth, const void* s, const void* z,
+                              const void* u, const void* uth, double* logp, void* workspace,
+                              void* stream);
+/* Backward: given dlogp[S], writes dmth [S][K_theta][D], ds [S][D], dz [S][N][K][D],
+ * du [S][N][K] and duth [S][K_theta] (each dlogp times the derivative of log P; any may
+ * be NULL to skip it).  Reads the workspace of the matching forward; mth, s, z, u must be
+ * unchanged since.  Sums over points and samples run in a fixed order (deterministic). */
+tmc_status tmc_star_gauss_bwd(tmc_plan_t plan, const void* mth, const void* s, const void* z,
+                              const void* u, const double* dlogp, void* workspace, void* dmth,
+                              void* ds, void* dz, void* du, void* duth, void* stream);
+
 /* ---- graphs ---- */
 /* Record the enqueue of one execute call (same arguments as the call) into a hipGraph
  * owned by the plan; which = 0 forward, 1 backward.  The pointers are baked into the
@@ -284,7 +336,9 @@ typedef enum tmc_kernel_class {
   TMC_KC_FUSED_FWD = 5,      /* fused: factor GEMM + forward message */
   TMC_KC_FUSED_BWD = 6,      /* fused: factor GEMM + marginals + gradient GEMM */
   TMC_KC_OTHER = 7,          /* initialisation, log-normaliser, reductions */
-  TMC_KC_COUNT = 8
+  TMC_KC_STAR_MSG = 8,       /* star model: local messages m_i (forward) */
+  TMC_KC_STAR_BWD = 9,       /* star model: local and global gradient passes */
+  TMC_KC_COUNT = 10
 } tmc_kernel_class;
 
 /* enable != 0: every later execute call on this plan records a hipEvent pair around

@@ -12,6 +12,7 @@ top of the chain):
     z[l]  [K_l, D_l]      samples of layer l
     mu[l] [K_{l+1}, D_l]  mean of z_l given sample j of its parent z_{l+1}
     s[l]  [D_l]           log std of P(z_l | z_{l+1}), shared by all parent samples
+    sp[l] [K_{l+1}, D_l]  (the *_pp functions) log std given parent sample j
     u[l]  [K_l]           unary log-terms (-log Q(z_l), log-likelihood on layer 0,
                           log-prior on the top layer)
     f[l]  [K_l, K_{l+1}]  pairwise log-factor log P(z_l^i | z_{l+1}^j)
@@ -423,6 +424,67 @@ def gauss_star_log_evidence(x: np.ndarray) -> float:
     from scipy.stats import multivariate_normal
     n = len(x)
     return float(multivariate_normal(mean=np.zeros(n), cov=np.ones((n, n)) + 2.0 * np.eye(n)).logpdf(x))
+
+
+# ---------------------------------------------------------------------------
+# parent-dependent scale: the general conditional N(z_l; mu(z_{l+1}), diag sigma(z_{l+1})^2)
+# of Sec. "Computational costs for TMC and IWAE" (the generative networks of Sec.
+# "Experiments" produce a standard deviation from the parent as well as a mean)
+# ---------------------------------------------------------------------------
+
+def gauss_pair_logfactor_pp(z: np.ndarray, mu: np.ndarray, sp: np.ndarray,
+                            chunk: int = 256) -> np.ndarray:
+    """f[i, j] = log N(z^i ; mu^j, diag exp(2 sp[j])), where sp [K_{l+1}, D] holds the log
+    standard deviation produced from parent sample j (as mu[j] holds its mean).  Direct
+    difference:  sum_d [ -1/2 exp(-2 sp_jd) (z_id - mu_jd)^2 - sp_jd - 1/2 log 2 pi ]."""
+    z = np.asarray(z, np.float64)
+    mu = np.asarray(mu, np.float64)
+    sp = np.asarray(sp, np.float64)
+    lam = np.exp(-2.0 * sp)                                  # [J, D]
+    const = -np.sum(sp, axis=1) - z.shape[1] * HALF_LOG_2PI   # [J]
+    out = np.empty((z.shape[0], mu.shape[0]))
+    for i0 in range(0, z.shape[0], chunk):
+        diff = z[i0:i0 + chunk, None, :] - mu[None, :, :]
+        out[i0:i0 + chunk] = -0.5 * np.sum(lam[None, :, :] * diff * diff, axis=-1) + const[None, :]
+    return out
+
+
+def gauss_chain_logp_pp(z, mu, sp, u) -> float:
+    """log P_TMC of a Gaussian chain whose scales depend on the parent sample."""
+    L = len(u)
+    f = [gauss_pair_logfactor_pp(z[l], mu[l], sp[l]) for l in range(L - 1)]
+    return chain_logp(f, u)
+
+
+def gauss_chain_grads_pp(z, mu, sp, u, chunk: int = 128):
+    """log P_TMC and its gradients for parent-dependent scales, by the chain rule through
+    the factors with G the pairwise marginals of `chain_marginals` and
+    lam_j = exp(-2 sp[j]) (the scale of parent sample j):
+        dz_l[i]   = sum_j G_l[i,j] * (-lam_j * (z_l[i] - mu_l[j]))
+        dmu_l[j]  = sum_i G_l[i,j] * ( lam_j * (z_l[i] - mu_l[j]))
+        dsp_l[j]  = sum_i G_l[i,j] * ( lam_j * (z_l[i] - mu_l[j])^2 - 1 )
+        du_l      = p_l
+    Returns (log P, dz list, dmu list, dsp list, du list)."""
+    L = len(u)
+    f = [gauss_pair_logfactor_pp(z[l], mu[l], sp[l]) for l in range(L - 1)]
+    logp, G, p = chain_marginals(f, u)
+    dz = [np.zeros_like(np.asarray(a, np.float64)) for a in z]
+    dmu, dsp = [], []
+    for l in range(L - 1):
+        lam = np.exp(-2.0 * np.asarray(sp[l], np.float64))    # [J, D]
+        zl = np.asarray(z[l], np.float64)
+        ml = np.asarray(mu[l], np.float64)
+        gmu = np.zeros_like(ml)
+        gs = np.zeros_like(lam)
+        for i0 in range(0, zl.shape[0], chunk):
+            diff = zl[i0:i0 + chunk, None, :] - ml[None, :, :]       # [i, j, d]
+            g = G[l][i0:i0 + chunk, :, None]
+            dz[l][i0:i0 + chunk] = np.sum(g * (-lam[None] * diff), axis=1)
+            gmu += np.sum(g * (lam[None] * diff), axis=0)
+            gs += np.sum(g * (lam[None] * diff * diff - 1.0), axis=0)
+        dmu.append(gmu)
+        dsp.append(gs)
+    return logp, dz, dmu, dsp, [np.asarray(a) for a in p]
 
 
 def finite_difference(fun, x: np.ndarray, h: float = 1e-5, idx=None) -> np.ndarray:

@@ -18,6 +18,7 @@
 #include "tmc_internal.h"
 #include "tmc_kernels.h"
 #include "tmc_scratch.h"
+#include "tmc_star.h"
 
 using namespace tmc;
 
@@ -65,9 +66,20 @@ struct DeviceGuard {
   }
 };
 
+// Star-model plan: shape, point grouping and workspace offsets (bytes).
+struct StarPlan {
+  int S = 0, N = 0, Kt = 0, K = 0, D = 0;
+  int P = 1, ngrp = 0, nkb = 0;
+  size_t msg = 0, gsum = 0, w = 0, lp = 0, dm = 0, dsp = 0;
+};
+
+constexpr int kKindChain = 0, kKindStar = 1;
+
 }  // namespace
 
 struct tmc_plan {
+  int kind = kKindChain;   // chain problem (tmc_plan_create) or star (tmc_star_plan_create)
+  StarPlan star;
   int device = 0;
   int prec = TMC_FP32;
   int engine = TMC_ENGINE_PLAIN;
@@ -531,8 +543,13 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   return TMC_OK;
 }
 
-tmc_status check_exec(tmc_plan* P, void* ws) {
+tmc_status check_exec(tmc_plan* P, void* ws, int kind = kKindChain) {
   if (!P) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+  if (P->kind != kind)
+    return fail(TMC_ERR_INVALID_ARG, P->kind == kKindStar
+                                         ? "a star-model plan: use the tmc_star_* entry points"
+                                         : "a chain plan: the tmc_star_* entry points need a "
+                                           "plan from tmc_star_plan_create");
   if (P->ws.total > 0) {
     if (!ws) return fail(TMC_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", P->ws.total);
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
@@ -740,6 +757,128 @@ tmc_status gauss_bwd_impl(tmc_plan* P, const void* z, const void* mu, const void
                           ws, nullptr, (float*)dz, (float*)dmu, (float*)ds, (float*)du, st);
 }
 
+// ---- star model ----
+template <typename T>
+StarArgs<T> star_args(tmc_plan* P, void* ws) {
+  const StarPlan& sp = P->star;
+  char* base = static_cast<char*>(ws);
+  StarArgs<T> a{};
+  a.S = sp.S;
+  a.N = sp.N;
+  a.Kt = sp.Kt;
+  a.K = sp.K;
+  a.D = sp.D;
+  a.P = sp.P;
+  a.ngrp = sp.ngrp;
+  a.nkb = sp.nkb;
+  a.msg = reinterpret_cast<double*>(base + sp.msg);
+  a.gsum = reinterpret_cast<double*>(base + sp.gsum);
+  a.w = reinterpret_cast<double*>(base + sp.w);
+  a.lp = reinterpret_cast<double*>(base + sp.lp);
+  const bool grad = !(P->flags & TMC_FLAG_FORWARD_ONLY);
+  a.dm = grad ? reinterpret_cast<double*>(base + sp.dm) : nullptr;
+  a.dsp = grad ? reinterpret_cast<double*>(base + sp.dsp) : nullptr;
+  a.flag = P->flag_d;
+  return a;
+}
+
+template <typename T>
+tmc_status star_fwd(tmc_plan* P, const T* mth, const T* s, const T* z, const T* u, const T* uth,
+                    double* logp, void* ws, hipStream_t st) {
+  StarArgs<T> a = star_args<T>(P, ws);
+  a.mth = mth;
+  a.s = s;
+  a.z = z;
+  a.u = u;
+  a.uth = uth;
+  a.logp = logp;
+  LAUNCH_KC(TMC_KC_STAR_MSG, launch_star_msg<T>(a, st));
+  LAUNCH(launch_star_colsum<T>(a, st));
+  LAUNCH(launch_star_logp<T>(a, st));
+  return TMC_OK;
+}
+
+template <typename T>
+tmc_status star_bwd(tmc_plan* P, const T* mth, const T* s, const T* z, const T* u,
+                    const double* dlogp, void* ws, T* dmth, T* ds, T* dz, T* du, T* duth,
+                    hipStream_t st) {
+  StarArgs<T> a = star_args<T>(P, ws);
+  a.mth = mth;
+  a.s = s;
+  a.z = z;
+  a.u = u;
+  a.dlogp = dlogp;
+  a.dmth = dmth;
+  a.ds = ds;
+  a.dz = dz;
+  a.du = du;
+  a.duth = duth;
+  if (dz || du || ds) LAUNCH_KC(TMC_KC_STAR_BWD, launch_star_bwd_local<T>(a, st));
+  if (dmth) LAUNCH_KC(TMC_KC_STAR_BWD, launch_star_bwd_global<T>(a, st));
+  if (dmth || ds || duth) LAUNCH(launch_star_reduce<T>(a, st));
+  return TMC_OK;
+}
+
+tmc_status star_validate(const tmc_star_problem* pr) {
+  if (!pr) return fail(TMC_ERR_INVALID_ARG, "problem is NULL");
+  if (pr->reserved != 0) return fail(TMC_ERR_INVALID_ARG, "reserved must be 0");
+  if (pr->flags & ~TMC_FLAG_FORWARD_ONLY)
+    return fail(TMC_ERR_INVALID_ARG, "unknown flags 0x%x for a star problem", pr->flags);
+  if (pr->precision == TMC_BF16X3)
+    return fail(TMC_ERR_UNSUPPORTED, "star problems run in TMC_FP64 or TMC_FP32");
+  if (pr->precision != TMC_FP64 && pr->precision != TMC_FP32)
+    return fail(TMC_ERR_INVALID_ARG, "unknown precision %d", pr->precision);
+  if (pr->n_instances < 1) return fail(TMC_ERR_INVALID_ARG, "n_instances must be >= 1");
+  const int64_t kMaxSamples = (int64_t)65535 * kStarLanes;
+  if (pr->N < 1) return fail(TMC_ERR_SHAPE, "N = %d must be >= 1", pr->N);
+  if (pr->K < 1 || pr->K > kMaxSamples)
+    return fail(TMC_ERR_SHAPE, "K = %d outside [1, %lld]", pr->K, (long long)kMaxSamples);
+  if (pr->K_theta < 1 || pr->K_theta > kMaxSamples)
+    return fail(TMC_ERR_SHAPE, "K_theta = %d outside [1, %lld]", pr->K_theta, (long long)kMaxSamples);
+  if (pr->D < 1 || pr->D > kStarMaxD)
+    return fail(TMC_ERR_SHAPE, "D = %d outside [1, %d]", pr->D, kStarMaxD);
+  if ((int64_t)pr->n_instances * pr->N > INT32_MAX)
+    return fail(TMC_ERR_INVALID_ARG, "n_instances * N exceeds one launch grid");
+  if ((int64_t)pr->K_theta * pr->D > (int64_t)65534 * kStarLanes)
+    return fail(TMC_ERR_INVALID_ARG, "K_theta * D exceeds one launch grid");
+  return TMC_OK;
+}
+
+void star_layout(tmc_plan* P, const tmc_star_problem* pr) {
+  StarPlan& sp = P->star;
+  sp.S = pr->n_instances;
+  sp.N = pr->N;
+  sp.Kt = pr->K_theta;
+  sp.K = pr->K;
+  sp.D = pr->D;
+  const int64_t nkt = (sp.Kt + kStarLanes - 1) / kStarLanes;
+  sp.nkb = (sp.K + kStarLanes - 1) / kStarLanes;
+  // points per workgroup: as few as keep about kStarTargetGroups workgroups in a launch
+  const int64_t want = (int64_t)sp.S * sp.N * nkt / kStarTargetGroups;
+  sp.P = (int)std::max<int64_t>(1, std::min<int64_t>(sp.N, want));
+  sp.ngrp = (sp.N + sp.P - 1) / sp.P;
+  const int64_t S = sp.S;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  sp.msg = take((size_t)(S * sp.N * sp.Kt) * 8);
+  sp.gsum = take((size_t)(S * sp.ngrp * sp.Kt) * 8);
+  sp.w = take((size_t)(S * sp.Kt) * 8);
+  sp.lp = take((size_t)S * 8);
+  if (!(P->flags & TMC_FLAG_FORWARD_ONLY)) {
+    sp.dm = take((size_t)(S * sp.ngrp * sp.Kt) * sp.D * 8);
+    sp.dsp = take((size_t)(S * sp.N * sp.nkb) * sp.D * 8);
+  }
+  P->ws = WsLayout{};
+  P->ws.total = off;
+  P->entries = S * sp.N * (int64_t)sp.Kt * sp.K;
+  P->max_depth = 2;
+  P->max_D = sp.D;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -803,6 +942,88 @@ tmc_status tmc_plan_create(const tmc_problem* problem, int device, tmc_plan_t* o
     return TMC_OK;
   } catch (const std::bad_alloc&) {
     return fail(TMC_ERR_INVALID_ARG, "host allocation failed");
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_star_plan_create(const tmc_star_problem* problem, int device, tmc_plan_t* out) {
+  try {
+    if (!out) return fail(TMC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    tmc_status st = star_validate(problem);
+    if (st != TMC_OK) return st;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev == 0)
+      return fail(TMC_ERR_HIP, "no HIP device available (%s)", hipGetErrorString(e));
+    if (device < 0 || device >= ndev)
+      return fail(TMC_ERR_INVALID_ARG, "device %d out of range [0, %d)", device, ndev);
+    DeviceGuard g(device);
+    if (!g.ok) return fail(TMC_ERR_HIP, "hipSetDevice(%d) failed", device);
+    tmc_plan* P = new tmc_plan();
+    P->kind = kKindStar;
+    P->device = device;
+    P->prec = problem->precision;
+    P->engine = TMC_ENGINE_PLAIN;
+    P->flags = problem->flags;
+    P->esz = problem->precision == TMC_FP64 ? 8 : 4;
+    star_layout(P, problem);
+    e = hipMalloc(&P->flag_d, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(P->flag_d, 0, sizeof(int));
+    if (e != hipSuccess) {
+      delete P;
+      return fail(TMC_ERR_HIP, "flag allocation: %s", hipGetErrorString(e));
+    }
+    P->scratch_err = "not available for star-model plans";
+    *out = P;
+    g_err.clear();
+    return TMC_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(TMC_ERR_INVALID_ARG, "host allocation failed");
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_star_gauss_fwd(tmc_plan_t plan, const void* mth, const void* s, const void* z,
+                              const void* u, const void* uth, double* logp, void* workspace,
+                              void* stream) {
+  try {
+    tmc_status st = check_exec(plan, workspace, kKindStar);
+    if (st != TMC_OK) return st;
+    if (!mth || !s || !z || !u || !uth || !logp)
+      return fail(TMC_ERR_INVALID_ARG, "NULL input or output pointer");
+    DeviceGuard g(plan->device);
+    hipStream_t hs = (hipStream_t)stream;
+    if (plan->prec == TMC_FP64)
+      return star_fwd<double>(plan, (const double*)mth, (const double*)s, (const double*)z,
+                              (const double*)u, (const double*)uth, logp, workspace, hs);
+    return star_fwd<float>(plan, (const float*)mth, (const float*)s, (const float*)z,
+                           (const float*)u, (const float*)uth, logp, workspace, hs);
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
+tmc_status tmc_star_gauss_bwd(tmc_plan_t plan, const void* mth, const void* s, const void* z,
+                              const void* u, const double* dlogp, void* workspace, void* dmth,
+                              void* ds, void* dz, void* du, void* duth, void* stream) {
+  try {
+    tmc_status st = check_exec(plan, workspace, kKindStar);
+    if (st != TMC_OK) return st;
+    if (plan->flags & TMC_FLAG_FORWARD_ONLY)
+      return fail(TMC_ERR_STATE, "plan was created with TMC_FLAG_FORWARD_ONLY");
+    if (!mth || !s || !z || !u || !dlogp) return fail(TMC_ERR_INVALID_ARG, "NULL input pointer");
+    DeviceGuard g(plan->device);
+    hipStream_t hs = (hipStream_t)stream;
+    if (plan->prec == TMC_FP64)
+      return star_bwd<double>(plan, (const double*)mth, (const double*)s, (const double*)z,
+                              (const double*)u, dlogp, workspace, (double*)dmth, (double*)ds,
+                              (double*)dz, (double*)du, (double*)duth, hs);
+    return star_bwd<float>(plan, (const float*)mth, (const float*)s, (const float*)z,
+                           (const float*)u, dlogp, workspace, (float*)dmth, (float*)ds,
+                           (float*)dz, (float*)du, (float*)duth, hs);
   } catch (...) {
     return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
   }
@@ -884,6 +1105,7 @@ tmc_status tmc_gauss_fwd_noalloc(tmc_plan_t plan, const void* z, const void* mu,
                                  const void* u, double* logp, void* stream) {
   try {
     if (!plan) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+    if (plan->kind != kKindChain) return check_exec(plan, nullptr);
     if (!plan->scratch)
       return fail(TMC_ERR_HIP, "static device workspace unavailable (%s)", plan->scratch_err.c_str());
     if (plan->ws.total > kNoallocWorkspaceBytes)
@@ -901,6 +1123,7 @@ tmc_status tmc_gauss_factors(tmc_plan_t plan, const void* z, const void* mu, con
                              void* f, void* stream) {
   try {
     if (!plan) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
+    if (plan->kind != kKindChain) return check_exec(plan, nullptr);
     if (plan->engine != TMC_ENGINE_PLAIN)
       return fail(TMC_ERR_UNSUPPORTED, "tmc_gauss_factors needs a plain-engine plan");
     if (!plan->gauss_err.empty()) return fail(TMC_ERR_INVALID_ARG, "%s", plan->gauss_err.c_str());

@@ -65,6 +65,11 @@ class tmc_plan_info(ctypes.Structure):
                 ("tuned", c_int32), ("wide_fwd", c_int32), ("wide_bwd", c_int32)]
 
 
+class tmc_star_problem(ctypes.Structure):
+    _fields_ = [("n_instances", c_int32), ("N", c_int32), ("K_theta", c_int32), ("K", c_int32),
+                ("D", c_int32), ("precision", c_int32), ("flags", c_int32), ("reserved", c_int32)]
+
+
 _P = c_void_p
 _SIGS = {
     "tmc_abi_version": (c_int, []),
@@ -87,6 +92,9 @@ _SIGS = {
     "tmc_plan_set_timing": (c_int, [_P, c_int]),
     "tmc_plan_timing": (c_int, [_P, c_int, POINTER(c_double), POINTER(c_int64)]),
     "tmc_plan_autotune": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int, _P]),
+    "tmc_star_plan_create": (c_int, [POINTER(tmc_star_problem), c_int, POINTER(c_void_p)]),
+    "tmc_star_gauss_fwd": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "tmc_star_gauss_bwd": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -215,7 +223,7 @@ def tmc_plan_graph_launch(plan, which, stream=None):
 
 
 KERNEL_CLASSES = ["plain_factor", "plain_lse_fwd", "plain_lse_bwd", "plain_grad", "fused_prep",
-                  "fused_fwd", "fused_bwd", "other"]
+                  "fused_fwd", "fused_bwd", "other", "star_msg", "star_bwd"]
 
 
 def tmc_plan_set_timing(plan, enable: bool):
@@ -236,9 +244,37 @@ def tmc_plan_autotune(plan, z, mu, s, u, dlogp, workspace, dz=None, dmu=None, ds
                                   _stream(stream)))
 
 
+def tmc_star_plan_create(problem: "StarProblem", device: int = 0) -> int:
+    h = c_void_p()
+    _check(_lib.tmc_star_plan_create(ctypes.byref(problem.c), device, ctypes.byref(h)))
+    return h.value
+
+
+def tmc_star_gauss_fwd(plan, mth, s, z, u, uth, logp, workspace, stream=None):
+    _check(_lib.tmc_star_gauss_fwd(plan, _ptr(mth), _ptr(s), _ptr(z), _ptr(u), _ptr(uth),
+                                   _ptr(logp), _ptr(workspace), _stream(stream)))
+
+
+def tmc_star_gauss_bwd(plan, mth, s, z, u, dlogp, workspace, dmth, ds, dz, du, duth, stream=None):
+    _check(_lib.tmc_star_gauss_bwd(plan, _ptr(mth), _ptr(s), _ptr(z), _ptr(u), _ptr(dlogp),
+                                   _ptr(workspace), _ptr(dmth), _ptr(ds), _ptr(dz), _ptr(du),
+                                   _ptr(duth), _stream(stream)))
+
+
 # ---------------------------------------------------------------------------
 # problem descriptors
 # ---------------------------------------------------------------------------
+
+class StarProblem:
+    """Star-model descriptor: S instances of N local latents (K samples, width D) sharing
+    one global latent (K_theta samples); buffers mth [S, Kt, D], s [S, D],
+    z [S, N, K, D], u [S, N, K], uth [S, Kt]."""
+
+    def __init__(self, S, N, Kt, K, D, precision="fp32", flags=0):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else precision
+        self.c = tmc_star_problem(S, N, Kt, K, D, prec, flags, 0)
+        self.shape = dict(S=S, N=N, Kt=Kt, K=K, D=D)
+
 
 class Problem:
     """Host-side problem descriptor (keeps the ctypes arrays alive).
@@ -307,12 +343,13 @@ def ragged_problem(shapes, precision="fp32", engine="auto", flags=0, share_s=Fal
 
 
 class Plan:
-    """Owning wrapper of a tmc_plan_t."""
+    """Owning wrapper of a tmc_plan_t (of a chain Problem or a StarProblem)."""
 
-    def __init__(self, problem: Problem, device: int = 0):
+    def __init__(self, problem, device: int = 0):
         self.problem = problem
         self.device = device
-        self.handle = tmc_plan_create(problem, device)
+        create = tmc_star_plan_create if isinstance(problem, StarProblem) else tmc_plan_create
+        self.handle = create(problem, device)
         self.workspace_bytes = tmc_plan_workspace_size(self.handle)
         self.info = tmc_plan_info_get(self.handle)
 

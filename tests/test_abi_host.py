@@ -19,7 +19,7 @@ def test_exports_every_declared_function():
     lib = ctypes.CDLL(T._LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert T.tmc_abi_version() == 4
+    assert T.tmc_abi_version() == 5
 
 
 def test_struct_layout_matches_header():
@@ -32,6 +32,8 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\n", offsetof(tmc_layer, f_off), offsetof(tmc_problem, layers),
          offsetof(tmc_problem, flags), offsetof(tmc_plan_info, waves_per_group),
          offsetof(tmc_problem, exponent));
+  printf("%zu %zu %zu %d\n", sizeof(tmc_star_problem), offsetof(tmc_star_problem, D),
+         offsetof(tmc_star_problem, reserved), (int)TMC_KC_COUNT);
   return 0;
 }
 '''
@@ -45,7 +47,9 @@ int main(void) {
     want = [ctypes.sizeof(T.tmc_layer), ctypes.sizeof(T.tmc_chain), ctypes.sizeof(T.tmc_problem),
             ctypes.sizeof(T.tmc_plan_info), T.tmc_layer.f_off.offset, T.tmc_problem.layers.offset,
             T.tmc_problem.flags.offset, T.tmc_plan_info.waves_per_group.offset,
-            T.tmc_problem.exponent.offset]
+            T.tmc_problem.exponent.offset, ctypes.sizeof(T.tmc_star_problem),
+            T.tmc_star_problem.D.offset, T.tmc_star_problem.reserved.offset,
+            len(T.KERNEL_CLASSES)]
     assert got == want
 
 
@@ -102,3 +106,30 @@ def test_valid_problem_needs_a_device():
         assert e.status == T.TMC_ERR_HIP
     else:
         T.tmc_plan_destroy(h)
+
+
+def _expect_star(problem, status, msg=None):
+    with pytest.raises(T.TMCError) as ei:
+        h = T.tmc_star_plan_create(problem)
+        T.tmc_plan_destroy(h)
+    assert ei.value.status == status, str(ei.value)
+    if msg:
+        assert msg in str(ei.value)
+
+
+def test_star_validation_errors():
+    """Star descriptors are validated before any device is touched."""
+    _expect_star(T.StarProblem(1, 8, 4, 4, 0), T.TMC_ERR_SHAPE, "D = 0")
+    _expect_star(T.StarProblem(1, 8, 4, 4, 33), T.TMC_ERR_SHAPE, "D = 33")
+    _expect_star(T.StarProblem(1, 0, 4, 4, 1), T.TMC_ERR_SHAPE, "N = 0")
+    _expect_star(T.StarProblem(1, 8, 0, 4, 1), T.TMC_ERR_SHAPE, "K_theta = 0")
+    _expect_star(T.StarProblem(1, 8, 4, 64 * 65535 + 1, 1), T.TMC_ERR_SHAPE, "K = ")
+    _expect_star(T.StarProblem(0, 8, 4, 4, 1), T.TMC_ERR_INVALID_ARG, "n_instances")
+    _expect_star(T.StarProblem(1, 8, 4, 4, 1, precision="bf16x3"), T.TMC_ERR_UNSUPPORTED)
+    _expect_star(T.StarProblem(1, 8, 4, 4, 1, flags=T.TMC_FLAG_PERSISTENT), T.TMC_ERR_INVALID_ARG,
+                 "flags")
+    p = T.StarProblem(1, 8, 4, 4, 1)
+    p.c.reserved = 3
+    _expect_star(p, T.TMC_ERR_INVALID_ARG, "reserved")
+    _expect_star(T.StarProblem(65536, 32768, 4, 4, 1), T.TMC_ERR_INVALID_ARG, "launch grid")
+    _expect_star(T.StarProblem(1, 8, 64 * 65535, 4, 2), T.TMC_ERR_INVALID_ARG, "launch grid")

@@ -19,6 +19,14 @@ def _mutant(func_name, old, new):
 
 
 MUTATIONS = [
+    ("gauss_pair_logfactor_pp", "-np.sum(sp, axis=1)", "-np.sum(sp, axis=0).sum() / sp.shape[0]",
+     P.test_pp_factor_equals_scipy_normal_logpdf),
+    ("gauss_pair_logfactor_pp", "lam[None, :, :] * diff * diff", "lam[None, :, :].mean(axis=1, keepdims=True) * diff * diff",
+     P.test_pp_factor_equals_scipy_normal_logpdf),
+    ("gauss_chain_grads_pp", "g * (lam[None] * diff * diff - 1.0), axis=0", "g * (lam[None] * diff * diff), axis=0",
+     P.test_pp_gradients_against_finite_differences),
+    ("gauss_chain_grads_pp", "np.sum(g * (-lam[None] * diff), axis=1)", "np.sum(g * (-lam.mean(axis=0) * diff), axis=1)",
+     P.test_pp_gradients_against_finite_differences),
     # (function, original text, planted mistake, pin that must fail)
     ("logsumexp", ") + m_safe", ")", P.test_logsumexp_matches_scipy_and_handles_inf),
     ("gauss_pair_logfactor", "-np.sum(s)", "np.sum(s)", P.test_gauss_factor_equals_scipy_normal_logpdf),

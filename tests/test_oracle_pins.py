@@ -480,3 +480,72 @@ def test_star_evidence_closed_form_against_quadrature():
     val, _ = integrate.quad(lambda t: stats.norm.pdf(t) * np.prod(stats.norm.pdf(x, loc=t, scale=np.sqrt(2.0))),
                             -12, 12)
     assert abs(O.gauss_star_log_evidence(x) - np.log(val)) < 1e-9
+
+
+# --- parent-dependent scale (sigma produced from the parent sample) ------------------
+
+def _rand_chain_pp(rng, K, D, scale=1.0):
+    z, mu, s, u = _rand_chain(rng, K, D, scale=scale)
+    sp = [rng.uniform(-1.0, 0.3, size=(K[l + 1], D[l])) for l in range(len(K) - 1)]
+    return z, mu, sp, u
+
+
+def test_pp_factor_equals_scipy_normal_logpdf():
+    """Each parent sample j brings its own scale exp(sp[j])."""
+    rng = np.random.default_rng(41)
+    z = rng.normal(size=(5, 4))
+    mu = rng.normal(size=(6, 4))
+    sp = rng.uniform(-1.5, 0.5, size=(6, 4))
+    f = O.gauss_pair_logfactor_pp(z, mu, sp, chunk=2)
+    ref = np.array([[stats.norm.logpdf(z[i], loc=mu[j], scale=np.exp(sp[j])).sum()
+                     for j in range(6)] for i in range(5)])
+    np.testing.assert_allclose(f, ref, rtol=1e-13, atol=1e-12)
+
+
+def test_pp_with_equal_rows_reduces_to_shared_scale():
+    """When every parent produces the same scale, the factor, log P and every gradient
+    equal those of the shared-scale chain, with ds = the sum over parents of dsp."""
+    rng = np.random.default_rng(42)
+    K, D = (5, 4, 6), (3, 2, 4)
+    z, mu, s, u = _rand_chain(rng, K, D)
+    sp = [np.tile(s[l], (K[l + 1], 1)) for l in range(len(K) - 1)]
+    a = O.gauss_chain_grads(z, mu, s, u)
+    b = O.gauss_chain_grads_pp(z, mu, sp, u)
+    assert abs(a[0] - b[0]) < 1e-12
+    for l in range(len(K)):
+        np.testing.assert_allclose(b[1][l], a[1][l], atol=1e-12)
+        np.testing.assert_allclose(b[4][l], a[4][l], atol=1e-12)
+    for l in range(len(K) - 1):
+        np.testing.assert_allclose(b[2][l], a[2][l], atol=1e-12)
+        np.testing.assert_allclose(b[3][l].sum(axis=0), a[3][l], atol=1e-11)
+
+
+def test_pp_chain_equals_brute_force():
+    rng = np.random.default_rng(43)
+    K, D = (3, 4, 2, 3), (2, 3, 1, 2)
+    z, mu, sp, u = _rand_chain_pp(rng, K, D)
+    f = [O.gauss_pair_logfactor_pp(z[l], mu[l], sp[l]) for l in range(len(K) - 1)]
+    assert abs(O.gauss_chain_logp_pp(z, mu, sp, u) - O.brute_force_logp(f, u)) < 1e-10
+
+
+def test_pp_gradients_against_finite_differences():
+    rng = np.random.default_rng(44)
+    K, D = (4, 5, 3), (3, 2, 2)
+    z, mu, sp, u = _rand_chain_pp(rng, K, D, scale=0.7)
+    logp, dz, dmu, dsp, du = O.gauss_chain_grads_pp(z, mu, sp, u, chunk=2)
+    L = len(K)
+
+    def with_(lst, l, a):
+        return [a if m == l else lst[m] for m in range(len(lst))]
+
+    for l in range(L):
+        fd = O.finite_difference(lambda a: O.gauss_chain_logp_pp(with_(z, l, a), mu, sp, u), z[l])
+        np.testing.assert_allclose(dz[l].reshape(-1), fd, atol=2e-7)
+        fd = O.finite_difference(lambda a: O.gauss_chain_logp_pp(z, mu, sp, with_(u, l, a)), u[l])
+        np.testing.assert_allclose(du[l], fd, atol=2e-7)
+    for l in range(L - 1):
+        fd = O.finite_difference(lambda a: O.gauss_chain_logp_pp(z, with_(mu, l, a), sp, u), mu[l])
+        np.testing.assert_allclose(dmu[l].reshape(-1), fd, atol=2e-7)
+        fd = O.finite_difference(lambda a: O.gauss_chain_logp_pp(z, mu, with_(sp, l, a), u), sp[l])
+        np.testing.assert_allclose(dsp[l].reshape(-1), fd, atol=2e-7)
+    assert np.all(dz[L - 1] == 0)

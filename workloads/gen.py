@@ -250,3 +250,95 @@ def pack(chains: List[Chain], dtype=np.float32):
                         mu=cat([a for c in chains for a in c.mu]),
                         s=cat([a for c in chains for a in c.s]),
                         u=cat([a for c in chains for a in c.u]))
+
+
+# ---------------------------------------------------------------------------
+# star model: one global latent theta shared by N local latents
+# ---------------------------------------------------------------------------
+
+# The Gaussian example of Sec. "Comparing TMC, SMC and IWAE" toward the large ends of its
+# two sweeps: N = 4096 data points with K = 128 samples (the sweep over N at K = 128), and
+# N = 128 with K = 2048 (the sweep over K at N = 128); K_theta = K.
+STAR_CONFIGS = {
+    "s1": dict(index=10, S=1, N=4096, Kt=128, K=128, D=1, kind="toy"),
+    "s2": dict(index=11, S=1, N=128, Kt=2048, K=2048, D=1, kind="toy"),
+}
+
+
+@dataclass
+class StarWorkload:
+    """S independent instances of the star model, as the estimator takes them:
+        mth [S, Kt, D]  mean of every local latent given global sample kt
+        s   [S, D]      log standard deviation of the local latents given theta
+        z   [S, N, K, D] samples of the local latents
+        u   [S, N, K]   log P(x_i | z_i^k) - log Q(z_i^k)
+        uth [S, Kt]     log P(theta^kt) - log Q(theta^kt)
+    plus the data x [S, N, D] and the global samples theta [S, Kt, D]."""
+    name: str
+    mth: np.ndarray
+    s: np.ndarray
+    z: np.ndarray
+    u: np.ndarray
+    uth: np.ndarray
+    x: np.ndarray
+    theta: np.ndarray
+
+    @property
+    def shape(self):
+        S, N, K, D = self.z.shape
+        return dict(S=S, N=N, Kt=self.mth.shape[1], K=K, D=D)
+
+    def entries(self) -> int:
+        sh = self.shape
+        return int(sh["S"] * sh["N"] * sh["Kt"] * sh["K"])
+
+
+def gauss_star(S=1, N=128, Kt=128, K=128, D=1, kind="toy", seed=SEED_BASE + 10,
+               name="star") -> StarWorkload:
+    """kind 'toy': the model of Sec. "Comparing TMC, SMC and IWAE" in each of D dimensions,
+    theta ~ N(0, 1), z_i | theta ~ N(theta, 1), x_i | z_i ~ N(z_i, 1), with the generative
+    marginals as proposals, Q(theta) = N(0, 1) and Q(z_i) = N(0, 2); so mth = theta, s = 0
+    and uth = 0.  kind 'general': the mean of the local latents is a nonlinear function of
+    theta, mth = tanh(A theta + b) (A entries N(0, 1/D), b ~ N(0, 0.1)), s ~ U(-1, 0) per
+    dimension, and Q(theta) = N(0, 1.5^2) so uth is not constant.  Instance i draws
+    from the stream keyed (seed, 1, i); shared parameters from (seed, 0)."""
+    mrng = _rng(seed, 0)
+    if kind == "general":
+        A = mrng.normal(0.0, 1.0 / np.sqrt(D), size=(D, D))
+        b = mrng.normal(0.0, 0.1, size=D)
+        s = np.tile(mrng.uniform(-1.0, 0.0, size=D), (S, 1))
+        qth = 1.5
+    elif kind == "toy":
+        s = np.zeros((S, D))
+        qth = 1.0
+    else:
+        raise ValueError(kind)
+    mth = np.empty((S, Kt, D))
+    theta = np.empty((S, Kt, D))
+    z = np.empty((S, N, K, D))
+    u = np.empty((S, N, K))
+    uth = np.empty((S, Kt))
+    x = np.empty((S, N, D))
+    for i in range(S):
+        rng = _rng(seed, 1, i)
+        th_true = rng.normal(size=D)
+        if kind == "general":
+            zt = np.tanh(A @ th_true + b) + np.exp(s[i]) * rng.normal(size=(N, D))
+        else:
+            zt = th_true + rng.normal(size=(N, D))
+        x[i] = zt + rng.normal(size=(N, D))
+        theta[i] = qth * rng.normal(size=(Kt, D))
+        mth[i] = np.tanh(theta[i] @ A.T + b) if kind == "general" else theta[i]
+        uth[i] = _normal_logpdf_rows(theta[i], 0.0, 1.0) - _normal_logpdf_rows(theta[i], 0.0, qth)
+        z[i] = np.sqrt(2.0) * rng.normal(size=(N, K, D))
+        u[i] = (_normal_logpdf_rows(x[i][:, None, :], z[i], 1.0)
+                - _normal_logpdf_rows(z[i], 0.0, np.sqrt(2.0)))
+    return StarWorkload(name=name, mth=mth, s=s, z=z, u=u, uth=uth, x=x, theta=theta)
+
+
+def make_star(config: str, **over) -> StarWorkload:
+    """A named star workload ('s1', 's2'); keyword arguments override its sizes."""
+    cfg = dict(STAR_CONFIGS[config])
+    cfg.update(over)
+    seed = SEED_BASE + cfg.pop("index")
+    return gauss_star(seed=seed, name=config, **cfg)
