@@ -221,6 +221,78 @@ def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=
     return out
 
 
+# Star model: vector-ALU lane-operations per factor entry of the message pass, the fewest
+# the computation takes: per dimension a difference, a product and a fused multiply-add
+# (3 D), then the running max, the exponent's argument (one FMA), the exponential (a
+# quarter-rate instruction: 4 issue slots) and the accumulation -> 3 D + 7.  Peak: one
+# lane-operation per lane per cycle, 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed FP32).
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9 / 1e12   # T lane-ops/s
+
+
+def star_ops_per_entry(D):
+    return 3 * D + 7
+
+
+def run_star(w, prec, steps, warmup):
+    """Times `steps` forward + backward steps of star workload w (inputs resident), then
+    a region of steps with the library's per-kernel HIP events."""
+    import numpy as np
+    import torch
+    from paper_1806_08593_amd import tmc as T
+    sh = w.shape
+    tdt = torch.float64 if prec == "fp64" else torch.float32
+    plan = T.Plan(T.StarProblem(sh["S"], sh["N"], sh["Kt"], sh["K"], sh["D"], prec))
+    ws = plan.new_workspace()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        d = {k: torch.tensor(np.ascontiguousarray(getattr(w, k)), dtype=tdt, device="cuda:0")
+             for k in ("mth", "s", "z", "u", "uth")}
+        g = {k: torch.empty_like(v) for k, v in d.items()}
+        logp = torch.empty(sh["S"], dtype=torch.float64, device="cuda:0")
+        dlogp = torch.ones(sh["S"], dtype=torch.float64, device="cuda:0")
+        h = plan.handle
+
+        def step():
+            T.tmc_star_gauss_fwd(h, d["mth"], d["s"], d["z"], d["u"], d["uth"], logp, ws, st)
+            T.tmc_star_gauss_bwd(h, d["mth"], d["s"], d["z"], d["u"], dlogp, ws, g["mth"], g["s"],
+                                 g["z"], g["u"], g["uth"], st)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        T.tmc_plan_check(h)
+        T.tmc_plan_set_timing(h, True)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        kc = {}
+        for i, name in enumerate(T.KERNEL_CLASSES):
+            tms, cnt = T.tmc_plan_timing(h, i)
+            if cnt:
+                kc[name] = dict(ms_per_step=tms / steps, launches_per_step=cnt / steps,
+                                avg_launch_us=1e3 * tms / cnt)
+        T.tmc_plan_set_timing(h, False)
+        lp = logp.cpu().numpy()
+    plan.close()
+    ent = w.entries()
+    out = dict(workload=w.name, shape=sh, precision=prec, ms_per_step=ms,
+               value=ent / (ms / 1e3), unit="factor entries/s (fwd+bwd)", kernels=kc, logp=lp)
+    if "star_msg" in kc:
+        per_launch = ent * star_ops_per_entry(sh["D"]) / kc["star_msg"]["launches_per_step"]
+        ach = per_launch / (kc["star_msg"]["avg_launch_us"] * 1e-6) / 1e12
+        out["roofline"] = dict(kernel="star_msg", bound="alu", achieved=round(ach, 3),
+                               peak=round(VALU_LANE_OPS_PEAK, 2), unit="T lane-ops/s",
+                               frac=round(ach / VALU_LANE_OPS_PEAK, 4),
+                               ops_per_entry=star_ops_per_entry(sh["D"]),
+                               avg_launch_us=round(kc["star_msg"]["avg_launch_us"], 3))
+    return out
+
+
 def host_cores():
     """Host threads the CPU legs use: the process's CPU affinity, at most 16 (the host
     share of one GPU on the benchmark machines)."""
@@ -287,6 +359,30 @@ def cpu_baseline(chains, budget_s):
     return state["entries"] / dt, n_thr, desc
 
 
+def star_section(args, log):
+    import numpy as np
+    from workloads import make_star
+    star = {}
+    for name in ("s1", "s2"):
+        try:
+            log(f"star workload {name}")
+            w = make_star(name)
+            r = run_star(w, "fp32", max(5, args.steps // 2), 3)
+            if name == "s1" and not args.no_oracle:
+                from oracle import tmc_oracle as O
+                c = lambda a: np.asarray(a, np.float32).astype(np.float64)
+                N = w.shape["N"]
+                f = [O.gauss_pair_logfactor(c(w.mth[0]), c(w.z[0, n]), c(w.s[0])) for n in range(N)]
+                ref = O.star_logp(c(w.uth[0]), f, [c(w.u[0, n]) for n in range(N)])
+                r["max_abs_err_logp"] = float(abs(r["logp"][0] - ref))
+                r["abs_logp"] = float(abs(ref))
+            r.pop("logp")
+            star[name] = r
+        except Exception as ex:
+            star[name] = dict(error=str(ex)[:200])
+    return star
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +400,10 @@ def main():
     ap.add_argument("--persistent", action="store_true", help="persistent launches (with --no-tune)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager launches instead of replays of the captured step graphs")
+    ap.add_argument("--no-star", action="store_true",
+                    help="skip the star-model measurement (Gaussian example, FP32)")
+    ap.add_argument("--star-only", action="store_true",
+                    help="only the star-model measurement (one JSON line with its results)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="first copy this many MiB with a plain device copy (a known-size "
                          "kernel for scaling memory counters)")
@@ -329,6 +429,10 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.star_only:
+        print(json.dumps({"star": star_section(args, log)}))
+        return
 
     prec = args.precision or ("fp64" if args.workload == "c1" else "bf16x3")
     log(f"generating workload {args.workload} ...")
@@ -434,6 +538,10 @@ def main():
             tol = LOGP_TOL[compare[name]["precision"]]
             compare[name]["within_tolerance"] = tol is not None and errs[name] <= tol
 
+    # the star model (global latent shared by N local latents): both Gaussian-example
+    # workloads in FP32; log P of the first against the oracle
+    star = {} if args.no_star else star_section(args, log)
+
     cpu = None
     if not args.no_cpu_baseline:
         npdt = np.float64 if prec == "fp64" else np.float32
@@ -504,6 +612,7 @@ def main():
         "kernels": kc,
         "kernel_roofline": kernel_roofline,
         "compare": compare,
+        "star": star,
     }
     print(json.dumps(line))
 
