@@ -221,16 +221,19 @@ def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=
     return out
 
 
-# Star model: vector-ALU lane-operations per factor entry of the message pass, the fewest
-# the computation takes: per dimension a difference, a product and a fused multiply-add
-# (3 D), then the running max, the exponent's argument (one FMA), the exponential (a
-# quarter-rate instruction: 4 issue slots) and the accumulation -> 3 D + 7.  Peak: one
-# lane-operation per lane per cycle, 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (no packed FP32).
-VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9 / 1e12   # T lane-ops/s
+# Star model: vector-ALU instructions per factor entry of the message pass: per
+# dimension a difference, a product and a fused multiply-add (3 D), then the running max,
+# the exponent's argument (one FMA), the exponential and the accumulation -> 3 D + 4 (the
+# count of the compiled inner loop at D = 1: 56 instructions per 8 entries).  Peak: one
+# wave64 instruction per SIMD every 4 cycles (16 lanes per cycle; the kernels are built
+# without packed FP32), 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s;
+# the exponential is counted as one issue (a quarter-rate exponential would put the
+# measured N = 128, K = 2048 message kernel above this peak).
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9 / 1e12   # T lane-instructions/s
 
 
 def star_ops_per_entry(D):
-    return 3 * D + 7
+    return 3 * D + 4
 
 
 def run_star(w, prec, steps, warmup):
@@ -286,7 +289,7 @@ def run_star(w, prec, steps, warmup):
         per_launch = ent * star_ops_per_entry(sh["D"]) / kc["star_msg"]["launches_per_step"]
         ach = per_launch / (kc["star_msg"]["avg_launch_us"] * 1e-6) / 1e12
         out["roofline"] = dict(kernel="star_msg", bound="alu", achieved=round(ach, 3),
-                               peak=round(VALU_LANE_OPS_PEAK, 2), unit="T lane-ops/s",
+                               peak=round(VALU_LANE_OPS_PEAK, 2), unit="T lane-instructions/s",
                                frac=round(ach / VALU_LANE_OPS_PEAK, 4),
                                ops_per_entry=star_ops_per_entry(sh["D"]),
                                avg_launch_us=round(kc["star_msg"]["avg_launch_us"], 3))
@@ -359,6 +362,53 @@ def cpu_baseline(chains, budget_s):
     return state["entries"] / dt, n_thr, desc
 
 
+def logmm_section(args, log):
+    """The log-domain matrix product on a batch of square matrices, every precision;
+    achieved = 2 M N K flops per product / launch time (the MFMA path issues 3x that in
+    BF16X3), against the dense peak of the MFMA type."""
+    import numpy as np
+    import torch
+    from paper_1806_08593_amd import tmc as T
+    from oracle import tmc_oracle as O
+    out = {}
+    B, M, K, N = 8, 1024, 1024, 1024
+    rng = np.random.default_rng(1806)
+    Xh = (rng.normal(size=(B, M, K)) * 3).astype(np.float32)
+    Yh = (rng.normal(size=(B, K, N)) * 3).astype(np.float32)
+    for prec, peak in (("bf16x3", MFMA_PEAK["bf16x3"]), ("fp32", MFMA_PEAK["fp32"]), ("fp64", VALU_PEAK)):
+        try:
+            log(f"log-domain product {prec}")
+            dt = torch.float64 if prec == "fp64" else torch.float32
+            X = torch.tensor(Xh, dtype=dt, device="cuda:0")
+            Y = torch.tensor(Yh, dtype=dt, device="cuda:0")
+            Z = torch.empty((B, M, N), dtype=dt, device="cuda:0")
+            nb = T.tmc_logmmexp_workspace_size(B, M, K, N, prec)
+            ws = torch.empty(max(nb, 256) + 256, dtype=torch.uint8, device="cuda:0")
+            wp = ws.data_ptr() + (-ws.data_ptr()) % 256
+            reps = 3 if prec == "fp64" else 10
+            T.tmc_logmmexp(B, M, K, N, prec, X, Y, Z, wp)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                T.tmc_logmmexp(B, M, K, N, prec, X, Y, Z, wp)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tf = 2.0 * B * M * N * K / (ms * 1e-3) / 1e12
+            r = dict(batch=B, M=M, K=K, N=N, ms=ms, tflops=round(tf, 3), peak=peak,
+                     frac=round(tf / peak, 4))
+            if not args.no_oracle:
+                z = Z[0, :64, :64].cpu().numpy().astype(np.float64)
+                ref = O.logmmexp(Xh[0, :64].astype(np.float64), Yh[0, :, :64].astype(np.float64))
+                r["max_abs_err_first_64x64"] = float(np.max(np.abs(z - ref)))
+            out[prec] = r
+            del X, Y, Z, ws
+        except Exception as ex:
+            out[prec] = dict(error=str(ex)[:200])
+    return out
+
+
 def star_section(args, log):
     import numpy as np
     from workloads import make_star
@@ -402,6 +452,8 @@ def main():
                     help="time eager launches instead of replays of the captured step graphs")
     ap.add_argument("--no-star", action="store_true",
                     help="skip the star-model measurement (Gaussian example, FP32)")
+    ap.add_argument("--no-logmm", action="store_true",
+                    help="skip the log-domain matrix product measurement")
     ap.add_argument("--star-only", action="store_true",
                     help="only the star-model measurement (one JSON line with its results)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
@@ -431,7 +483,8 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     if args.star_only:
-        print(json.dumps({"star": star_section(args, log)}))
+        print(json.dumps({"star": star_section(args, log),
+                          "logmm": {} if args.no_logmm else logmm_section(args, log)}))
         return
 
     prec = args.precision or ("fp64" if args.workload == "c1" else "bf16x3")
@@ -541,6 +594,7 @@ def main():
     # the star model (global latent shared by N local latents): both Gaussian-example
     # workloads in FP32; log P of the first against the oracle
     star = {} if args.no_star else star_section(args, log)
+    logmm = {} if args.no_logmm else logmm_section(args, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -613,6 +667,7 @@ def main():
         "kernel_roofline": kernel_roofline,
         "compare": compare,
         "star": star,
+        "logmm": logmm,
     }
     print(json.dumps(line))
 

@@ -34,6 +34,7 @@
  *                    (e.g. the exact discrete marginalisation of the Appendix).
  *   tmc_star_*       not a chain: one global latent shared by many local latents (the
  *                    latent-variable model of Sec. "Efficient averaging"), below.
+ * and the log-domain matrix product itself (tmc_logmmexp).
  *
  * Memory.  Every data pointer is DEVICE memory on the plan's device unless marked
  * (host).  The caller allocates and owns every buffer, including the workspace; the
@@ -45,7 +46,8 @@
  * offset of each layer's block.  Row-major:
  *   z  : z_l    [K_l][D_l]        at layers[l].z_off
  *   mu : mu_l   [K_{l+1}][D_l]    at layers[l].mu_off  (row j = mean given z_{l+1}^j)
- *   s  : s_l    [D_l]             at layers[l].s_off   (several layers may share one)
+ *   s  : s_l    [D_l]             at layers[l].s_off   (several layers may share one;
+ *                                 [K_{l+1}][D_l] with TMC_FLAG_PARENT_SCALE)
  *   u  : u_l    [K_l]             at layers[l].u_off
  *   f  : f_l    [K_l][K_{l+1}]    at layers[l].f_off
  * Gradient buffers use the same offsets as the matching input.  Element type is
@@ -108,6 +110,16 @@ typedef enum tmc_engine {
 #define TMC_FLAG_PERSISTENT 2    /* fused engine: run each pass as one persistent
                                     launch per width bucket over a queue of whole
                                     chains instead of one launch per chain depth */
+#define TMC_FLAG_PARENT_SCALE 4  /* parent-dependent scales: the general conditional of
+                                    Sec. "Computational costs for TMC and IWAE",
+                                    N(z_l; mu(z_{l+1}), diag sigma(z_{l+1})^2), whose
+                                    standard deviation, like its mean, is produced from
+                                    the parent sample.  Every s_l block is then
+                                    [K_{l+1}][D_l] (row j: log standard deviation given
+                                    parent sample j, the layout of mu_l), blocks of
+                                    different layers may not overlap, and ds has the same
+                                    layout.  Plain engine (TMC_FP64, TMC_FP32); the auto
+                                    engine picks it, TMC_ENGINE_FUSED is rejected. */
 
 /* One latent layer of one chain (host struct). */
 typedef struct tmc_layer {
@@ -116,8 +128,9 @@ typedef struct tmc_layer {
   int64_t z_off;   /* element offset of z_l [K][D]; not read for the top layer */
   int64_t u_off;   /* element offset of u_l [K] */
   int64_t mu_off;  /* element offset of mu_l [K_{l+1}][D]; ignored for the top layer */
-  int64_t s_off;   /* element offset of s_l [D]; ignored for the top layer.  Layers
-                      (of any chains) may share an s block; their ds is then summed. */
+  int64_t s_off;   /* element offset of s_l [D] ([K_{l+1}][D] with TMC_FLAG_PARENT_SCALE);
+                      ignored for the top layer.  Layers (of any chains) may share a [D]
+                      block; their ds is then summed. */
   int64_t f_off;   /* element offset of f_l [K][K_{l+1}] (logfactor entry points);
                       ignored for the top layer */
 } tmc_layer;
@@ -284,6 +297,28 @@ tmc_status tmc_star_gauss_fwd(tmc_plan_t plan, const void* mth, const void* s, c
 tmc_status tmc_star_gauss_bwd(tmc_plan_t plan, const void* mth, const void* s, const void* z,
                               const void* u, const double* dlogp, void* workspace, void* dmth,
                               void* ds, void* dz, void* du, void* duth, void* stream);
+
+/* ---- Log-domain matrix product ---- */
+/* The Appendix "Numerically stable matrix (tensor) products in the log-domain" in its
+ * matrix-matrix form (what loopy graphs, and the messages of several chains at once,
+ * contract: Sec. "Efficient averaging"): for b < batch,
+ *   Z_b[i,k] = log sum_j exp(X_b[i,j] + Y_b[j,k]),
+ * X [batch][M][K], Y [batch][K][N], Z [batch][M][N], row-major device buffers of double
+ * (TMC_FP64) or float (TMC_FP32, TMC_BF16X3).  TMC_FP64: every entry exactly, with its own
+ * maximum over j, on the vector ALU.  TMC_FP32 / TMC_BF16X3: the Appendix's shift by the
+ * row maxima of X and the column maxima of Y, the shifted exponentials multiplied on the
+ * matrix cores (FP32 MFMA, or BF16 hi/lo products as for the Gaussian factors), then
+ * every entry whose shifted product fell below e^-60 (where the shift underflows: the
+ * maxima of X's row and Y's column at indices j far apart) recomputed exactly.  All -inf
+ * rows or columns give -inf; NaN propagates; +inf inputs give NaN.  The workspace holds
+ * the shifts: tmc_logmmexp_workspace_size bytes (0 for TMC_FP64), 256-byte aligned.  No
+ * plan: the call validates, enqueues on `stream` and returns.  Errors: TMC_ERR_SHAPE
+ * (batch or M outside [1, 65535], K or N outside [1, 2^24]), TMC_ERR_INVALID_ARG (NULL
+ * pointer, unknown precision), TMC_ERR_WORKSPACE, TMC_ERR_HIP. */
+tmc_status tmc_logmmexp_workspace_size(int32_t batch, int32_t M, int32_t K, int32_t N,
+                                       int32_t precision, size_t* bytes);
+tmc_status tmc_logmmexp(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t precision,
+                        const void* X, const void* Y, void* Z, void* workspace, void* stream);
 
 /* ---- graphs ---- */
 /* Record the enqueue of one execute call (same arguments as the call) into a hipGraph

@@ -487,6 +487,37 @@ def gauss_chain_grads_pp(z, mu, sp, u, chunk: int = 128):
     return logp, dz, dmu, dsp, [np.asarray(a) for a in p]
 
 
+# ---------------------------------------------------------------------------
+# log-domain matrix product (Appendix "Numerically stable matrix (tensor) products in
+# the log-domain"): the matrix-matrix form that loopy graphs and the discrete
+# marginalisation of several chains at once need (Sec. "Efficient averaging")
+# ---------------------------------------------------------------------------
+
+def logmmexp(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """Z[..., i, k] = log sum_j exp(X[..., i, j] + Y[..., j, k]), by definition: every
+    sum X_ij + Y_jk is formed and reduced with the exact-max `logsumexp` (so no shift can
+    underflow).  Leading axes are batch axes."""
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    return logsumexp(X[..., :, :, None] + Y[..., None, :, :], axis=-2)
+
+
+def logmmexp_shifted(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """The Appendix's form: shift each row of X by its max x_i and each column of Y by
+    its max y_k, multiply the exponentials as ordinary matrices and add the shifts back,
+        Z_ik = log sum_j exp(X_ij - x_i) exp(Y_jk - y_k) + x_i + y_k.
+    Equal to `logmmexp` while no product underflows; used by the pins to show where the
+    per-operand shift loses the result."""
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    x = np.max(X, axis=-1, keepdims=True)
+    y = np.max(Y, axis=-2, keepdims=True)
+    xs = np.where(np.isfinite(x), x, 0.0)
+    ys = np.where(np.isfinite(y), y, 0.0)
+    with np.errstate(divide="ignore"):
+        return np.log(np.exp(X - xs) @ np.exp(Y - ys)) + xs + ys
+
+
 def finite_difference(fun, x: np.ndarray, h: float = 1e-5, idx=None) -> np.ndarray:
     """Central differences (fun(x + h e) - fun(x - h e)) / 2h at the flat indices
     `idx` (all entries when None)."""

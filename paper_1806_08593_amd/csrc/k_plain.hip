@@ -66,8 +66,11 @@ __device__ __forceinline__ void store_vec(T* __restrict__ p, const T (&x)[V]) {
 // so the element type holds differences of O(the spread of a row) instead of values
 // of O(|f|): an FP32 row near -480 keeps ~1e-6 absolute precision instead of ~3e-5.
 // With anchor == 0 (tmc_gauss_factors) f itself is written.
+// PP (parent-dependent scale): s is [Kc][D], row j the log standard deviation produced
+// from parent sample j, so lam and the constant are per column:
+//   f_l[i,j] = sum_d -1/2 exp(-2 s_jd) (z_id - mu_jd)^2 - sum_d s_jd - D/2 ln 2 pi.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool PP>
 __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict__ Ls,
                                                       const Item* __restrict__ items,
                                                       const T* __restrict__ z,
@@ -79,7 +82,9 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
   __shared__ T zt[TR][DC + 1];
   __shared__ T mt[TC][DC + 1];
   __shared__ T m0[DC];
-  __shared__ T lam[DC];
+  __shared__ T lam[DC];                       // lam of the layer (PP: of column 0)
+  __shared__ T lamt[PP ? TC : 1][DC + 1];       // PP: lam of the tile's columns
+  __shared__ double cj[PP ? TC : 1];            // PP: constant of each column minus c0
   __shared__ double red[kMaxWaves];
   __shared__ double arow[TR];
   const Item it = items[blockIdx.x];
@@ -91,10 +96,20 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
   const int tid = threadIdx.x;
   const bool anchored = anchor != nullptr;
 
+  // (PP: s[so + d] is row 0 of the block, so c0 is column 0's constant)
   double ssum = 0.0;
   for (int d = tid; d < D; d += blockDim.x) ssum += (double)s[so + d];
   ssum = block_sum(ssum, red);
   const double c0 = -ssum - 0.5 * (double)D * log(2.0 * M_PI);
+  if constexpr (PP) {
+    // column constants relative to c0, each an FP64 sum over d in increasing d
+    if (tid < TC) {
+      double sj = 0.0;
+      if (j0 + tid < Kc)
+        for (int d = 0; d < D; ++d) sj += (double)s[so + (int64_t)(j0 + tid) * D + d];
+      cj[tid] = -sj - 0.5 * (double)D * log(2.0 * M_PI) - c0;
+    }
+  }
 
   const int col = tid % TC, rsub = tid / TC;
   double acc[TR / 4];
@@ -116,10 +131,18 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
       lam[tid] = (d0 + tid < D) ? (T)exp(-2.0 * (double)s[so + d0 + tid]) : (T)0;
       m0[tid] = (d0 + tid < D) ? mu[mo + d0 + tid] : (T)0;
     }
+    if constexpr (PP) {
+      for (int e = tid; e < TC * DC; e += 256) {
+        const int c = e / DC, dd = e % DC;
+        lamt[c][dd] = (j0 + c < Kc && d0 + dd < D)
+                          ? (T)exp(-2.0 * (double)s[so + (int64_t)(j0 + c) * D + d0 + dd])
+                          : (T)0;
+      }
+    }
     __syncthreads();
 #pragma unroll 4
     for (int dd = 0; dd < DC; ++dd) {
-      const T m = mt[col][dd], l = lam[dd];
+      const T m = mt[col][dd], l = PP ? lamt[col][dd] : lam[dd];
 #pragma unroll
       for (int q = 0; q < TR / 4; ++q) {
         const T t = zt[rsub + 4 * q][dd] - m;
@@ -142,12 +165,13 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
   T* fb = f + (caller_off ? L.f_off : L.wf_off);
   const int j = j0 + col;
   if (j < Kc) {
+    const double cc = PP ? cj[col] : 0.0;   // this column's constant minus c0
 #pragma unroll
     for (int q = 0; q < TR / 4; ++q) {
       const int i = i0 + rsub + 4 * q;
       if (i < K)
-        fb[(int64_t)i * Kc + j] = anchored ? (T)(-0.5 * (acc[q] - arow[rsub + 4 * q]))
-                                           : (T)(-0.5 * acc[q] + c0);
+        fb[(int64_t)i * Kc + j] = anchored ? (T)(-0.5 * (acc[q] - arow[rsub + 4 * q]) + cc)
+                                           : (T)(-0.5 * acc[q] + c0 + cc);
     }
   }
 }
@@ -331,8 +355,12 @@ __global__ __launch_bounds__(64 * kPlainBwdWaves) void k_plain_lse_bwd(
 // Gaussian gradients from the materialised marginals G (plain engine)
 //   dz_l[i]  = -dlogp * lam * (p_l[i] z_l[i] - (G mu)_i)
 //   dmu_l[j] =  dlogp * lam * ((G^T z)_j - p_{l+1}[j] mu_j)
+// PP (lam_j per parent sample): the same sums with lam inside, by direct difference,
+//   dz_l[i]  = -dlogp * sum_j G_ij lam_j (z_i - mu_j)
+//   dmu_l[j] =  dlogp * lam_j sum_i G_ij (z_i - mu_j)
+//   ds_l[j]  =  dlogp * (lam_j sum_i G_ij (z_i - mu_j)^2 - p_{l+1}[j])
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool PP>
 __global__ __launch_bounds__(256) void k_plain_gmu(const LayerDev* __restrict__ Ls,
                                                    const Item* __restrict__ items,
                                                    const T* __restrict__ G,
@@ -345,6 +373,7 @@ __global__ __launch_bounds__(256) void k_plain_gmu(const LayerDev* __restrict__ 
   constexpr int TR = kPlainGemmRows, TD = kPlainGemmD, TJ = 32;
   __shared__ T gt[TR][TJ + 1];
   __shared__ T mt[TJ][TD + 1];
+  __shared__ T lt[PP ? TJ : 1][TD + 1];
   const Item it = items[blockIdx.x];
   const LayerDev& L = Ls[it.layer];
   const int K = L.K, Kc = L.Kc, D = L.D;
@@ -353,9 +382,16 @@ __global__ __launch_bounds__(256) void k_plain_gmu(const LayerDev* __restrict__ 
   const int tid = threadIdx.x, dl = tid % TD, rs = tid / TD;
   const T* Gb = G + L.wf_off;
   const int64_t mo = L.mu_off;
-  T acc[TR / 4];
+  T acc[TR / 4], zr[PP ? TR / 4 : 1];
 #pragma unroll
   for (int q = 0; q < TR / 4; ++q) acc[q] = (T)0;
+  if constexpr (PP) {
+#pragma unroll
+    for (int q = 0; q < TR / 4; ++q) {
+      const int i = i0 + rs + 4 * q;
+      zr[q] = (i < K && d0 + dl < D) ? z[L.z_off + (int64_t)i * D + d0 + dl] : (T)0;
+    }
+  }
   for (int j0 = 0; j0 < Kc; j0 += TJ) {
     __syncthreads();
     for (int e = tid; e < TR * TJ; e += 256) {
@@ -365,19 +401,37 @@ __global__ __launch_bounds__(256) void k_plain_gmu(const LayerDev* __restrict__ 
     for (int e = tid; e < TJ * TD; e += 256) {
       const int jj = e / TD, dd = e % TD;
       mt[jj][dd] = (j0 + jj < Kc && d0 + dd < D) ? mu[mo + (int64_t)(j0 + jj) * D + d0 + dd] : (T)0;
+      if constexpr (PP)
+        lt[jj][dd] = (j0 + jj < Kc && d0 + dd < D)
+                         ? (T)exp(-2.0 * (double)s[L.s_off + (int64_t)(j0 + jj) * D + d0 + dd])
+                         : (T)0;
     }
     __syncthreads();
 #pragma unroll 8
     for (int jj = 0; jj < TJ; ++jj) {
       const T m = mt[jj][dl];
+      if constexpr (PP) {
+        const T lm = lt[jj][dl];
 #pragma unroll
-      for (int q = 0; q < TR / 4; ++q) acc[q] += gt[rs + 4 * q][jj] * m;
+        for (int q = 0; q < TR / 4; ++q) acc[q] += gt[rs + 4 * q][jj] * (lm * (zr[q] - m));
+      } else {
+#pragma unroll
+        for (int q = 0; q < TR / 4; ++q) acc[q] += gt[rs + 4 * q][jj] * m;
+      }
     }
   }
   const int d = d0 + dl;
   if (d >= D) return;
-  const T lam = (T)exp(-2.0 * (double)s[L.s_off + d]);
   const T g = (T)(dlogp[L.chain] * L.kappa);
+  if constexpr (PP) {
+#pragma unroll
+    for (int q = 0; q < TR / 4; ++q) {
+      const int i = i0 + rs + 4 * q;
+      if (i < K) dz[L.z_off + (int64_t)i * D + d] = -g * acc[q];
+    }
+    return;
+  }
+  const T lam = (T)exp(-2.0 * (double)s[L.s_off + d]);
 #pragma unroll
   for (int q = 0; q < TR / 4; ++q) {
     const int i = i0 + rs + 4 * q;
@@ -388,7 +442,7 @@ __global__ __launch_bounds__(256) void k_plain_gmu(const LayerDev* __restrict__ 
   }
 }
 
-template <typename T>
+template <typename T, bool PP>
 __global__ __launch_bounds__(256) void k_plain_gtz(const LayerDev* __restrict__ Ls,
                                                    const Item* __restrict__ items,
                                                    const T* __restrict__ G,
@@ -397,7 +451,8 @@ __global__ __launch_bounds__(256) void k_plain_gtz(const LayerDev* __restrict__ 
                                                    const T* __restrict__ s,
                                                    const T* __restrict__ p,
                                                    const double* __restrict__ dlogp,
-                                                   T* __restrict__ gtz, T* __restrict__ dmu) {
+                                                   T* __restrict__ gtz, T* __restrict__ dmu,
+                                                   T* __restrict__ ds_pp) {
   constexpr int TC = kPlainGemmRows, TD = kPlainGemmD, TI = 32;
   __shared__ T gt[TI][TC + 1];
   __shared__ T zt[TI][TD + 1];
@@ -409,9 +464,17 @@ __global__ __launch_bounds__(256) void k_plain_gtz(const LayerDev* __restrict__ 
   const int tid = threadIdx.x, dl = tid % TD, cs = tid / TD;
   const T* Gb = G + L.wf_off;
   const int64_t zo = L.z_off;
-  T acc[TC / 4];
+  T acc[TC / 4], acc2[PP ? TC / 4 : 1], mr[PP ? TC / 4 : 1];
 #pragma unroll
   for (int q = 0; q < TC / 4; ++q) acc[q] = (T)0;
+  if constexpr (PP) {
+#pragma unroll
+    for (int q = 0; q < TC / 4; ++q) {
+      const int j = j0 + cs + 4 * q;
+      acc2[q] = (T)0;
+      mr[q] = (j < Kc && d0 + dl < D) ? mu[L.mu_off + (int64_t)j * D + d0 + dl] : (T)0;
+    }
+  }
   for (int i0 = 0; i0 < K; i0 += TI) {
     __syncthreads();
     for (int e = tid; e < TI * TC; e += 256) {
@@ -426,14 +489,36 @@ __global__ __launch_bounds__(256) void k_plain_gtz(const LayerDev* __restrict__ 
 #pragma unroll 8
     for (int ii = 0; ii < TI; ++ii) {
       const T zv = zt[ii][dl];
+      if constexpr (PP) {
 #pragma unroll
-      for (int q = 0; q < TC / 4; ++q) acc[q] += gt[ii][cs + 4 * q] * zv;
+        for (int q = 0; q < TC / 4; ++q) {
+          const T gv = gt[ii][cs + 4 * q], df = zv - mr[q];
+          acc[q] += gv * df;
+          acc2[q] += gv * df * df;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < TC / 4; ++q) acc[q] += gt[ii][cs + 4 * q] * zv;
+      }
     }
   }
   const int d = d0 + dl;
   if (d >= D) return;
-  const T lam = (T)exp(-2.0 * (double)s[L.s_off + d]);
   const T g = (T)(dlogp[L.chain] * L.kappa);
+  if constexpr (PP) {
+#pragma unroll
+    for (int q = 0; q < TC / 4; ++q) {
+      const int j = j0 + cs + 4 * q;
+      if (j < Kc) {
+        const int64_t e = (int64_t)j * D + d;
+        const T lam = (T)exp(-2.0 * (double)s[L.s_off + e]);
+        if (dmu) dmu[L.mu_off + e] = g * lam * acc[q];
+        if (ds_pp) ds_pp[L.s_off + e] = g * (lam * acc2[q] - p[L.p_up_off + j]);
+      }
+    }
+    return;
+  }
+  const T lam = (T)exp(-2.0 * (double)s[L.s_off + d]);
 #pragma unroll
   for (int q = 0; q < TC / 4; ++q) {
     const int j = j0 + cs + 4 * q;
@@ -489,10 +574,14 @@ __global__ __launch_bounds__(256) void k_pair_dsp(const LayerDev* __restrict__ L
 template <typename T>
 hipError_t launch_plain_factor(const LayerDev* layers, const Item* items, int n_items,
                                const T* z, const T* mu, const T* s, T* f, bool caller_off,
-                               double* anchor, hipStream_t st) {
+                               double* anchor, bool parent_scale, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plain_factor<T>, dim3(n_items), dim3(256), 0, st, layers, items, z, mu, s,
-                     f, (int)caller_off, anchor);
+  if (parent_scale)
+    hipLaunchKernelGGL((k_plain_factor<T, true>), dim3(n_items), dim3(256), 0, st, layers, items, z,
+                       mu, s, f, (int)caller_off, anchor);
+  else
+    hipLaunchKernelGGL((k_plain_factor<T, false>), dim3(n_items), dim3(256), 0, st, layers, items, z,
+                       mu, s, f, (int)caller_off, anchor);
   return hipGetLastError();
 }
 
@@ -533,20 +622,28 @@ hipError_t launch_plain_lse_bwd(const LayerDev* layers, const Item* items, int n
 template <typename T>
 hipError_t launch_plain_gmu(const LayerDev* layers, const Item* items, int n_items, const T* g,
                             const T* z, const T* mu, const T* s, const T* p, const double* dlogp,
-                            T* dz, hipStream_t st) {
+                            T* dz, bool parent_scale, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plain_gmu<T>, dim3(n_items), dim3(256), 0, st, layers, items, g, z, mu, s,
-                     p, dlogp, dz);
+  if (parent_scale)
+    hipLaunchKernelGGL((k_plain_gmu<T, true>), dim3(n_items), dim3(256), 0, st, layers, items, g, z,
+                       mu, s, p, dlogp, dz);
+  else
+    hipLaunchKernelGGL((k_plain_gmu<T, false>), dim3(n_items), dim3(256), 0, st, layers, items, g, z,
+                       mu, s, p, dlogp, dz);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_plain_gtz(const LayerDev* layers, const Item* items, int n_items, const T* g,
                             const T* z, const T* mu, const T* s, const T* p, const double* dlogp,
-                            T* gtz, T* dmu, hipStream_t st) {
+                            T* gtz, T* dmu, T* ds_pp, bool parent_scale, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plain_gtz<T>, dim3(n_items), dim3(256), 0, st, layers, items, g, z, mu, s,
-                     p, dlogp, gtz, dmu);
+  if (parent_scale)
+    hipLaunchKernelGGL((k_plain_gtz<T, true>), dim3(n_items), dim3(256), 0, st, layers, items, g, z,
+                       mu, s, p, dlogp, gtz, dmu, ds_pp);
+  else
+    hipLaunchKernelGGL((k_plain_gtz<T, false>), dim3(n_items), dim3(256), 0, st, layers, items, g, z,
+                       mu, s, p, dlogp, gtz, dmu, ds_pp);
   return hipGetLastError();
 }
 
@@ -562,7 +659,8 @@ hipError_t launch_pair_dsp(const LayerDev* layers, const int* pair_ids, int n_pa
 
 #define TMC_INST(T)                                                                              \
   template hipError_t launch_plain_factor<T>(const LayerDev*, const Item*, int, const T*,        \
-                                             const T*, const T*, T*, bool, double*, hipStream_t); \
+                                             const T*, const T*, T*, bool, double*, bool,        \
+                                             hipStream_t);                                       \
   template hipError_t launch_plain_lse_fwd<T>(const LayerDev*, const Item*, int, int, int,       \
                                               const T*, bool, const T*, double*, T*, double*,    \
                                               const double*, hipStream_t);                       \
@@ -572,10 +670,10 @@ hipError_t launch_pair_dsp(const LayerDev* layers, const int* pair_ids, int n_pa
                                               hipStream_t);                                      \
   template hipError_t launch_plain_gmu<T>(const LayerDev*, const Item*, int, const T*,           \
                                           const T*, const T*, const T*, const T*,                \
-                                          const double*, T*, hipStream_t);                       \
+                                          const double*, T*, bool, hipStream_t);                 \
   template hipError_t launch_plain_gtz<T>(const LayerDev*, const Item*, int, const T*,           \
                                           const T*, const T*, const T*, const T*,                \
-                                          const double*, T*, T*, hipStream_t);                   \
+                                          const double*, T*, T*, T*, bool, hipStream_t);         \
   template hipError_t launch_pair_dsp<T>(const LayerDev*, const int*, int, const T*, const T*,   \
                                          const T*, const T*, const T*, const double*, T*,        \
                                          hipStream_t);

@@ -13,11 +13,14 @@
 //   d u_i[k] = sum_kt G,  d z_ik = -lam sum_kt G (z_ik - mth[kt]),
 //   d mth[kt] = lam sum_i sum_k G (z_ik - mth[kt]),
 //   d s = sum_i sum_{kt,k} G (lam (z_ik - mth[kt])^2 - 1),  lam = exp(-2 s).
-// Workgroups are 8 waves: the 64 lanes of a wave take 64 samples of one index, the waves
-// split the other; every sum across lanes, waves, points or workgroups runs in a fixed
-// order, so results are deterministic.  Per-entry arithmetic is in T (the plan's
+// The 64 lanes of a wave take 64 samples of one index and the wave walks the other,
+// reading those rows (shared by all its lanes) with scalar loads: no LDS staging and no
+// barrier in the loops.  Every sum across lanes, waves, points or workgroups runs in a
+// fixed order, so results are deterministic.  Per-entry arithmetic is in T (the plan's
 // precision); per-row results and sums over rows are double.
 #include <math.h>
+
+#include <limits>
 
 #include "dev_util.h"
 #include "tmc_internal.h"
@@ -28,157 +31,146 @@ namespace tmc {
 namespace {
 
 constexpr int kStarThreads = kStarWaves * kWave;
-constexpr int kRowsPerWave = kStarChunk / kStarWaves;
 constexpr double kLn2Pi = 1.8378770664093454836;
+constexpr double kLog2eD = 1.4426950408889634074;
 
-// lam_d = exp(-2 s_d) (0 past D); returns c = -sum_d s_d - D/2 ln(2 pi).
+// The wave's index as a wave-uniform value: addresses built from it stay in scalar
+// registers, so rows that every lane of a wave reads (a point's local samples, a global
+// sample's mean) are fetched once per wave by scalar loads and used as scalar operands.
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
+
+__device__ __forceinline__ float exp2_t(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double exp2_t(double x) { return exp2(x); }
+
+// Per-instance constants: nlam_d = -1/2 exp(-2 s_d) (0 past D); returns
+// c = -sum_d s_d - D/2 ln(2 pi) (FP64).
 template <typename T, int DB>
-__device__ __forceinline__ T star_consts(const T* __restrict__ s, int D, T (&lam)[DB]) {
+__device__ __forceinline__ double star_consts(const T* __restrict__ s, int D, T (&nlam)[DB]) {
   double ssum = 0.0;
 #pragma unroll
   for (int d = 0; d < DB; ++d) {
     const double sd = d < D ? (double)s[d] : 0.0;
-    lam[d] = d < D ? (T)exp(-2.0 * sd) : (T)0;
+    nlam[d] = d < D ? (T)(-0.5 * exp(-2.0 * sd)) : (T)0;
     ssum += sd;
   }
-  return (T)(-ssum - 0.5 * (double)D * kLn2Pi);
+  return -ssum - 0.5 * (double)D * kLn2Pi;
 }
 
-// -1/2 sum_d lam_d (x_d - y_d)^2; entries past D are 0 on both sides and lam is 0 there.
-template <typename T, int DB, class X, class Y>
-__device__ __forceinline__ T star_quad(const X& x, const Y& y, const T (&lam)[DB]) {
-  T acc = (T)0;
+// u + f - c for one (local row zr, global mean mt): u + sum_d nlam_d (zr_d - mt_d)^2.
+// For DB = 1 the width is 1 (rows are consecutive values).
+template <typename T, int DB>
+__device__ __forceinline__ T star_x(const T* __restrict__ zr, const T (&mt)[DB], const T (&nlam)[DB],
+                                    int D, T u) {
+  T x = u;
 #pragma unroll
   for (int d = 0; d < DB; ++d) {
-    const T t = x[d] - y[d];
-    acc += lam[d] * t * t;
+    if (DB == 1 || d < D) {   // (uniform)
+      const T t = zr[d] - mt[d];
+      x = fma(nlam[d] * t, t, x);
+    }
   }
-  return (T)(-0.5) * acc;
+  return x;
 }
 
-// Rows [r0, r0 + n) of a row-major [*][D] array into LDS rows of stride DB (the padding
-// columns d >= D keep the zeros written at kernel start).
-template <typename T, int DB>
-__device__ __forceinline__ void star_stage(T* dst, const T* __restrict__ src, int r0, int n, int D) {
-  for (int e = threadIdx.x; e < n * D; e += blockDim.x) {
-    const int r = e / D;
-    dst[r * DB + (e - r * D)] = src[(int64_t)r0 * D + e];
-  }
-}
-
-template <typename T, int N>
-__device__ __forceinline__ void lds_zero(T* dst) {
-  for (int e = threadIdx.x; e < N; e += blockDim.x) dst[e] = (T)0;
-}
-
-// Sum over the waves, in wave order, of each lane's v; the result is valid in wave 0.
-// Every thread of the workgroup must call it.
-template <typename T>
-__device__ __forceinline__ double waves_sum(T v, T (*cb)[kStarLanes], int wv, int lane) {
-  __syncthreads();
-  cb[wv][lane] = v;
-  __syncthreads();
-  double r = 0.0;
-  if (wv == 0) {
+// Adds rows [k0, k0 + NR) of one point to a lane's running log-sum-exp (mx, sm), sm in
+// units of exp(mx): the rows' maximum first, one rescale, then the exponentials, each
+// exp(x - mx) as exp2 of one fused multiply-add.  Branch-free: the maximum ignores NaN
+// (fmax) while a NaN row still makes the sum NaN; an all -inf prefix keeps (mx, sm) =
+// (-inf, 0).
+template <typename T, int DB, int NR>
+__device__ __forceinline__ void star_rows(const T* __restrict__ z, const T* __restrict__ u, int k0,
+                                          int D, const T (&mt)[DB], const T (&nlam)[DB], T& mx, T& sm) {
+  const T l2e = (T)kLog2eD;
+  const int stride = DB == 1 ? 1 : D;
+  T ur[NR], x[NR];
 #pragma unroll
-    for (int w = 0; w < kStarWaves; ++w) r += (double)cb[w][lane];
-  }
-  return r;
+  for (int r = 0; r < NR; ++r) ur[r] = u[k0 + r];   // (all loads of the step first)
+#pragma unroll
+  for (int r = 0; r < NR; ++r) x[r] = star_x<T, DB>(z + (int64_t)(k0 + r) * stride, mt, nlam, D, ur[r]);
+  T m = mx;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) m = fmax(m, x[r]);
+  const T nsh = m == (T)(-INFINITY) ? (T)0 : -m * l2e;
+  T acc = sm * exp2_t(fma(mx, l2e, nsh));
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc += exp2_t(fma(x[r], l2e, nsh));
+  sm = acc;
+  mx = m;
 }
 
 }  // namespace
 
-// Messages: a workgroup per (instance, group of P points, 64 global samples).  Lane ->
-// global sample kt; wave wv takes local rows wv, wv + 8, .. of each staged chunk of 64,
-// keeping a running (max, sum) per lane; the waves' pairs are merged in wave order.
+// Messages.  A workgroup per (instance, group of P points, 64 global samples); lane ->
+// global sample kt, and the waves take the group's points in turn (wave wv: points
+// wv, wv + 4, ..).  A wave walks all K local samples of its point, kStarRows at a time,
+// reading them with scalar loads, and keeps a running (max, sum) per lane; no LDS and no
+// barrier until the group's sums of m_i are combined in wave order.
 template <typename T, int DB>
 __global__ __launch_bounds__(kStarThreads) void k_star_msg(StarArgs<T> a) {
-  __shared__ T zs[kStarChunk * DB];
-  __shared__ T us[kStarChunk];
-  __shared__ T cm[kStarWaves][kStarLanes];
-  __shared__ T cs[kStarWaves][kStarLanes];
+  __shared__ double part[kStarWaves][kStarLanes];
   const int inst = blockIdx.x / a.ngrp, grp = blockIdx.x - inst * a.ngrp;
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave, wv = wave_index();
   const int D = a.D, K = a.K, Kt = a.Kt;
   const int kt = blockIdx.y * kStarLanes + lane;
   const bool ktv = kt < Kt;
-  T lam[DB], mt[DB];
-  const T c0 = star_consts<T, DB>(a.s + (int64_t)inst * D, D, lam);
+  T nlam[DB], mt[DB];
+  const double c0 = star_consts<T, DB>(a.s + (int64_t)inst * D, D, nlam);
 #pragma unroll
   for (int d = 0; d < DB; ++d) mt[d] = (ktv && d < D) ? a.mth[((int64_t)inst * Kt + kt) * D + d] : (T)0;
-  lds_zero<T, kStarChunk * DB>(zs);
-  const T ninf = (T)(-INFINITY);
-  const double lnK = log((double)K);
+  const double cK = c0 - log((double)K);
   double gacc = 0.0;
-  const int p0 = grp * a.P, p1 = min(a.N, p0 + a.P);
-  for (int pt = p0; pt < p1; ++pt) {
+  const int p1 = min(a.N, (grp + 1) * a.P);
+  for (int pt = grp * a.P + wv; pt < p1; pt += kStarWaves) {
     const int64_t pi = (int64_t)inst * a.N + pt;
     const T* z = a.z + pi * K * D;
     const T* u = a.u + pi * K;
-    T mx = ninf, sm = (T)0;
-    for (int k0 = 0; k0 < K; k0 += kStarChunk) {
-      const int nk = min(kStarChunk, K - k0);
-      __syncthreads();   // (also orders the previous point's reads of cm, cs)
-      star_stage<T, DB>(zs, z, k0, nk, D);
-      for (int e = threadIdx.x; e < nk; e += blockDim.x) us[e] = u[k0 + e];
-      __syncthreads();
-      T x[kRowsPerWave];
-      T m = ninf;
-#pragma unroll
-      for (int r = 0; r < kRowsPerWave; ++r) {
-        const int k = wv + kStarWaves * r;
-        x[r] = k < nk ? us[k] + c0 + star_quad<T, DB>(&zs[k * DB], mt, lam) : ninf;
-        m = nan_max(m, x[r]);
-      }
-      if (m != m) {
-        mx = m;
-        sm = m;
-      } else if (m != ninf && mx == mx) {
-        if (m > mx) {
-          sm *= fast_exp(mx - m);
-          mx = m;
-        }
-#pragma unroll
-        for (int r = 0; r < kRowsPerWave; ++r) sm += fast_exp(x[r] - mx);
-      }
+    T mx = (T)(-INFINITY), sm = (T)0;
+    int k = 0;
+    for (; k + kStarRows <= K; k += kStarRows) star_rows<T, DB, kStarRows>(z, u, k, D, mt, nlam, mx, sm);
+    for (; k < K; ++k) star_rows<T, DB, 1>(z, u, k, D, mt, nlam, mx, sm);
+    // (all -inf: -inf + log 0 = -inf; a NaN row: log NaN = NaN)
+    const double lse = (double)mx + log((double)sm);   // m_i + ln K - c
+    const double mi = lse + cK;
+    if (ktv) {
+      a.msg[pi * Kt + kt] = mi;
+      // clamped: an all -inf point meets only -inf exponents there (never inf - inf)
+      a.nsh[pi * Kt + kt] = (T)fmin(-lse * kLog2eD, (double)std::numeric_limits<T>::max());
     }
-    cm[wv][lane] = mx;
-    cs[wv][lane] = sm;
-    __syncthreads();
-    if (wv == 0) {
-      T M = cm[0][lane];
-#pragma unroll
-      for (int w = 1; w < kStarWaves; ++w) M = nan_max(M, cm[w][lane]);
-      double mi;
-      if (M != M) {
-        mi = (double)M;
-      } else if (M == ninf) {
-        mi = -INFINITY;
-      } else {
-        T S = (T)0;
-#pragma unroll
-        for (int w = 0; w < kStarWaves; ++w) S += cs[w][lane] * fast_exp(cm[w][lane] - M);
-        mi = (double)M + log((double)S) - lnK;
-      }
-      if (ktv) a.msg[pi * Kt + kt] = mi;
-      gacc += mi;
-    }
+    gacc += mi;
   }
-  if (wv == 0 && ktv) a.gsum[((int64_t)inst * a.ngrp + grp) * Kt + kt] = gacc;
+  part[wv][lane] = gacc;
+  __syncthreads();
+  if (wv == 0 && ktv) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kStarWaves; ++w) v += part[w][lane];
+    a.gsum[((int64_t)inst * a.ngrp + grp) * Kt + kt] = v;
+  }
 }
 
-// Logits of the global samples: w[kt] = uth[kt] + sum over groups of gsum (wave wv sums
-// groups wv, wv + 8, ..; then the waves in order).  A workgroup per (instance, 64 kt).
+// Logits of the global samples: w[kt] = uth[kt] + sum over groups of gsum.  A workgroup
+// per (instance, 64 kt); wave wv sums groups wv, wv + 4, .. (loads issued 8 at a time,
+// added in group order), then the waves in order.
 template <typename T>
 __global__ __launch_bounds__(kStarThreads) void k_star_colsum(StarArgs<T> a) {
   __shared__ double part[kStarWaves][kStarLanes];
   const int inst = blockIdx.x;
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave, wv = wave_index();
   const int kt = blockIdx.y * kStarLanes + lane;
   const bool ktv = kt < a.Kt;
+  const double* gs = a.gsum + (int64_t)inst * a.ngrp * a.Kt + (ktv ? kt : 0);
   double acc = 0.0;
-  if (ktv)
-    for (int g = wv; g < a.ngrp; g += kStarWaves) acc += a.gsum[((int64_t)inst * a.ngrp + g) * a.Kt + kt];
+  constexpr int U = 8;
+  for (int g0 = wv; g0 < a.ngrp; g0 += kStarWaves * U) {
+    double v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int g = g0 + kStarWaves * q;
+      v[q] = g < a.ngrp ? gs[(int64_t)g * a.Kt] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) acc += v[q];
+  }
   part[wv][lane] = acc;
   __syncthreads();
   if (wv == 0 && ktv) {
@@ -214,166 +206,199 @@ __global__ __launch_bounds__(256) void k_star_logp(StarArgs<T> a) {
     if (lp != lp || lp == INFINITY) atomicOr(a.flag, kFlagNonFinite);
   }
   const bool fin = lp == lp && lp != INFINITY && lp != -INFINITY;
-  for (int kt = threadIdx.x; kt < Kt; kt += blockDim.x)
-    w[kt] = fin ? exp(w[kt] - lnKt - lp) : (lp == -INFINITY ? 0.0 : (double)NAN);
+  for (int kt = threadIdx.x; kt < Kt; kt += blockDim.x) {
+    const double v = fin ? exp(w[kt] - lnKt - lp) : (lp == -INFINITY ? 0.0 : (double)NAN);
+    w[kt] = v;
+    a.wT[(int64_t)inst * Kt + kt] = (T)v;
+  }
 }
 
-// Local gradients: a workgroup per (instance and point, 64 local samples).  Lane ->
-// local sample k; wave wv takes global rows wv, wv + 8, .. of each staged chunk.
-// Writes du, dz, and this block's part of ds: sum_{kt,k} G (lam diff^2 - 1).
+// Local gradients.  A wave per (instance and point, 64 local samples): lane -> local
+// sample k; the wave walks every global sample t, kStarRows at a time (mean, weight and
+// this point's message by scalar loads; samples of weight 0 add 0) and accumulates
+//   gs = sum_t G,  gz_d = sum_t G (z_kd - mth_td),  gq_d = sum_t G (z_kd - mth_td)^2
+// with G = w_t exp(u_k + f[t, k] - m_i[t] - ln K).  Writes du, dz and this block's part of
+// ds: sum_k (lam_d gq_d - gs) over its lanes.
 template <typename T, int DB>
 __global__ __launch_bounds__(kStarThreads) void k_star_bwd_local(StarArgs<T> a) {
-  __shared__ T ms[kStarChunk * DB];
-  __shared__ T wt[kStarChunk];
-  __shared__ T mg[kStarChunk];
-  __shared__ T cb[kStarWaves][kStarLanes];
-  const int64_t pi = blockIdx.x;
+  const int lane = threadIdx.x % kWave, wv = wave_index();
+  const int64_t task = (int64_t)blockIdx.x * kStarWaves + wv;
+  if (task >= (int64_t)a.S * a.N * a.nkb) return;   // (uniform per wave; no barrier below)
+  const int64_t pi = task / a.nkb;
+  const int kb = (int)(task - pi * a.nkb);
   const int inst = (int)(pi / a.N);
-  const int kb = blockIdx.y;
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const int D = a.D, K = a.K, Kt = a.Kt;
   const int k = kb * kStarLanes + lane;
   const bool kv = k < K;
-  T lam[DB], zk[DB];
-  const T c0 = star_consts<T, DB>(a.s + (int64_t)inst * D, D, lam);
+  T nlam[DB], zk[DB];
+  (void)star_consts<T, DB>(a.s + (int64_t)inst * D, D, nlam);
 #pragma unroll
   for (int d = 0; d < DB; ++d) zk[d] = (kv && d < D) ? a.z[(pi * K + k) * D + d] : (T)0;
-  const T uk = kv ? a.u[pi * K + k] : (T)0;
-  lds_zero<T, kStarChunk * DB>(ms);
-  const double lnK = log((double)K);
+  const T uk = kv ? a.u[pi * K + k] : (T)(-INFINITY);
   const T* mth = a.mth + (int64_t)inst * Kt * D;
+  const T* w = a.wT + (int64_t)inst * Kt;
+  const T* nshp = a.nsh + pi * Kt;
+  const T l2e = (T)kLog2eD;
   T gs = (T)0, gz[DB], gq[DB];
 #pragma unroll
   for (int d = 0; d < DB; ++d) gz[d] = gq[d] = (T)0;
-  for (int t0 = 0; t0 < Kt; t0 += kStarChunk) {
-    const int nt = min(kStarChunk, Kt - t0);
-    __syncthreads();
-    star_stage<T, DB>(ms, mth, t0, nt, D);
-    for (int e = threadIdx.x; e < nt; e += blockDim.x) {
-      wt[e] = (T)a.w[(int64_t)inst * Kt + t0 + e];
-      mg[e] = (T)(a.msg[pi * Kt + t0 + e] + lnK);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kRowsPerWave; ++r) {
-      const int t = wv + kStarWaves * r;
-      if (t < nt) {
-        const T* mrow = &ms[t * DB];
-        const T x = uk + c0 + star_quad<T, DB>(zk, mrow, lam);
-        const T wtt = wt[t];
-        const T G = (kv && wtt != (T)0) ? wtt * fast_exp(x - mg[t]) : (T)0;
-        gs += G;
-#pragma unroll
-        for (int d = 0; d < DB; ++d) {
-          const T df = zk[d] - mrow[d];
-          gz[d] += G * df;
-          gq[d] += G * df * df;
-        }
-      }
-    }
-  }
-  const double g = a.dlogp[inst];
-  const double Gs = waves_sum<T>(gs, cb, wv, lane);
-  if (wv == 0 && kv && a.du) a.du[pi * K + k] = (T)(g * Gs);
-  if (a.dz) {
+  // one global sample (weight wt, exponent offset nt) into the lane's sums; a sample of
+  // weight 0 adds 0 (its offset is finite, or the lane's exponent is -inf)
+  auto row = [&](const T* mr, T wt, T nt) {
+    T x = uk, df[DB];
 #pragma unroll
     for (int d = 0; d < DB; ++d) {
-      if (d < D) {   // (uniform)
-        const double v = waves_sum<T>(gz[d], cb, wv, lane);
-        if (wv == 0 && kv) a.dz[(pi * K + k) * D + d] = (T)(-g * (double)lam[d] * v);
-      }
+      df[d] = (DB == 1 || d < D) ? zk[d] - mr[d] : (T)0;
+      x = fma(nlam[d] * df[d], df[d], x);
     }
+    const T G = wt * exp2_t(fma(x, l2e, nt));
+    gs += G;
+#pragma unroll
+    for (int d = 0; d < DB; ++d) {
+      gz[d] = fma(G, df[d], gz[d]);
+      gq[d] = fma(G * df[d], df[d], gq[d]);
+    }
+  };
+  const int stride = DB == 1 ? 1 : D;
+  int t = 0;
+  for (; t + kStarRows <= Kt; t += kStarRows) {
+    T wr[kStarRows], nr[kStarRows];
+#pragma unroll
+    for (int r = 0; r < kStarRows; ++r) {   // (all loads of the step first)
+      wr[r] = w[t + r];
+      nr[r] = nshp[t + r];
+    }
+#pragma unroll
+    for (int r = 0; r < kStarRows; ++r) row(mth + (int64_t)(t + r) * stride, wr[r], nr[r]);
+  }
+  for (; t < Kt; ++t) row(mth + (int64_t)t * stride, w[t], nshp[t]);
+  const double g = a.dlogp[inst];
+  if (kv && a.du) a.du[pi * K + k] = (T)(g * (double)gs);
+  if (a.dz && kv) {
+    // dz = -dlogp lam sum_t G (z - mth_t),  -lam = 2 nlam
+#pragma unroll
+    for (int d = 0; d < DB; ++d)
+      if (d < D) a.dz[(pi * K + k) * D + d] = (T)(g * 2.0 * (double)nlam[d] * (double)gz[d]);
   }
   if (a.ds) {
 #pragma unroll
     for (int d = 0; d < DB; ++d) {
       if (d < D) {   // (uniform)
-        const double v = waves_sum<T>(gq[d], cb, wv, lane);
-        // sum_{kt} G (lam diff^2 - 1) of this lane's sample, then over the lanes
-        const double lv = wave_sum(kv ? (double)lam[d] * v - Gs : 0.0);
-        if (wv == 0 && lane == 0) a.dsp[(pi * a.nkb + kb) * D + d] = lv;
+        const double lam = -2.0 * (double)nlam[d];
+        const double lv = wave_sum(kv ? lam * (double)gq[d] - (double)gs : 0.0);
+        if (lane == 0) a.dsp[(pi * a.nkb + kb) * D + d] = g * lv;
       }
     }
   }
 }
 
-// d mth parts: a workgroup per (instance, group of P points, 64 global samples), the
-// loop structure of k_star_msg; per lane sum_i sum_k G (z_ik - mth[kt]) over the group.
+// d mth parts: a workgroup per (instance, group of P points, 64 global samples) as in
+// k_star_msg; per lane, gm_d = sum over the wave's points and their local samples of
+// G (z_kd - mth_d), with G = w exp(u_k + f - m_i - ln K) (lanes of weight 0: G = 0); the
+// waves' sums combined in wave order.
 template <typename T, int DB>
 __global__ __launch_bounds__(kStarThreads) void k_star_bwd_global(StarArgs<T> a) {
-  __shared__ T zs[kStarChunk * DB];
-  __shared__ T us[kStarChunk];
-  __shared__ T cb[kStarWaves][kStarLanes];
+  __shared__ double part[kStarWaves][kStarLanes];
   const int inst = blockIdx.x / a.ngrp, grp = blockIdx.x - inst * a.ngrp;
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave, wv = wave_index();
   const int D = a.D, K = a.K, Kt = a.Kt;
   const int kt = blockIdx.y * kStarLanes + lane;
   const bool ktv = kt < Kt;
-  T lam[DB], mt[DB], gm[DB];
-  const T c0 = star_consts<T, DB>(a.s + (int64_t)inst * D, D, lam);
+  T nlam[DB], mt[DB], gm[DB];
+  (void)star_consts<T, DB>(a.s + (int64_t)inst * D, D, nlam);
 #pragma unroll
   for (int d = 0; d < DB; ++d) {
     mt[d] = (ktv && d < D) ? a.mth[((int64_t)inst * Kt + kt) * D + d] : (T)0;
     gm[d] = (T)0;
   }
-  lds_zero<T, kStarChunk * DB>(zs);
-  const T wk = ktv ? (T)a.w[(int64_t)inst * Kt + kt] : (T)0;
-  const double lnK = log((double)K);
-  const int p0 = grp * a.P, p1 = min(a.N, p0 + a.P);
-  for (int pt = p0; pt < p1; ++pt) {
+  const T wk = ktv ? a.wT[(int64_t)inst * Kt + kt] : (T)0;
+  const T l2e = (T)kLog2eD;
+  const int stride = DB == 1 ? 1 : D;
+  const int p1 = min(a.N, (grp + 1) * a.P);
+  for (int pt = grp * a.P + wv; pt < p1; pt += kStarWaves) {
     const int64_t pi = (int64_t)inst * a.N + pt;
     const T* z = a.z + pi * K * D;
     const T* u = a.u + pi * K;
-    const T mgt = ktv ? (T)(a.msg[pi * Kt + kt] + lnK) : (T)0;
-    for (int k0 = 0; k0 < K; k0 += kStarChunk) {
-      const int nk = min(kStarChunk, K - k0);
-      __syncthreads();
-      star_stage<T, DB>(zs, z, k0, nk, D);
-      for (int e = threadIdx.x; e < nk; e += blockDim.x) us[e] = u[k0 + e];
-      __syncthreads();
-      if (wk != (T)0) {
+    // (a lane of weight 0 has a finite offset or only -inf exponents: its G are 0)
+    const T nsh = ktv ? a.nsh[pi * Kt + kt] : (T)0;
+    int k = 0;
+    for (; k + kStarRows <= K; k += kStarRows) {
+      T ur[kStarRows];
 #pragma unroll
-        for (int r = 0; r < kRowsPerWave; ++r) {
-          const int k = wv + kStarWaves * r;
-          if (k < nk) {
-            const T* zrow = &zs[k * DB];
-            const T G = wk * fast_exp(us[k] + c0 + star_quad<T, DB>(zrow, mt, lam) - mgt);
+      for (int r = 0; r < kStarRows; ++r) ur[r] = u[k + r];
 #pragma unroll
-            for (int d = 0; d < DB; ++d) gm[d] += G * (zrow[d] - mt[d]);
-          }
+      for (int r = 0; r < kStarRows; ++r) {
+        const T* zr = z + (int64_t)(k + r) * stride;
+        T x = ur[r], df[DB];
+#pragma unroll
+        for (int d = 0; d < DB; ++d) {
+          df[d] = (DB == 1 || d < D) ? zr[d] - mt[d] : (T)0;
+          x = fma(nlam[d] * df[d], df[d], x);
         }
+        const T G = (T)wk * exp2_t(fma(x, l2e, nsh));
+#pragma unroll
+        for (int d = 0; d < DB; ++d) gm[d] = fma(G, df[d], gm[d]);
       }
+    }
+    for (; k < K; ++k) {
+      const T* zr = z + (int64_t)k * stride;
+      T x = u[k], df[DB];
+#pragma unroll
+      for (int d = 0; d < DB; ++d) {
+        df[d] = (DB == 1 || d < D) ? zr[d] - mt[d] : (T)0;
+        x = fma(nlam[d] * df[d], df[d], x);
+      }
+      const T G = (T)wk * exp2_t(fma(x, l2e, nsh));
+#pragma unroll
+      for (int d = 0; d < DB; ++d) gm[d] = fma(G, df[d], gm[d]);
     }
   }
 #pragma unroll
   for (int d = 0; d < DB; ++d) {
     if (d < D) {   // (uniform)
-      const double v = waves_sum<T>(gm[d], cb, wv, lane);
-      if (wv == 0 && ktv) a.dm[(((int64_t)inst * a.ngrp + grp) * Kt + kt) * D + d] = v;
+      __syncthreads();
+      part[wv][lane] = (double)gm[d];
+      __syncthreads();
+      if (wv == 0 && ktv) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kStarWaves; ++w) v += part[w][lane];
+        a.dm[(((int64_t)inst * a.ngrp + grp) * Kt + kt) * D + d] = v;
+      }
     }
   }
 }
 
 // Final sums.  Blocks y < ceil(Kt D / 64): d mth of 64 entries (wave wv sums groups
-// wv, wv + 8, ..; then the waves in order), scaled by dlogp lam.  Block y = last: ds
-// (the workgroup strides over the N * nkb parts, then a fixed-order tree) and
-// d uth = dlogp w.
+// wv, wv + 4, .., loads issued 8 at a time; then the waves in order), scaled by dlogp lam.
+// Block y = last: ds (the workgroup strides over the N nkb parts, then a fixed-order
+// tree) and d uth = dlogp w.
 template <typename T>
 __global__ __launch_bounds__(kStarThreads) void k_star_reduce(StarArgs<T> a) {
   __shared__ double part[kStarWaves][kStarLanes];
   __shared__ double red[kMaxWaves];
   const int inst = blockIdx.x;
-  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave, wv = wave_index();
   const int D = a.D, Kt = a.Kt;
   const int64_t KD = (int64_t)Kt * D;
   const double g = a.dlogp[inst];
+  constexpr int U = 8;
   if (blockIdx.y + 1 < gridDim.y) {
     if (!a.dmth) return;   // (uniform)
     const int64_t e = (int64_t)blockIdx.y * kStarLanes + lane;
     const bool ev = e < KD;
+    const double* dm = a.dm + (int64_t)inst * a.ngrp * KD + (ev ? e : 0);
     double acc = 0.0;
-    if (ev)
-      for (int gi = wv; gi < a.ngrp; gi += kStarWaves) acc += a.dm[((int64_t)inst * a.ngrp + gi) * KD + e];
+    for (int g0 = wv; g0 < a.ngrp; g0 += kStarWaves * U) {
+      double v[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int gi = g0 + kStarWaves * q;
+        v[q] = gi < a.ngrp ? dm[(int64_t)gi * KD] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) acc += v[q];
+    }
     part[wv][lane] = acc;
     __syncthreads();
     if (wv == 0 && ev) {
@@ -391,9 +416,18 @@ __global__ __launch_bounds__(kStarThreads) void k_star_reduce(StarArgs<T> a) {
     const double* dsp = a.dsp + (int64_t)inst * nparts * D;
     for (int d = 0; d < D; ++d) {
       double acc = 0.0;
-      for (int64_t j = threadIdx.x; j < nparts; j += blockDim.x) acc += dsp[j * D + d];
+      for (int64_t j0 = threadIdx.x; j0 < nparts; j0 += (int64_t)blockDim.x * U) {
+        double v[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const int64_t j = j0 + (int64_t)blockDim.x * q;
+          v[q] = j < nparts ? dsp[j * D + d] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) acc += v[q];
+      }
       acc = block_sum(acc, red);
-      if (threadIdx.x == 0) a.ds[(int64_t)inst * D + d] = (T)(g * acc);
+      if (threadIdx.x == 0) a.ds[(int64_t)inst * D + d] = (T)acc;
     }
   }
   if (a.duth)
@@ -432,7 +466,8 @@ hipError_t launch_star_logp(const StarArgs<T>& a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_star_bwd_local(const StarArgs<T>& a, hipStream_t st) {
-  const dim3 grid(a.S * a.N, a.nkb);
+  const int64_t tasks = (int64_t)a.S * a.N * a.nkb;
+  const dim3 grid((unsigned)((tasks + kStarWaves - 1) / kStarWaves));
   TMC_STAR_BY_WIDTH(k_star_bwd_local, grid);
   return hipGetLastError();
 }

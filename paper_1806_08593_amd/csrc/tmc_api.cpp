@@ -18,6 +18,7 @@
 #include "tmc_internal.h"
 #include "tmc_kernels.h"
 #include "tmc_scratch.h"
+#include "tmc_logmm.h"
 #include "tmc_star.h"
 
 using namespace tmc;
@@ -70,7 +71,7 @@ struct DeviceGuard {
 struct StarPlan {
   int S = 0, N = 0, Kt = 0, K = 0, D = 0;
   int P = 1, ngrp = 0, nkb = 0;
-  size_t msg = 0, gsum = 0, w = 0, lp = 0, dm = 0, dsp = 0;
+  size_t msg = 0, gsum = 0, w = 0, lp = 0, dm = 0, dsp = 0, nsh = 0, wT = 0;
 };
 
 constexpr int kKindChain = 0, kKindStar = 1;
@@ -174,11 +175,15 @@ tmc_status validate(const tmc_problem* pr, int* engine_out, std::string* gauss_e
     return fail(TMC_ERR_INVALID_ARG, "unknown precision %d", pr->precision);
   if (pr->engine < TMC_ENGINE_AUTO || pr->engine > TMC_ENGINE_PLAIN)
     return fail(TMC_ERR_INVALID_ARG, "unknown engine %d", pr->engine);
-  if (pr->flags & ~(TMC_FLAG_FORWARD_ONLY | TMC_FLAG_PERSISTENT))
+  if (pr->flags & ~(TMC_FLAG_FORWARD_ONLY | TMC_FLAG_PERSISTENT | TMC_FLAG_PARENT_SCALE))
     return fail(TMC_ERR_INVALID_ARG, "unknown flag bits 0x%x", pr->flags);
+  const bool pp = (pr->flags & TMC_FLAG_PARENT_SCALE) != 0;
   int engine = pr->engine;
   if (engine == TMC_ENGINE_AUTO)
-    engine = (pr->precision == TMC_FP64 || !kFusedAvailable) ? TMC_ENGINE_PLAIN : TMC_ENGINE_FUSED;
+    engine = (pr->precision == TMC_FP64 || pp || !kFusedAvailable) ? TMC_ENGINE_PLAIN
+                                                                   : TMC_ENGINE_FUSED;
+  if (engine == TMC_ENGINE_FUSED && pp)
+    return fail(TMC_ERR_UNSUPPORTED, "parent-dependent scales run on the plain engine");
   if (engine == TMC_ENGINE_PLAIN && pr->precision == TMC_BF16X3)
     return fail(TMC_ERR_UNSUPPORTED, "the plain engine has no BF16X3 mode");
   if (engine == TMC_ENGINE_FUSED && pr->precision == TMC_FP64)
@@ -222,7 +227,7 @@ tmc_status validate(const tmc_problem* pr, int* engine_out, std::string* gauss_e
         if (L.f_off < 0) neg_f = true;
         rm.push_back({L.mu_off, L.mu_off + (int64_t)U.K * L.D, l});
         rf.push_back({L.f_off, L.f_off + (int64_t)L.K * U.K, l});
-        rs.push_back({L.s_off, L.s_off + L.D, l});
+        rs.push_back({L.s_off, L.s_off + (pp ? (int64_t)U.K : 1) * L.D, l});
       }
     }
   }
@@ -242,9 +247,13 @@ tmc_status validate(const tmc_problem* pr, int* engine_out, std::string* gauss_e
       return x.b < y.b || (x.b == y.b && x.e < y.e);
     });
     for (size_t i = 1; i < rs.size(); ++i) {
-      const bool same = rs[i].b == rs[i - 1].b && rs[i].e == rs[i - 1].e;
+      // shared-scale blocks may be shared whole (their ds is summed); parent-dependent
+      // blocks belong to one layer's parents and may not be shared at all
+      const bool same = !pp && rs[i].b == rs[i - 1].b && rs[i].e == rs[i - 1].e;
       if (!same && rs[i].b < rs[i - 1].e) {
-        snprintf(buf, sizeof buf, "s blocks of layers %d and %d partially overlap", rs[i - 1].who, rs[i].who);
+        snprintf(buf, sizeof buf, pp ? "s blocks of layers %d and %d overlap"
+                                     : "s blocks of layers %d and %d partially overlap",
+                 rs[i - 1].who, rs[i].who);
         *gauss_err = buf;
         break;
       }
@@ -543,6 +552,8 @@ tmc_status build_plan(tmc_plan* P, const tmc_problem* pr) {
   return TMC_OK;
 }
 
+bool parent_scale(const tmc_plan* P) { return (P->flags & TMC_FLAG_PARENT_SCALE) != 0; }
+
 tmc_status check_exec(tmc_plan* P, void* ws, int kind = kKindChain) {
   if (!P) return fail(TMC_ERR_INVALID_ARG, "plan is NULL");
   if (P->kind != kind)
@@ -597,7 +608,7 @@ tmc_status plain_fwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, co
   double* anchor = caller ? nullptr : wsp<double>(ws, W.anchor);
   if (!caller && P->factor.n > 0)
     LAUNCH_KC(TMC_KC_PLAIN_FACTOR, launch_plain_factor<T>(P->layers_d, it + P->factor.off, P->factor.n, z, mu, s, wf, false,
-                                                          anchor, st));
+                                                          anchor, parent_scale(P), st));
   LAUNCH(launch_init_top<T>(P->chains_d, P->n_chains, P->layers_d, u, wsp<double>(ws, W.alpha), st));
   for (size_t t = 0; t < P->fwd.size(); ++t)
     LAUNCH_KC(TMC_KC_PLAIN_LSE_FWD, launch_plain_lse_fwd<T>(P->layers_d, it + P->fwd[t].off, P->fwd[t].n, P->fwd_maxkc[t],
@@ -631,10 +642,18 @@ tmc_status plain_bwd(tmc_plan* P, const T* f_caller, const T* z, const T* mu, co
   }
   if (caller) return TMC_OK;
   if (dz)
-    LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_plain_gmu<T>(P->layers_d, it + P->gmu.off, P->gmu.n, g, z, mu, s, p, dlogp, dz, st));
+    LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_plain_gmu<T>(P->layers_d, it + P->gmu.off, P->gmu.n, g, z, mu, s, p, dlogp, dz,
+                                                     parent_scale(P), st));
+  if (parent_scale(P)) {
+    // dmu and the per-parent ds of each pair directly (no shared blocks to sum over)
+    if (dmu || ds)
+      LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_plain_gtz<T>(P->layers_d, it + P->gtz.off, P->gtz.n, g, z, mu, s, p,
+                                                       dlogp, nullptr, dmu, ds, true, st));
+    return TMC_OK;
+  }
   if (dmu || ds)
     LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_plain_gtz<T>(P->layers_d, it + P->gtz.off, P->gtz.n, g, z, mu, s, p, dlogp,
-                               wsp<T>(ws, W.gtz), dmu, st));
+                               wsp<T>(ws, W.gtz), dmu, nullptr, false, st));
   if (ds) {
     LAUNCH_KC(TMC_KC_PLAIN_GRAD, launch_pair_dsp<T>(P->layers_d, P->ints_d + P->pair_ids_off, P->n_pairs, z, mu, s, p,
                               wsp<T>(ws, W.gtz), dlogp, wsp<T>(ws, W.dsp), st));
@@ -775,6 +794,8 @@ StarArgs<T> star_args(tmc_plan* P, void* ws) {
   a.gsum = reinterpret_cast<double*>(base + sp.gsum);
   a.w = reinterpret_cast<double*>(base + sp.w);
   a.lp = reinterpret_cast<double*>(base + sp.lp);
+  a.nsh = reinterpret_cast<T*>(base + sp.nsh);
+  a.wT = reinterpret_cast<T*>(base + sp.wT);
   const bool grad = !(P->flags & TMC_FLAG_FORWARD_ONLY);
   a.dm = grad ? reinterpret_cast<double*>(base + sp.dm) : nullptr;
   a.dsp = grad ? reinterpret_cast<double*>(base + sp.dsp) : nullptr;
@@ -853,9 +874,10 @@ void star_layout(tmc_plan* P, const tmc_star_problem* pr) {
   sp.D = pr->D;
   const int64_t nkt = (sp.Kt + kStarLanes - 1) / kStarLanes;
   sp.nkb = (sp.K + kStarLanes - 1) / kStarLanes;
-  // points per workgroup: as few as keep about kStarTargetGroups workgroups in a launch
+  // points per workgroup: one per wave at least, more while the forward grid would
+  // exceed about kStarTargetGroups workgroups
   const int64_t want = (int64_t)sp.S * sp.N * nkt / kStarTargetGroups;
-  sp.P = (int)std::max<int64_t>(1, std::min<int64_t>(sp.N, want));
+  sp.P = (int)std::max<int64_t>(std::min<int64_t>(sp.N, kStarWaves), std::min<int64_t>(sp.N, want));
   sp.ngrp = (sp.N + sp.P - 1) / sp.P;
   const int64_t S = sp.S;
   size_t off = 0;
@@ -868,6 +890,9 @@ void star_layout(tmc_plan* P, const tmc_star_problem* pr) {
   sp.gsum = take((size_t)(S * sp.ngrp * sp.Kt) * 8);
   sp.w = take((size_t)(S * sp.Kt) * 8);
   sp.lp = take((size_t)S * 8);
+  const size_t esz = pr->precision == TMC_FP64 ? 8 : 4;
+  sp.nsh = take((size_t)(S * sp.N * sp.Kt) * esz);
+  sp.wT = take((size_t)(S * sp.Kt) * esz);
   if (!(P->flags & TMC_FLAG_FORWARD_ONLY)) {
     sp.dm = take((size_t)(S * sp.ngrp * sp.Kt) * sp.D * 8);
     sp.dsp = take((size_t)(S * sp.N * sp.nkb) * sp.D * 8);
@@ -1029,6 +1054,65 @@ tmc_status tmc_star_gauss_bwd(tmc_plan_t plan, const void* mth, const void* s, c
   }
 }
 
+namespace {
+tmc_status logmm_check(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t precision) {
+  if (precision != TMC_FP64 && precision != TMC_FP32 && precision != TMC_BF16X3)
+    return fail(TMC_ERR_INVALID_ARG, "unknown precision %d", precision);
+  if (batch < 1 || batch > 65535) return fail(TMC_ERR_SHAPE, "batch = %d outside [1, 65535]", batch);
+  if (M < 1 || M > 65535) return fail(TMC_ERR_SHAPE, "M = %d outside [1, 65535]", M);
+  if (K < 1 || K > (1 << 24)) return fail(TMC_ERR_SHAPE, "K = %d outside [1, 2^24]", K);
+  if (N < 1 || N > (1 << 24)) return fail(TMC_ERR_SHAPE, "N = %d outside [1, 2^24]", N);
+  return TMC_OK;
+}
+
+size_t logmm_ws(int32_t batch, int32_t M, int32_t N, int32_t precision) {
+  if (precision == TMC_FP64) return 0;
+  return align_up((size_t)batch * M * 4, 256) + align_up((size_t)batch * N * 4, 256);
+}
+}  // namespace
+
+tmc_status tmc_logmmexp_workspace_size(int32_t batch, int32_t M, int32_t K, int32_t N,
+                                       int32_t precision, size_t* bytes) {
+  if (!bytes) return fail(TMC_ERR_INVALID_ARG, "bytes is NULL");
+  const tmc_status st = logmm_check(batch, M, K, N, precision);
+  if (st != TMC_OK) return st;
+  *bytes = logmm_ws(batch, M, N, precision);
+  return TMC_OK;
+}
+
+tmc_status tmc_logmmexp(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t precision,
+                        const void* X, const void* Y, void* Z, void* workspace, void* stream) {
+  try {
+    tmc_status st = logmm_check(batch, M, K, N, precision);
+    if (st != TMC_OK) return st;
+    if (!X || !Y || !Z) return fail(TMC_ERR_INVALID_ARG, "NULL X, Y or Z");
+    LogmmArgs a{};
+    a.B = batch;
+    a.M = M;
+    a.K = K;
+    a.N = N;
+    if (precision == TMC_FP64) {
+      a.Xd = (const double*)X;
+      a.Yd = (const double*)Y;
+      a.Zd = (double*)Z;
+    } else {
+      if (!workspace) return fail(TMC_ERR_WORKSPACE, "workspace is NULL");
+      if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(TMC_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+      a.X = (const float*)X;
+      a.Y = (const float*)Y;
+      a.Z = (float*)Z;
+      a.xs = (float*)workspace;
+      a.ys = (float*)((char*)workspace + align_up((size_t)batch * M * 4, 256));
+    }
+    const hipError_t e = launch_logmm(a, precision, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(TMC_ERR_HIP, "log-domain product launch: %s", hipGetErrorString(e));
+    return TMC_OK;
+  } catch (...) {
+    return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");
+  }
+}
+
 tmc_status tmc_plan_destroy(tmc_plan_t plan) {
   if (!plan) return TMC_OK;
   try {
@@ -1136,10 +1220,12 @@ tmc_status tmc_gauss_factors(tmc_plan_t plan, const void* z, const void* mu, con
     tmc_plan* P = plan;
     if (plan->prec == TMC_FP64)
       LAUNCH(launch_plain_factor<double>(plan->layers_d, it, plan->factor.n, (const double*)z,
-                                         (const double*)mu, (const double*)s, (double*)f, true, nullptr, st));
+                                         (const double*)mu, (const double*)s, (double*)f, true, nullptr,
+                                         parent_scale(plan), st));
     else
       LAUNCH(launch_plain_factor<float>(plan->layers_d, it, plan->factor.n, (const float*)z,
-                                        (const float*)mu, (const float*)s, (float*)f, true, nullptr, st));
+                                        (const float*)mu, (const float*)s, (float*)f, true, nullptr,
+                                        parent_scale(plan), st));
     return TMC_OK;
   } catch (...) {
     return fail(TMC_ERR_INVALID_ARG, "unexpected host exception");

@@ -25,7 +25,7 @@ hipError_t launch_ds_reduce(const int64_t* part_off, const int* slot_start, cons
 template <typename T>
 hipError_t launch_plain_factor(const LayerDev* layers, const Item* items, int n_items,
                                const T* z, const T* mu, const T* s, T* f, bool caller_off,
-                               double* anchor, hipStream_t st);
+                               double* anchor, bool parent_scale, hipStream_t st);
 template <typename T>
 hipError_t launch_plain_lse_fwd(const LayerDev* layers, const Item* items, int n_items,
                                 int max_kc, int vec, const T* f, bool caller_off, const T* u,
@@ -40,11 +40,12 @@ hipError_t launch_plain_lse_bwd(const LayerDev* layers, const Item* items, int n
 template <typename T>
 hipError_t launch_plain_gmu(const LayerDev* layers, const Item* items, int n_items,
                             const T* g, const T* z, const T* mu, const T* s, const T* p,
-                            const double* dlogp, T* dz, hipStream_t st);
+                            const double* dlogp, T* dz, bool parent_scale, hipStream_t st);
 template <typename T>
 hipError_t launch_plain_gtz(const LayerDev* layers, const Item* items, int n_items,
                             const T* g, const T* z, const T* mu, const T* s, const T* p,
-                            const double* dlogp, T* gtz, T* dmu, hipStream_t st);
+                            const double* dlogp, T* gtz, T* dmu, T* ds_pp, bool parent_scale,
+                            hipStream_t st);
 template <typename T>
 hipError_t launch_pair_dsp(const LayerDev* layers, const int* pair_ids, int n_pairs,
                            const T* z, const T* mu, const T* s, const T* p, const T* gtz,

@@ -1,0 +1,27 @@
+// Log-domain matrix product: argument block and launcher (host runtime and k_logmm.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tmc {
+
+constexpr int kLogmmTile = 64;   // output rows and columns per workgroup of the MFMA pass
+
+struct LogmmArgs {
+  int B, M, K, N;
+  const float* X;    // [B][M][K]  (FP32 and BF16X3)
+  const float* Y;    // [B][K][N]
+  float* Z;          // [B][M][N]
+  float* xs;         // workspace [B][M]: row maxima of X
+  float* ys;         // workspace [B][N]: column maxima of Y
+  const double* Xd;  // FP64
+  const double* Yd;
+  double* Zd;
+};
+
+// Enqueues the whole product on st: FP64 exact per entry; FP32 / BF16X3 shifts, the
+// shifted product on MFMA and the exact fix-up of underflowed entries.
+hipError_t launch_logmm(const LogmmArgs& a, int precision, hipStream_t st);
+
+}  // namespace tmc

@@ -7,9 +7,9 @@
 
 namespace tmc {
 
-constexpr int kStarLanes = 64;     // samples of the lane index per workgroup (one wave wide)
-constexpr int kStarWaves = 8;      // waves per workgroup; they split the other sample index
-constexpr int kStarChunk = 64;     // rows of the other index staged in LDS per step
+constexpr int kStarLanes = 64;     // samples of the lane index per wave
+constexpr int kStarWaves = 4;      // waves per workgroup
+constexpr int kStarRows = 8;       // rows of the other index a wave evaluates per step
 constexpr int kStarMaxD = 32;      // widest local latent
 constexpr int kStarTargetGroups = 2048;   // workgroups the forward grid aims for
 
@@ -17,10 +17,15 @@ constexpr int kStarTargetGroups = 2048;   // workgroups the forward grid aims fo
 //   msg   double [S][N][Kt]        m_i[kt] = logsumexp_k(u_i[k] + f_i[kt, k]) - ln K
 //   gsum  double [S][ngrp][Kt]     sum of m_i[kt] over the points of each point group
 //   w     double [S][Kt]           uth[kt] + sum_i m_i[kt], then the normalised weight
+//   nsh   T      [S][N][Kt]        -(m_i[kt] + ln K - c) log2 e, at most the largest finite
+//                                  T (the exponent offset of the gradient passes)
+//   wT    T      [S][Kt]           the weights in T
 //   lp    double [S]               log P
 //   dm    double [S][ngrp][Kt][D]  per group: sum_i sum_k G_i[kt, k] (z_ik - mth[kt])
 //   dsp   double [S][N][nkb][D]    per (point, block of 64 local samples):
 //                                  sum_{kt, k} G (lam (z - mth)^2 - 1)
+// Point groups: P = max(min(N, kStarWaves), min(N, S N ceil(Kt/64) / kStarTargetGroups))
+// consecutive points; the waves of a group's workgroup take its points in turn.
 template <typename T>
 struct StarArgs {
   int S, N, Kt, K, D;
@@ -35,6 +40,8 @@ struct StarArgs {
   double* msg;
   double* gsum;
   double* w;
+  T* nsh;
+  T* wT;
   double* lp;
   double* dm;
   double* dsp;

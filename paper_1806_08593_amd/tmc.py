@@ -37,7 +37,7 @@ TMC_OK, TMC_ERR_INVALID_ARG, TMC_ERR_SHAPE, TMC_ERR_WORKSPACE = 0, 1, 2, 3
 TMC_ERR_UNSUPPORTED, TMC_ERR_HIP, TMC_ERR_NUMERIC, TMC_ERR_STATE = 4, 5, 6, 7
 TMC_FP64, TMC_FP32, TMC_BF16X3 = 0, 1, 2
 TMC_ENGINE_AUTO, TMC_ENGINE_FUSED, TMC_ENGINE_PLAIN = 0, 1, 2
-TMC_FLAG_FORWARD_ONLY, TMC_FLAG_PERSISTENT = 1, 2
+TMC_FLAG_FORWARD_ONLY, TMC_FLAG_PERSISTENT, TMC_FLAG_PARENT_SCALE = 1, 2, 4
 
 PRECISIONS = {"fp64": TMC_FP64, "fp32": TMC_FP32, "bf16x3": TMC_BF16X3}
 ENGINES = {"auto": TMC_ENGINE_AUTO, "fused": TMC_ENGINE_FUSED, "plain": TMC_ENGINE_PLAIN}
@@ -92,6 +92,9 @@ _SIGS = {
     "tmc_plan_set_timing": (c_int, [_P, c_int]),
     "tmc_plan_timing": (c_int, [_P, c_int, POINTER(c_double), POINTER(c_int64)]),
     "tmc_plan_autotune": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, c_int, _P]),
+    "tmc_logmmexp_workspace_size": (c_int, [c_int32, c_int32, c_int32, c_int32, c_int32,
+                                            POINTER(c_size_t)]),
+    "tmc_logmmexp": (c_int, [c_int32, c_int32, c_int32, c_int32, c_int32, _P, _P, _P, _P, _P]),
     "tmc_star_plan_create": (c_int, [POINTER(tmc_star_problem), c_int, POINTER(c_void_p)]),
     "tmc_star_gauss_fwd": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "tmc_star_gauss_bwd": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -244,6 +247,19 @@ def tmc_plan_autotune(plan, z, mu, s, u, dlogp, workspace, dz=None, dmu=None, ds
                                   _stream(stream)))
 
 
+def tmc_logmmexp_workspace_size(batch, M, K, N, precision) -> int:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else precision
+    n = c_size_t()
+    _check(_lib.tmc_logmmexp_workspace_size(batch, M, K, N, prec, ctypes.byref(n)))
+    return n.value
+
+
+def tmc_logmmexp(batch, M, K, N, precision, X, Y, Z, workspace, stream=None):
+    prec = PRECISIONS[precision] if isinstance(precision, str) else precision
+    _check(_lib.tmc_logmmexp(batch, M, K, N, prec, _ptr(X), _ptr(Y), _ptr(Z), _ptr(workspace),
+                             _stream(stream)))
+
+
 def tmc_star_plan_create(problem: "StarProblem", device: int = 0) -> int:
     h = c_void_p()
     _check(_lib.tmc_star_plan_create(ctypes.byref(problem.c), device, ctypes.byref(h)))
@@ -305,15 +321,17 @@ def homogeneous_problem(B, L, K, D, precision="fp32", engine="auto", flags=0,
                         exponent=1.0) -> Problem:
     """B chains of L layers, K samples and width D each, laid out as
     z [B, L, K, D], mu [B, L-1, K, D], s [L-1, D] (shared by the batch),
-    u [B, L, K] and f [B, L-1, K, K]."""
+    u [B, L, K] and f [B, L-1, K, K].  With TMC_FLAG_PARENT_SCALE in flags, s is
+    [B, L-1, K, D] (one row per parent sample, the layout of mu)."""
+    pp = bool(flags & TMC_FLAG_PARENT_SCALE)
     layers, chains = [], []
     for b in range(B):
         chains.append((b * L, L))
         for l in range(L):
             top = l == L - 1
+            mo = 0 if top else ((b * (L - 1) + l) * K) * D
             layers.append(dict(K=K, D=D, z_off=((b * L + l) * K) * D, u_off=(b * L + l) * K,
-                               mu_off=0 if top else ((b * (L - 1) + l) * K) * D,
-                               s_off=0 if top else l * D,
+                               mu_off=mo, s_off=0 if top else (mo if pp else l * D),
                                f_off=0 if top else ((b * (L - 1) + l) * K) * K))
     return Problem(chains, layers, precision, engine, flags, exponent)
 
@@ -321,7 +339,9 @@ def homogeneous_problem(B, L, K, D, precision="fp32", engine="auto", flags=0,
 def ragged_problem(shapes, precision="fp32", engine="auto", flags=0, share_s=False, exponent=1.0):
     """Chains given as a list of (K_list, D_list) (one entry per layer), packed
     back to back in flat z, mu, s, u and f buffers.  Returns (problem, sizes) with
-    sizes the element counts of the flat buffers."""
+    sizes the element counts of the flat buffers.  With TMC_FLAG_PARENT_SCALE in flags
+    each s block is [K_{l+1}][D_l]."""
+    pp = bool(flags & TMC_FLAG_PARENT_SCALE)
     layers, chains = [], []
     zo = uo = mo = so = fo = 0
     for Ks, Ds in shapes:
@@ -335,7 +355,7 @@ def ragged_problem(shapes, precision="fp32", engine="auto", flags=0, share_s=Fal
             if not top:
                 d.update(mu_off=mo, s_off=so, f_off=fo)
                 mo += Ks[l + 1] * Ds[l]
-                so += Ds[l]
+                so += (Ks[l + 1] if pp else 1) * Ds[l]
                 fo += Ks[l] * Ks[l + 1]
             layers.append(d)
     return (Problem(chains, layers, precision, engine, flags, exponent),

@@ -1,0 +1,113 @@
+"""GPU parity of the log-domain matrix product (tmc_logmmexp) against the FP64 oracle,
+element by element: shapes with ragged 64 x 64 output tiles and 32-wide reduction steps,
+batches, every precision, -inf rows and columns, NaN, and entries where the Appendix's
+per-operand shift underflows (recomputed exactly by the fix-up pass)."""
+import numpy as np
+import pytest
+
+from oracle import tmc_oracle as O
+from tests.gpu_helpers import to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# |Z - oracle| <= TOL + REL |Z|: FP64 exact per entry; FP32 MFMA: FP32 exponentials and
+# products (relative error of C ~1e-6 over K terms; measured 2.7e-6); BF16X3: hi/lo
+# products (~2^-16 per product; measured 2.0e-5); REL: a few units in the last place of the
+# output type, for entries of large magnitude (the exact fix-up at Z ~ -400 in FP32).
+TOL = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 1e-4}
+REL = {"fp64": 4e-16, "fp32": 4e-7, "bf16x3": 4e-7}
+
+
+def run(X, Y, prec):
+    from paper_1806_08593_amd import tmc as T
+    B, M, K = X.shape
+    N = Y.shape[2]
+    dt = np.float64 if prec == "fp64" else np.float32
+    x, y = to_dev(X.astype(dt)), to_dev(Y.astype(dt))
+    z = torch.full((B, M, N), float("nan"), dtype=x.dtype, device="cuda:0")
+    nb = T.tmc_logmmexp_workspace_size(B, M, K, N, prec)
+    ws = torch.empty(max(nb, 256) + 256, dtype=torch.uint8, device="cuda:0")
+    off = (-ws.data_ptr()) % 256
+    T.tmc_logmmexp(B, M, K, N, prec, x, y, z, ws.data_ptr() + off)
+    torch.cuda.synchronize()
+    return z.cpu().numpy().astype(np.float64)
+
+
+def ref(X, Y, prec):
+    dt = np.float64 if prec == "fp64" else np.float32
+    return O.logmmexp(X.astype(dt).astype(np.float64), Y.astype(dt).astype(np.float64))
+
+
+def check(got, want, prec, label):
+    fin = np.isfinite(want)
+    assert np.array_equal(np.isfinite(got), fin), label
+    assert np.array_equal(np.isnan(got), np.isnan(want)), label
+    assert np.all(got[~fin & ~np.isnan(want)] == want[~fin & ~np.isnan(want)]), label
+    d = np.abs(got[fin] - want[fin])
+    bound = TOL[prec] + REL[prec] * np.abs(want[fin])
+    err = float(np.max(d)) if fin.any() else 0.0
+    print(f"ERRREC logmm-{label} {err:.3e}")
+    assert np.all(d <= bound), (label, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (3, 70, 45, 130), (2, 64, 64, 64), (1, 129, 33, 65),
+                                   (1, 5, 300, 7), (2, 200, 96, 3)])
+def test_logmm_matches_oracle(prec, shape):
+    B, M, K, N = shape
+    rng = np.random.default_rng(sum(shape))
+    X = rng.normal(size=(B, M, K)) * 4 - 10
+    Y = rng.normal(size=(B, K, N)) * 4 + 3
+    check(run(X, Y, prec), ref(X, Y, prec), prec, f"{prec}-{shape}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_logmm_underflowing_shift_and_infinities(prec):
+    """Rows of X peaking at small j and columns of Y peaking at large j by hundreds of nats
+    (the shifted product underflows; the fix-up pass recomputes those entries), plus an
+    all -inf row of X, an all -inf column of Y and a NaN entry."""
+    rng = np.random.default_rng(7)
+    B, M, K, N = 2, 40, 70, 50
+    X = rng.normal(size=(B, M, K))
+    Y = rng.normal(size=(B, K, N))
+    X[:, :10, 35:] -= 400.0          # rows 0..9 peak in j < 35
+    Y[:, :35, :12] -= 400.0          # columns 0..11 peak in j >= 35
+    X[0, 20, :] = -np.inf
+    Y[1, :, 30] = -np.inf
+    X[1, 33, 5] = np.nan
+    want = ref(X, Y, prec)
+    assert np.all(want[:, :10, :12] < -300)   # the entries the shift loses
+    check(run(X, Y, prec), want, prec, f"{prec}-underflow")
+
+
+def test_logmm_chain_of_products_is_the_discrete_estimator():
+    """Several discrete chains at once: the running products of their log-factor matrices
+    on the GPU give each chain's estimator of eq. (is) (oracle by enumeration)."""
+    rng = np.random.default_rng(9)
+    K = (40, 70, 33, 64)
+    C = 3
+    chains = []
+    for c in range(C):
+        f = [rng.normal(size=(K[l], K[l + 1])) * 2 for l in range(3)]
+        u = [rng.normal(size=k) for k in K]
+        chains.append((f, u))
+    prod = None
+    for l in range(3):
+        Ml = np.stack([ch[1][l][:, None] + ch[0][l] - np.log(K[l + 1]) for ch in chains])
+        prod = Ml if prod is None else run(prod, Ml, "fp64")
+    top = np.stack([ch[1][3] for ch in chains])[:, :, None]
+    col = run(prod, top, "fp64")[:, :, 0]
+    got = O.logsumexp(col, axis=1) - np.log(K[0])
+    for c, (f, u) in enumerate(chains):
+        assert abs(got[c] - O.chain_logp(f, u)) < 1e-10
+
+
+def test_logmm_rejects_bad_arguments():
+    from paper_1806_08593_amd import tmc as T
+    with pytest.raises(T.TMCError) as ei:
+        T.tmc_logmmexp_workspace_size(1, 0, 4, 4, "fp32")
+    assert ei.value.status == T.TMC_ERR_SHAPE
+    with pytest.raises(T.TMCError) as ei:
+        T.tmc_logmmexp(1, 4, 4, 4, "fp32", 1, 1, 1, None)
+    assert ei.value.status == T.TMC_ERR_WORKSPACE

@@ -91,8 +91,7 @@ def test_star_parity_small(prec, D):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_star_parity_groups(prec):
-    """Enough points that the forward groups several per workgroup (N K_theta blocks =
-    6002 > 2048: 2 points per group, the last group with one)."""
+    """Many points: groups of four (one per wave), the last group with one point."""
     w = gauss_star(S=1, N=3001, Kt=100, K=20, D=2, kind="general")
     out = run_star(w, prec)
     assert out["plan"].workspace_bytes > 0

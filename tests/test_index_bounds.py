@@ -466,29 +466,31 @@ def test_replica_detects_unclamped_rows(monkeypatch):
 # star-model kernels
 # ---------------------------------------------------------------------------
 
-STAR_LANES, STAR_WAVES, STAR_CHUNK, STAR_TARGET = 64, 8, 64, 2048
+STAR_LANES, STAR_WAVES, STAR_TARGET = 64, 4, 2048
 
 
 def star_layout(S, N, Kt, K, D):
     """The plan's point grouping (points per group P, groups, local-sample blocks)."""
     nkt = cdiv(Kt, STAR_LANES)
-    P = max(1, min(N, S * N * nkt // STAR_TARGET))
+    P = max(min(N, STAR_WAVES), min(N, S * N * nkt // STAR_TARGET))
     return dict(S=S, N=N, Kt=Kt, K=K, D=D, P=P, ngrp=cdiv(N, P), nkb=cdiv(K, STAR_LANES), nkt=nkt)
 
 
 def check_star(S, N, Kt, K, D):
-    """Every global access of the six star kernels, per workgroup (vectorised over its
-    threads), against the caller's buffers and the workspace arrays."""
+    """Every global access of the six star kernels, per wave (vectorised over its lanes;
+    rows that a whole wave reads are scalar loads at one address), against the caller's
+    buffers and the workspace arrays."""
     a = star_layout(S, N, Kt, K, D)
     P, ngrp, nkb, nkt = a["P"], a["ngrp"], a["nkb"], a["nkt"]
     B = Buffers(mth=S * Kt * D, s=S * D, z=S * N * K * D, u=S * N * K, uth=S * Kt,
                 msg=S * N * Kt, gsum=S * ngrp * Kt, w=S * Kt, dm=S * ngrp * Kt * D,
                 dsp=S * N * nkb * D, dz=S * N * K * D, du=S * N * K, dmth=S * Kt * D,
-                ds=S * D, duth=S * Kt)
-    tid = np.arange(STAR_LANES * STAR_WAVES)
-    lane = tid % WAVE
+                ds=S * D, duth=S * Kt, nsh=S * N * Kt, wT=S * Kt)
+    lane = np.arange(STAR_LANES)
+    stride = 1 if D == 1 else D
     assert S * ngrp < 2 ** 31 and nkt <= 65535 and nkb <= 65535
-    # k_star_msg and k_star_bwd_global: grid (S ngrp, nkt), lane -> kt, points of a group
+    # k_star_msg and k_star_bwd_global: grid (S ngrp, nkt) of 4 waves, lane -> kt; wave wv
+    # walks points grp P + wv, + 4, ... and all K rows of each (scalar loads)
     for bx in range(S * ngrp):
         inst, grp = bx // ngrp, bx % ngrp
         assert inst < S
@@ -497,52 +499,58 @@ def check_star(S, N, Kt, K, D):
             ktv = kt < Kt
             for d in range(D):
                 B.check("mth", (inst * Kt + kt) * D + d, mask=ktv)
-            B.check("w", inst * Kt + kt, mask=ktv)
-            B.check("gsum", (inst * ngrp + grp) * Kt + kt, mask=ktv)
-            for d in range(D):
                 B.check("dm", ((inst * ngrp + grp) * Kt + kt) * D + d, mask=ktv)
-            for pt in range(grp * P, min(N, grp * P + P)):
-                pi = inst * N + pt
-                B.check("msg", pi * Kt + kt, mask=ktv)
-                for k0 in range(0, K, STAR_CHUNK):
-                    nk = min(STAR_CHUNK, K - k0)
-                    e = np.arange(nk * D)
-                    B.check("z", pi * K * D + k0 * D + e, block=(pi * K * D, (pi + 1) * K * D))
-                    B.check("u", pi * K + k0 + np.arange(nk), block=(pi * K, (pi + 1) * K))
-                    assert (e // D).max() < STAR_CHUNK
-    # k_star_colsum: grid (S, nkt)
+            B.check("wT", inst * Kt + kt, mask=ktv)
+            B.check("gsum", (inst * ngrp + grp) * Kt + kt, mask=ktv)
+            for wv in range(STAR_WAVES):
+                for pt in range(grp * P + wv, min(N, (grp + 1) * P), STAR_WAVES):
+                    pi = inst * N + pt
+                    B.check("msg", pi * Kt + kt, mask=ktv)
+                    B.check("nsh", pi * Kt + kt, mask=ktv)
+                    k = np.arange(K)
+                    zb = (pi * K * D, (pi + 1) * K * D)
+                    for d in range(D):
+                        B.check("z", pi * K * D + k * stride + d, block=zb)
+                    B.check("u", pi * K + k, block=(pi * K, (pi + 1) * K))
+    # k_star_colsum: grid (S, nkt); lanes past Kt read column 0
     for inst in range(S):
         for by in range(nkt):
             kt = by * STAR_LANES + lane
+            kc = np.where(kt < Kt, kt, 0)
             for g in range(ngrp):
-                B.check("gsum", (inst * ngrp + g) * Kt + kt, mask=kt < Kt)
+                B.check("gsum", (inst * ngrp + g) * Kt + kc)
             B.check("uth", inst * Kt + kt, mask=kt < Kt)
-    # k_star_bwd_local: grid (S N, nkb), lane -> k, staged chunks of the global samples
-    for pi in range(S * N):
+    # k_star_bwd_local: one wave per (instance and point, 64 local samples), grid of 4-wave
+    # workgroups over the S N nkb tasks (waves past the last task return at once)
+    tasks = S * N * nkb
+    for task in range(cdiv(tasks, STAR_WAVES) * STAR_WAVES):
+        if task >= tasks:
+            continue
+        pi, kb = task // nkb, task % nkb
         inst = pi // N
-        for kb in range(nkb):
-            k = kb * STAR_LANES + lane
-            kv = k < K
-            for d in range(D):
-                B.check("z", (pi * K + k) * D + d, mask=kv)
-                B.check("dz", (pi * K + k) * D + d, mask=kv)
-                B.check("dsp", (pi * nkb + kb) * D + d)
-            B.check("u", pi * K + k, mask=kv)
-            B.check("du", pi * K + k, mask=kv)
-            for t0 in range(0, Kt, STAR_CHUNK):
-                nt = min(STAR_CHUNK, Kt - t0)
-                B.check("mth", inst * Kt * D + t0 * D + np.arange(nt * D))
-                B.check("w", inst * Kt + t0 + np.arange(nt))
-                B.check("msg", pi * Kt + t0 + np.arange(nt), block=(pi * Kt, (pi + 1) * Kt))
-    # k_star_reduce: grid (S, ceil(Kt D / 64) + 1)
+        k = kb * STAR_LANES + lane
+        kv = k < K
+        for d in range(D):
+            B.check("z", (pi * K + k) * D + d, mask=kv)
+            B.check("dz", (pi * K + k) * D + d, mask=kv)
+            B.check("dsp", (pi * nkb + kb) * D + d)
+        B.check("u", pi * K + k, mask=kv)
+        B.check("du", pi * K + k, mask=kv)
+        t = np.arange(Kt)
+        for d in range(D):
+            B.check("mth", inst * Kt * D + t * stride + d, block=(inst * Kt * D, (inst + 1) * Kt * D))
+        B.check("wT", inst * Kt + t)
+        B.check("nsh", pi * Kt + t, block=(pi * Kt, (pi + 1) * Kt))
+    # k_star_reduce: grid (S, ceil(Kt D / 64) + 1); lanes past Kt D read entry 0
     KD = Kt * D
     ny = cdiv(KD, STAR_LANES) + 1
     assert ny <= 65535
     for inst in range(S):
         for by in range(ny - 1):
             e = by * STAR_LANES + lane
+            ec = np.where(e < KD, e, 0)
             for gi in range(ngrp):
-                B.check("dm", (inst * ngrp + gi) * KD + e, mask=e < KD)
+                B.check("dm", (inst * ngrp + gi) * KD + ec)
             B.check("dmth", inst * KD + e, mask=e < KD)
             B.check("s", inst * D + e % D, mask=e < KD)
         j = np.arange(N * nkb)
@@ -551,22 +559,26 @@ def check_star(S, N, Kt, K, D):
             B.check("ds", inst * D + d)
         B.check("duth", inst * Kt + np.arange(Kt))
         B.check("w", inst * Kt + np.arange(Kt))
+        B.check("wT", inst * Kt + np.arange(Kt))
     assert not B.bad, B.bad[:5]
     return a
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1, 1, 1), (2, 37, 150, 100, 3), (1, 3001, 100, 20, 2),
-                                   (3, 5, 64, 128, 32), (1, 4, 65, 129, 16), (2, 2, 1, 1, 7)])
+                                   (3, 5, 64, 128, 32), (1, 4, 65, 129, 16), (2, 2, 1, 1, 7),
+                                   (1, 9, 70, 13, 1)])
 def test_star_accesses_in_bounds(shape):
     check_star(*shape)
 
 
 def test_star_grouping():
-    """Point groups: one point each while the grid is small, several once the forward grid
-    would exceed the target (the last group ragged), never more than N."""
-    assert star_layout(2, 37, 150, 100, 3)["P"] == 1
+    """Point groups: at least one point per wave, more once the forward grid would exceed
+    the target (the last group ragged), never more than N."""
+    assert star_layout(2, 37, 150, 100, 3)["P"] == 4
     a = star_layout(1, 3001, 100, 20, 2)
-    assert (a["P"], a["ngrp"]) == (2, 1501)
+    assert (a["P"], a["ngrp"]) == (4, 751)
     a = star_layout(1, 4096, 128, 128, 1)
     assert (a["P"], a["ngrp"]) == (4, 1024)
-    assert star_layout(1, 5, 64 * 5000, 8, 1)["P"] == 5
+    a = star_layout(1, 9000, 128, 128, 1)
+    assert (a["P"], a["ngrp"]) == (8, 1125)
+    assert star_layout(1, 2, 64 * 5000, 8, 1)["P"] == 2

@@ -19,6 +19,10 @@ def _mutant(func_name, old, new):
 
 
 MUTATIONS = [
+    ("logmmexp", "Y[..., None, :, :], axis=-2)", "Y[..., None, :, :], axis=-1)",
+     P.test_logmmexp_equals_scipy_and_matrix_product),
+    ("logmmexp", "X[..., :, :, None] + Y[..., None, :, :]", "X[..., :, :, None] + np.swapaxes(Y, -1, -2)[..., None, :, :]",
+     P.test_logmmexp_chain_is_the_discrete_tmc_estimator),
     ("gauss_pair_logfactor_pp", "-np.sum(sp, axis=1)", "-np.sum(sp, axis=0).sum() / sp.shape[0]",
      P.test_pp_factor_equals_scipy_normal_logpdf),
     ("gauss_pair_logfactor_pp", "lam[None, :, :] * diff * diff", "lam[None, :, :].mean(axis=1, keepdims=True) * diff * diff",

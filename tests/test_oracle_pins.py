@@ -549,3 +549,57 @@ def test_pp_gradients_against_finite_differences():
         fd = O.finite_difference(lambda a: O.gauss_chain_logp_pp(z, mu, with_(sp, l, a), u), sp[l])
         np.testing.assert_allclose(dsp[l].reshape(-1), fd, atol=2e-7)
     assert np.all(dz[L - 1] == 0)
+
+
+# --- log-domain matrix product (matrix-matrix form) ------------------------------
+
+def test_logmmexp_equals_scipy_and_matrix_product():
+    """Against scipy's logsumexp written per entry, and against log(exp(X) @ exp(Y)) where
+    the plain product cannot under- or overflow."""
+    rng = np.random.default_rng(51)
+    X = rng.normal(size=(2, 5, 7)) * 3
+    Y = rng.normal(size=(2, 7, 4)) * 3
+    Z = O.logmmexp(X, Y)
+    for b in range(2):
+        for i in range(5):
+            for k in range(4):
+                assert abs(Z[b, i, k] - special.logsumexp(X[b, i, :] + Y[b, :, k])) < 1e-12
+    np.testing.assert_allclose(Z, np.log(np.exp(X) @ np.exp(Y)), rtol=1e-12, atol=1e-12)
+
+
+def test_logmmexp_chain_is_the_discrete_tmc_estimator():
+    """Summing a discrete chain's indices with matrix-matrix log-products (several chains
+    at once, their messages as columns) gives the chain estimator of eq. (is) of each."""
+    rng = np.random.default_rng(52)
+    K = (4, 5, 3)
+    chains = []
+    for c in range(3):
+        f = [rng.normal(size=(K[l], K[l + 1])) for l in range(2)]
+        u = [rng.normal(size=k) for k in K]
+        chains.append((f, u))
+    # M[l][i, j] = u_l[i] + f_l[i, j] - ln K_{l+1}: one chain per batch entry
+    prod = None
+    for l in range(2):
+        M = np.stack([ch[1][l][:, None] + ch[0][l] - O.log_k(K[l + 1]) for ch in chains])
+        prod = M if prod is None else O.logmmexp(prod, M)
+    top = np.stack([ch[1][2] for ch in chains])[:, :, None]            # [c, K_top, 1]
+    col = O.logmmexp(prod, top)[:, :, 0]                               # [c, K_0]
+    got = O.logsumexp(col, axis=1) - O.log_k(K[0])
+    for c, (f, u) in enumerate(chains):
+        assert abs(got[c] - O.brute_force_logp(f, u)) < 1e-11
+
+
+def test_logmmexp_where_the_operand_shift_underflows():
+    """X_i peaks at j = 0 and Y_k at j = 1: every product of the per-operand shifted
+    exponentials underflows (the Appendix's form gives -inf), while the exact value is
+    finite: max_j (X_ij + Y_jk) = -800."""
+    X = np.array([[0.0, -900.0]])
+    Y = np.array([[-800.0], [0.0]])
+    with np.errstate(over="ignore", under="ignore"):
+        assert O.logmmexp_shifted(X, Y)[0, 0] == -np.inf
+    z = O.logmmexp(X, Y)[0, 0]
+    assert abs(z - (-800.0 + np.log1p(np.exp(-100.0)))) < 1e-12
+    # all -inf rows and columns give -inf, never NaN
+    X2 = np.array([[-np.inf, -np.inf], [0.0, 1.0]])
+    Z2 = O.logmmexp(X2, np.zeros((2, 3)))
+    assert np.all(Z2[0] == -np.inf) and np.all(np.isfinite(Z2[1]))
