@@ -3,7 +3,7 @@ the FP64 oracle on the same cast inputs, through the C ABI.
 
 Tolerances on log P per instance: FP32 1e-4 absolute, BF16X3 2e-3 absolute.
 Gradients against the oracle's closed-form gradients, per layer block: relative L2
-(FP32 1e-3, BF16X3 1e-2) and element by element (GRAD_ELEM_TOL: every element within
+(FP32 1e-4, BF16X3 1e-2) and element by element (GRAD_ELEM_TOL: every element within
 a fraction of the block's largest reference value plus a relative term)."""
 import numpy as np
 import pytest
@@ -17,7 +17,7 @@ from .gpu_helpers import (GRAD_ELEM_TOL, assert_elem, cast_chains, oracle_grads,
 pytestmark = pytest.mark.gpu
 
 LOGP_TOL = {"fp32": 1e-4, "bf16x3": 2e-3}
-GRAD_TOL = {"fp32": 1e-3, "bf16x3": 1e-2}
+GRAD_TOL = {"fp32": 1e-4, "bf16x3": 1e-2}   # relative L2 per layer block (and GRAD_ELEM_TOL per element)
 
 
 def _rand_chain(rng, Ks, Ds):
@@ -160,7 +160,7 @@ def test_fused_shared_s_autograd():
     chains = cast_chains(w.chains, "fp32")
     ref = oracle_grads(chains)
     ds_ref = sum(np.stack(r[3]) for r in ref)
-    assert rel_l2(t["s"].grad.cpu().numpy(), ds_ref) < 1e-3
+    assert rel_l2(t["s"].grad.cpu().numpy(), ds_ref) < 1e-4
     for b in range(B):
         assert abs(logp[b].item() - ref[b][0]) < 1e-4
 
