@@ -1,4 +1,4 @@
-"""torch.autograd wrapper of the Gaussian-chain TMC estimator.
+"""torch.autograd wrappers of the Gaussian-chain TMC estimator (and of the DReGs surrogate).
 
 Only marshalling: the forward and backward passes are the library's tmc_gauss_fwd /
 tmc_gauss_bwd kernels.  torch provides device memory, the stream, and carries the
@@ -7,6 +7,7 @@ caller's parameters and of the reparameterised samples z).
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import tmc as T
@@ -63,6 +64,61 @@ class RaggedGaussChainTMC:
             if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
                 raise ValueError(f"{name}: needs a contiguous {self.dtype} tensor on {self.device}")
         return _GaussChainFn.apply(z, mu, s, u, self)
+
+
+class GaussChainDReGs:
+    """The DReGs surrogate of the Appendix "Combining DReGs and TMC" for a homogeneous batch:
+        S = 1/2 stopgrad(sum_t w_t^2 / (sum_t w_t)^2) log sum_t w_t^2     (per chain)
+    over the importance weights w_t of every index tuple t, whose gradient is the DReGs
+    estimator (the caller stops the direct dependence of u on the proposal parameters).
+    A forward with kappa = 1 gives log P_1 and a forward with kappa = 2 (the squared
+    weights) log P_2 = log sum_t w_t^2 - sum_l ln K_l; the coefficient is
+    c = exp(log P_2 - 2 log P_1 - sum_l ln K_l), S = c (log P_2 + sum_l ln K_l) / 2, and the
+    backward is the kappa = 2 backward with upstream gradient c g / 2.  Same shapes as
+    GaussChainTMC; returns S [B] (float64)."""
+
+    def __init__(self, B, L, K, D, precision="fp32", engine="auto", device=0):
+        self.shape = (B, L, K, D)
+        self.plan1 = T.Plan(T.homogeneous_problem(B, L, K, D, precision, engine,
+                                                  T.TMC_FLAG_FORWARD_ONLY, exponent=1.0), device)
+        self.plan2 = T.Plan(T.homogeneous_problem(B, L, K, D, precision, engine, 0, exponent=2.0),
+                            device)
+        self.dtype = _DT[self.plan2.problem.c.precision]
+        self.device = torch.device(f"cuda:{device}")
+        self.sum_log_k = L * float(np.log(K))
+
+    def __call__(self, z, mu, s, u):
+        GaussChainTMC._check(self, z, mu, s, u)
+        return _DReGsFn.apply(z, mu, s, u, self)
+
+
+class _DReGsFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, z, mu, s, u, runner: GaussChainDReGs):
+        B = runner.shape[0]
+        lp1 = torch.empty(B, dtype=torch.float64, device=z.device)
+        lp2 = torch.empty(B, dtype=torch.float64, device=z.device)
+        ws1 = runner.plan1.new_workspace()
+        T.tmc_gauss_fwd(runner.plan1.handle, z, mu, s, u, lp1, ws1)
+        ws2 = runner.plan2.new_workspace()
+        T.tmc_gauss_fwd(runner.plan2.handle, z, mu, s, u, lp2, ws2)
+        c = torch.exp(lp2 - 2.0 * lp1 - runner.sum_log_k)
+        ctx.save_for_backward(z, mu, s, u, c)
+        ctx.ws2 = ws2
+        ctx.runner = runner
+        return 0.5 * c * (lp2 + runner.sum_log_k)
+
+    @staticmethod
+    def backward(ctx, g):
+        z, mu, s, u, c = ctx.saved_tensors
+        dlogp = (0.5 * c * g.to(torch.float64)).contiguous()
+        need = ctx.needs_input_grad
+        dz = torch.empty_like(z) if need[0] else None
+        dmu = torch.empty_like(mu) if need[1] else None
+        ds = torch.empty_like(s) if need[2] else None
+        du = torch.empty_like(u) if need[3] else None
+        T.tmc_gauss_bwd(ctx.runner.plan2.handle, z, mu, s, u, dlogp, ctx.ws2, dz, dmu, ds, du)
+        return dz, dmu, ds, du, None
 
 
 class _GaussChainFn(torch.autograd.Function):

@@ -26,7 +26,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = kLogmmTile;   // output rows and columns of a workgroup
 constexpr int kKC = 32;             // reduction indices staged per step
-constexpr int kPadB = 8;            // bf16 row padding of the LDS tiles
+constexpr int kPadB = 8;            // bf16 row padding of the LDS tiles (16 B)
 constexpr int kPadF = 4;            // float row padding
 constexpr float kLogmmFloor = -60.0f;
 
@@ -51,29 +51,32 @@ struct LogmmSmem<TMC_FP32> {
   float b[kTile][kKC + kPadF];
 };
 
-// Stores 8 consecutive reduction-index values of one row of a tile.
+// Stores 16 consecutive reduction-index values of one row (column) of a staged tile.
 template <int PREC>
-__device__ __forceinline__ void stage8(LogmmSmem<PREC>& S, bool is_a, int row, int j, const float (&v)[8]) {
+__device__ __forceinline__ void stage16(LogmmSmem<PREC>& S, bool is_a, int row, int j, const float (&v)[16]) {
   if constexpr (PREC == TMC_BF16X3) {
-    uint32_t h[4], l[4];
+    uint32_t h[8], l[8];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) split_pair(v[2 * p], v[2 * p + 1], h[p], l[p]);
+    for (int p = 0; p < 8; ++p) split_pair(v[2 * p], v[2 * p + 1], h[p], l[p]);
     __bf16* hp = is_a ? &S.a[0][row][j] : &S.b[0][row][j];
     __bf16* lp = is_a ? &S.a[1][row][j] : &S.b[1][row][j];
     *reinterpret_cast<u32x4*>(hp) = (u32x4){h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<u32x4*>(hp + 8) = (u32x4){h[4], h[5], h[6], h[7]};
     *reinterpret_cast<u32x4*>(lp) = (u32x4){l[0], l[1], l[2], l[3]};
+    *reinterpret_cast<u32x4*>(lp + 8) = (u32x4){l[4], l[5], l[6], l[7]};
   } else {
     float* p = is_a ? &S.a[row][j] : &S.b[row][j];
-    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
-    *reinterpret_cast<float4*>(p + 4) = make_float4(v[4], v[5], v[6], v[7]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<float4*>(p + 4 * q) = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
   }
 }
 
 }  // namespace
 
 // Shifts: xs[b][i] = max_j X_b[i,j] (a wave per row, lanes over j) and ys[b][k] =
-// max_j Y_b[j,k] (a thread per column); an all -inf row or column gets 0 (its
-// exponentials are then 0, never NaN).
+// max_j Y_b[j,k] (below); an all -inf row or column gets 0 (its exponentials are then 0,
+// never NaN).
 __global__ __launch_bounds__(256) void k_logmm_rowmax(LogmmArgs a) {
   const int b = blockIdx.z;
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
@@ -85,23 +88,44 @@ __global__ __launch_bounds__(256) void k_logmm_rowmax(LogmmArgs a) {
   if (threadIdx.x % kWave == 0) a.xs[(int64_t)b * a.M + row] = (m == -INFINITY) ? 0.0f : m;
 }
 
-__global__ __launch_bounds__(256) void k_logmm_colmax(LogmmArgs a) {
+// Column maxima: a workgroup of 16 waves per 64 columns (lane -> column), wave w takes
+// rows w, w + 16, .. (loads issued 8 at a time); the waves' maxima are merged in LDS.
+__global__ __launch_bounds__(1024) void k_logmm_colmax(LogmmArgs a) {
+  __shared__ float part[16][kWave];
   const int b = blockIdx.z;
-  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (col >= a.N) return;
-  const float* y = a.Y + (int64_t)b * a.K * a.N + col;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int64_t col = (int64_t)blockIdx.x * kWave + lane;
+  const bool cv = col < a.N;
+  const float* y = a.Y + (int64_t)b * a.K * a.N + (cv ? col : 0);
   float m = -INFINITY;
-  for (int j = 0; j < a.K; ++j) m = nan_max(m, y[(int64_t)j * a.N]);
-  a.ys[(int64_t)b * a.N + col] = (m == -INFINITY) ? 0.0f : m;
+  constexpr int U = 8;
+  for (int j0 = w; j0 < a.K; j0 += 16 * U) {
+    float v[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int j = j0 + 16 * q;
+      v[q] = j < a.K ? y[(int64_t)j * a.N] : -INFINITY;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) m = nan_max(m, v[q]);
+  }
+  part[w][lane] = m;
+  __syncthreads();
+  if (w == 0 && cv) {
+#pragma unroll
+    for (int q = 1; q < 16; ++q) m = nan_max(m, part[q][lane]);
+    a.ys[(int64_t)b * a.N + col] = (m == -INFINITY) ? 0.0f : m;
+  }
 }
 
-// The shifted product on MFMA: a workgroup of 4 waves per 64 x 64 output tile (wave w:
-// rows 32 (w / 2), columns 32 (w % 2)), the reduction index staged 32 at a time.  Thread
-// t stages row t / 4 of the X tile and column t % 64 of the Y tile, 8 consecutive j each,
-// as exponentials of the shifted values (0 past the matrix edges).  Operand fragments:
-// lane l holds row (column) l % 32 and j = 16 s + 8 (l / 32) .. + 7 of step s (both
-// operands in that order); accumulator value v of lane l is row 8 (v / 4) + 4 (l / 32)
-// + v % 4, column l % 32.
+// The shifted product on MFMA: a workgroup of 4 waves per 128 x 128 output tile (wave w:
+// rows 64 (w / 2), columns 64 (w % 2), as 2 x 2 accumulators of 32 x 32), the reduction
+// index staged 32 at a time.  Thread t stages row t / 2 of the X tile and column t % 128
+// of the Y tile, 16 consecutive j each, as exponentials of the shifted values (0 past the
+// matrix edges); the global loads of the next slice are issued before the current
+// slice's MFMAs.  Operand fragments: lane l holds row (column) l % 32 of its block and
+// j = 16 s + 8 (l / 32) .. + 7 of step s (both operands in that order); accumulator
+// value v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
   __shared__ LogmmSmem<PREC> S;
@@ -112,58 +136,99 @@ __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
   const float* X = a.X + (int64_t)b * M * K;
   const float* Y = a.Y + (int64_t)b * K * N;
   // staging roles
-  const int ar = t / 4, ajg = (t % 4) * 8;          // X tile row, first j
-  const int bc = t % kTile, bjg = (t / kTile) * 8;  // Y tile column, first j
+  const int ar = t / 2, ajg = (t % 2) * 16;          // X tile row, first j
+  const int bc = t % kTile, bjg = (t / kTile) * 16;  // Y tile column, first j
   const int ai = i0 + ar, bk = k0 + bc;
-  const float xsh = ai < M ? a.xs[(int64_t)b * M + ai] : 0.0f;
-  const float ysh = bk < N ? a.ys[(int64_t)b * N + bk] : 0.0f;
-  const float* xrow = X + (int64_t)(ai < M ? ai : 0) * K;
-  const float* ycol = Y + (bk < N ? bk : 0);
-  f32x16 acc = {};
-  const int wr = 32 * (w / 2), wc = 32 * (w % 2);
-  for (int j0 = 0; j0 < K; j0 += kKC) {
-    float va[8], vb[8];
+  const bool av = ai < M, bv = bk < N;
+  const float xsh = av ? a.xs[(int64_t)b * M + ai] : 0.0f;
+  const float ysh = bv ? a.ys[(int64_t)b * N + bk] : 0.0f;
+  const float* xrow = X + (int64_t)(av ? ai : 0) * K;
+  const float* ycol = Y + (bv ? bk : 0);
+  float ra[16], rb[16];   // raw values of the next slice (clamped addresses, masked below)
+  auto fetch = [&](int j0) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const int ja = j0 + ajg + s, jb = j0 + bjg + s;
-      va[s] = (ai < M && ja < K) ? __expf(xrow[ja] - xsh) : 0.0f;
-      vb[s] = (bk < N && jb < K) ? __expf(ycol[(int64_t)jb * N] - ysh) : 0.0f;
+    for (int s = 0; s < 16; ++s) {
+      const int ja = min(j0 + ajg + s, K - 1), jb = min(j0 + bjg + s, K - 1);
+      ra[s] = xrow[ja];
+      rb[s] = ycol[(int64_t)jb * N];
     }
-    __syncthreads();   // (the previous step's fragment reads are done)
-    stage8<PREC>(S, true, ar, ajg, va);
-    stage8<PREC>(S, false, bc, bjg, vb);
+  };
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = (f32x16){};
+  const int wr = 64 * (w / 2), wc = 64 * (w % 2);
+  fetch(0);
+  for (int j0 = 0; j0 < K; j0 += kKC) {
+    float va[16], vb[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      va[s] = (av && j0 + ajg + s < K) ? __expf(ra[s] - xsh) : 0.0f;
+      vb[s] = (bv && j0 + bjg + s < K) ? __expf(rb[s] - ysh) : 0.0f;
+    }
+    __syncthreads();   // (the previous slice's fragment reads are done)
+    stage16<PREC>(S, true, ar, ajg, va);
+    stage16<PREC>(S, false, bc, bjg, vb);
     __syncthreads();
+    if (j0 + kKC < K) fetch(j0 + kKC);   // in flight during the MFMAs below
 #pragma unroll
     for (int st = 0; st < kKC / 16; ++st) {
       const int jj = 16 * st + 8 * (lane / 32);
       if constexpr (PREC == TMC_BF16X3) {
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&S.a[0][wr + lane % 32][jj]);
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(&S.a[1][wr + lane % 32][jj]);
-        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&S.b[0][wc + lane % 32][jj]);
-        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&S.b[1][wc + lane % 32][jj]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-      } else {
-        const float4 a0 = *reinterpret_cast<const float4*>(&S.a[wr + lane % 32][jj]);
-        const float4 a1 = *reinterpret_cast<const float4*>(&S.a[wr + lane % 32][jj + 4]);
-        const float4 b0 = *reinterpret_cast<const float4*>(&S.b[wc + lane % 32][jj]);
-        const float4 b1 = *reinterpret_cast<const float4*>(&S.b[wc + lane % 32][jj + 4]);
-        const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-        const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+        bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[s], bv[s], acc, 0, 0, 0);
+        for (int p = 0; p < 2; ++p) {
+          ah[p] = *reinterpret_cast<const bf16x8*>(&S.a[0][wr + 32 * p + lane % 32][jj]);
+          al[p] = *reinterpret_cast<const bf16x8*>(&S.a[1][wr + 32 * p + lane % 32][jj]);
+          bh[p] = *reinterpret_cast<const bf16x8*>(&S.b[0][wc + 32 * p + lane % 32][jj]);
+          bl[p] = *reinterpret_cast<const bf16x8*>(&S.b[1][wc + 32 * p + lane % 32][jj]);
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[p], bh[q], acc[p][q], 0, 0, 0);
+            acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[p], bl[q], acc[p][q], 0, 0, 0);
+            acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[p], bh[q], acc[p][q], 0, 0, 0);
+          }
+      } else {
+        float af[2][8], bfv[2][8];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const float4 a0 = *reinterpret_cast<const float4*>(&S.a[wr + 32 * p + lane % 32][jj]);
+          const float4 a1 = *reinterpret_cast<const float4*>(&S.a[wr + 32 * p + lane % 32][jj + 4]);
+          const float4 b0 = *reinterpret_cast<const float4*>(&S.b[wc + 32 * p + lane % 32][jj]);
+          const float4 b1 = *reinterpret_cast<const float4*>(&S.b[wc + 32 * p + lane % 32][jj + 4]);
+          af[p][0] = a0.x; af[p][1] = a0.y; af[p][2] = a0.z; af[p][3] = a0.w;
+          af[p][4] = a1.x; af[p][5] = a1.y; af[p][6] = a1.z; af[p][7] = a1.w;
+          bfv[p][0] = b0.x; bfv[p][1] = b0.y; bfv[p][2] = b0.z; bfv[p][3] = b0.w;
+          bfv[p][4] = b1.x; bfv[p][5] = b1.y; bfv[p][6] = b1.z; bfv[p][7] = b1.w;
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+          for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+              acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[p][s2], bfv[q][s2], acc[p][q], 0, 0, 0);
       }
     }
   }
   // Z = log C + x + y
-  const int k = k0 + wc + lane % 32;
-  if (k >= N) return;
-  const float ys = a.ys[(int64_t)b * N + k];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int i = i0 + wr + 8 * (v / 4) + 4 * (lane / 32) + v % 4;
-    if (i < M) a.Z[((int64_t)b * M + i) * N + k] = __logf(acc[v]) + a.xs[(int64_t)b * M + i] + ys;
+  for (int q = 0; q < 2; ++q) {
+    const int k = k0 + wc + 32 * q + lane % 32;
+    if (k >= N) continue;
+    const float ys = a.ys[(int64_t)b * N + k];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = i0 + wr + 32 * p + 8 * (v / 4) + 4 * (lane / 32) + v % 4;
+        if (i < M) a.Z[((int64_t)b * M + i) * N + k] = __logf(acc[p][q][v]) + a.xs[(int64_t)b * M + i] + ys;
+      }
+    }
   }
 }
 
@@ -204,7 +269,7 @@ hipError_t launch_logmm(const LogmmArgs& a, int precision, hipStream_t st) {
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_logmm_rowmax, dim3((a.M + 3) / 4, 1, a.B), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(k_logmm_colmax, dim3((a.N + 255) / 256, 1, a.B), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_logmm_colmax, dim3((a.N + kWave - 1) / kWave, 1, a.B), dim3(1024), 0, st, a);
   const dim3 grid((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile, a.B);
   if (precision == TMC_BF16X3)
     hipLaunchKernelGGL((k_logmm_mfma<TMC_BF16X3>), grid, dim3(256), 0, st, a);

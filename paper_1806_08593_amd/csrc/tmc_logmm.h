@@ -6,7 +6,7 @@
 
 namespace tmc {
 
-constexpr int kLogmmTile = 64;   // output rows and columns per workgroup of the MFMA pass
+constexpr int kLogmmTile = 128;  // output rows and columns per workgroup of the MFMA pass
 
 struct LogmmArgs {
   int B, M, K, N;

@@ -103,3 +103,39 @@ def test_dregs_surrogate_from_two_tempered_passes(prec, engine):
                     assert np.abs(got[l]).max() == 0
                 else:
                     assert_elem(got[l], rb, ea, er, f"dregs-{prec}/d{k}/chain{c}/layer{l}")
+
+
+@pytest.mark.parametrize("prec,engine", [("fp64", "plain"), ("fp32", "fused")])
+def test_dregs_autograd_wrapper(prec, engine):
+    """The torch wrapper of the surrogate (autograd.GaussChainDReGs) on a homogeneous batch
+    with s shared by the batch: its value 1/2 c (log P_2 + sum ln K) and the gradients that
+    torch receives (ds summed over the batch) against the oracle's DReGs gradients."""
+    from paper_1806_08593_amd.autograd import GaussChainDReGs
+    w = make("c2", B=3)
+    B, L, K, D = w.z.shape
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    npdt = np.float64 if prec == "fp64" else np.float32
+    t = {k: torch.tensor(np.asarray(getattr(w, k), npdt), dtype=dt, device="cuda:0", requires_grad=True)
+         for k in ("z", "mu", "s", "u")}
+    run = GaussChainDReGs(B, L, K, D, prec, engine)
+    S = run(t["z"], t["mu"], t["s"], t["u"])
+    S.sum().backward()
+    torch.cuda.synchronize()
+    chains = cast_chains(w.chains, prec)
+    ea, er = GRAD_ELEM_TOL[prec]
+    lnK = L * math.log(K)
+    ds_ref = 0.0
+    for c, ch in enumerate(chains):
+        rc, dz, dmu, ds, du = O.dregs_gradients(ch.z, ch.mu, ch.s, ch.u)
+        lp2 = O.tempered_chain_logp(O.gauss_chain_factors(ch.z, ch.mu, ch.s), ch.u, 2.0)
+        want = 0.5 * rc * (lp2 + lnK)
+        assert abs(S[c].item() - want) <= (1e-9 if prec == "fp64" else 5e-3) * abs(want), (c, S[c].item(), want)
+        for k, blocks in (("z", dz), ("mu", dmu), ("u", du)):
+            got = t[k].grad[c].cpu().numpy().astype(np.float64)
+            for l, rb in enumerate(blocks):
+                if np.abs(rb).max() == 0:
+                    assert np.abs(got[l]).max() == 0
+                else:
+                    assert_elem(got[l], rb, 10 * ea, 10 * er, f"dregs-autograd-{prec}/d{k}/chain{c}/layer{l}")
+        ds_ref = ds_ref + np.stack(ds)
+    assert_elem(t["s"].grad.cpu().numpy().astype(np.float64), ds_ref, 10 * ea, 10 * er, f"dregs-autograd-{prec}/ds")

@@ -582,3 +582,72 @@ def test_star_grouping():
     a = star_layout(1, 9000, 128, 128, 1)
     assert (a["P"], a["ngrp"]) == (8, 1125)
     assert star_layout(1, 2, 64 * 5000, 8, 1)["P"] == 2
+
+
+# ---------------------------------------------------------------------------
+# log-domain matrix product
+# ---------------------------------------------------------------------------
+
+LOGMM_TILE = 128
+
+
+def check_logmm(B, M, K, N):
+    """Every global access of the four log-domain product kernels (row and column maxima,
+    the MFMA tile kernel with its clamped slice fetches, the exact fix-up) per thread."""
+    Bf = Buffers(X=B * M * K, Y=B * K * N, Z=B * M * N, xs=B * M, ys=B * N)
+    t = np.arange(256)
+    for b in range(B):
+        # rows: a wave per row, lanes over j
+        for bx in range(cdiv(M, 4)):
+            row = bx * 4 + t // 64
+            ok = row < M
+            for j0 in range(0, K, 64):
+                j = j0 + t % 64
+                Bf.check("X", (b * M + row) * K + j, mask=ok & (j < K))
+            Bf.check("xs", b * M + row, mask=ok & (t % 64 == 0))
+        # columns: 16 waves per 64 columns, lanes past N read column 0
+        for bx in range(cdiv(N, 64)):
+            col = bx * 64 + np.arange(64)
+            cc = np.where(col < N, col, 0)
+            for j in range(K):
+                Bf.check("Y", b * K * N + j * N + cc)
+            Bf.check("ys", b * N + col, mask=col < N)
+        # MFMA tiles
+        for by in range(cdiv(M, LOGMM_TILE)):
+            for bx in range(cdiv(N, LOGMM_TILE)):
+                i0, k0 = by * LOGMM_TILE, bx * LOGMM_TILE
+                ai, bk = i0 + t // 2, k0 + t % 128
+                av, bv = ai < M, bk < N
+                ajg, bjg = (t % 2) * 16, (t // 128) * 16
+                Bf.check("xs", b * M + ai, mask=av)
+                Bf.check("ys", b * N + bk, mask=bv)
+                for j0 in range(0, K, 32):
+                    for s in range(16):
+                        ja = np.minimum(j0 + ajg + s, K - 1)
+                        jb = np.minimum(j0 + bjg + s, K - 1)
+                        Bf.check("X", b * M * K + np.where(av, ai, 0) * K + ja)
+                        Bf.check("Y", b * K * N + jb * N + np.where(bv, bk, 0))
+                lane, w = t % 64, t // 64
+                wr, wc = 64 * (w // 2), 64 * (w % 2)
+                for q in range(2):
+                    k = k0 + wc + 32 * q + lane % 32
+                    for p in range(2):
+                        for v in range(16):
+                            i = i0 + wr + 32 * p + 8 * (v // 4) + 4 * (lane // 32) + v % 4
+                            Bf.check("Z", (b * M + i) * N + k, mask=(k < N) & (i < M))
+                            Bf.check("xs", b * M + i, mask=(k < N) & (i < M))
+        # exact entries
+        for i in range(M):
+            k = np.arange(cdiv(N, 256) * 256)
+            ok = k < N
+            Bf.check("Z", (b * M + i) * N + k, mask=ok)
+            Bf.check("ys", b * N + k, mask=ok)
+            for j in range(K):
+                Bf.check("X", (b * M + i) * K + j)
+                Bf.check("Y", b * K * N + j * N + k, mask=ok)
+    assert not Bf.bad, Bf.bad[:5]
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (3, 70, 45, 130), (2, 129, 33, 257), (1, 5, 300, 7)])
+def test_logmm_accesses_in_bounds(shape):
+    check_logmm(*shape)
