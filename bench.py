@@ -455,7 +455,7 @@ def main():
     ap.add_argument("--no-logmm", action="store_true",
                     help="skip the log-domain matrix product measurement")
     ap.add_argument("--star-only", action="store_true",
-                    help="only the star-model measurement (one JSON line with its results)")
+                    help="only the star-model and log-domain product measurements (one JSON line)")
     ap.add_argument("--calibrate-copy", type=float, default=0.0,
                     help="first copy this many MiB with a plain device copy (a known-size "
                          "kernel for scaling memory counters)")
@@ -483,7 +483,7 @@ def main():
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     if args.star_only:
-        print(json.dumps({"star": star_section(args, log),
+        print(json.dumps({"star": {} if args.no_star else star_section(args, log),
                           "logmm": {} if args.no_logmm else logmm_section(args, log)}))
         return
 
