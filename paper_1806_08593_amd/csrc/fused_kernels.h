@@ -1053,12 +1053,22 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   }
 }
 
+// Work item of workgroup b of n: the hardware hands workgroup b to XCD b mod 8, and
+// consecutive items (the row or column blocks of one layer pair, which sweep the same
+// operand) go to workgroups of one XCD, so that they share its L2.  A tail of n mod 8
+// workgroups keeps its own index (a bijection on [0, n)).
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int X = 8;
+  const int per = n / X;
+  return b < per * X ? (b % X) * per + b / X : b;
+}
+
 // One workgroup of WV waves (32 WV rows) per work item (level-synchronous launch):
 // 4 waves, two workgroups per compute unit, or 8 waves, one per compute unit.
 template <int PREC, int NKC, bool GRAD, int NS, int WV>
 __global__ __launch_bounds__(64 * WV, (WV == 8 ? 1 : (NKC <= 8 ? 2 : 1))) void k_fused_fwd(FwdArgs args) {
   __shared__ __align__(16) FwdSmem<PREC, NKC, GRAD, NS> T;
-  const Item it = args.items[blockIdx.x];
+  const Item it = args.items[xcd_item(blockIdx.x, gridDim.x)];
   const LayerDev L = args.Ls[it.layer];
   fwd_item<PREC, NKC, GRAD, NS, WV>(T, it, L, args);
 }
@@ -1501,7 +1511,7 @@ template <int PREC, int NKC, int NS, int WV>
 __global__ __launch_bounds__(64 * WV, (WV == 8 ? 1 : (NKC <= 8 ? 2 : 1))) void k_fused_bwd(BwdArgs args) {
   __shared__ __align__(16) BwdSmem<PREC, NKC, NS> T;
   __shared__ float accD[(WV / 4) * BwdSmem<PREC, NKC, NS>::DT];
-  const Item it = args.items[blockIdx.x];
+  const Item it = args.items[xcd_item(blockIdx.x, gridDim.x)];
   const LayerDev L = args.Ls[it.layer];
   bwd_item<PREC, NKC, NS, WV>(T, accD, it, L, args);
 }
