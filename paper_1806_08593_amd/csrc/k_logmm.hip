@@ -3,11 +3,12 @@
 //   Z_b[i,k] = log sum_j exp(X_b[i,j] + Y_b[j,k]),  X_b [M][K], Y_b [K][N], Z_b [M][N].
 // Matrix-core path (FP32, BF16X3): the Appendix's shift, x_i = max_j X_ij and
 // y_k = max_j Y_jk, makes every exponential at most 1, so the sum is an ordinary matrix
-// product C = exp(X - x) exp(Y - y) on MFMA, with the exponentials formed while the
-// operand tiles are staged in LDS; Z = log C + x + y.  Where that shift underflows (log C
-// below kLogmmFloor: the maxima of X's row and Y's column sit at indices j far apart), a
-// fix-up pass recomputes the entry exactly, with its own maximum over j, on the vector
-// ALU.  FP64: every entry exactly on the vector ALU.
+// product C = exp(X - x) exp(Y - y) on MFMA; the shifted exponentials are formed once, in
+// the operand layout of the product (BF16 hi/lo planes or FP32, Y's transposed, the
+// reduction index padded with zeros to a multiple of 32), and Z = log C + x + y.  Where that shift underflows (log C
+// below kLogmmFloor: the maxima of X's row and Y's column sit at indices j far apart), the
+// epilogue recomputes the entry exactly, with its own maximum over j, on the vector ALU.
+// FP64: every entry exactly on the vector ALU.
 #include <math.h>
 
 #include "../../include/tmc.h"
@@ -51,43 +52,86 @@ struct LogmmSmem<TMC_FP32> {
   float b[kTile][kKC + kPadF];
 };
 
-// Stores 16 consecutive reduction-index values of one row (column) of a staged tile.
+// Prepared operand element e (one row of 8 consecutive j): BF16X3 writes its hi part at
+// e in the first plane and its lo part at e in the second (plane stride ps); FP32 the values.
 template <int PREC>
-__device__ __forceinline__ void stage16(LogmmSmem<PREC>& S, bool is_a, int row, int j, const float (&v)[16]) {
+__device__ __forceinline__ void store_operand(void* base, int64_t ps, int64_t e, const float (&v)[8]) {
   if constexpr (PREC == TMC_BF16X3) {
-    uint32_t h[8], l[8];
+    uint32_t h[4], l[4];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) split_pair(v[2 * p], v[2 * p + 1], h[p], l[p]);
+    for (int p = 0; p < 4; ++p) split_pair(v[2 * p], v[2 * p + 1], h[p], l[p]);
+    __bf16* bp = static_cast<__bf16*>(base);
+    *reinterpret_cast<u32x4*>(bp + e) = (u32x4){h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<u32x4*>(bp + ps + e) = (u32x4){l[0], l[1], l[2], l[3]};
+  } else {
+    float* fp = static_cast<float*>(base);
+    *reinterpret_cast<float4*>(fp + e) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4*>(fp + e + 4) = make_float4(v[4], v[5], v[6], v[7]);
+  }
+}
+
+// 16 consecutive j of one operand row, as loaded (BF16X3: hi and lo, 32 B each; FP32: 64 B).
+template <int PREC>
+struct OperandRegs;
+template <>
+struct OperandRegs<TMC_BF16X3> {
+  u32x4 h[2], l[2];
+};
+template <>
+struct OperandRegs<TMC_FP32> {
+  float4 v[4];
+};
+
+template <int PREC>
+__device__ __forceinline__ void load_operand(const void* base, int64_t ps, int64_t e, OperandRegs<PREC>& r) {
+  if constexpr (PREC == TMC_BF16X3) {
+    const __bf16* bp = static_cast<const __bf16*>(base);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      r.h[q] = *reinterpret_cast<const u32x4*>(bp + e + 8 * q);
+      r.l[q] = *reinterpret_cast<const u32x4*>(bp + ps + e + 8 * q);
+    }
+  } else {
+    const float* fp = static_cast<const float*>(base);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.v[q] = *reinterpret_cast<const float4*>(fp + e + 4 * q);
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ void stage_operand(LogmmSmem<PREC>& S, bool is_a, int row, int j,
+                                              const OperandRegs<PREC>& r) {
+  if constexpr (PREC == TMC_BF16X3) {
     __bf16* hp = is_a ? &S.a[0][row][j] : &S.b[0][row][j];
     __bf16* lp = is_a ? &S.a[1][row][j] : &S.b[1][row][j];
-    *reinterpret_cast<u32x4*>(hp) = (u32x4){h[0], h[1], h[2], h[3]};
-    *reinterpret_cast<u32x4*>(hp + 8) = (u32x4){h[4], h[5], h[6], h[7]};
-    *reinterpret_cast<u32x4*>(lp) = (u32x4){l[0], l[1], l[2], l[3]};
-    *reinterpret_cast<u32x4*>(lp + 8) = (u32x4){l[4], l[5], l[6], l[7]};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      *reinterpret_cast<u32x4*>(hp + 8 * q) = r.h[q];
+      *reinterpret_cast<u32x4*>(lp + 8 * q) = r.l[q];
+    }
   } else {
     float* p = is_a ? &S.a[row][j] : &S.b[row][j];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      *reinterpret_cast<float4*>(p + 4 * q) = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<float4*>(p + 4 * q) = r.v[q];
   }
+}
+
+// log sum_j exp(x[j] + y[j N]) by its own maximum over j (two passes); -inf when every
+// term is -inf, NaN when one is NaN.
+template <typename T>
+__device__ T exact_entry(const T* __restrict__ x, const T* __restrict__ y, int K, int N) {
+  T m = (T)(-INFINITY);
+  for (int j = 0; j < K; ++j) m = nan_max(m, x[j] + y[(int64_t)j * N]);
+  if (m == (T)(-INFINITY) || m != m) return m;
+  T s = (T)0;
+  for (int j = 0; j < K; ++j) s += exp(x[j] + y[(int64_t)j * N] - m);
+  return m + log(s);
 }
 
 }  // namespace
 
-// Shifts: xs[b][i] = max_j X_b[i,j] (a wave per row, lanes over j) and ys[b][k] =
-// max_j Y_b[j,k] (below); an all -inf row or column gets 0 (its exponentials are then 0,
-// never NaN).
-__global__ __launch_bounds__(256) void k_logmm_rowmax(LogmmArgs a) {
-  const int b = blockIdx.z;
-  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;
-  if (row >= a.M) return;   // (uniform per wave)
-  const float* x = a.X + ((int64_t)b * a.M + row) * a.K;
-  float m = -INFINITY;
-  for (int j = threadIdx.x % kWave; j < a.K; j += kWave) m = nan_max(m, x[j]);
-  m = wave_max(m);
-  if (threadIdx.x % kWave == 0) a.xs[(int64_t)b * a.M + row] = (m == -INFINITY) ? 0.0f : m;
-}
-
+// Shifts: xs[b][i] = max_j X_b[i,j] (in k_logmm_prep_x) and ys[b][k] = max_j Y_b[j,k]
+// (below); an all -inf row or column gets 0 (its exponentials are then 0, never NaN).
 // Column maxima: a workgroup of 16 waves per 64 columns (lane -> column), wave w takes
 // rows w, w + 16, .. (loads issued 8 at a time); the waves' maxima are merged in LDS.
 __global__ __launch_bounds__(1024) void k_logmm_colmax(LogmmArgs a) {
@@ -118,60 +162,97 @@ __global__ __launch_bounds__(1024) void k_logmm_colmax(LogmmArgs a) {
   }
 }
 
+// Operands of the product: A[b][i][j] = exp(X_b[i,j] - x_i) and Bt[b][k][j] =
+// exp(Y_b[j,k] - y_k) (Y transposed), j padded with zeros to Kp; BF16X3 stores hi and lo
+// planes (one after the other, each [B][rows][Kp]), FP32 the values.  Rows of X: a wave per
+// row finds the row maximum x_i (written to xs; an all -inf row gets 0), then writes the
+// row, 8 consecutive j per lane and step.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_logmm_prep_x(LogmmArgs a) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;   // b M + i
+  if (row >= (int64_t)a.B * a.M) return;   // (uniform per wave)
+  const int lane = threadIdx.x % kWave;
+  const float* x = a.X + row * a.K;
+  float m = -INFINITY;
+  for (int j = lane; j < a.K; j += kWave) m = nan_max(m, x[j]);
+  m = wave_max(m);
+  const float sh = (m == -INFINITY) ? 0.0f : m;
+  if (lane == 0) a.xs[row] = sh;
+  for (int j0 = 8 * lane; j0 < a.Kp; j0 += 8 * kWave) {
+    float v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = j0 + s < a.K ? __expf(x[j0 + s] - sh) : 0.0f;
+    store_operand<PREC>(a.opa, (int64_t)a.B * a.M * a.Kp, row * a.Kp + j0, v);
+  }
+}
+
+// Columns of Y into rows of Bt: a workgroup per 64 j x 64 k tile, read along k (coalesced),
+// transposed through LDS, written along j.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_logmm_prep_y(LogmmArgs a) {
+  __shared__ float tile[64][64 + 1];
+  const int b = blockIdx.z, j0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+  const int t = threadIdx.x;
+  {
+    const int kl = t % 64, k = k0 + kl;
+    const float ysh = k < a.N ? a.ys[(int64_t)b * a.N + k] : 0.0f;
+    const float* y = a.Y + (int64_t)b * a.K * a.N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int jl = 16 * (t / 64) + r, j = j0 + jl;
+      tile[kl][jl] = (j < a.K && k < a.N) ? __expf(y[(int64_t)j * a.N + k] - ysh) : 0.0f;
+    }
+  }
+  __syncthreads();
+  const int kl = t / 4, k = k0 + kl, jc = (t % 4) * 16;
+  if (k >= a.N) return;
+  const int64_t rowo = ((int64_t)b * a.N + k) * a.Kp + j0 + jc;
+  float v[8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = tile[kl][jc + 8 * h + s];
+    if (j0 + jc + 8 * h < a.Kp) store_operand<PREC>(a.opb, (int64_t)a.B * a.N * a.Kp, rowo + 8 * h, v);
+  }
+}
+
 // The shifted product on MFMA: a workgroup of 4 waves per 128 x 128 output tile (wave w:
 // rows 64 (w / 2), columns 64 (w % 2), as 2 x 2 accumulators of 32 x 32), the reduction
-// index staged 32 at a time.  Thread t stages row t / 2 of the X tile and column t % 128
-// of the Y tile, 16 consecutive j each, as exponentials of the shifted values (0 past the
-// matrix edges); the global loads of the next slice are issued before the current
-// slice's MFMAs.  Operand fragments: lane l holds row (column) l % 32 of its block and
-// j = 16 s + 8 (l / 32) .. + 7 of step s (both operands in that order); accumulator
+// index staged 32 at a time from the prepared operands (thread t: row t / 2 of each
+// operand tile, 16 consecutive j; rows past the matrix edge read the last row and their
+// results are discarded); the global loads of the next slice are in flight during the
+// current slice's MFMAs.  Operand fragments: lane l holds row (column) l % 32 of its block
+// and j = 16 s + 8 (l / 32) .. + 7 of step s (both operands in that order); accumulator
 // value v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
   __shared__ LogmmSmem<PREC> S;
   const int b = blockIdx.z;
   const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
-  const int M = a.M, K = a.K, N = a.N;
+  const int M = a.M, N = a.N, Kp = a.Kp;
   const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
-  const float* X = a.X + (int64_t)b * M * K;
-  const float* Y = a.Y + (int64_t)b * K * N;
-  // staging roles
-  const int ar = t / 2, ajg = (t % 2) * 16;          // X tile row, first j
-  const int bc = t % kTile, bjg = (t / kTile) * 16;  // Y tile column, first j
-  const int ai = i0 + ar, bk = k0 + bc;
-  const bool av = ai < M, bv = bk < N;
-  const float xsh = av ? a.xs[(int64_t)b * M + ai] : 0.0f;
-  const float ysh = bv ? a.ys[(int64_t)b * N + bk] : 0.0f;
-  const float* xrow = X + (int64_t)(av ? ai : 0) * K;
-  const float* ycol = Y + (bv ? bk : 0);
-  float ra[16], rb[16];   // raw values of the next slice (clamped addresses, masked below)
-  auto fetch = [&](int j0) {
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int ja = min(j0 + ajg + s, K - 1), jb = min(j0 + bjg + s, K - 1);
-      ra[s] = xrow[ja];
-      rb[s] = ycol[(int64_t)jb * N];
-    }
-  };
+  const int r = t / 2, jg = (t % 2) * 16;
+  const int64_t ra = ((int64_t)b * M + min(i0 + r, M - 1)) * Kp + jg;
+  const int64_t rb = ((int64_t)b * N + min(k0 + r, N - 1)) * Kp + jg;
+  const int64_t pa = (int64_t)a.B * M * Kp, pb = (int64_t)a.B * N * Kp;   // plane sizes
+  OperandRegs<PREC> xa, xb;
   f32x16 acc[2][2];
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[p][q] = (f32x16){};
   const int wr = 64 * (w / 2), wc = 64 * (w % 2);
-  fetch(0);
-  for (int j0 = 0; j0 < K; j0 += kKC) {
-    float va[16], vb[16];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      va[s] = (av && j0 + ajg + s < K) ? __expf(ra[s] - xsh) : 0.0f;
-      vb[s] = (bv && j0 + bjg + s < K) ? __expf(rb[s] - ysh) : 0.0f;
-    }
+  load_operand<PREC>(a.opa, pa, ra, xa);
+  load_operand<PREC>(a.opb, pb, rb, xb);
+  for (int j0 = 0; j0 < Kp; j0 += kKC) {
     __syncthreads();   // (the previous slice's fragment reads are done)
-    stage16<PREC>(S, true, ar, ajg, va);
-    stage16<PREC>(S, false, bc, bjg, vb);
+    stage_operand<PREC>(S, true, r, jg, xa);
+    stage_operand<PREC>(S, false, r, jg, xb);
     __syncthreads();
-    if (j0 + kKC < K) fetch(j0 + kKC);   // in flight during the MFMAs below
+    if (j0 + kKC < Kp) {   // in flight during the MFMAs below
+      load_operand<PREC>(a.opa, pa, ra + j0 + kKC, xa);
+      load_operand<PREC>(a.opb, pb, rb + j0 + kKC, xb);
+    }
 #pragma unroll
     for (int st = 0; st < kKC / 16; ++st) {
       const int jj = 16 * st + 8 * (lane / 32);
@@ -215,7 +296,9 @@ __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
       }
     }
   }
-  // Z = log C + x + y
+  // Z = log C + x + y; an entry whose shifted product fell below the floor (or is not a
+  // number) is recomputed exactly here (rare: the lane loops over j on its own)
+  const float floor_c = __expf(kLogmmFloor);
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int k = k0 + wc + 32 * q + lane % 32;
@@ -226,7 +309,12 @@ __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int i = i0 + wr + 32 * p + 8 * (v / 4) + 4 * (lane / 32) + v % 4;
-        if (i < M) a.Z[((int64_t)b * M + i) * N + k] = __logf(acc[p][q][v]) + a.xs[(int64_t)b * M + i] + ys;
+        if (i >= M) continue;
+        const float c = acc[p][q][v];
+        a.Z[((int64_t)b * M + i) * N + k] =
+            c >= floor_c ? __logf(c) + a.xs[(int64_t)b * M + i] + ys
+                         : exact_entry<float>(a.X + ((int64_t)b * M + i) * a.K,
+                                              a.Y + (int64_t)b * a.K * N + k, a.K, N);
       }
     }
   }
@@ -234,49 +322,36 @@ __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
 
 // Exact entries: a thread per column k of one output row (the row of X read by scalar
 // loads, Y's row j coalesced across the threads): m = max_j (X_ij + Y_jk), then
-// m + log sum_j exp(X_ij + Y_jk - m).  With fix_only, only entries whose shifted product
-// fell below kLogmmFloor (log C = Z - x_i - y_k) are recomputed.
+// m + log sum_j exp(X_ij + Y_jk - m).
 template <typename T>
 __global__ __launch_bounds__(256) void k_logmm_exact(LogmmArgs a, const T* __restrict__ X,
-                                                     const T* __restrict__ Y, T* __restrict__ Z,
-                                                     int fix_only) {
+                                                     const T* __restrict__ Y, T* __restrict__ Z) {
   const int b = blockIdx.z, i = blockIdx.y;
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= a.N) return;
-  const int K = a.K;
-  T* zp = Z + ((int64_t)b * a.M + i) * a.N + k;
-  if (fix_only) {
-    const float r = (float)*zp - a.xs[(int64_t)b * a.M + i] - a.ys[(int64_t)b * a.N + k];
-    if (r >= kLogmmFloor) return;
-  }
-  const T* x = X + ((int64_t)b * a.M + i) * K;
-  const T* y = Y + (int64_t)b * K * a.N + k;
-  T m = (T)(-INFINITY);
-  for (int j = 0; j < K; ++j) m = nan_max(m, x[j] + y[(int64_t)j * a.N]);
-  if (m == (T)(-INFINITY) || m != m) {
-    *zp = m;
-    return;
-  }
-  T s = (T)0;
-  for (int j = 0; j < K; ++j) s += exp(x[j] + y[(int64_t)j * a.N] - m);
-  *zp = m + log(s);
+  Z[((int64_t)b * a.M + i) * a.N + k] =
+      exact_entry<T>(X + ((int64_t)b * a.M + i) * a.K, Y + (int64_t)b * a.K * a.N + k, a.K, a.N);
 }
 
 hipError_t launch_logmm(const LogmmArgs& a, int precision, hipStream_t st) {
   if (precision == TMC_FP64) {
     hipLaunchKernelGGL((k_logmm_exact<double>), dim3((a.N + 255) / 256, a.M, a.B), dim3(256), 0, st, a,
-                       a.Xd, a.Yd, a.Zd, 0);
+                       a.Xd, a.Yd, a.Zd);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_logmm_rowmax, dim3((a.M + 3) / 4, 1, a.B), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_logmm_colmax, dim3((a.N + kWave - 1) / kWave, 1, a.B), dim3(1024), 0, st, a);
   const dim3 grid((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile, a.B);
-  if (precision == TMC_BF16X3)
+  const dim3 gx((unsigned)(((int64_t)a.B * a.M + 3) / 4));
+  const dim3 gy((a.Kp + 63) / 64, (a.N + 63) / 64, a.B);
+  if (precision == TMC_BF16X3) {
+    hipLaunchKernelGGL((k_logmm_prep_x<TMC_BF16X3>), gx, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_logmm_prep_y<TMC_BF16X3>), gy, dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_logmm_mfma<TMC_BF16X3>), grid, dim3(256), 0, st, a);
-  else
+  } else {
+    hipLaunchKernelGGL((k_logmm_prep_x<TMC_FP32>), gx, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_logmm_prep_y<TMC_FP32>), gy, dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_logmm_mfma<TMC_FP32>), grid, dim3(256), 0, st, a);
-  hipLaunchKernelGGL((k_logmm_exact<float>), dim3((a.N + 255) / 256, a.M, a.B), dim3(256), 0, st, a,
-                     a.X, a.Y, a.Z, 1);
+  }
   return hipGetLastError();
 }
 

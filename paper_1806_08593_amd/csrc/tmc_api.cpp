@@ -1065,9 +1065,15 @@ tmc_status logmm_check(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t p
   return TMC_OK;
 }
 
-size_t logmm_ws(int32_t batch, int32_t M, int32_t N, int32_t precision) {
+int32_t logmm_kp(int32_t K) { return (K + 31) / 32 * 32; }
+
+// Shifts (floats), then the prepared operands: 4 bytes per element in both modes (two
+// BF16 planes, or FP32).
+size_t logmm_ws(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t precision) {
   if (precision == TMC_FP64) return 0;
-  return align_up((size_t)batch * M * 4, 256) + align_up((size_t)batch * N * 4, 256);
+  const size_t kp = (size_t)logmm_kp(K);
+  return align_up((size_t)batch * M * 4, 256) + align_up((size_t)batch * N * 4, 256) +
+         align_up((size_t)batch * M * kp * 4, 256) + align_up((size_t)batch * N * kp * 4, 256);
 }
 }  // namespace
 
@@ -1076,7 +1082,7 @@ tmc_status tmc_logmmexp_workspace_size(int32_t batch, int32_t M, int32_t K, int3
   if (!bytes) return fail(TMC_ERR_INVALID_ARG, "bytes is NULL");
   const tmc_status st = logmm_check(batch, M, K, N, precision);
   if (st != TMC_OK) return st;
-  *bytes = logmm_ws(batch, M, N, precision);
+  *bytes = logmm_ws(batch, M, K, N, precision);
   return TMC_OK;
 }
 
@@ -1102,8 +1108,15 @@ tmc_status tmc_logmmexp(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t 
       a.X = (const float*)X;
       a.Y = (const float*)Y;
       a.Z = (float*)Z;
-      a.xs = (float*)workspace;
-      a.ys = (float*)((char*)workspace + align_up((size_t)batch * M * 4, 256));
+      char* w = (char*)workspace;
+      a.Kp = logmm_kp(K);
+      a.xs = (float*)w;
+      w += align_up((size_t)batch * M * 4, 256);
+      a.ys = (float*)w;
+      w += align_up((size_t)batch * N * 4, 256);
+      a.opa = w;
+      w += align_up((size_t)batch * M * a.Kp * 4, 256);
+      a.opb = w;
     }
     const hipError_t e = launch_logmm(a, precision, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TMC_ERR_HIP, "log-domain product launch: %s", hipGetErrorString(e));

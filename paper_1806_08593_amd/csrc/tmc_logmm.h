@@ -10,11 +10,14 @@ constexpr int kLogmmTile = 128;  // output rows and columns per workgroup of the
 
 struct LogmmArgs {
   int B, M, K, N;
+  int Kp;            // K rounded up to a multiple of 32 (the prepared operands' row length)
   const float* X;    // [B][M][K]  (FP32 and BF16X3)
   const float* Y;    // [B][K][N]
   float* Z;          // [B][M][N]
   float* xs;         // workspace [B][M]: row maxima of X
   float* ys;         // workspace [B][N]: column maxima of Y
+  void* opa;         // workspace: exp(X - x) as the product's operand, [B][M][Kp] per plane
+  void* opb;         // workspace: exp(Y - y) transposed, [B][N][Kp] per plane
   const double* Xd;  // FP64
   const double* Yd;
   double* Zd;

@@ -592,19 +592,27 @@ LOGMM_TILE = 128
 
 
 def check_logmm(B, M, K, N):
-    """Every global access of the four log-domain product kernels (row and column maxima,
-    the MFMA tile kernel with its clamped slice fetches, the exact fix-up) per thread."""
-    Bf = Buffers(X=B * M * K, Y=B * K * N, Z=B * M * N, xs=B * M, ys=B * N)
+    """Every global access of the log-domain product kernels (row and column maxima, the
+    operand preparation, the MFMA tile kernel, the exact fix-up) per thread.  Operand
+    buffers are counted in elements of one BF16 plane pair (2 B M Kp, 2 B N Kp); the FP32
+    form uses the first half of each with 4-byte elements, the same bytes."""
+    Kp = cdiv(K, 32) * 32
+    Bf = Buffers(X=B * M * K, Y=B * K * N, Z=B * M * N, xs=B * M, ys=B * N,
+                 opa=2 * B * M * Kp, opb=2 * B * N * Kp)
     t = np.arange(256)
+    # operand preparation of X: a wave per row (its maximum, then 8 consecutive j per lane)
+    for row in range(B * M):
+        lane = np.arange(64)
+        for jj in range(0, K, 64):
+            Bf.check("X", row * K + jj + lane, mask=jj + lane < K)
+        Bf.check("xs", row)
+        for j0 in range(0, Kp, 8 * 64):
+            jl = j0 + 8 * lane
+            for s_ in range(8):
+                Bf.check("X", row * K + jl + s_, mask=(jl < Kp) & (jl + s_ < K))
+                Bf.check("opa", row * Kp + jl + s_, mask=jl < Kp)
+                Bf.check("opa", B * M * Kp + row * Kp + jl + s_, mask=jl < Kp)
     for b in range(B):
-        # rows: a wave per row, lanes over j
-        for bx in range(cdiv(M, 4)):
-            row = bx * 4 + t // 64
-            ok = row < M
-            for j0 in range(0, K, 64):
-                j = j0 + t % 64
-                Bf.check("X", (b * M + row) * K + j, mask=ok & (j < K))
-            Bf.check("xs", b * M + row, mask=ok & (t % 64 == 0))
         # columns: 16 waves per 64 columns, lanes past N read column 0
         for bx in range(cdiv(N, 64)):
             col = bx * 64 + np.arange(64)
@@ -612,21 +620,37 @@ def check_logmm(B, M, K, N):
             for j in range(K):
                 Bf.check("Y", b * K * N + j * N + cc)
             Bf.check("ys", b * N + col, mask=col < N)
-        # MFMA tiles
+        # operand preparation of Y: 64 j x 64 k tiles through LDS
+        for jx in range(cdiv(Kp, 64)):
+            for ky in range(cdiv(N, 64)):
+                jb0, kb0 = jx * 64, ky * 64
+                k = kb0 + t % 64
+                Bf.check("ys", b * N + k, mask=k < N)
+                for r in range(16):
+                    j = jb0 + 16 * (t // 64) + r
+                    Bf.check("Y", b * K * N + j * N + k, mask=(j < K) & (k < N))
+                kw = kb0 + t // 4
+                jc = (t % 4) * 16
+                for h in range(2):
+                    m = (kw < N) & (jb0 + jc + 8 * h < Kp)
+                    for s_ in range(8):
+                        o = (b * N + kw) * Kp + jb0 + jc + 8 * h + s_
+                        Bf.check("opb", o, mask=m, block=None)
+                        Bf.check("opb", B * N * Kp + o, mask=m)
+        # MFMA tiles: row t / 2 of each operand tile (clamped), 16 consecutive j per slice
         for by in range(cdiv(M, LOGMM_TILE)):
             for bx in range(cdiv(N, LOGMM_TILE)):
                 i0, k0 = by * LOGMM_TILE, bx * LOGMM_TILE
-                ai, bk = i0 + t // 2, k0 + t % 128
-                av, bv = ai < M, bk < N
-                ajg, bjg = (t % 2) * 16, (t // 128) * 16
-                Bf.check("xs", b * M + ai, mask=av)
-                Bf.check("ys", b * N + bk, mask=bv)
-                for j0 in range(0, K, 32):
-                    for s in range(16):
-                        ja = np.minimum(j0 + ajg + s, K - 1)
-                        jb = np.minimum(j0 + bjg + s, K - 1)
-                        Bf.check("X", b * M * K + np.where(av, ai, 0) * K + ja)
-                        Bf.check("Y", b * K * N + jb * N + np.where(bv, bk, 0))
+                r, jg = t // 2, (t % 2) * 16
+                ra = (b * M + np.minimum(i0 + r, M - 1)) * Kp + jg
+                rb = (b * N + np.minimum(k0 + r, N - 1)) * Kp + jg
+                for jj in range(0, Kp, 32):
+                    for s_ in range(16):
+                        Bf.check("opa", ra + jj + s_, block=None)
+                        Bf.check("opa", B * M * Kp + ra + jj + s_)
+                        Bf.check("opb", rb + jj + s_, block=None)
+                        Bf.check("opb", B * N * Kp + rb + jj + s_)
+                        assert np.all((jg + s_) < 32)
                 lane, w = t % 64, t // 64
                 wr, wc = 64 * (w // 2), 64 * (w % 2)
                 for q in range(2):
@@ -634,17 +658,23 @@ def check_logmm(B, M, K, N):
                     for p in range(2):
                         for v in range(16):
                             i = i0 + wr + 32 * p + 8 * (v // 4) + 4 * (lane // 32) + v % 4
-                            Bf.check("Z", (b * M + i) * N + k, mask=(k < N) & (i < M))
-                            Bf.check("xs", b * M + i, mask=(k < N) & (i < M))
-        # exact entries
+                            live = (k < N) & (i < M)
+                            Bf.check("Z", (b * M + i) * N + k, mask=live)
+                            Bf.check("xs", b * M + i, mask=live)
+                            if p == 0 and v == 0:   # the exact recompute of an entry (rows i, columns k)
+                                for j in range(K):
+                                    Bf.check("X", (b * M + i) * K + j, mask=live)
+                                    Bf.check("Y", b * K * N + j * N + k, mask=live)
+                    Bf.check("ys", b * N + k, mask=k < N)
+        # exact entries (FP64)
         for i in range(M):
             k = np.arange(cdiv(N, 256) * 256)
-            ok = k < N
-            Bf.check("Z", (b * M + i) * N + k, mask=ok)
-            Bf.check("ys", b * N + k, mask=ok)
+            okk = k < N
+            Bf.check("Z", (b * M + i) * N + k, mask=okk)
+            Bf.check("ys", b * N + k, mask=okk)
             for j in range(K):
                 Bf.check("X", (b * M + i) * K + j)
-                Bf.check("Y", b * K * N + j * N + k, mask=ok)
+                Bf.check("Y", b * K * N + j * N + k, mask=okk)
     assert not Bf.bad, Bf.bad[:5]
 
 
