@@ -114,7 +114,7 @@ def recorded_counters(kernel, workload, prec, waves=4):
     return out
 
 
-def upload(w, prec, engine, flags=0):
+def upload(w, prec, engine, flags=0, exponent=1.0, s_override=None):
     """Device buffers and the problem for workload w (homogeneous layout with s shared
     by the batch when w is a stacked batch, packed ragged layout otherwise)."""
     import numpy as np
@@ -125,8 +125,10 @@ def upload(w, prec, engine, flags=0):
     npdt = np.float64 if prec == "fp64" else np.float32
     if w.z is not None:
         B, L, K, D = w.z.shape
-        prob = T.homogeneous_problem(B, L, K, D, prec, engine, flags)
+        prob = T.homogeneous_problem(B, L, K, D, prec, engine, flags, exponent=exponent)
         arrs = {k: getattr(w, k) for k in ("z", "mu", "s", "u")}
+        if s_override is not None:
+            arrs["s"] = s_override
     else:
         shapes, arrs = pack(w.chains, npdt)
         prob, _ = T.ragged_problem(shapes, prec, engine, flags)
@@ -134,7 +136,8 @@ def upload(w, prec, engine, flags=0):
     return prob, dev
 
 
-def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=True):
+def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=True, exponent=1.0,
+             s_override=None):
     """Times `steps` steps of workload w after `warmup` eager steps, all on one stream.
     graph: the step is a replay of the forward and backward graphs captured from the
     library's own launches (the same kernels; no host launch gaps).  timing: afterwards,
@@ -145,7 +148,7 @@ def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=
     from paper_1806_08593_amd import tmc as T
     torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
-    prob, d = upload(w, prec, engine, flags)
+    prob, d = upload(w, prec, engine, flags, exponent, s_override)
     plan = T.Plan(prob)
     ws = plan.new_workspace()
     n = prob.n_chains
@@ -161,10 +164,13 @@ def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=
             T.tmc_plan_autotune(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"],
                                 g["s"], g["u"], reps=3, stream=st)
 
+        fwd_only = bool(flags & T.TMC_FLAG_FORWARD_ONLY)
+
         def eager():
             T.tmc_gauss_fwd(h, d["z"], d["mu"], d["s"], d["u"], logp, ws, st)
-            T.tmc_gauss_bwd(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"], g["s"],
-                            g["u"], st)
+            if not fwd_only:
+                T.tmc_gauss_bwd(h, d["z"], d["mu"], d["s"], d["u"], dlogp, ws, g["z"], g["mu"],
+                                g["s"], g["u"], st)
 
         for _ in range(warmup):
             eager()
@@ -174,12 +180,14 @@ def run_mode(w, prec, engine, steps, warmup, timing, tune=False, flags=0, graph=
         if graph:
             T.tmc_plan_graph_capture_gauss(h, 0, d["z"], d["mu"], d["s"], d["u"], logp, None, ws,
                                            None, None, None, None, st)
-            T.tmc_plan_graph_capture_gauss(h, 1, d["z"], d["mu"], d["s"], d["u"], None, dlogp, ws,
-                                           g["z"], g["mu"], g["s"], g["u"], st)
+            if not fwd_only:
+                T.tmc_plan_graph_capture_gauss(h, 1, d["z"], d["mu"], d["s"], d["u"], None, dlogp,
+                                               ws, g["z"], g["mu"], g["s"], g["u"], st)
 
             def step():
                 T.tmc_plan_graph_launch(h, 0, st)
-                T.tmc_plan_graph_launch(h, 1, st)
+                if not fwd_only:
+                    T.tmc_plan_graph_launch(h, 1, st)
 
             step()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -362,6 +370,50 @@ def cpu_baseline(chains, budget_s):
     return state["entries"] / dt, n_thr, desc
 
 
+def widen_section(args, log, w5):
+    """The widened estimators at benchmark shapes: parent-dependent scales (the C3 shapes,
+    one log standard deviation per parent sample, plain engine) and the DReGs surrogate at C5
+    (a kappa = 1 forward-only pass plus a kappa = 2 forward and backward)."""
+    import numpy as np
+    from paper_1806_08593_amd import tmc as T
+    from workloads import make
+    out = {}
+    try:
+        log("parent-dependent scales, C3 shapes, FP32 plain")
+        w3 = make("c3")
+        B, L, K, D = w3.z.shape
+        rng = np.random.default_rng(1806)
+        sp = (np.asarray(w3.s)[None, :, None, :] + 0.2 * rng.normal(size=(B, L - 1, K, D))).astype(np.float32)
+        r = run_mode(w3, "fp32", "plain", max(3, args.steps // 3), 2, timing=True,
+                     flags=T.TMC_FLAG_PARENT_SCALE, s_override=sp)
+        e = dict(workload="c3 shapes, s per parent sample", precision="fp32", engine="plain",
+                 ms_per_step=r["ms_per_step"], value=w3.entries() / (r["ms_per_step"] / 1e3),
+                 kernels={k: round(v["avg_launch_us"], 2) for k, v in r["kernels"].items()})
+        for kk, nbytes in (("plain_lse_fwd", 4), ("plain_lse_bwd", 8)):
+            if kk in r["kernels"]:
+                per = nbytes * w3.entries() / r["kernels"][kk]["launches_per_step"]
+                e[kk + "_gbs"] = round(per / (r["kernels"][kk]["avg_launch_us"] * 1e-6) / 1e9, 1)
+        out["parent_scale"] = e
+    except Exception as ex:
+        out["parent_scale"] = dict(error=str(ex)[:200])
+    try:
+        log("DReGs surrogate passes at C5, BF16X3")
+        steps = max(3, args.steps // 3)
+        r1 = run_mode(w5, "bf16x3", "fused", steps, 2, timing=False, tune=not args.no_tune,
+                      flags=T.TMC_FLAG_FORWARD_ONLY, graph=not args.no_graph)
+        r2 = run_mode(w5, "bf16x3", "fused", steps, 2, timing=False, tune=not args.no_tune,
+                      exponent=2.0, graph=not args.no_graph)
+        # (the forward-only run times a forward; a step of the surrogate is that forward plus a
+        # squared-weight forward and backward)
+        ms = r1["ms_per_step"] + r2["ms_per_step"]
+        out["dregs"] = dict(workload="c5", precision="bf16x3", ms_forward_kappa1=r1["ms_per_step"],
+                            ms_fwd_bwd_kappa2=r2["ms_per_step"], ms_per_step=ms,
+                            value=w5.entries() / (ms / 1e3))
+    except Exception as ex:
+        out["dregs"] = dict(error=str(ex)[:200])
+    return out
+
+
 def logmm_section(args, log):
     """The log-domain matrix product on a batch of square matrices, every precision;
     achieved = 2 M N K flops per product / launch time (the MFMA path issues 3x that in
@@ -452,6 +504,8 @@ def main():
                     help="time eager launches instead of replays of the captured step graphs")
     ap.add_argument("--no-star", action="store_true",
                     help="skip the star-model measurement (Gaussian example, FP32)")
+    ap.add_argument("--no-widen", action="store_true",
+                    help="skip the parent-scale and DReGs-surrogate measurements")
     ap.add_argument("--no-logmm", action="store_true",
                     help="skip the log-domain matrix product measurement")
     ap.add_argument("--star-only", action="store_true",
@@ -595,6 +649,7 @@ def main():
     # workloads in FP32; log P of the first against the oracle
     star = {} if args.no_star else star_section(args, log)
     logmm = {} if args.no_logmm else logmm_section(args, log)
+    widen = {} if (args.no_widen or args.workload != "c5") else widen_section(args, log, w)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -668,6 +723,7 @@ def main():
         "compare": compare,
         "star": star,
         "logmm": logmm,
+        "widen": widen,
     }
     print(json.dumps(line))
 

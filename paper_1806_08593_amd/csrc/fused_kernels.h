@@ -362,6 +362,24 @@ __device__ __forceinline__ void mma_t(f32x16& acc, const TFrag<PREC>& T, const P
 // (hi, lo), FP32 one float plane.  BF16X3 has no d-major copies: the second GEMM reads
 // the row-major copy through LDS transpose reads (tile_rowT_frag).
 // ---------------------------------------------------------------------------
+// Row stride (elements) of the BF16 row-major copy.  The LDS has 64 banks of 4 bytes
+// and serves 16 lanes of a 64- or 128-bit access per pass.  With a stride of sigma
+// dwords, sigma = 4 s (mod 64), the 16 rows of one pass of a fragment read (16 bytes
+// each, same columns) sit at 16-byte slots s r (mod 16): distinct for odd s.  The four
+// rows of one pass of a transpose read (32 bytes each) sit at slots 0, s, 2 s, 3 s, which
+// must stay two slots apart: s in {3, 7, 9, 13}.  One-subtile layouts (the ones read
+// through transpose reads) take the smallest such stride from DT + 8; two-subtile
+// layouts (no transpose reads) keep DT + 8, which leaves room for two workgroups per CU.
+constexpr int bf_row_stride(int DT, int NS) {
+  if (NS != 1) return DT + 8;
+  int rs = DT + 8;
+  for (;; rs += 8) {
+    const int sl = ((rs / 2) % 64) / 4;
+    if (sl == 3 || sl == 7 || sl == 9 || sl == 13) break;
+  }
+  return rs;
+}
+
 template <int PREC, int NKC, int NS_, int NB_, bool COL_, bool RAW_ = false>
 struct TileSmem {
   static constexpr int NS = NS_, NB = NB_;
@@ -374,7 +392,7 @@ struct TileSmem {
                                                     // d span the staging threads cover
   static constexpr bool BF = PREC == TMC_BF16X3;
   static constexpr int NPL = BF ? 2 : 1;
-  static constexpr int RS = BF ? DT + 8 : DT + 4;   // row stride (elements)
+  static constexpr int RS = BF ? bf_row_stride(DT, NS) : DT + 4;   // row stride (elements)
   static constexpr int CS = BF ? 40 : 36;           // d-major stride (elements)
   static constexpr int ROWN = 32 * RS, COLN = DT * CS;
   static constexpr int COLSZ = COL ? NS * COLN : 2;
@@ -382,7 +400,11 @@ struct TileSmem {
   E row[NB][NPL][NS * ROWN];
   E col[NB][NPL][COLSZ];
   E raw[NB][NPL][RAW ? NS * ROWN : 2];
-  __attribute__((aligned(16))) double lamd[DT];   // lam_d in FP64 (column norms)
+  // lam_d in FP64 (column norms), split so that the staging threads' reads of 4
+  // consecutive d (two 16-byte reads each) are contiguous across threads:
+  // lamdA[f] = (lam_4f, lam_4f+1), lamdB[f] = (lam_4f+2, lam_4f+3)
+  double2 lamdA[DT / 4];
+  double2 lamdB[DT / 4];
   float lamf[DT];        // lam_d = exp(-2 s_d)            (0 past D)
   float lam2[DT];        // log2(e) * lam_d
   float rlam2[DT];       // 1 / (log2(e) lam_d)             (0 past D)
@@ -405,7 +427,7 @@ __device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const PairPr
     const float k2 = (float)L.kappa * kLog2e;   // weights raised to the power kappa
     T.lam2[d] = lf * k2;
     T.rlam2[d] = lf > 0.0f ? 1.0f / (lf * k2) : 0.0f;
-    T.lamd[d] = (double)lf;
+    reinterpret_cast<double*>((d & 2) ? &T.lamdB[d >> 2] : &T.lamdA[d >> 2])[d & 1] = (double)lf;
   }
 }
 
@@ -525,76 +547,87 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS, WV>& pf, const 
 // waves: float4 column f of the row goes to partial A if f mod 16 < 8, else to B, each
 // partial summed in increasing f; then A + B, then a butterfly over f mod 8 (so both
 // workgroup sizes give identical norms, complete in every thread of the row).
+// tile_store_part writes float4 column m of subtile sb and adds its terms to the
+// partials qa; tile_store_norm completes a subtile's norm; tile_store does it all.
+template <class TS, int NKC, bool Q, int WV>
+__device__ __forceinline__ void tile_store_part(TS& T, int b, const TilePrefetch<NKC, TS::NS, WV>& pf,
+                                                bool scale, int sb, int m, double (&qa)[2]) {
+  constexpr int TPR = TilePrefetch<NKC, TS::NS, WV>::TPR;
+  const int t = threadIdx.x, r = t / TPR, sub = t % TPR;
+  const int pr = tile_perm(r);
+  // d < DT always (the row stride and the lam tables cover DT, so no thread
+  // branches here); slots past the data are harmless (see TilePrefetch)
+  const int d = 4 * (sub + TPR * m);
+  double& qp = qa[WV == 4 ? (m & 1) : 0];
+  const float x[4] = {pf.v[sb][m].x, pf.v[sb][m].y, pf.v[sb][m].z, pf.v[sb][m].w};
+  if constexpr (Q) {
+    const double2 la = T.lamdA[d >> 2];
+    const double2 lb = T.lamdB[d >> 2];
+    qp += la.x * (double)x[0] * (double)x[0];
+    qp += la.y * (double)x[1] * (double)x[1];
+    qp += lb.x * (double)x[2] * (double)x[2];
+    qp += lb.y * (double)x[3] * (double)x[3];
+  }
+  const int ro = sb * TS::ROWN + r * TS::RS + d;
+  const int co = sb * TS::COLN + d * TS::CS + pr;
+  if constexpr (TS::BF) {
+    uint32_t xh[2], xl[2];
+    split2(x[0], x[1], xh[0], xl[0]);
+    split2(x[2], x[3], xh[1], xl[1]);
+    if constexpr (TS::RAW) {
+      *reinterpret_cast<bf16x4*>(&T.raw[b][0][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xh[0], xh[1]});
+      *reinterpret_cast<bf16x4*>(&T.raw[b][1][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xl[0], xl[1]});
+    }
+    if constexpr (TS::COL) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        T.col[b][0][co + e * TS::CS] =
+            __builtin_bit_cast(__bf16, (uint16_t)(xh[e >> 1] >> (16 * (e & 1))));
+        T.col[b][1][co + e * TS::CS] =
+            __builtin_bit_cast(__bf16, (uint16_t)(xl[e >> 1] >> (16 * (e & 1))));
+      }
+    }
+    if (scale) {
+      const float4 l2 = *reinterpret_cast<const float4*>(&T.lam2[d]);
+      split2(x[0] * l2.x, x[1] * l2.y, xh[0], xl[0]);
+      split2(x[2] * l2.z, x[3] * l2.w, xh[1], xl[1]);
+    }
+    *reinterpret_cast<bf16x4*>(&T.row[b][0][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xh[0], xh[1]});
+    *reinterpret_cast<bf16x4*>(&T.row[b][1][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xl[0], xl[1]});
+  } else {
+    if constexpr (TS::COL) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) T.col[b][0][co + e * TS::CS] = x[e];
+    }
+    float y[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) y[e] = scale ? x[e] * T.lam2[d + e] : x[e];
+    *reinterpret_cast<float4*>(&T.row[b][0][ro]) = make_float4(y[0], y[1], y[2], y[3]);
+  }
+}
+
+// The norm of one subtile from its two partials (see tile_store).
+template <int WV>
+__device__ __forceinline__ double tile_store_norm(const double (&qa)[2]) {
+  // 4 waves: this thread holds A (even m) and B (odd m); 8 waves: threads with
+  // sub < 8 hold A, their xor-8 partners B
+  double qs = (WV == 4) ? qa[0] + qa[1] : xor_add_f64<8>(qa[0]);
+  qs = xor_add_f64<1>(qs);
+  qs = xor_add_f64<2>(qs);
+  qs = xor_add_f64<4>(qs);
+  return -0.5 * qs;
+}
+
 template <class TS, int NKC, bool Q, int WV>
 __device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC, TS::NS, WV>& pf,
                                            bool scale, double (&q)[TS::NS]) {
-  constexpr int TPR = TilePrefetch<NKC, TS::NS, WV>::TPR, NFT = TilePrefetch<NKC, TS::NS, WV>::NFT;
-  const int t = threadIdx.x, r = t / TPR, sub = t % TPR;
-  const int pr = tile_perm(r);
+  constexpr int NFT = TilePrefetch<NKC, TS::NS, WV>::NFT;
 #pragma unroll
   for (int sb = 0; sb < TS::NS; ++sb) {
     double qa[2] = {0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < NFT; ++m) {
-      // d < DT always (the row stride and the lam tables cover DT, so no thread
-      // branches here); slots past the data are harmless (see TilePrefetch)
-      const int d = 4 * (sub + TPR * m);
-      double& qp = qa[WV == 4 ? (m & 1) : 0];
-      const float x[4] = {pf.v[sb][m].x, pf.v[sb][m].y, pf.v[sb][m].z, pf.v[sb][m].w};
-      if constexpr (Q) {
-        const double2 la = *reinterpret_cast<const double2*>(&T.lamd[d]);
-        const double2 lb = *reinterpret_cast<const double2*>(&T.lamd[d + 2]);
-        qp += la.x * (double)x[0] * (double)x[0];
-        qp += la.y * (double)x[1] * (double)x[1];
-        qp += lb.x * (double)x[2] * (double)x[2];
-        qp += lb.y * (double)x[3] * (double)x[3];
-      }
-      const int ro = sb * TS::ROWN + r * TS::RS + d;
-      const int co = sb * TS::COLN + d * TS::CS + pr;
-      if constexpr (TS::BF) {
-        uint32_t xh[2], xl[2];
-        split2(x[0], x[1], xh[0], xl[0]);
-        split2(x[2], x[3], xh[1], xl[1]);
-        if constexpr (TS::RAW) {
-          *reinterpret_cast<bf16x4*>(&T.raw[b][0][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xh[0], xh[1]});
-          *reinterpret_cast<bf16x4*>(&T.raw[b][1][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xl[0], xl[1]});
-        }
-        if constexpr (TS::COL) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            T.col[b][0][co + e * TS::CS] =
-                __builtin_bit_cast(__bf16, (uint16_t)(xh[e >> 1] >> (16 * (e & 1))));
-            T.col[b][1][co + e * TS::CS] =
-                __builtin_bit_cast(__bf16, (uint16_t)(xl[e >> 1] >> (16 * (e & 1))));
-          }
-        }
-        if (scale) {
-          const float4 l2 = *reinterpret_cast<const float4*>(&T.lam2[d]);
-          split2(x[0] * l2.x, x[1] * l2.y, xh[0], xl[0]);
-          split2(x[2] * l2.z, x[3] * l2.w, xh[1], xl[1]);
-        }
-        *reinterpret_cast<bf16x4*>(&T.row[b][0][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xh[0], xh[1]});
-        *reinterpret_cast<bf16x4*>(&T.row[b][1][ro]) = __builtin_bit_cast(bf16x4, (u32x2){xl[0], xl[1]});
-      } else {
-        if constexpr (TS::COL) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) T.col[b][0][co + e * TS::CS] = x[e];
-        }
-        float y[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) y[e] = scale ? x[e] * T.lam2[d + e] : x[e];
-        *reinterpret_cast<float4*>(&T.row[b][0][ro]) = make_float4(y[0], y[1], y[2], y[3]);
-      }
-    }
-    if constexpr (Q) {
-      // 4 waves: this thread holds A (even m) and B (odd m); 8 waves: threads with
-      // sub < 8 hold A, their xor-8 partners B
-      double qs = (WV == 4) ? qa[0] + qa[1] : xor_add_f64<8>(qa[0]);
-      qs = xor_add_f64<1>(qs);
-      qs = xor_add_f64<2>(qs);
-      qs = xor_add_f64<4>(qs);
-      q[sb] = -0.5 * qs;
-    }
+    for (int m = 0; m < NFT; ++m) tile_store_part<TS, NKC, Q, WV>(T, b, pf, scale, sb, m, qa);
+    if constexpr (Q) q[sb] = tile_store_norm<WV>(qa);
   }
 }
 
