@@ -504,6 +504,8 @@ def main():
                     help="time eager launches instead of replays of the captured step graphs")
     ap.add_argument("--no-star", action="store_true",
                     help="skip the star-model measurement (Gaussian example, FP32)")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the measured machine peaks (HBM, MFMA, vector ALU, LDS probes)")
     ap.add_argument("--no-widen", action="store_true",
                     help="skip the parent-scale and DReGs-surrogate measurements")
     ap.add_argument("--no-logmm", action="store_true",
@@ -651,6 +653,40 @@ def main():
     logmm = {} if args.no_logmm else logmm_section(args, log)
     widen = {} if (args.no_widen or args.workload != "c5") else widen_section(args, log, w)
 
+    # the machine's measured peaks next to the datasheet ones the roofline uses
+    peaks = {}
+    if not args.no_peaks:
+        log("measured machine peaks")
+        from paper_1806_08593_amd import peaks as PK
+        try:
+            peaks = PK.measure()
+        except Exception as ex:
+            peaks = dict(error=str(ex)[:200])
+
+        def attach(rf, pr):
+            # measured counterpart of the roofline's peak: MFMA of the kernel's precision,
+            # HBM copy, or (vector-ALU bound) the FMA rate in lane instructions per second
+            if not rf or "error" in peaks:
+                return
+            k = {"mfma": "mfma_bf16" if pr == "bf16x3" else "mfma_fp32", "hbm": "hbm_copy",
+                 "alu": "valu_fma_fp32"}.get(rf.get("bound"))
+            if k is None or k not in peaks:
+                return
+            pm = peaks[k]["value"] / (2.0 if rf["bound"] == "alu" else 1.0)
+            rf["peak_measured"] = round(pm, 2)
+            rf["frac_of_measured"] = round(rf["achieved"] / pm, 4)
+
+        for rf in [roofline] + list(kernel_roofline.values()):
+            attach(rf, prec)
+        for v in star.values():
+            if isinstance(v, dict):
+                attach(v.get("roofline"), v.get("precision", "fp32"))
+        for pr, v in logmm.items():
+            k = {"bf16x3": "mfma_bf16", "fp32": "mfma_fp32", "fp64": "valu_fma_fp64"}.get(pr)
+            if isinstance(v, dict) and "tflops" in v and k in peaks:
+                v["peak_measured"] = peaks[k]["value"]
+                v["frac_of_measured"] = round(v["tflops"] / peaks[k]["value"], 4)
+
     cpu = None
     if not args.no_cpu_baseline:
         npdt = np.float64 if prec == "fp64" else np.float32
@@ -724,6 +760,7 @@ def main():
         "star": star,
         "logmm": logmm,
         "widen": widen,
+        "measured_peaks": peaks,
     }
     print(json.dumps(line))
 

@@ -3,7 +3,8 @@
     python -m paper_1806_08593_amd.build_lib [--jobs N]
 
 Objects go to _build/ at the repository root; the library to
-paper_1806_08593_amd/lib/libtmc.so.  Always recompiles every source.
+paper_1806_08593_amd/lib/libtmc.so, the machine-peak probes to lib/libtmc_peaks.so.
+Always recompiles every source.
 """
 import argparse
 import concurrent.futures as cf
@@ -97,6 +98,20 @@ def build(jobs=None, verbose=False, incremental=False):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(tmp, out)
+    build_peaks()
+    return out
+
+
+def build_peaks():
+    """The machine-peak probes (csrc/probe/peaks.hip) as lib/libtmc_peaks.so."""
+    src = os.path.join(CSRC, "probe", "peaks.hip")
+    out = os.path.join(LIBDIR, "libtmc_peaks.so")
+    tmp = out + ".tmp"
+    cmd = [HIPCC, "-shared", *FLAGS, src, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stderr}")
     os.replace(tmp, out)
     return out
 

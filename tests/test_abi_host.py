@@ -133,3 +133,13 @@ def test_star_validation_errors():
     _expect_star(p, T.TMC_ERR_INVALID_ARG, "reserved")
     _expect_star(T.StarProblem(65536, 32768, 4, 4, 1), T.TMC_ERR_INVALID_ARG, "launch grid")
     _expect_star(T.StarProblem(1, 8, 64 * 65535, 4, 2), T.TMC_ERR_INVALID_ARG, "launch grid")
+
+
+def test_peak_probe_library_loads():
+    """The machine-peak probes are built beside the library and export their one entry
+    point (no GPU call here)."""
+    from paper_1806_08593_amd import peaks as PK
+    lib = ctypes.CDLL(PK._LIB)
+    assert hasattr(lib, "tmc_peaks_run")
+    assert [p[0] for p in PK.PROBES] == ["hbm_copy", "hbm_read", "mfma_bf16", "mfma_fp32",
+                                         "valu_fma_fp32", "valu_exp2", "valu_fma_fp64", "lds_read"]
