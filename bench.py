@@ -416,8 +416,8 @@ def widen_section(args, log, w5):
 
 def logmm_section(args, log):
     """The log-domain matrix product on a batch of square matrices, every precision;
-    achieved = 2 M N K flops per product / launch time (the MFMA path issues 3x that in
-    BF16X3), against the dense peak of the MFMA type."""
+    achieved = 2 M N K flops per product / call time (BF16X3 issues 3x that on the
+    matrix cores), against the dense matrix-core peak of the operand type."""
     import numpy as np
     import torch
     from paper_1806_08593_amd import tmc as T
@@ -427,7 +427,7 @@ def logmm_section(args, log):
     rng = np.random.default_rng(1806)
     Xh = (rng.normal(size=(B, M, K)) * 3).astype(np.float32)
     Yh = (rng.normal(size=(B, K, N)) * 3).astype(np.float32)
-    for prec, peak in (("bf16x3", MFMA_PEAK["bf16x3"]), ("fp32", MFMA_PEAK["fp32"]), ("fp64", VALU_PEAK)):
+    for prec, peak in (("bf16x3", MFMA_PEAK["bf16x3"]), ("fp32", MFMA_PEAK["fp32"]), ("fp64", MFMA_PEAK["fp64"])):
         try:
             log(f"log-domain product {prec}")
             dt = torch.float64 if prec == "fp64" else torch.float32
@@ -682,7 +682,7 @@ def main():
             if isinstance(v, dict):
                 attach(v.get("roofline"), v.get("precision", "fp32"))
         for pr, v in logmm.items():
-            k = {"bf16x3": "mfma_bf16", "fp32": "mfma_fp32", "fp64": "valu_fma_fp64"}.get(pr)
+            k = {"bf16x3": "mfma_bf16", "fp32": "mfma_fp32", "fp64": "mfma_fp64"}.get(pr)
             if isinstance(v, dict) and "tflops" in v and k in peaks:
                 v["peak_measured"] = peaks[k]["value"]
                 v["frac_of_measured"] = round(v["tflops"] / peaks[k]["value"], 4)

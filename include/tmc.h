@@ -73,7 +73,7 @@
 extern "C" {
 #endif
 
-#define TMC_ABI_VERSION 5
+#define TMC_ABI_VERSION 6
 
 typedef enum tmc_status {
   TMC_OK = 0,
@@ -304,17 +304,18 @@ tmc_status tmc_star_gauss_bwd(tmc_plan_t plan, const void* mth, const void* s, c
  * contract: Sec. "Efficient averaging"): for b < batch,
  *   Z_b[i,k] = log sum_j exp(X_b[i,j] + Y_b[j,k]),
  * X [batch][M][K], Y [batch][K][N], Z [batch][M][N], row-major device buffers of double
- * (TMC_FP64) or float (TMC_FP32, TMC_BF16X3).  TMC_FP64: every entry exactly, with its own
- * maximum over j, on the vector ALU.  TMC_FP32 / TMC_BF16X3: the Appendix's shift by the
- * row maxima of X and the column maxima of Y, the shifted exponentials multiplied on the
- * matrix cores (FP32 MFMA, or BF16 hi/lo products as for the Gaussian factors), then
- * every entry whose shifted product fell below e^-60 (where the shift underflows: the
- * maxima of X's row and Y's column at indices j far apart) recomputed exactly.  All -inf
+ * (TMC_FP64) or float (TMC_FP32, TMC_BF16X3).  The Appendix's shift by the row maxima of X
+ * and the column maxima of Y, the shifted exponentials multiplied on the matrix cores
+ * (FP64 MFMA, FP32 MFMA, or BF16 hi/lo products as for the Gaussian factors), then every
+ * entry whose shifted product fell below e^-600 (TMC_FP64) or e^-60 (the others) --
+ * where the shift underflows: the maxima of X's row and Y's column at indices j far
+ * apart -- recomputed exactly, with its own maximum over j, on the vector ALU.  All -inf
  * rows or columns give -inf; NaN propagates; +inf inputs give NaN.  The workspace holds
- * the shifts: tmc_logmmexp_workspace_size bytes (0 for TMC_FP64), 256-byte aligned.  No
- * plan: the call validates, enqueues on `stream` and returns.  Errors: TMC_ERR_SHAPE
- * (batch or M outside [1, 65535], K or N outside [1, 2^24]), TMC_ERR_INVALID_ARG (NULL
- * pointer, unknown precision), TMC_ERR_WORKSPACE, TMC_ERR_HIP. */
+ * the shifts and the prepared operands: tmc_logmmexp_workspace_size bytes (every
+ * precision), 256-byte aligned.  No plan: the call validates, enqueues on `stream` and
+ * returns.  Errors: TMC_ERR_SHAPE (batch or M outside [1, 65535], K or N outside
+ * [1, 2^24]), TMC_ERR_INVALID_ARG (NULL pointer, unknown precision), TMC_ERR_WORKSPACE,
+ * TMC_ERR_HIP. */
 tmc_status tmc_logmmexp_workspace_size(int32_t batch, int32_t M, int32_t K, int32_t N,
                                        int32_t precision, size_t* bytes);
 tmc_status tmc_logmmexp(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t precision,

@@ -1,14 +1,14 @@
 // Log-domain matrix product (Appendix "Numerically stable matrix (tensor) products in the
 // log-domain"), batched:
 //   Z_b[i,k] = log sum_j exp(X_b[i,j] + Y_b[j,k]),  X_b [M][K], Y_b [K][N], Z_b [M][N].
-// Matrix-core path (FP32, BF16X3): the Appendix's shift, x_i = max_j X_ij and
-// y_k = max_j Y_jk, makes every exponential at most 1, so the sum is an ordinary matrix
-// product C = exp(X - x) exp(Y - y) on MFMA; the shifted exponentials are formed once, in
-// the operand layout of the product (BF16 hi/lo planes or FP32, Y's transposed, the
-// reduction index padded with zeros to a multiple of 32), and Z = log C + x + y.  Where that shift underflows (log C
-// below kLogmmFloor: the maxima of X's row and Y's column sit at indices j far apart), the
-// epilogue recomputes the entry exactly, with its own maximum over j, on the vector ALU.
-// FP64: every entry exactly on the vector ALU.
+// The Appendix's shift, x_i = max_j X_ij and y_k = max_j Y_jk, makes every exponential
+// at most 1, so the sum is an ordinary matrix product C = exp(X - x) exp(Y - y) on the
+// matrix cores; the shifted exponentials are formed once, in the operand layout of the
+// product (BF16 hi/lo planes, FP32 or FP64, Y's transposed, the reduction index padded
+// with zeros to a multiple of 32), and Z = log C + x + y.  Where that shift underflows
+// (log C below the floor, -60 in FP32 / BF16X3 and -600 in FP64: the maxima of X's row
+// and Y's column sit at indices j far apart), the epilogue recomputes the entry exactly,
+// with its own maximum over j, on the vector ALU.
 #include <math.h>
 
 #include "../../include/tmc.h"
@@ -24,12 +24,18 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// (register arrays of the operand staging use native vector types: arrays of HIP's
+// float4 / double2 structs are not promoted to registers here)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kTile = kLogmmTile;   // output rows and columns of a workgroup
 constexpr int kKC = 32;             // reduction indices staged per step
 constexpr int kPadB = 8;            // bf16 row padding of the LDS tiles (16 B)
 constexpr int kPadF = 4;            // float row padding
 constexpr float kLogmmFloor = -60.0f;
+constexpr double kLogmmFloorD = -600.0;   // FP64: far above the underflow of a product
+                                          // of two exponentials (e^-745) summed K times
 
 // x = hi + lo for two values at once (hi = bf16(x), lo = bf16(x - hi), round to nearest).
 __device__ __forceinline__ void split_pair(float a, float b, uint32_t& hi, uint32_t& lo) {
@@ -54,9 +60,13 @@ struct LogmmSmem<TMC_FP32> {
 
 // Prepared operand element e (one row of 8 consecutive j): BF16X3 writes its hi part at
 // e in the first plane and its lo part at e in the second (plane stride ps); FP32 the values.
-template <int PREC>
-__device__ __forceinline__ void store_operand(void* base, int64_t ps, int64_t e, const float (&v)[8]) {
-  if constexpr (PREC == TMC_BF16X3) {
+template <int PREC, typename T>
+__device__ __forceinline__ void store_operand(void* base, int64_t ps, int64_t e, const T (&v)[8]) {
+  if constexpr (PREC == TMC_FP64) {
+    double* dp = static_cast<double*>(base);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<double2*>(dp + e + 2 * q) = make_double2(v[2 * q], v[2 * q + 1]);
+  } else if constexpr (PREC == TMC_BF16X3) {
     uint32_t h[4], l[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) split_pair(v[2 * p], v[2 * p + 1], h[p], l[p]);
@@ -79,7 +89,7 @@ struct OperandRegs<TMC_BF16X3> {
 };
 template <>
 struct OperandRegs<TMC_FP32> {
-  float4 v[4];
+  f32x4 v[4];
 };
 
 template <int PREC>
@@ -94,7 +104,7 @@ __device__ __forceinline__ void load_operand(const void* base, int64_t ps, int64
   } else {
     const float* fp = static_cast<const float*>(base);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r.v[q] = *reinterpret_cast<const float4*>(fp + e + 4 * q);
+    for (int q = 0; q < 4; ++q) r.v[q] = *reinterpret_cast<const f32x4*>(fp + e + 4 * q);
   }
 }
 
@@ -112,7 +122,7 @@ __device__ __forceinline__ void stage_operand(LogmmSmem<PREC>& S, bool is_a, int
   } else {
     float* p = is_a ? &S.a[row][j] : &S.b[row][j];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) *reinterpret_cast<float4*>(p + 4 * q) = r.v[q];
+    for (int q = 0; q < 4; ++q) *reinterpret_cast<f32x4*>(p + 4 * q) = r.v[q];
   }
 }
 
@@ -134,21 +144,23 @@ __device__ T exact_entry(const T* __restrict__ x, const T* __restrict__ y, int K
 // (below); an all -inf row or column gets 0 (its exponentials are then 0, never NaN).
 // Column maxima: a workgroup of 16 waves per 64 columns (lane -> column), wave w takes
 // rows w, w + 16, .. (loads issued 8 at a time); the waves' maxima are merged in LDS.
-__global__ __launch_bounds__(1024) void k_logmm_colmax(LogmmArgs a) {
-  __shared__ float part[16][kWave];
+template <typename T>
+__global__ __launch_bounds__(1024) void k_logmm_colmax(LogmmArgs a, const T* __restrict__ Y,
+                                                       T* __restrict__ ys) {
+  __shared__ T part[16][kWave];
   const int b = blockIdx.z;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int64_t col = (int64_t)blockIdx.x * kWave + lane;
   const bool cv = col < a.N;
-  const float* y = a.Y + (int64_t)b * a.K * a.N + (cv ? col : 0);
-  float m = -INFINITY;
+  const T* y = Y + (int64_t)b * a.K * a.N + (cv ? col : 0);
+  T m = (T)(-INFINITY);
   constexpr int U = 8;
   for (int j0 = w; j0 < a.K; j0 += 16 * U) {
-    float v[U];
+    T v[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const int j = j0 + 16 * q;
-      v[q] = j < a.K ? y[(int64_t)j * a.N] : -INFINITY;
+      v[q] = j < a.K ? y[(int64_t)j * a.N] : (T)(-INFINITY);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) m = nan_max(m, v[q]);
@@ -158,9 +170,13 @@ __global__ __launch_bounds__(1024) void k_logmm_colmax(LogmmArgs a) {
   if (w == 0 && cv) {
 #pragma unroll
     for (int q = 1; q < 16; ++q) m = nan_max(m, part[q][lane]);
-    a.ys[(int64_t)b * a.N + col] = (m == -INFINITY) ? 0.0f : m;
+    ys[(int64_t)b * a.N + col] = (m == (T)(-INFINITY)) ? (T)0 : m;
   }
 }
+
+// exp in the operand's precision (FP64: the libm exp; otherwise the fast FP32 one)
+__device__ __forceinline__ float op_exp(float v) { return __expf(v); }
+__device__ __forceinline__ double op_exp(double v) { return exp(v); }
 
 // Operands of the product: A[b][i][j] = exp(X_b[i,j] - x_i) and Bt[b][k][j] =
 // exp(Y_b[j,k] - y_k) (Y transposed), j padded with zeros to Kp; BF16X3 stores hi and lo
@@ -169,19 +185,20 @@ __global__ __launch_bounds__(1024) void k_logmm_colmax(LogmmArgs a) {
 // row, 8 consecutive j per lane and step.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_logmm_prep_x(LogmmArgs a) {
+  typedef typename std::conditional<PREC == TMC_FP64, double, float>::type T;
   const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / kWave;   // b M + i
   if (row >= (int64_t)a.B * a.M) return;   // (uniform per wave)
   const int lane = threadIdx.x % kWave;
-  const float* x = a.X + row * a.K;
-  float m = -INFINITY;
+  const T* x = (PREC == TMC_FP64 ? (const T*)a.Xd : (const T*)a.X) + row * a.K;
+  T m = (T)(-INFINITY);
   for (int j = lane; j < a.K; j += kWave) m = nan_max(m, x[j]);
   m = wave_max(m);
-  const float sh = (m == -INFINITY) ? 0.0f : m;
-  if (lane == 0) a.xs[row] = sh;
+  const T sh = (m == (T)(-INFINITY)) ? (T)0 : m;
+  if (lane == 0) (PREC == TMC_FP64 ? (T*)a.xsd : (T*)a.xs)[row] = sh;
   for (int j0 = 8 * lane; j0 < a.Kp; j0 += 8 * kWave) {
-    float v[8];
+    T v[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) v[s] = j0 + s < a.K ? __expf(x[j0 + s] - sh) : 0.0f;
+    for (int s = 0; s < 8; ++s) v[s] = j0 + s < a.K ? op_exp(x[j0 + s] - sh) : (T)0;
     store_operand<PREC>(a.opa, (int64_t)a.B * a.M * a.Kp, row * a.Kp + j0, v);
   }
 }
@@ -190,24 +207,26 @@ __global__ __launch_bounds__(256) void k_logmm_prep_x(LogmmArgs a) {
 // transposed through LDS, written along j.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_logmm_prep_y(LogmmArgs a) {
-  __shared__ float tile[64][64 + 1];
+  typedef typename std::conditional<PREC == TMC_FP64, double, float>::type T;
+  __shared__ T tile[64][64 + 1];
   const int b = blockIdx.z, j0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
   const int t = threadIdx.x;
   {
     const int kl = t % 64, k = k0 + kl;
-    const float ysh = k < a.N ? a.ys[(int64_t)b * a.N + k] : 0.0f;
-    const float* y = a.Y + (int64_t)b * a.K * a.N;
+    const T* ysp = PREC == TMC_FP64 ? (const T*)a.ysd : (const T*)a.ys;
+    const T ysh = k < a.N ? ysp[(int64_t)b * a.N + k] : (T)0;
+    const T* y = (PREC == TMC_FP64 ? (const T*)a.Yd : (const T*)a.Y) + (int64_t)b * a.K * a.N;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int jl = 16 * (t / 64) + r, j = j0 + jl;
-      tile[kl][jl] = (j < a.K && k < a.N) ? __expf(y[(int64_t)j * a.N + k] - ysh) : 0.0f;
+      tile[kl][jl] = (j < a.K && k < a.N) ? op_exp(y[(int64_t)j * a.N + k] - ysh) : (T)0;
     }
   }
   __syncthreads();
   const int kl = t / 4, k = k0 + kl, jc = (t % 4) * 16;
   if (k >= a.N) return;
   const int64_t rowo = ((int64_t)b * a.N + k) * a.Kp + j0 + jc;
-  float v[8];
+  T v[8];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -249,9 +268,12 @@ __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
     stage_operand<PREC>(S, true, r, jg, xa);
     stage_operand<PREC>(S, false, r, jg, xb);
     __syncthreads();
-    if (j0 + kKC < Kp) {   // in flight during the MFMAs below
-      load_operand<PREC>(a.opa, pa, ra + j0 + kKC, xa);
-      load_operand<PREC>(a.opb, pb, rb + j0 + kKC, xb);
+    {
+      // the next slice, in flight during the MFMAs below (after the last slice, the last
+      // slice again: unconditional, so the operands stay in registers)
+      const int jn = min(j0 + kKC, Kp - kKC);
+      load_operand<PREC>(a.opa, pa, ra + jn, xa);
+      load_operand<PREC>(a.opb, pb, rb + jn, xb);
     }
 #pragma unroll
     for (int st = 0; st < kKC / 16; ++st) {
@@ -296,53 +318,154 @@ __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
       }
     }
   }
-  // Z = log C + x + y; an entry whose shifted product fell below the floor (or is not a
-  // number) is recomputed exactly here (rare: the lane loops over j on its own)
+  // Z = log C + x + y; the entries whose shifted product fell below the floor (or is
+  // not a number) are marked and recomputed exactly afterwards (rare: the lane loops
+  // over j on its own)
   const float floor_c = __expf(kLogmmFloor);
+  uint64_t redo = 0;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int k = k0 + wc + 32 * q + lane % 32;
-    if (k >= N) continue;
-    const float ys = a.ys[(int64_t)b * N + k];
+    const float ys = k < N ? a.ys[(int64_t)b * N + k] : 0.0f;
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int i = i0 + wr + 32 * p + 8 * (v / 4) + 4 * (lane / 32) + v % 4;
-        if (i >= M) continue;
         const float c = acc[p][q][v];
-        a.Z[((int64_t)b * M + i) * N + k] =
-            c >= floor_c ? __logf(c) + a.xs[(int64_t)b * M + i] + ys
-                         : exact_entry<float>(a.X + ((int64_t)b * M + i) * a.K,
-                                              a.Y + (int64_t)b * a.K * N + k, a.K, N);
+        if (k < N && i < M) {
+          if (c >= floor_c)
+            a.Z[((int64_t)b * M + i) * N + k] = __logf(c) + a.xs[(int64_t)b * M + i] + ys;
+          else
+            redo |= 1ull << (32 * q + 16 * p + v);
+        }
       }
-    }
+  }
+  while (redo) {
+    const int e = __builtin_ctzll(redo);
+    redo &= redo - 1;
+    const int q = e / 32, p = (e / 16) % 2, v = e % 16;
+    const int k = k0 + wc + 32 * q + lane % 32;
+    const int i = i0 + wr + 32 * p + 8 * (v / 4) + 4 * (lane / 32) + v % 4;
+    a.Z[((int64_t)b * M + i) * N + k] =
+        exact_entry<float>(a.X + ((int64_t)b * M + i) * a.K, a.Y + (int64_t)b * a.K * N + k, a.K, N);
   }
 }
 
-// Exact entries: a thread per column k of one output row (the row of X read by scalar
-// loads, Y's row j coalesced across the threads): m = max_j (X_ij + Y_jk), then
-// m + log sum_j exp(X_ij + Y_jk - m).
-template <typename T>
-__global__ __launch_bounds__(256) void k_logmm_exact(LogmmArgs a, const T* __restrict__ X,
-                                                     const T* __restrict__ Y, T* __restrict__ Z) {
-  const int b = blockIdx.z, i = blockIdx.y;
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k >= a.N) return;
-  Z[((int64_t)b * a.M + i) * a.N + k] =
-      exact_entry<T>(X + ((int64_t)b * a.M + i) * a.K, Y + (int64_t)b * a.K * a.N + k, a.K, a.N);
+// The shifted product in FP64 (v_mfma_f64_16x16x4_f64): a workgroup of 8 waves per
+// 128 x 128 output tile (wave w: rows 64 (w / 4), columns 32 (w % 4), as 4 x 2
+// accumulators of 16 x 16), the reduction index staged 16 at a time (thread t: row t / 4
+// of each operand tile, 4 consecutive j; rows past the matrix edge read the last row and
+// their results are discarded), the next slice's global loads in flight during the
+// current slice's MFMAs.  Operand fragments of k-step s: lane l holds row (column)
+// l % 16 of its block at j = 4 s + l / 16; accumulator value v of lane l is row
+// l / 16 + 4 v, column l % 16.
+constexpr int kKCd = 16;   // reduction indices per FP64 slice
+constexpr int kPadD = 2;   // row padding of the FP64 LDS tiles (keeps 16-byte rows aligned)
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(512) void k_logmm_mfma_f64(LogmmArgs a) {
+  __shared__ __attribute__((aligned(16))) double SA[kTile][kKCd + kPadD];
+  __shared__ __attribute__((aligned(16))) double SB[kTile][kKCd + kPadD];
+  const int b = blockIdx.z;
+  const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
+  const int M = a.M, N = a.N, Kp = a.Kp;
+  const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
+  const int r = t / 4, jg = (t % 4) * 4;
+  const double* opa = static_cast<const double*>(a.opa);
+  const double* opb = static_cast<const double*>(a.opb);
+  const double* pa = opa + ((int64_t)b * M + min(i0 + r, M - 1)) * Kp + jg;
+  const double* pb = opb + ((int64_t)b * N + min(k0 + r, N - 1)) * Kp + jg;
+  f64x2 xa[2], xb[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    xa[q] = *reinterpret_cast<const f64x2*>(pa + 2 * q);
+    xb[q] = *reinterpret_cast<const f64x2*>(pb + 2 * q);
+  }
+  f64x4 acc[4][2];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  const int wr = 64 * (w / 4), wc = 32 * (w % 4);
+  const int fr = lane % 16, fj = lane / 16;
+  for (int j0 = 0; j0 < Kp; j0 += kKCd) {
+    __syncthreads();   // (the previous slice's fragment reads are done)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      *reinterpret_cast<f64x2*>(&SA[r][jg + 2 * q]) = xa[q];
+      *reinterpret_cast<f64x2*>(&SB[r][jg + 2 * q]) = xb[q];
+    }
+    __syncthreads();
+    {
+      // the next slice, in flight during the MFMAs below (after the last slice, the last
+      // slice again: unconditional, so the operands stay in registers)
+      const int jn = min(j0 + kKCd, Kp - kKCd);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        xa[q] = *reinterpret_cast<const f64x2*>(pa + jn + 2 * q);
+        xb[q] = *reinterpret_cast<const f64x2*>(pb + jn + 2 * q);
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < kKCd / 4; ++st) {
+      double fa[4], fb[2];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) fa[p] = SA[wr + 16 * p + fr][4 * st + fj];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) fb[q] = SB[wc + 16 * q + fr][4 * st + fj];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[p], fb[q], acc[p][q], 0, 0, 0);
+    }
+  }
+  // Z = log C + x + y; the entries whose shifted product fell below the floor (or is
+  // not a number) are marked and recomputed exactly afterwards (rare)
+  const double floor_c = exp(kLogmmFloorD);
+  uint32_t redo = 0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int k = k0 + wc + 16 * q + fr;
+    const double ys = k < N ? a.ysd[(int64_t)b * N + k] : 0.0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr + 16 * p + fj + 4 * v;
+        const double c = acc[p][q][v];
+        if (k < N && i < M) {
+          if (c >= floor_c)
+            a.Zd[((int64_t)b * M + i) * N + k] = log(c) + a.xsd[(int64_t)b * M + i] + ys;
+          else
+            redo |= 1u << (16 * q + 4 * p + v);
+        }
+      }
+  }
+  while (redo) {
+    const int e = __builtin_ctz(redo);
+    redo &= redo - 1;
+    const int q = e / 16, p = (e / 4) % 4, v = e % 4;
+    const int k = k0 + wc + 16 * q + fr, i = i0 + wr + 16 * p + fj + 4 * v;
+    a.Zd[((int64_t)b * M + i) * N + k] =
+        exact_entry<double>(a.Xd + ((int64_t)b * M + i) * a.K, a.Yd + (int64_t)b * a.K * N + k, a.K, N);
+  }
 }
 
 hipError_t launch_logmm(const LogmmArgs& a, int precision, hipStream_t st) {
-  if (precision == TMC_FP64) {
-    hipLaunchKernelGGL((k_logmm_exact<double>), dim3((a.N + 255) / 256, a.M, a.B), dim3(256), 0, st, a,
-                       a.Xd, a.Yd, a.Zd);
-    return hipGetLastError();
-  }
-  hipLaunchKernelGGL(k_logmm_colmax, dim3((a.N + kWave - 1) / kWave, 1, a.B), dim3(1024), 0, st, a);
+  const dim3 gc((a.N + kWave - 1) / kWave, 1, a.B);
   const dim3 grid((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile, a.B);
   const dim3 gx((unsigned)(((int64_t)a.B * a.M + 3) / 4));
   const dim3 gy((a.Kp + 63) / 64, (a.N + 63) / 64, a.B);
+  if (precision == TMC_FP64) {
+    hipLaunchKernelGGL(k_logmm_colmax<double>, gc, dim3(1024), 0, st, a, a.Yd, a.ysd);
+    hipLaunchKernelGGL((k_logmm_prep_x<TMC_FP64>), gx, dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_logmm_prep_y<TMC_FP64>), gy, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_logmm_mfma_f64, grid, dim3(512), 0, st, a);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_logmm_colmax<float>, gc, dim3(1024), 0, st, a, a.Y, a.ys);
   if (precision == TMC_BF16X3) {
     hipLaunchKernelGGL((k_logmm_prep_x<TMC_BF16X3>), gx, dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_logmm_prep_y<TMC_BF16X3>), gy, dim3(256), 0, st, a);

@@ -12,6 +12,7 @@
 //     5  VALU exp2: lane results per second of v_exp_f32
 //     6  VALU FP64 FMA: flop/s
 //     7  LDS: bytes per second of ds_read_b128 summed over the CUs
+//     8  MFMA FP64: flop/s of v_mfma_f64_16x16x4_f64
 // Every probe launches 4 x (number of CUs) workgroups of 512 threads and times 5
 // launches after one warm-up with HIP events; the matrix-core probes also run with one
 // workgroup per CU (2 waves per SIMD, the occupancy of the fused kernels) and report the
@@ -83,6 +84,25 @@ __global__ __launch_bounds__(512) void k_mfma_f32(float* out, int iters) {
   for (int k = 0; k < 4; ++k)
     for (int i = 0; i < 16; ++i) s += c[k][i];
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(512) void k_mfma_f64(float* out, int iters) {
+  const int l = threadIdx.x & 63;
+  const double a = 1e-3 * (double)l, b = 2e-3 * (double)l;
+  f64x4 c[4];
+  for (int k = 0; k < 4; ++k) c[k] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c[k], 0, 0, 0);
+  }
+  double s = 0.0;
+  for (int k = 0; k < 4; ++k)
+    for (int i = 0; i < 4; ++i) s += c[k][i];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = (float)s;
 }
 
 // 8 independent chains x 8 steps per iteration
@@ -187,6 +207,7 @@ int run_one(int kind, int per_cu, double* value) {
       case 5: hipLaunchKernelGGL(k_exp2, dim3(grid), dim3(block), 0, 0, out, 1024); break;
       case 6: hipLaunchKernelGGL(k_fma_f64, dim3(grid), dim3(block), 0, 0, out, 1024, 0.999); break;
       case 7: hipLaunchKernelGGL(k_lds, dim3(grid), dim3(block), 0, 0, out, 4096); break;
+      case 8: hipLaunchKernelGGL(k_mfma_f64, dim3(grid), dim3(block), 0, 0, out, 256); break;
     }
   };
   const double waves = (double)grid * block / 64;
@@ -199,6 +220,7 @@ int run_one(int kind, int per_cu, double* value) {
     case 5: work = (double)grid * block * 1024 * 64; break;
     case 6: work = (double)grid * block * 1024 * 64 * 2.0; break;
     case 7: work = (double)grid * block * 4096 * 8 * 16.0; break;
+    case 8: work = waves * 256 * 16 * 2048.0; break;
     default: (void)hipFree(out); return (int)hipErrorInvalidValue;
   }
   if (kind <= 1) {
@@ -230,9 +252,9 @@ int run_one(int kind, int per_cu, double* value) {
 }  // namespace
 
 extern "C" int tmc_peaks_run(int kind, double* value) {
-  if (!value || kind < 0 || kind > 7) return (int)hipErrorInvalidValue;
+  if (!value || kind < 0 || kind > 8) return (int)hipErrorInvalidValue;
   int rc = run_one(kind, 4, value);
-  if (rc == 0 && (kind == 2 || kind == 3)) {
+  if (rc == 0 && (kind == 2 || kind == 3 || kind == 8)) {
     double v1 = 0.0;
     rc = run_one(kind, 1, &v1);
     if (rc == 0 && v1 > *value) *value = v1;

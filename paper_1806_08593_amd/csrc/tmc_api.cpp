@@ -1067,13 +1067,12 @@ tmc_status logmm_check(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t p
 
 int32_t logmm_kp(int32_t K) { return (K + 31) / 32 * 32; }
 
-// Shifts (floats), then the prepared operands: 4 bytes per element in both modes (two
-// BF16 planes, or FP32).
+// Shifts, then the prepared operands, in the element size of the mode: 4 bytes (two
+// BF16 planes, or FP32) or 8 (FP64).
 size_t logmm_ws(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t precision) {
-  if (precision == TMC_FP64) return 0;
-  const size_t kp = (size_t)logmm_kp(K);
-  return align_up((size_t)batch * M * 4, 256) + align_up((size_t)batch * N * 4, 256) +
-         align_up((size_t)batch * M * kp * 4, 256) + align_up((size_t)batch * N * kp * 4, 256);
+  const size_t kp = (size_t)logmm_kp(K), es = precision == TMC_FP64 ? 8 : 4;
+  return align_up((size_t)batch * M * es, 256) + align_up((size_t)batch * N * es, 256) +
+         align_up((size_t)batch * M * kp * es, 256) + align_up((size_t)batch * N * kp * es, 256);
 }
 }  // namespace
 
@@ -1092,31 +1091,36 @@ tmc_status tmc_logmmexp(int32_t batch, int32_t M, int32_t K, int32_t N, int32_t 
     tmc_status st = logmm_check(batch, M, K, N, precision);
     if (st != TMC_OK) return st;
     if (!X || !Y || !Z) return fail(TMC_ERR_INVALID_ARG, "NULL X, Y or Z");
+    if (!workspace) return fail(TMC_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+      return fail(TMC_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     LogmmArgs a{};
     a.B = batch;
     a.M = M;
     a.K = K;
     a.N = N;
+    a.Kp = logmm_kp(K);
+    const size_t es = precision == TMC_FP64 ? 8 : 4;
+    char* w = (char*)workspace;
+    void* xs = w;
+    w += align_up((size_t)batch * M * es, 256);
+    void* ys = w;
+    w += align_up((size_t)batch * N * es, 256);
+    a.opa = w;
+    w += align_up((size_t)batch * M * a.Kp * es, 256);
+    a.opb = w;
     if (precision == TMC_FP64) {
       a.Xd = (const double*)X;
       a.Yd = (const double*)Y;
       a.Zd = (double*)Z;
+      a.xsd = (double*)xs;
+      a.ysd = (double*)ys;
     } else {
-      if (!workspace) return fail(TMC_ERR_WORKSPACE, "workspace is NULL");
-      if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
-        return fail(TMC_ERR_WORKSPACE, "workspace must be 256-byte aligned");
       a.X = (const float*)X;
       a.Y = (const float*)Y;
       a.Z = (float*)Z;
-      char* w = (char*)workspace;
-      a.Kp = logmm_kp(K);
-      a.xs = (float*)w;
-      w += align_up((size_t)batch * M * 4, 256);
-      a.ys = (float*)w;
-      w += align_up((size_t)batch * N * 4, 256);
-      a.opa = w;
-      w += align_up((size_t)batch * M * a.Kp * 4, 256);
-      a.opb = w;
+      a.xs = (float*)xs;
+      a.ys = (float*)ys;
     }
     const hipError_t e = launch_logmm(a, precision, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TMC_ERR_HIP, "log-domain product launch: %s", hipGetErrorString(e));

@@ -18,13 +18,15 @@ struct LogmmArgs {
   float* ys;         // workspace [B][N]: column maxima of Y
   void* opa;         // workspace: exp(X - x) as the product's operand, [B][M][Kp] per plane
   void* opb;         // workspace: exp(Y - y) transposed, [B][N][Kp] per plane
-  const double* Xd;  // FP64
+  const double* Xd;  // FP64: inputs, output and the shifts (operands in opa, opb)
   const double* Yd;
   double* Zd;
+  double* xsd;
+  double* ysd;
 };
 
-// Enqueues the whole product on st: FP64 exact per entry; FP32 / BF16X3 shifts, the
-// shifted product on MFMA and the exact fix-up of underflowed entries.
+// Enqueues the whole product on st: the shifts, the shifted product on MFMA (FP64,
+// FP32 or BF16X3 hi/lo products) and the exact fix-up of underflowed entries.
 hipError_t launch_logmm(const LogmmArgs& a, int precision, hipStream_t st);
 
 }  // namespace tmc

@@ -1,6 +1,6 @@
 """Measured machine peaks of the GPU (lib/libtmc_peaks.so): HBM copy and read bandwidth,
 the dense BF16 and FP32 MFMA rates, the FP32 FMA, exp2 and FP64 FMA rates of the vector
-ALU, and the LDS read bandwidth -- the rates the rooflines are judged against, measured
+ALU, the LDS read bandwidth and the dense FP64 MFMA rate -- the rates the rooflines are judged against, measured
 on the device instead of taken from the datasheet.
 
     python -m paper_1806_08593_amd.peaks      # one JSON line
@@ -21,6 +21,7 @@ PROBES = [
     ("valu_exp2", "T results/s", 1e-12, None),
     ("valu_fma_fp64", "TFLOP/s", 1e-12, 78.6),
     ("lds_read", "TB/s", 1e-12, None),
+    ("mfma_fp64", "TFLOP/s", 1e-12, 78.6),
 ]
 
 

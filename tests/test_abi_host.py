@@ -19,7 +19,7 @@ def test_exports_every_declared_function():
     lib = ctypes.CDLL(T._LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert T.tmc_abi_version() == 5
+    assert T.tmc_abi_version() == 6
 
 
 def test_struct_layout_matches_header():
@@ -142,4 +142,4 @@ def test_peak_probe_library_loads():
     lib = ctypes.CDLL(PK._LIB)
     assert hasattr(lib, "tmc_peaks_run")
     assert [p[0] for p in PK.PROBES] == ["hbm_copy", "hbm_read", "mfma_bf16", "mfma_fp32",
-                                         "valu_fma_fp32", "valu_exp2", "valu_fma_fp64", "lds_read"]
+                                         "valu_fma_fp32", "valu_exp2", "valu_fma_fp64", "lds_read", "mfma_fp64"]

@@ -7,7 +7,8 @@ pytestmark = pytest.mark.gpu
 
 # (low, high) as fractions of the datasheet figure; absolute bands where there is none
 BANDS = {"hbm_copy": (0.3, 1.05), "hbm_read": (0.3, 1.05), "mfma_bf16": (0.3, 1.05),
-         "mfma_fp32": (0.3, 1.05), "valu_fma_fp32": (0.3, 1.05), "valu_fma_fp64": (0.3, 1.05)}
+         "mfma_fp32": (0.3, 1.05), "valu_fma_fp32": (0.3, 1.05), "valu_fma_fp64": (0.3, 1.05),
+         "mfma_fp64": (0.3, 1.05)}
 ABS = {"valu_exp2": (2.0, 80.0), "lds_read": (10.0, 160.0)}
 
 

@@ -644,7 +644,9 @@ def check_logmm(B, M, K, N):
                 r, jg = t // 2, (t % 2) * 16
                 ra = (b * M + np.minimum(i0 + r, M - 1)) * Kp + jg
                 rb = (b * N + np.minimum(k0 + r, N - 1)) * Kp + jg
-                for jj in range(0, Kp, 32):
+                # the first slice, then in each step the next one (the last slice again
+                # after the last step)
+                for jj in [0] + [min(j0 + 32, Kp - 32) for j0 in range(0, Kp, 32)]:
                     for s_ in range(16):
                         Bf.check("opa", ra + jj + s_, block=None)
                         Bf.check("opa", B * M * Kp + ra + jj + s_)
@@ -666,18 +668,50 @@ def check_logmm(B, M, K, N):
                                     Bf.check("X", (b * M + i) * K + j, mask=live)
                                     Bf.check("Y", b * K * N + j * N + k, mask=live)
                     Bf.check("ys", b * N + k, mask=k < N)
-        # exact entries (FP64)
-        for i in range(M):
-            k = np.arange(cdiv(N, 256) * 256)
-            okk = k < N
-            Bf.check("Z", (b * M + i) * N + k, mask=okk)
-            Bf.check("ys", b * N + k, mask=okk)
-            for j in range(K):
-                Bf.check("X", (b * M + i) * K + j)
-                Bf.check("Y", b * K * N + j * N + k, mask=okk)
+    assert not Bf.bad, Bf.bad[:5]
+
+
+def check_logmm_f64(B, M, K, N):
+    """The FP64 product kernel (8 waves per 128 x 128 tile, 16-wide slices, thread t: row
+    t / 4 and 4 consecutive j of each operand tile; accumulator value v of lane l at row
+    l / 16 + 4 v, column l % 16 of its 16 x 16 block).  Buffers in doubles; the row and
+    column maxima and the operand preparation index like the FP32 form (one plane)."""
+    Kp = cdiv(K, 32) * 32
+    Bf = Buffers(X=B * M * K, Y=B * K * N, Z=B * M * N, xs=B * M, ys=B * N,
+                 opa=B * M * Kp, opb=B * N * Kp)
+    t = np.arange(512)
+    for b in range(B):
+        for by in range(cdiv(M, LOGMM_TILE)):
+            for bx in range(cdiv(N, LOGMM_TILE)):
+                i0, k0 = by * LOGMM_TILE, bx * LOGMM_TILE
+                r, jg = t // 4, (t % 4) * 4
+                ra = (b * M + np.minimum(i0 + r, M - 1)) * Kp + jg
+                rb = (b * N + np.minimum(k0 + r, N - 1)) * Kp + jg
+                for jj in [0] + [min(j0 + 16, Kp - 16) for j0 in range(0, Kp, 16)]:
+                    for s_ in range(4):
+                        Bf.check("opa", ra + jj + s_, block=None)
+                        Bf.check("opb", rb + jj + s_, block=None)
+                        assert np.all((jg + s_) < 16)
+                lane, w = t % 64, t // 64
+                wr, wc = 64 * (w // 4), 32 * (w % 4)
+                assert np.all(wr + 48 + 15 < LOGMM_TILE) and np.all(wc + 16 + 15 < LOGMM_TILE)
+                for q in range(2):
+                    k = k0 + wc + 16 * q + lane % 16
+                    Bf.check("ys", b * N + k, mask=k < N)
+                    for p in range(4):
+                        for v in range(4):
+                            i = i0 + wr + 16 * p + lane // 16 + 4 * v
+                            live = (k < N) & (i < M)
+                            Bf.check("Z", (b * M + i) * N + k, mask=live)
+                            Bf.check("xs", b * M + i, mask=live)
+                            if p == 0 and v == 0:   # the exact recompute of an entry
+                                for j in range(K):
+                                    Bf.check("X", (b * M + i) * K + j, mask=live)
+                                    Bf.check("Y", b * K * N + j * N + k, mask=live)
     assert not Bf.bad, Bf.bad[:5]
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1, 1), (3, 70, 45, 130), (2, 129, 33, 257), (1, 5, 300, 7)])
 def test_logmm_accesses_in_bounds(shape):
     check_logmm(*shape)
+    check_logmm_f64(*shape)
