@@ -77,6 +77,15 @@ __device__ __forceinline__ T star_x(const T* __restrict__ zr, const T (&mt)[DB],
 // exp(x - mx) as exp2 of one fused multiply-add.  Branch-free: the maximum ignores NaN
 // (fmax) while a NaN row still makes the sum NaN; an all -inf prefix keeps (mx, sm) =
 // (-inf, 0).
+// Rows a step batches (loads first): kStarRows for narrow latents, fewer for wide ones
+// (a row's working set is DB values per lane; batching 8 of them at d = 32 exceeds the
+// register file).  The rows are still taken in order, so the sums do not change.
+template <typename T, int DB>
+constexpr int kRowsFor = (DB * (int)sizeof(T) <= 16)    ? kStarRows
+                         : (DB * (int)sizeof(T) <= 64)  ? kStarRows / 2
+                         : (DB * (int)sizeof(T) <= 128) ? kStarRows / 4
+                                                        : 1;
+
 template <typename T, int DB, int NR>
 __device__ __forceinline__ void star_rows(const T* __restrict__ z, const T* __restrict__ u, int k0,
                                           int D, const T (&mt)[DB], const T (&nlam)[DB], T& mx, T& sm) {
@@ -102,7 +111,7 @@ __device__ __forceinline__ void star_rows(const T* __restrict__ z, const T* __re
 
 // Messages.  A workgroup per (instance, group of P points, 64 global samples); lane ->
 // global sample kt, and the waves take the group's points in turn (wave wv: points
-// wv, wv + 4, ..).  A wave walks all K local samples of its point, kStarRows at a time,
+// wv, wv + 4, ..).  A wave walks all K local samples of its point, kRowsFor at a time,
 // reading them with scalar loads, and keeps a running (max, sum) per lane; no LDS and no
 // barrier until the group's sums of m_i are combined in wave order.
 template <typename T, int DB>
@@ -126,7 +135,8 @@ __global__ __launch_bounds__(kStarThreads) void k_star_msg(StarArgs<T> a) {
     const T* u = a.u + pi * K;
     T mx = (T)(-INFINITY), sm = (T)0;
     int k = 0;
-    for (; k + kStarRows <= K; k += kStarRows) star_rows<T, DB, kStarRows>(z, u, k, D, mt, nlam, mx, sm);
+    constexpr int NRB = kRowsFor<T, DB>;
+    for (; k + NRB <= K; k += NRB) star_rows<T, DB, NRB>(z, u, k, D, mt, nlam, mx, sm);
     for (; k < K; ++k) star_rows<T, DB, 1>(z, u, k, D, mt, nlam, mx, sm);
     // (all -inf: -inf + log 0 = -inf; a NaN row: log NaN = NaN)
     const double lse = (double)mx + log((double)sm);   // m_i + ln K - c
@@ -214,7 +224,7 @@ __global__ __launch_bounds__(256) void k_star_logp(StarArgs<T> a) {
 }
 
 // Local gradients.  A wave per (instance and point, 64 local samples): lane -> local
-// sample k; the wave walks every global sample t, kStarRows at a time (mean, weight and
+// sample k; the wave walks every global sample t, kRowsFor at a time (mean, weight and
 // this point's message by scalar loads; samples of weight 0 add 0) and accumulates
 //   gs = sum_t G,  gz_d = sum_t G (z_kd - mth_td),  gq_d = sum_t G (z_kd - mth_td)^2
 // with G = w_t exp(u_k + f[t, k] - m_i[t] - ln K).  Writes du, dz and this block's part of
@@ -261,15 +271,16 @@ __global__ __launch_bounds__(kStarThreads) void k_star_bwd_local(StarArgs<T> a) 
   };
   const int stride = DB == 1 ? 1 : D;
   int t = 0;
-  for (; t + kStarRows <= Kt; t += kStarRows) {
-    T wr[kStarRows], nr[kStarRows];
+  constexpr int NRB = kRowsFor<T, DB>;
+  for (; t + NRB <= Kt; t += NRB) {
+    T wr[NRB], nr[NRB];
 #pragma unroll
-    for (int r = 0; r < kStarRows; ++r) {   // (all loads of the step first)
+    for (int r = 0; r < NRB; ++r) {   // (all loads of the step first)
       wr[r] = w[t + r];
       nr[r] = nshp[t + r];
     }
 #pragma unroll
-    for (int r = 0; r < kStarRows; ++r) row(mth + (int64_t)(t + r) * stride, wr[r], nr[r]);
+    for (int r = 0; r < NRB; ++r) row(mth + (int64_t)(t + r) * stride, wr[r], nr[r]);
   }
   for (; t < Kt; ++t) row(mth + (int64_t)t * stride, w[t], nshp[t]);
   const double g = a.dlogp[inst];
@@ -322,12 +333,13 @@ __global__ __launch_bounds__(kStarThreads) void k_star_bwd_global(StarArgs<T> a)
     // (a lane of weight 0 has a finite offset or only -inf exponents: its G are 0)
     const T nsh = ktv ? a.nsh[pi * Kt + kt] : (T)0;
     int k = 0;
-    for (; k + kStarRows <= K; k += kStarRows) {
-      T ur[kStarRows];
+    constexpr int NRB = kRowsFor<T, DB>;
+    for (; k + NRB <= K; k += NRB) {
+      T ur[NRB];
 #pragma unroll
-      for (int r = 0; r < kStarRows; ++r) ur[r] = u[k + r];
+      for (int r = 0; r < NRB; ++r) ur[r] = u[k + r];
 #pragma unroll
-      for (int r = 0; r < kStarRows; ++r) {
+      for (int r = 0; r < NRB; ++r) {
         const T* zr = z + (int64_t)(k + r) * stride;
         T x = ur[r], df[DB];
 #pragma unroll
