@@ -158,24 +158,31 @@ __global__ __launch_bounds__(kStarThreads) void k_star_msg(StarArgs<T> a) {
   }
 }
 
+// The sums over point groups (logits of the global samples, the d mth parts) are few
+// but long: a workgroup of kRedWaves waves per 64 sums, each wave a strided share of the
+// groups with kRedUnroll loads in flight, so that the latency of the loads is spread
+// over many waves.
+constexpr int kRedWaves = 16;
+constexpr int kRedUnroll = 16;
+
 // Logits of the global samples: w[kt] = uth[kt] + sum over groups of gsum.  A workgroup
-// per (instance, 64 kt); wave wv sums groups wv, wv + 4, .. (loads issued 8 at a time,
-// added in group order), then the waves in order.
+// per (instance, 64 kt); wave wv sums groups wv, wv + kRedWaves, .. (added in group
+// order), then the waves in order.
 template <typename T>
-__global__ __launch_bounds__(kStarThreads) void k_star_colsum(StarArgs<T> a) {
-  __shared__ double part[kStarWaves][kStarLanes];
+__global__ __launch_bounds__(kRedWaves * kWave) void k_star_colsum(StarArgs<T> a) {
+  __shared__ double part[kRedWaves][kStarLanes];
   const int inst = blockIdx.x;
   const int lane = threadIdx.x % kWave, wv = wave_index();
   const int kt = blockIdx.y * kStarLanes + lane;
   const bool ktv = kt < a.Kt;
   const double* gs = a.gsum + (int64_t)inst * a.ngrp * a.Kt + (ktv ? kt : 0);
   double acc = 0.0;
-  constexpr int U = 8;
-  for (int g0 = wv; g0 < a.ngrp; g0 += kStarWaves * U) {
+  constexpr int U = kRedUnroll;
+  for (int g0 = wv; g0 < a.ngrp; g0 += kRedWaves * U) {
     double v[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int g = g0 + kStarWaves * q;
+      const int g = g0 + kRedWaves * q;
       v[q] = g < a.ngrp ? gs[(int64_t)g * a.Kt] : 0.0;
     }
 #pragma unroll
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(kStarThreads) void k_star_colsum(StarArgs<T> a) {
   if (wv == 0 && ktv) {
     double v = (double)a.uth[(int64_t)inst * a.Kt + kt];
 #pragma unroll
-    for (int w = 0; w < kStarWaves; ++w) v += part[w][lane];
+    for (int w = 0; w < kRedWaves; ++w) v += part[w][lane];
     a.w[(int64_t)inst * a.Kt + kt] = v;
   }
 }
@@ -382,30 +389,30 @@ __global__ __launch_bounds__(kStarThreads) void k_star_bwd_global(StarArgs<T> a)
 }
 
 // Final sums.  Blocks y < ceil(Kt D / 64): d mth of 64 entries (wave wv sums groups
-// wv, wv + 4, .., loads issued 8 at a time; then the waves in order), scaled by dlogp lam.
-// Block y = last: ds (the workgroup strides over the N nkb parts, then a fixed-order
-// tree) and d uth = dlogp w.
+// wv, wv + kRedWaves, ..; then the waves in order), scaled by dlogp lam.  Block y = last:
+// ds (the workgroup strides over the N nkb parts, then a fixed-order tree) and
+// d uth = dlogp w.
 template <typename T>
-__global__ __launch_bounds__(kStarThreads) void k_star_reduce(StarArgs<T> a) {
-  __shared__ double part[kStarWaves][kStarLanes];
+__global__ __launch_bounds__(kRedWaves * kWave) void k_star_reduce(StarArgs<T> a) {
+  __shared__ double part[kRedWaves][kStarLanes];
   __shared__ double red[kMaxWaves];
   const int inst = blockIdx.x;
   const int lane = threadIdx.x % kWave, wv = wave_index();
   const int D = a.D, Kt = a.Kt;
   const int64_t KD = (int64_t)Kt * D;
   const double g = a.dlogp[inst];
-  constexpr int U = 8;
+  constexpr int U = kRedUnroll;
   if (blockIdx.y + 1 < gridDim.y) {
     if (!a.dmth) return;   // (uniform)
     const int64_t e = (int64_t)blockIdx.y * kStarLanes + lane;
     const bool ev = e < KD;
     const double* dm = a.dm + (int64_t)inst * a.ngrp * KD + (ev ? e : 0);
     double acc = 0.0;
-    for (int g0 = wv; g0 < a.ngrp; g0 += kStarWaves * U) {
+    for (int g0 = wv; g0 < a.ngrp; g0 += kRedWaves * U) {
       double v[U];
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const int gi = g0 + kStarWaves * q;
+        const int gi = g0 + kRedWaves * q;
         v[q] = gi < a.ngrp ? dm[(int64_t)gi * KD] : 0.0;
       }
 #pragma unroll
@@ -416,7 +423,7 @@ __global__ __launch_bounds__(kStarThreads) void k_star_reduce(StarArgs<T> a) {
     if (wv == 0 && ev) {
       double v = 0.0;
 #pragma unroll
-      for (int w = 0; w < kStarWaves; ++w) v += part[w][lane];
+      for (int w = 0; w < kRedWaves; ++w) v += part[w][lane];
       const int d = (int)(e % D);
       const double lam = exp(-2.0 * (double)a.s[(int64_t)inst * D + d]);
       a.dmth[(int64_t)inst * KD + e] = (T)(g * lam * v);
@@ -466,7 +473,7 @@ hipError_t launch_star_msg(const StarArgs<T>& a, hipStream_t st) {
 template <typename T>
 hipError_t launch_star_colsum(const StarArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL((k_star_colsum<T>), dim3(a.S, (a.Kt + kStarLanes - 1) / kStarLanes),
-                     dim3(kStarThreads), 0, st, a);
+                     dim3(kRedWaves * kWave), 0, st, a);
   return hipGetLastError();
 }
 
@@ -495,7 +502,7 @@ template <typename T>
 hipError_t launch_star_reduce(const StarArgs<T>& a, hipStream_t st) {
   const int64_t KD = (int64_t)a.Kt * a.D;
   const int ny = (int)((KD + kStarLanes - 1) / kStarLanes) + 1;
-  hipLaunchKernelGGL((k_star_reduce<T>), dim3(a.S, ny), dim3(kStarThreads), 0, st, a);
+  hipLaunchKernelGGL((k_star_reduce<T>), dim3(a.S, ny), dim3(kRedWaves * kWave), 0, st, a);
   return hipGetLastError();
 }
 #undef TMC_STAR_BY_WIDTH
