@@ -24,6 +24,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // (register arrays of the operand staging use native vector types: arrays of HIP's
 // float4 / double2 structs are not promoted to registers here)
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -190,6 +191,70 @@ __global__ __launch_bounds__(256) void k_logmm_prep_x(LogmmArgs a) {
   if (row >= (int64_t)a.B * a.M) return;   // (uniform per wave)
   const int lane = threadIdx.x % kWave;
   const T* x = (PREC == TMC_FP64 ? (const T*)a.Xd : (const T*)a.X) + row * a.K;
+  if constexpr (PREC != TMC_FP64) {
+    // Rows of at most 1024 floats, 16-byte aligned: one read into registers (lane: 4
+    // consecutive j of each 256-wide chunk), the maximum, then the exponentials from the
+    // registers -- X is read once instead of twice (FP64 below: 2 j of 8 chunks).
+    if (a.Kp <= 1024 && (a.K % 4) == 0 && (reinterpret_cast<uintptr_t>(a.X) % 16) == 0) {
+      f32x4 v[4];
+      float m = -INFINITY;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int e = 4 * (lane + kWave * c);
+        v[c] = e < a.K ? *reinterpret_cast<const f32x4*>(x + e)
+                       : (f32x4){-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) m = nan_max(m, v[c][i]);
+      }
+      m = wave_max(m);
+      const float sh = (m == -INFINITY) ? 0.0f : m;
+      if (lane == 0) a.xs[row] = sh;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int e = 4 * (lane + kWave * c);
+        if (e >= a.Kp) continue;
+        float o[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = e + i < a.K ? __expf(v[c][i] - sh) : 0.0f;
+        const int64_t eo = row * a.Kp + e;
+        if constexpr (PREC == TMC_BF16X3) {
+          uint32_t h[2], l[2];
+          split_pair(o[0], o[1], h[0], l[0]);
+          split_pair(o[2], o[3], h[1], l[1]);
+          __bf16* bp = static_cast<__bf16*>(a.opa);
+          const int64_t ps = (int64_t)a.B * a.M * a.Kp;
+          *reinterpret_cast<u32x2*>(bp + eo) = (u32x2){h[0], h[1]};
+          *reinterpret_cast<u32x2*>(bp + ps + eo) = (u32x2){l[0], l[1]};
+        } else {
+          *reinterpret_cast<f32x4*>(static_cast<float*>(a.opa) + eo) = (f32x4){o[0], o[1], o[2], o[3]};
+        }
+      }
+      return;
+    }
+  } else {
+    // FP64 rows of at most 1024 doubles: lane j pairs 2 (lane + 64 c), c < 8
+    if (a.Kp <= 1024 && (a.K % 2) == 0 && (reinterpret_cast<uintptr_t>(a.Xd) % 16) == 0) {
+      f64x2 v[8];
+      double m = -INFINITY;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int e = 2 * (lane + kWave * c);
+        v[c] = e < a.K ? *reinterpret_cast<const f64x2*>(x + e) : (f64x2){-INFINITY, -INFINITY};
+        m = nan_max(m, nan_max(v[c][0], v[c][1]));
+      }
+      m = wave_max(m);
+      const double sh = (m == -INFINITY) ? 0.0 : m;
+      if (lane == 0) a.xsd[row] = sh;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int e = 2 * (lane + kWave * c);
+        if (e >= a.Kp) continue;
+        const f64x2 o = {e < a.K ? exp(v[c][0] - sh) : 0.0, e + 1 < a.K ? exp(v[c][1] - sh) : 0.0};
+        *reinterpret_cast<f64x2*>(static_cast<double*>(a.opa) + row * a.Kp + e) = o;
+      }
+      return;
+    }
+  }
   T m = (T)(-INFINITY);
   for (int j = lane; j < a.K; j += kWave) m = nan_max(m, x[j]);
   m = wave_max(m);

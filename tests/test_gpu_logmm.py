@@ -54,7 +54,7 @@ def check(got, want, prec, label):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("shape", [(1, 1, 1, 1), (3, 70, 45, 130), (2, 64, 64, 64), (1, 129, 33, 65),
-                                   (1, 5, 300, 7), (2, 200, 96, 3)])
+                                   (1, 5, 300, 7), (2, 200, 96, 3), (1, 3, 1024, 5), (1, 2, 1028, 3)])
 def test_logmm_matches_oracle(prec, shape):
     B, M, K, N = shape
     rng = np.random.default_rng(sum(shape))
@@ -63,15 +63,16 @@ def test_logmm_matches_oracle(prec, shape):
     check(run(X, Y, prec), ref(X, Y, prec), prec, f"{prec}-{shape}")
 
 
+@pytest.mark.parametrize("K", [70, 72])
 @pytest.mark.parametrize("prec,gap", [("fp64", 400.0), ("fp64", 800.0), ("fp32", 400.0),
                                       ("bf16x3", 400.0)])
-def test_logmm_underflowing_shift_and_infinities(prec, gap):
+def test_logmm_underflowing_shift_and_infinities(prec, gap, K):
     """Rows of X peaking at small j and columns of Y peaking at large j by `gap` nats (past
     the floor of the shifted product -- e^-60, or e^-600 in FP64 -- the fix-up pass
     recomputes those entries; FP64 at a gap of 400 keeps them on the matrix cores), plus an
     all -inf row of X, an all -inf column of Y and a NaN entry."""
     rng = np.random.default_rng(7)
-    B, M, K, N = 2, 40, 70, 50
+    B, M, N = 2, 40, 50   # (K = 72: rows of X prepared in one read)
     X = rng.normal(size=(B, M, K))
     Y = rng.normal(size=(B, K, N))
     X[:, :10, 35:] -= gap            # rows 0..9 peak in j < 35
@@ -81,7 +82,7 @@ def test_logmm_underflowing_shift_and_infinities(prec, gap):
     X[1, 33, 5] = np.nan
     want = ref(X, Y, prec)
     assert np.all(want[:, :10, :12] < 20 - gap)   # the entries the shift loses
-    check(run(X, Y, prec), want, prec, f"{prec}-underflow-{gap:.0f}")
+    check(run(X, Y, prec), want, prec, f"{prec}-underflow-{gap:.0f}-K{K}")
 
 
 def test_logmm_chain_of_products_is_the_discrete_estimator():

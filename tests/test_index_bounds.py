@@ -600,7 +600,20 @@ def check_logmm(B, M, K, N):
     Bf = Buffers(X=B * M * K, Y=B * K * N, Z=B * M * N, xs=B * M, ys=B * N,
                  opa=2 * B * M * Kp, opb=2 * B * N * Kp)
     t = np.arange(256)
-    # operand preparation of X: a wave per row (its maximum, then 8 consecutive j per lane)
+    # operand preparation of X, rows of at most 1024 aligned floats: one read of 4
+    # consecutive j per lane and 256-wide chunk, the same positions written
+    if Kp <= 1024 and K % 4 == 0:
+        lane = np.arange(64)
+        for row in range(B * M):
+            for c in range(4):
+                e = 4 * (lane + 64 * c)
+                for i in range(4):
+                    Bf.check("X", row * K + e + i, mask=e < K)
+                    Bf.check("opa", row * Kp + e + i, mask=e < Kp)
+                    Bf.check("opa", B * M * Kp + row * Kp + e + i, mask=e < Kp)
+            Bf.check("xs", row)
+    # operand preparation of X otherwise: a wave per row (its maximum, then 8 consecutive
+    # j per lane)
     for row in range(B * M):
         lane = np.arange(64)
         for jj in range(0, K, 64):
@@ -679,6 +692,15 @@ def check_logmm_f64(B, M, K, N):
     Kp = cdiv(K, 32) * 32
     Bf = Buffers(X=B * M * K, Y=B * K * N, Z=B * M * N, xs=B * M, ys=B * N,
                  opa=B * M * Kp, opb=B * N * Kp)
+    if Kp <= 1024 and K % 2 == 0:   # rows of X in one read: 2 j of 8 chunks per lane
+        lane = np.arange(64)
+        for row in range(B * M):
+            for c in range(8):
+                e = 2 * (lane + 64 * c)
+                for i in range(2):
+                    Bf.check("X", row * K + e + i, mask=e < K)
+                    Bf.check("opa", row * Kp + e + i, mask=e < Kp)
+            Bf.check("xs", row)
     t = np.arange(512)
     for b in range(B):
         for by in range(cdiv(M, LOGMM_TILE)):
@@ -711,7 +733,8 @@ def check_logmm_f64(B, M, K, N):
     assert not Bf.bad, Bf.bad[:5]
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (3, 70, 45, 130), (2, 129, 33, 257), (1, 5, 300, 7)])
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (3, 70, 45, 130), (2, 129, 33, 257), (1, 5, 300, 7),
+                                   (2, 3, 1024, 5), (1, 2, 996, 3), (1, 2, 1028, 3)])
 def test_logmm_accesses_in_bounds(shape):
     check_logmm(*shape)
     check_logmm_f64(*shape)
