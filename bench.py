@@ -675,6 +675,8 @@ def main():
             pm = peaks[k]["value"] / (2.0 if rf["bound"] == "alu" else 1.0)
             rf["peak_measured"] = round(pm, 2)
             rf["frac_of_measured"] = round(rf["achieved"] / pm, 4)
+            if "issued_tflops" in rf:
+                rf["issued_frac_of_measured"] = round(rf["issued_tflops"] / pm, 4)
 
         for rf in [roofline] + list(kernel_roofline.values()):
             attach(rf, prec)
