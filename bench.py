@@ -600,22 +600,30 @@ def main():
     compare = {}
     runs = {}
     if not args.no_compare and prec != "fp64":
-        cands = [("fp32_fused", w, "fp32", "fused"), ("fp32_plain", w, "fp32", "plain")]
+        cands = [("fp32_fused", w, "fp32", "fused", 0), ("fp32_plain", w, "fp32", "plain", 0)]
         if args.workload != "c3":
             wc3 = make("c3")
-            cands += [("c3_bf16x3", wc3, "bf16x3", "auto"), ("c3_fp32_fused", wc3, "fp32", "fused"),
-                      ("c3_fp32_plain", wc3, "fp32", "plain")]
-        for name, wl, cp, ce in cands:
+            cands += [("c3_bf16x3", wc3, "bf16x3", "auto", 0), ("c3_fp32_fused", wc3, "fp32", "fused", 0),
+                      ("c3_fp32_plain", wc3, "fp32", "plain", 0)]
+        if args.workload != "c4":
+            # the ragged batch in its configuration's precision: tuned per-depth launches and
+            # persistent launches over the chain queue
+            wc4 = make("c4")
+            cands += [("c4_fp32_fused", wc4, "fp32", "fused", 0),
+                      ("c4_fp32_persistent", wc4, "fp32", "fused", T.TMC_FLAG_PERSISTENT)]
+        for name, wl, cp, ce, fl in cands:
             if (wl is w) and (cp, ce) == (prec, args.engine):
                 continue
             try:
                 log(f"comparator {name}")
                 r = run_mode(wl, cp, ce, max(3, args.steps // 3), 2, timing=True,
-                             tune=not args.no_tune and ce != "plain", graph=not args.no_graph)
+                             tune=not args.no_tune and ce != "plain" and not fl, flags=fl,
+                             graph=not args.no_graph)
                 ent = wl.entries()
                 e = dict(workload=wl.name, precision=cp, engine=ce, ms_per_step=r["ms_per_step"],
                          value=ent / (r["ms_per_step"] / 1e3),
-                         mem_high_water_bytes=r["mem_high_water_bytes"])
+                         mem_high_water_bytes=r["mem_high_water_bytes"],
+                         launch="persistent" if r["info"]["persistent"] else "per-depth")
                 # HBM rate of the plain engine's log-sum-exp passes over the stored factors
                 for kk in ("plain_lse_fwd", "plain_lse_bwd"):
                     if kk in r["kernels"]:
