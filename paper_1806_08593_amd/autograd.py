@@ -1,7 +1,8 @@
-"""torch.autograd wrappers of the Gaussian-chain TMC estimator (and of the DReGs surrogate).
+"""torch.autograd wrappers of the Gaussian-chain TMC estimator, of the DReGs surrogate and of
+the star model.
 
 Only marshalling: the forward and backward passes are the library's tmc_gauss_fwd /
-tmc_gauss_bwd kernels.  torch provides device memory, the stream, and carries the
+tmc_gauss_bwd (tmc_star_gauss_fwd / _bwd) kernels.  torch provides device memory, the stream, and carries the
 returned gradients on into the caller's networks (mu and u are functions of the
 caller's parameters and of the reparameterised samples z).
 """
@@ -143,3 +144,57 @@ class _GaussChainFn(torch.autograd.Function):
         du = torch.empty_like(u) if need[3] else None
         T.tmc_gauss_bwd(ctx.runner.plan.handle, z, mu, s, u, dlogp, ctx.ws, dz, dmu, ds, du)
         return dz, dmu, ds, du, None
+
+
+class StarGaussTMC:
+    """S instances of the star model -- one global latent with K_theta samples shared by N
+    local latents with K samples of width D each:
+        mth [S, Kt, D] (mean of every local latent given global sample kt), s [S, D],
+        z [S, N, K, D], u [S, N, K], uth [S, Kt]
+    -> log P_TMC [S] (float64), differentiable in all five.
+    precision: 'fp64' | 'fp32'."""
+
+    def __init__(self, S, N, Kt, K, D, precision="fp32", device=0):
+        self.problem = T.StarProblem(S, N, Kt, K, D, precision)
+        self.plan = T.Plan(self.problem, device)
+        self.shape = (S, N, Kt, K, D)
+        self.dtype = _DT[self.problem.c.precision]
+        self.device = torch.device(f"cuda:{device}")
+
+    def __call__(self, mth, s, z, u, uth):
+        S, N, Kt, K, D = self.shape
+        want = {"mth": (mth, (S, Kt, D)), "s": (s, (S, D)), "z": (z, (S, N, K, D)),
+                "u": (u, (S, N, K)), "uth": (uth, (S, Kt))}
+        for name, (t, shp) in want.items():
+            if tuple(t.shape) != shp:
+                raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {shp}")
+            if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous():
+                raise ValueError(f"{name}: needs a contiguous {self.dtype} tensor on {self.device}")
+        return _StarFn.apply(mth, s, z, u, uth, self)
+
+
+class _StarFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mth, s, z, u, uth, runner: StarGaussTMC):
+        ws = runner.plan.new_workspace()
+        logp = torch.empty(runner.shape[0], dtype=torch.float64, device=z.device)
+        T.tmc_star_gauss_fwd(runner.plan.handle, mth, s, z, u, uth, logp, ws)
+        ctx.save_for_backward(mth, s, z, u)
+        ctx.ws = ws
+        ctx.runner = runner
+        ctx.uth_like = uth
+        return logp
+
+    @staticmethod
+    def backward(ctx, dlogp):
+        mth, s, z, u = ctx.saved_tensors
+        dlogp = dlogp.to(torch.float64).contiguous()
+        need = ctx.needs_input_grad
+        dmth = torch.empty_like(mth) if need[0] else None
+        ds = torch.empty_like(s) if need[1] else None
+        dz = torch.empty_like(z) if need[2] else None
+        du = torch.empty_like(u) if need[3] else None
+        duth = torch.empty_like(ctx.uth_like) if need[4] else None
+        T.tmc_star_gauss_bwd(ctx.runner.plan.handle, mth, s, z, u, dlogp, ctx.ws, dmth, ds, dz,
+                             du, duth)
+        return dmth, ds, dz, du, duth, None

@@ -214,3 +214,21 @@ def test_star_full_size(config, prec):
     exact = _exact_evidence(config)
     N = w.shape["N"]
     assert exact - 0.1 * N < out["logp"][0] < exact + 0.01 * N, (out["logp"][0], exact)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_star_autograd_wrapper(prec):
+    """torch.autograd over the star model: a weighted sum of the instances' log P
+    differentiates to the weighted oracle gradients of all five inputs."""
+    from paper_1806_08593_amd import autograd as A
+    w = gauss_star(S=3, N=9, Kt=70, K=65, D=3, kind="general")
+    sh = w.shape
+    run = A.StarGaussTMC(sh["S"], sh["N"], sh["Kt"], sh["K"], sh["D"], precision=prec)
+    dt = np_dtype(prec)
+    t = {k: to_dev(getattr(w, k).astype(dt)).requires_grad_(True) for k in ("mth", "s", "z", "u", "uth")}
+    logp = run(t["mth"], t["s"], t["z"], t["u"], t["uth"])
+    wts = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64, device="cuda:0")
+    (logp * wts).sum().backward()
+    got = {"logp": logp.detach().cpu().numpy(), "dlogp": wts.cpu().numpy()}
+    got.update({"d" + k: v.grad.cpu().numpy().astype(np.float64) for k, v in t.items()})
+    check(w, prec, got, oracle_star(w, prec), f"star-autograd-{prec}")
