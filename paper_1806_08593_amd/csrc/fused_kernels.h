@@ -925,6 +925,73 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
     if (GRAD) o_gemm(cur, P);
   };
 
+  // BF16X3, one subtile, 8 waves, gradient forward: the two phases of the pipelined sweep in
+  // issue order with their LDS fragments read ahead.  Phase A: d chunk kc of the next
+  // tile's factor GEMM (three MFMAs; its fragment read two chunks earlier), then the
+  // exponentials of two entries of the current tile and their hi/lo split.  Phase B: d
+  // block q of the current tile's second GEMM (six MFMAs; fragments read one block
+  // earlier), then a share of the staging of tile t+2 (its float4 columns, then the
+  // norm and the column term) and finally the fetch of tile t+3.  Every sum keeps the
+  // order of s_gemm, soft_exp and o_gemm.
+  constexpr bool kAhead = PREC == TMC_BF16X3 && GRAD && NS == 1 && NKC == 8 && WV == 8;
+  auto phase_a = [&](int nb, float (&x)[NS][16], f32x16 (&Sn)[NS], PFrag<PREC> (&P)[NS]) {
+    if constexpr (kAhead) {
+      const float msafe = (m == -INFINITY) ? 0.0f : m;
+      float ps = 0.0f;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) Sn[0][v] = 0.0f;
+      Frag<PREC> B3[3];
+      tile_row_frag<TS, PREC>(T, nb, 0, 0, B3[0]);
+      tile_row_frag<TS, PREC>(T, nb, 0, 1, B3[1]);
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc) {
+        if (kc + 2 < NKC) tile_row_frag<TS, PREC>(T, nb, 0, kc + 2, B3[(kc + 2) % 3]);
+        mma_chunk<PREC>(Sn[0], B3[kc % 3], A[kc]);
+#pragma unroll
+        for (int e = 2 * kc; e < 2 * kc + 2; ++e) {
+          x[0][e] = __builtin_amdgcn_exp2f(x[0][e] - msafe);
+          ps += x[0][e];
+        }
+        uint32_t hu, lu;
+        split2(x[0][2 * kc], x[0][2 * kc + 1], hu, lu);
+        Frag<TMC_BF16X3>& f = P[0].f[kc / 4];
+        u32x4 hv = __builtin_bit_cast(u32x4, f.hi), lv = __builtin_bit_cast(u32x4, f.lo);
+        hv[kc % 4] = hu;
+        lv[kc % 4] = lu;
+        f.hi = __builtin_bit_cast(bf16x8, hv);
+        f.lo = __builtin_bit_cast(bf16x8, lv);
+      }
+      ssum += ps;
+    }
+  };
+  auto phase_b = [&](int cb, int b, int t, const PFrag<PREC> (&P)[NS], double (&qs)[NS]) {
+    if constexpr (kAhead) {
+      constexpr int NFT = TilePrefetch<NKC, NS, WV>::NFT;
+      constexpr int NA = NFT + 2;   // staging parts: NFT columns, norm + gamma, fetch
+      const int j0 = 32 * (t + 2);
+      double qa[2] = {0.0, 0.0};
+      TFrag<PREC> T2[2];
+      tile_rowT_frag<TS>(T, cb, 0, 0, T2[0]);
+#pragma unroll
+      for (int q = 0; q < ND32; ++q) {
+        if (q + 1 < ND32) tile_rowT_frag<TS>(T, cb, 0, q + 1, T2[(q + 1) & 1]);
+        mma_t<PREC>(O[q], T2[q & 1], P[0]);
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          if (k * ND32 / NA != q) continue;
+          if (k < NFT) {
+            tile_store_part<TS, NKC, true, WV>(T, b, pf, false, 0, k, qa);
+          } else if (k == NFT) {
+            qs[0] = tile_store_norm<WV>(qa);
+            T.gam[b][srow] = col_gamma(qs[0], pf.a[0], j0 + srow, L.Kc, maxa, L.kappa);
+          } else {
+            fetch_cols(pf, L, mu, alpha, 32 * (t + 3));
+          }
+        }
+      }
+    }
+  };
+
   if constexpr (NB == 3) {
     // Pipelined sweep over three LDS stages.  While the wave works on tile t, tile t+1
     // is already staged and tile t+2 is being staged: phase A issues the factor-GEMM
@@ -956,18 +1023,23 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       const int stg = nxt == 2 ? 0 : nxt + 1;
       float x[NS][16];
       soft_max(cur, S, x);
-      // phase A
       f32x16 Sn[NS];
       PFrag<PREC> P[NS];
-      s_gemm(nxt, Sn);
-      soft_exp(x, P);
-      interleave_phase_a<kGemmMfma<PREC, NKC> * NS, 8>();
-      // phase B
       double qs[NS];
-      if (GRAD) o_gemm(cur, P);
-      stage(stg, 32 * NS * (t + 2), qs);
-      fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 3));
-      if (GRAD) interleave_phase_b<ND32 * NS * 2 * (PREC == TMC_BF16X3 ? 3 : 8)>();
+      if constexpr (kAhead) {
+        phase_a(nxt, x, Sn, P);
+        phase_b(cur, stg, t, P, qs);
+      } else {
+        // phase A
+        s_gemm(nxt, Sn);
+        soft_exp(x, P);
+        interleave_phase_a<kGemmMfma<PREC, NKC> * NS, 8>();
+        // phase B
+        if (GRAD) o_gemm(cur, P);
+        stage(stg, 32 * NS * (t + 2), qs);
+        fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 3));
+        if (GRAD) interleave_phase_b<ND32 * NS * 2 * (PREC == TMC_BF16X3 ? 3 : 8)>();
+      }
       store_q(32 * NS * (t + 2), qs);
       lds_barrier();
 #pragma unroll
