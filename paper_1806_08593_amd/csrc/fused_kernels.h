@@ -1295,11 +1295,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   // also re-stages its last tile, which is never fresh),
   //   dz_i = -dlogp lam p_i (z_i - e_i),  sums of p_i z_id^2 and of p_i;
   // thread t serves the rows and column slots it staged.
-  auto stage = [&](int b, bool fresh) {
-    double qs[NS];
-    tile_store<TS, NKC, false, WV>(T, b, pf, true, qs);
-    const int rr = tid & (32 * NS - 1);
-    T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
+  auto row_terms = [&](bool fresh) {
     if (fresh) {
       const int sub = tid % TPR;
 #pragma unroll
@@ -1327,6 +1323,13 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
         }
       }
     }
+  };
+  auto stage = [&](int b, bool fresh) {
+    double qs[NS];
+    tile_store<TS, NKC, false, WV>(T, b, pf, true, qs);
+    const int rr = tid & (32 * NS - 1);
+    T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
+    row_terms(fresh);
   };
   f32x16 GT[ND32];
 #pragma unroll
@@ -1390,6 +1393,74 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
     gt_gemm(cur, P);
   };
 
+  // BF16X3, one subtile, 8 waves: the two phases in issue order with their LDS fragments
+  // read ahead, as in the forward.  Phase A: d chunk kc of the next tile's factor GEMM
+  // (fragment read two chunks earlier), then the marginals of two entries of the current
+  // tile and their hi/lo split.  Phase B: d block q of G^T z (fragments read one block
+  // earlier), then a share of the staging of tile t+2 (its float4 columns, then the row
+  // shifts and row terms) and finally the fetch of tile t+3.  Every sum keeps the order
+  // of s_gemm, marg_exp and gt_gemm.
+  constexpr bool kAhead = PREC == TMC_BF16X3 && NS == 1 && NKC == 8 && WV == 8;
+  auto phase_a = [&](int nb, int cb, const f32x16 (&S)[NS], f32x16 (&Sn)[NS], PFrag<PREC> (&P)[NS]) {
+    if constexpr (kAhead) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) Sn[0][v] = 0.0f;
+      Frag<PREC> B3[3];
+      tile_row_frag<TS, PREC>(T, nb, 0, 0, B3[0]);
+      tile_row_frag<TS, PREC>(T, nb, 0, 1, B3[1]);
+      float2 l2[2];
+      l2[0] = *reinterpret_cast<const float2*>(&T.lamT[cb][4 * h]);
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc) {
+        if (kc + 2 < NKC) tile_row_frag<TS, PREC>(T, nb, 0, kc + 2, B3[(kc + 2) % 3]);
+        if (kc + 1 < NKC)   // row shifts of entries 2 kc + 2, 2 kc + 3
+          l2[(kc + 1) & 1] = *reinterpret_cast<const float2*>(
+              &T.lamT[cb][8 * ((kc + 1) / 2) + 4 * h + 2 * ((kc + 1) % 2)]);
+        mma_chunk<PREC>(Sn[0], B3[kc % 3], Bf[kc]);
+        const float2 lv = l2[kc & 1];
+        const float g0 = __builtin_amdgcn_exp2f(S[0][2 * kc] + gj - lv.x);
+        const float g1 = __builtin_amdgcn_exp2f(S[0][2 * kc + 1] + gj - lv.y);
+        csum += g0;
+        csum += g1;
+        uint32_t hu, lu;
+        split2(g0, g1, hu, lu);
+        Frag<TMC_BF16X3>& f = P[0].f[kc / 4];
+        u32x4 hv = __builtin_bit_cast(u32x4, f.hi), lv4 = __builtin_bit_cast(u32x4, f.lo);
+        hv[kc % 4] = hu;
+        lv4[kc % 4] = lu;
+        f.hi = __builtin_bit_cast(bf16x8, hv);
+        f.lo = __builtin_bit_cast(bf16x8, lv4);
+      }
+    }
+  };
+  auto phase_b = [&](int cb, int b, int t, const PFrag<PREC> (&P)[NS]) {
+    if constexpr (kAhead) {
+      constexpr int NFT = TilePrefetch<NKC, NS, WV>::NFT;
+      constexpr int NA = NFT + 2;   // staging parts: NFT columns, row shifts + row terms, fetch
+      double qa[2] = {0.0, 0.0};
+      TFrag<PREC> T2[2];
+      tile_rowT_frag<TS>(T, cb, 0, 0, T2[0]);
+#pragma unroll
+      for (int q = 0; q < ND32; ++q) {
+        if (q + 1 < ND32) tile_rowT_frag<TS>(T, cb, 0, q + 1, T2[(q + 1) & 1]);
+        mma_t<PREC>(GT[q], T2[q & 1], P[0]);
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+          if (k * ND32 / NA != q) continue;
+          if (k < NFT) {
+            tile_store_part<TS, NKC, false, WV>(T, b, pf, true, 0, k, qa);
+          } else if (k == NFT) {
+            const int rr = tid & 31;
+            T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
+            row_terms(t + 2 < nt && own(t + 2));
+          } else {
+            fetch_rows(pf, L, z, lamrow, 32 * (t + 3), evp, p, t + 3 < nt && own(t + 3));
+          }
+        }
+      }
+    }
+  };
+
   if constexpr (NB == 3) {
     // Pipelined sweep over three LDS stages (see the forward): phase A issues the
     // factor-GEMM MFMAs of tile t+1 with the marginals of tile t between them, phase B
@@ -1408,17 +1479,22 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
     for (int t = 0; t < nt; ++t) {
       const int nxt = cur == 2 ? 0 : cur + 1;
       const int stg = nxt == 2 ? 0 : nxt + 1;
-      // phase A
       f32x16 Sn[NS];
       PFrag<PREC> P[NS];
-      s_gemm(nxt, Sn);
-      marg_exp(cur, S, P);
-      interleave_phase_a<kGemmMfma<PREC, NKC> * NS, 8>();
-      // phase B
-      gt_gemm(cur, P);
-      stage(stg, t + 2 < nt && own(t + 2));
-      fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 3), evp, p, t + 3 < nt && own(t + 3));
-      interleave_phase_b<ND32 * NS * 2 * (PREC == TMC_BF16X3 ? 3 : 8)>();
+      if constexpr (kAhead) {
+        phase_a(nxt, cur, S, Sn, P);
+        phase_b(cur, stg, t, P);
+      } else {
+        // phase A
+        s_gemm(nxt, Sn);
+        marg_exp(cur, S, P);
+        interleave_phase_a<kGemmMfma<PREC, NKC> * NS, 8>();
+        // phase B
+        gt_gemm(cur, P);
+        stage(stg, t + 2 < nt && own(t + 2));
+        fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 3), evp, p, t + 3 < nt && own(t + 3));
+        interleave_phase_b<ND32 * NS * 2 * (PREC == TMC_BF16X3 ? 3 : 8)>();
+      }
       lds_barrier();
 #pragma unroll
       for (int sb = 0; sb < NS; ++sb) S[sb] = Sn[sb];
