@@ -1433,7 +1433,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       }
     }
   };
-  auto phase_b = [&](int cb, int b, int t, const PFrag<PREC> (&P)[NS]) {
+  auto phase_b = [&](int cb, int b, bool fresh, int r3, bool fresh3, const PFrag<PREC> (&P)[NS]) {
     if constexpr (kAhead) {
       constexpr int NFT = TilePrefetch<NKC, NS, WV>::NFT;
       constexpr int NA = NFT + 2;   // staging parts: NFT columns, row shifts + row terms, fetch
@@ -1452,9 +1452,9 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
           } else if (k == NFT) {
             const int rr = tid & 31;
             T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
-            row_terms(t + 2 < nt && own(t + 2));
+            row_terms(fresh);
           } else {
-            fetch_rows(pf, L, z, lamrow, 32 * (t + 3), evp, p, t + 3 < nt && own(t + 3));
+            fetch_rows(pf, L, z, lamrow, r3, evp, p, fresh3);
           }
         }
       }
@@ -1483,7 +1483,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       PFrag<PREC> P[NS];
       if constexpr (kAhead) {
         phase_a(nxt, cur, S, Sn, P);
-        phase_b(cur, stg, t, P);
+        phase_b(cur, stg, t + 2 < nt && own(t + 2), 32 * (t + 3), t + 3 < nt && own(t + 3), P);
       } else {
         // phase A
         s_gemm(nxt, Sn);
