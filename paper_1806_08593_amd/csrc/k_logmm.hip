@@ -300,6 +300,22 @@ __global__ __launch_bounds__(256) void k_logmm_prep_y(LogmmArgs a) {
   }
 }
 
+// Output tile of this workgroup, XCD-aware: workgroups are handed to the 8 XCDs in turn
+// by flattened index, so workgroup w runs on XCD w mod 8.  The first 8 floor(n / 8) tiles
+// (x fastest, then y, then the batch) are dealt out in 8 contiguous ranges, range c to the
+// workgroups of XCD c, so the tiles one XCD runs share their row and column panels in its
+// L2 (at 8 x 1024^3 an XCD runs one product of the batch); the rest keep their own index.
+__device__ __forceinline__ void logmm_tile(int& bx, int& by, int& bz) {
+  const int nx = gridDim.x, ny = gridDim.y;
+  const int n = nx * ny * gridDim.z;
+  int w = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+  const int full = n & ~7;
+  if (w < full) w = (w & 7) * (full >> 3) + (w >> 3);
+  bx = w % nx;
+  by = (w / nx) % ny;
+  bz = w / (nx * ny);
+}
+
 // The shifted product on MFMA: a workgroup of 4 waves per 128 x 128 output tile (wave w:
 // rows 64 (w / 2), columns 64 (w % 2), as 2 x 2 accumulators of 32 x 32), the reduction
 // index staged 32 at a time from the prepared operands (thread t: row t / 2 of each
@@ -310,9 +326,10 @@ __global__ __launch_bounds__(256) void k_logmm_prep_y(LogmmArgs a) {
 // value v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
-  __shared__ LogmmSmem<PREC> S;
-  const int b = blockIdx.z;
-  const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
+  __shared__ LogmmSmem<PREC> SB[2];   // slice s is read from SB[s % 2]
+  int bx, by, b;
+  logmm_tile(bx, by, b);
+  const int i0 = by * kTile, k0 = bx * kTile;
   const int M = a.M, N = a.N, Kp = a.Kp;
   const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
   const int r = t / 2, jg = (t % 2) * 16;
@@ -326,20 +343,19 @@ __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[p][q] = (f32x16){};
   const int wr = 64 * (w / 2), wc = 64 * (w % 2);
+  const int ns = Kp / kKC;
   load_operand<PREC>(a.opa, pa, ra, xa);
   load_operand<PREC>(a.opb, pb, rb, xb);
-  for (int j0 = 0; j0 < Kp; j0 += kKC) {
-    __syncthreads();   // (the previous slice's fragment reads are done)
-    stage_operand<PREC>(S, true, r, jg, xa);
-    stage_operand<PREC>(S, false, r, jg, xb);
-    __syncthreads();
-    {
-      // the next slice, in flight during the MFMAs below (after the last slice, the last
-      // slice again: unconditional, so the operands stay in registers)
-      const int jn = min(j0 + kKC, Kp - kKC);
-      load_operand<PREC>(a.opa, pa, ra + jn, xa);
-      load_operand<PREC>(a.opb, pb, rb + jn, xb);
-    }
+  stage_operand<PREC>(SB[0], true, r, jg, xa);
+  stage_operand<PREC>(SB[0], false, r, jg, xb);
+  {
+    const int jn = min(kKC, Kp - kKC);
+    load_operand<PREC>(a.opa, pa, ra + jn, xa);
+    load_operand<PREC>(a.opb, pb, rb + jn, xb);
+  }
+  __syncthreads();
+  for (int sl = 0; sl < ns; ++sl) {
+    const LogmmSmem<PREC>& S = SB[sl & 1];
 #pragma unroll
     for (int st = 0; st < kKC / 16; ++st) {
       const int jj = 16 * st + 8 * (lane / 32);
@@ -382,6 +398,16 @@ __global__ __launch_bounds__(256) void k_logmm_mfma(LogmmArgs a) {
               acc[p][q] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[p][s2], bfv[q][s2], acc[p][q], 0, 0, 0);
       }
     }
+    // Slice sl + 1 into the other buffer (its last reads, slice sl - 1, ended before the
+    // barrier that closed the previous step), then slice sl + 2 in flight.  Both are
+    // unconditional -- past the end they repeat the last slice into a buffer no one reads
+    // again -- so the operands stay in registers.
+    stage_operand<PREC>(SB[(sl + 1) & 1], true, r, jg, xa);
+    stage_operand<PREC>(SB[(sl + 1) & 1], false, r, jg, xb);
+    const int jn = min((sl + 2) * kKC, Kp - kKC);
+    load_operand<PREC>(a.opa, pa, ra + jn, xa);
+    load_operand<PREC>(a.opb, pb, rb + jn, xb);
+    __syncthreads();
   }
   // Z = log C + x + y; the entries whose shifted product fell below the floor (or is
   // not a number) are marked and recomputed exactly afterwards (rare: the lane loops
@@ -432,8 +458,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(512) void k_logmm_mfma_f64(LogmmArgs a) {
   __shared__ __attribute__((aligned(16))) double SA[kTile][kKCd + kPadD];
   __shared__ __attribute__((aligned(16))) double SB[kTile][kKCd + kPadD];
-  const int b = blockIdx.z;
-  const int i0 = blockIdx.y * kTile, k0 = blockIdx.x * kTile;
+  int bx, by, b;
+  logmm_tile(bx, by, b);
+  const int i0 = by * kTile, k0 = bx * kTile;
   const int M = a.M, N = a.N, Kp = a.Kp;
   const int t = threadIdx.x, lane = t % kWave, w = t / kWave;
   const int r = t / 4, jg = (t % 4) * 4;

@@ -180,7 +180,10 @@ __global__ __launch_bounds__(256) void k_plain_factor(const LayerDev* __restrict
 // forward message: a wave owns kPlainFwdRowsPerWave rows and streams them together,
 // one vector of V elements per lane and row per step, so that every lane has that many
 // loads in flight; each lane keeps an online (max, sum) per row over the columns it
-// reads (no cross-lane work inside the loop), merged across the wave at the end.
+// reads (no cross-lane work inside the loop), merged across the wave at the end.  Few
+// rows per wave keep the register count low, so many waves stay resident per CU and
+// they, not deep per-wave buffers, hold the bytes in flight; the kPlainFwdWaves waves
+// of a workgroup share one copy of the column shifts, formed once in its prologue.
 // ---------------------------------------------------------------------------
 template <typename T, int V, int R>
 __device__ __forceinline__ void rows_lse(const T* __restrict__ fb, int64_t row0, int nrow,
@@ -231,7 +234,7 @@ __device__ __forceinline__ void rows_lse(const T* __restrict__ fb, int64_t row0,
 }
 
 template <typename T, int V>
-__global__ __launch_bounds__(256) void k_plain_lse_fwd(const LayerDev* __restrict__ Ls,
+__global__ __launch_bounds__(64 * kPlainFwdWaves) void k_plain_lse_fwd(const LayerDev* __restrict__ Ls,
                                                        const Item* __restrict__ items,
                                                        const T* __restrict__ f, int caller_off,
                                                        const T* __restrict__ u,
@@ -593,10 +596,10 @@ hipError_t launch_plain_lse_fwd(const LayerDev* layers, const Item* items, int n
   constexpr int VV = sizeof(T) == 4 ? 4 : 2;
   const size_t smem = (size_t)max_kc * sizeof(T);
   if (vec)
-    hipLaunchKernelGGL((k_plain_lse_fwd<T, VV>), dim3(n_items), dim3(256), smem, st, layers, items,
+    hipLaunchKernelGGL((k_plain_lse_fwd<T, VV>), dim3(n_items), dim3(64 * kPlainFwdWaves), smem, st, layers, items,
                        f, (int)caller_off, u, alpha, rl, pairM, anchor);
   else
-    hipLaunchKernelGGL((k_plain_lse_fwd<T, 1>), dim3(n_items), dim3(256), smem, st, layers, items,
+    hipLaunchKernelGGL((k_plain_lse_fwd<T, 1>), dim3(n_items), dim3(64 * kPlainFwdWaves), smem, st, layers, items,
                        f, (int)caller_off, u, alpha, rl, pairM, anchor);
   return hipGetLastError();
 }

@@ -53,8 +53,9 @@ hipError_t launch_pair_dsp(const LayerDev* layers, const int* pair_ids, int n_pa
 
 // plain tiling constants (host and device agree)
 constexpr int kPlainFactorRows = 32, kPlainFactorCols = 64;
-constexpr int kPlainFwdRowsPerWave = 8;        // rows a forward wave streams together
-constexpr int kPlainFwdRowsPerBlock = 32;      // 4 waves x 8 rows
+constexpr int kPlainFwdRowsPerWave = 4;        // rows a forward wave streams together
+constexpr int kPlainFwdWaves = 16;             // waves of a forward workgroup
+constexpr int kPlainFwdRowsPerBlock = kPlainFwdWaves * kPlainFwdRowsPerWave;
 constexpr int kPlainBwdWaves = 16;             // waves of a backward workgroup (one column strip)
 constexpr int kPlainBwdRowsPerStep = 4;        // rows a backward wave loads before using them
 constexpr int kPlainBwdColsScalar = 64;        // one column per lane

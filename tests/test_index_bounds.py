@@ -345,6 +345,9 @@ def check_fused(shapes, prec, z_shift=0):
 # plain engine (k_plain.hip): stored factors
 # ---------------------------------------------------------------------------
 
+PLAIN_FWD_R, PLAIN_FWD_W = 4, 16  # forward log-sum-exp: rows per wave, waves per workgroup
+
+
 def check_plain(shapes, esz):
     layers, sizes = layout(shapes)
     VV = 4 if esz == 4 else 2
@@ -369,20 +372,20 @@ def check_plain(shapes, esz):
                 B.check("wf", L["wf_off"] + i * Kc + j, mask=(j < Kc) & (i < K),
                         block=(L["wf_off"], L["wf_off"] + K * Kc))
             B.check("anchor", L["alpha_off"] + i0 + tid, mask=(j0 == 0) & (tid < 32) & (i0 + tid < K))
-        # forward row sweeps: 8 rows per wave, 4 waves
+        # forward row sweeps: PLAIN_FWD_R rows per wave, PLAIN_FWD_W waves
         vec = Kc % VV == 0 and L["wf_off"] % VV == 0
         V = VV if vec else 1
-        for start in range(0, K, 32):
-            for w in range(4):
-                i0 = start + 8 * w
+        for start in range(0, K, PLAIN_FWD_R * PLAIN_FWD_W):
+            for w in range(PLAIN_FWD_W):
+                i0 = start + PLAIN_FWD_R * w
                 if i0 >= K:
                     continue
-                nrow = min(8, K - i0)
+                nrow = min(PLAIN_FWD_R, K - i0)
                 lane = np.arange(64)
                 for base in range(0, Kc, 64 * V):
                     jj = base + lane * V
                     ok = jj < Kc
-                    for r in range(8):
+                    for r in range(PLAIN_FWD_R):
                         rr = min(r, nrow - 1)
                         B.check("wf", L["wf_off"] + (i0 + rr) * Kc + jj, V, mask=ok,
                                 vec=V == 4 and esz == 4, block=(L["wf_off"], L["wf_off"] + K * Kc))
@@ -657,9 +660,10 @@ def check_logmm(B, M, K, N):
                 r, jg = t // 2, (t % 2) * 16
                 ra = (b * M + np.minimum(i0 + r, M - 1)) * Kp + jg
                 rb = (b * N + np.minimum(k0 + r, N - 1)) * Kp + jg
-                # the first slice, then in each step the next one (the last slice again
-                # after the last step)
-                for jj in [0] + [min(j0 + 32, Kp - 32) for j0 in range(0, Kp, 32)]:
+                # slices 0 and 1 before the loop, then in step s slice s + 2 (past the
+                # end the last slice again)
+                ns = Kp // 32
+                for jj in [0, min(32, Kp - 32)] + [min((s2 + 2) * 32, Kp - 32) for s2 in range(ns)]:
                     for s_ in range(16):
                         Bf.check("opa", ra + jj + s_, block=None)
                         Bf.check("opa", B * M * Kp + ra + jj + s_)
@@ -731,6 +735,31 @@ def check_logmm_f64(B, M, K, N):
                                     Bf.check("X", (b * M + i) * K + j, mask=live)
                                     Bf.check("Y", b * K * N + j * N + k, mask=live)
     assert not Bf.bad, Bf.bad[:5]
+
+
+def logmm_tile(bid, grid):
+    """The product kernels' XCD-aware tile of workgroup bid = (x, y, z) in grid (nx, ny, nz)."""
+    nx, ny, nz = grid
+    n = nx * ny * nz
+    w = bid[0] + nx * (bid[1] + ny * bid[2])
+    full = n & ~7
+    if w < full:
+        w = (w & 7) * (full >> 3) + (w >> 3)
+    return (w % nx, (w // nx) % ny, w // (nx * ny))
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (8, 8, 8), (3, 5, 2), (9, 1, 1), (8, 8, 3), (1, 1, 7),
+                                  (5, 7, 9), (1, 1, 8), (2, 9, 13)])
+def test_logmm_tile_mapping_is_a_permutation(grid):
+    tiles = [logmm_tile((x, y, z), grid) for z in range(grid[2]) for y in range(grid[1])
+             for x in range(grid[0])]
+    assert sorted(tiles) == sorted(set(tiles))
+    assert set(tiles) == {(x, y, z) for x in range(grid[0]) for y in range(grid[1]) for z in range(grid[2])}
+    if grid == (8, 8, 8):   # workgroup w runs on XCD w mod 8: each XCD gets one product
+        per_xcd = {}
+        for w, t in enumerate(tiles):
+            per_xcd.setdefault(w % 8, set()).add(t[2])
+        assert all(len(v) == 1 for v in per_xcd.values())
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1, 1), (3, 70, 45, 130), (2, 129, 33, 257), (1, 5, 300, 7),
