@@ -32,6 +32,7 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kTile = kLogmmTile;   // output rows and columns of a workgroup
 constexpr int kKC = 32;             // reduction indices staged per step
+constexpr int kColmaxCW = 32;       // columns of a column-maximum workgroup
 constexpr int kPadB = 8;            // bf16 row padding of the LDS tiles (16 B)
 constexpr int kPadF = 4;            // float row padding
 constexpr float kLogmmFloor = -60.0f;
@@ -143,35 +144,46 @@ __device__ T exact_entry(const T* __restrict__ x, const T* __restrict__ y, int K
 
 // Shifts: xs[b][i] = max_j X_b[i,j] (in k_logmm_prep_x) and ys[b][k] = max_j Y_b[j,k]
 // (below); an all -inf row or column gets 0 (its exponentials are then 0, never NaN).
-// Column maxima: a workgroup of 16 waves per 64 columns (lane -> column), wave w takes
-// rows w, w + 16, .. (loads issued 8 at a time); the waves' maxima are merged in LDS.
-template <typename T>
+// Column maxima: a workgroup of 16 waves per CW columns; lane l of wave w takes column
+// l % CW and rows (64 / CW) w + l / CW + 1024 / CW * q (loads issued 8 at a time), so a
+// wave reads 64 / CW rows of CW consecutive columns per load and the grid has 64 / CW
+// times as many workgroups as with one column per lane (at 8 x 1024 x 1024 and CW = 64
+// only 128 workgroups for 256 CUs); the partial maxima are merged in LDS.  CW = 32
+// (128-byte row pieces in FP32) measured best: 10.2 us at 8 x 1024 x 1024 FP32, against
+// 11.5 at CW = 64 and 17.5 at CW = 16 (64-byte pieces).
+template <typename T, int CW>
 __global__ __launch_bounds__(1024) void k_logmm_colmax(LogmmArgs a, const T* __restrict__ Y,
                                                        T* __restrict__ ys) {
-  __shared__ T part[16][kWave];
+  constexpr int RG = kWave / CW;    // row groups of a wave
+  constexpr int RS = 16 * RG;       // rows of one load step of the workgroup
+  __shared__ T part[16 * RG][CW];
   const int b = blockIdx.z;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int64_t col = (int64_t)blockIdx.x * kWave + lane;
+  const int c = lane % CW, g = RG * w + lane / CW;   // column in the block, row group
+  const int64_t col = (int64_t)blockIdx.x * CW + c;
   const bool cv = col < a.N;
   const T* y = Y + (int64_t)b * a.K * a.N + (cv ? col : 0);
   T m = (T)(-INFINITY);
   constexpr int U = 8;
-  for (int j0 = w; j0 < a.K; j0 += 16 * U) {
+  for (int j0 = g; j0 < a.K; j0 += RS * U) {
     T v[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-      const int j = j0 + 16 * q;
+      const int j = j0 + RS * q;
       v[q] = j < a.K ? y[(int64_t)j * a.N] : (T)(-INFINITY);
     }
 #pragma unroll
     for (int q = 0; q < U; ++q) m = nan_max(m, v[q]);
   }
-  part[w][lane] = m;
+  part[g][c] = m;
   __syncthreads();
-  if (w == 0 && cv) {
-#pragma unroll
-    for (int q = 1; q < 16; ++q) m = nan_max(m, part[q][lane]);
-    ys[(int64_t)b * a.N + col] = (m == (T)(-INFINITY)) ? (T)0 : m;
+  if (threadIdx.x < CW) {
+    const int cc = threadIdx.x;
+    const int64_t colc = (int64_t)blockIdx.x * CW + cc;
+    T mm = part[0][cc];
+#pragma unroll 4
+    for (int q = 1; q < 16 * RG; ++q) mm = nan_max(mm, part[q][cc]);
+    if (colc < a.N) ys[(int64_t)b * a.N + colc] = (mm == (T)(-INFINITY)) ? (T)0 : mm;
   }
 }
 
@@ -546,18 +558,18 @@ __global__ __launch_bounds__(512) void k_logmm_mfma_f64(LogmmArgs a) {
 }
 
 hipError_t launch_logmm(const LogmmArgs& a, int precision, hipStream_t st) {
-  const dim3 gc((a.N + kWave - 1) / kWave, 1, a.B);
+  const dim3 gc((a.N + kColmaxCW - 1) / kColmaxCW, 1, a.B);
   const dim3 grid((a.N + kTile - 1) / kTile, (a.M + kTile - 1) / kTile, a.B);
   const dim3 gx((unsigned)(((int64_t)a.B * a.M + 3) / 4));
   const dim3 gy((a.Kp + 63) / 64, (a.N + 63) / 64, a.B);
   if (precision == TMC_FP64) {
-    hipLaunchKernelGGL(k_logmm_colmax<double>, gc, dim3(1024), 0, st, a, a.Yd, a.ysd);
+    hipLaunchKernelGGL((k_logmm_colmax<double, kColmaxCW>), gc, dim3(1024), 0, st, a, a.Yd, a.ysd);
     hipLaunchKernelGGL((k_logmm_prep_x<TMC_FP64>), gx, dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_logmm_prep_y<TMC_FP64>), gy, dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_logmm_mfma_f64, grid, dim3(512), 0, st, a);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_logmm_colmax<float>, gc, dim3(1024), 0, st, a, a.Y, a.ys);
+  hipLaunchKernelGGL((k_logmm_colmax<float, kColmaxCW>), gc, dim3(1024), 0, st, a, a.Y, a.ys);
   if (precision == TMC_BF16X3) {
     hipLaunchKernelGGL((k_logmm_prep_x<TMC_BF16X3>), gx, dim3(256), 0, st, a);
     hipLaunchKernelGGL((k_logmm_prep_y<TMC_BF16X3>), gy, dim3(256), 0, st, a);

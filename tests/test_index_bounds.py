@@ -594,6 +594,9 @@ def test_star_grouping():
 LOGMM_TILE = 128
 
 
+COLMAX_CW = 32   # columns of a column-maximum workgroup of the log-domain product
+
+
 def check_logmm(B, M, K, N):
     """Every global access of the log-domain product kernels (row and column maxima, the
     operand preparation, the MFMA tile kernel, the exact fix-up) per thread.  Operand
@@ -629,13 +632,21 @@ def check_logmm(B, M, K, N):
                 Bf.check("opa", row * Kp + jl + s_, mask=jl < Kp)
                 Bf.check("opa", B * M * Kp + row * Kp + jl + s_, mask=jl < Kp)
     for b in range(B):
-        # columns: 16 waves per 64 columns, lanes past N read column 0
-        for bx in range(cdiv(N, 64)):
-            col = bx * 64 + np.arange(64)
+        # column maxima: 16 waves per COLMAX_CW columns (lane: column l % CW, row group
+        # 64 / CW w + l / CW), lanes past N read column 0
+        CW = COLMAX_CW
+        tc = np.arange(1024)
+        c, g = (tc % 64) % CW, (64 // CW) * (tc // 64) + (tc % 64) // CW
+        rs = 16 * (64 // CW)
+        for bx in range(cdiv(N, CW)):
+            col = bx * CW + c
             cc = np.where(col < N, col, 0)
-            for j in range(K):
-                Bf.check("Y", b * K * N + j * N + cc)
-            Bf.check("ys", b * N + col, mask=col < N)
+            for j0 in range(0, K, rs * 8):
+                for q in range(8):
+                    j = j0 + g + rs * q
+                    Bf.check("Y", b * K * N + j * N + cc, mask=j < K)
+            colm = bx * CW + np.arange(CW)
+            Bf.check("ys", b * N + colm, mask=colm < N)
         # operand preparation of Y: 64 j x 64 k tiles through LDS
         for jx in range(cdiv(Kp, 64)):
             for ky in range(cdiv(N, 64)):
