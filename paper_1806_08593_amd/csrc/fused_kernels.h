@@ -1630,30 +1630,33 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   // one column part per 128 columns (waves 4 h .. 4 h + 3), whatever the workgroup size;
   // the two halves of an 8-wave workgroup are reduced side by side in their own buffers
   // (the tile copies are free once the sweep is done)
+  // (rows of the reduction buffer are DT + 1 floats apart: the 32 lanes of a wave that
+  // write one slot of 32 different rows then hit distinct banks, not one or a few)
+  constexpr int RB = TS::DT + 1;
   float* buf = reinterpret_cast<float*>(TS::COL ? (void*)&T.col[0][0][0] : (void*)&T.row[0][0][0]);
-  static_assert((TS::COL ? sizeof(T.col) : sizeof(T.row)) >= (WV / 4) * 32 * TS::DT * sizeof(float),
+  static_assert((TS::COL ? sizeof(T.col) : sizeof(T.row)) >= (WV / 4) * 32 * RB * sizeof(float),
                 "reduction buffer");
   if constexpr (WV == 8) {
     if (dzw) {
       // row part of ds over the workgroup's rows: the 32 row slots' sums, reduced in a
       // fixed order, into row partial wg_c (workgroup 0 zeroes partials nwg .. nrow - 1)
-      static_assert((WV / 4) * 32 * TS::DT >= 32 * TS::DT + 32, "row reduction buffer");
+      static_assert((WV / 4) * 32 * RB >= 32 * RB + 32, "row reduction buffer");
       lds_barrier();
       const int r = tid / TPR, sub = tid % TPR;
 #pragma unroll
       for (int m = 0; m < NFT; ++m)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) buf[r * TS::DT + 4 * (sub + TPR * m) + e] = rsum[m][e];
-      if (sub == 0) buf[32 * TS::DT + r] = psum;
+        for (int e = 0; e < 4; ++e) buf[r * RB + 4 * (sub + TPR * m) + e] = rsum[m][e];
+      if (sub == 0) buf[32 * RB + r] = psum;
       lds_barrier();
       float P = 0.0f;
-      for (int c = 0; c < 32; ++c) P += buf[32 * TS::DT + c];
+      for (int c = 0; c < 32; ++c) P += buf[32 * RB + c];
       const int ncol = (L.Kc + kFusedBwdColsDev - 1) / kFusedBwdColsDev;
       const int nrow = (L.K + kFusedDzRowsDev - 1) / kFusedDzRowsDev;
       float* part = dsp + L.dsp_off + (int64_t)(ncol + wg_c) * L.D;
       for (int d = tid; d < L.D; d += blockDim.x) {
         float acc = 0.0f;
-        for (int c = 0; c < 32; ++c) acc += buf[c * TS::DT + d];
+        for (int c = 0; c < 32; ++c) acc += buf[c * RB + d];
         part[d] = g32 * (T.lamf[d] * acc - P);
       }
       if (wg_c == 0)
@@ -1663,18 +1666,18 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   for (int w2 = 0; w2 < 4; ++w2) {
     lds_barrier();
     if ((w & 3) == w2) {
-      float* bw = buf + (w >> 2) * 32 * TS::DT;
+      float* bw = buf + (w >> 2) * 32 * RB;
 #pragma unroll
       for (int q = 0; q < ND32; ++q)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) bw[jr * TS::DT + 32 * q + 8 * (v / 4) + 4 * h + (v % 4)] = colt[q][v];
+        for (int v = 0; v < 16; ++v) bw[jr * RB + 32 * q + 8 * (v / 4) + 4 * h + (v % 4)] = colt[q][v];
     }
     lds_barrier();
     for (int e = tid; e < (WV / 4) * TS::DT; e += blockDim.x) {
-      const float* bh = buf + (e / TS::DT) * 32 * TS::DT;
+      const float* bh = buf + (e / TS::DT) * 32 * RB;
       const int d = e % TS::DT;
       float acc = 0.0f;
-      for (int c = 0; c < 32; ++c) acc += bh[c * TS::DT + d];
+      for (int c = 0; c < 32; ++c) acc += bh[c * RB + d];
       accD[e] += acc;
     }
   }
