@@ -256,28 +256,28 @@ __device__ __forceinline__ float4 load_f4(const float* __restrict__ row, int d, 
 // The small per-pair inputs of a workgroup's prologue, loaded from clamped addresses
 // before the bulk operand loads so that consuming them waits for them alone: this
 // lane's partial max of alpha_{l+1} (see pair_maxa), this lane's s values for the
-// constant c (d = lane + 64 k, D <= 256), and s_d for d = threadIdx.x (lam into LDS).
+// constant c (d = lane + 64 k, D <= 256), and s_d for d = tix (lam into LDS).
 struct PairPre {
   double wm;
   float sv[4];
   float slam;
 };
 
-__device__ __forceinline__ void pair_preload(const LayerDev& L, const double* __restrict__ wmax,
+__device__ __forceinline__ void pair_preload(int tix, const LayerDev& L, const double* __restrict__ wmax,
                                              const float* __restrict__ s, PairPre& P) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tix & 63;
   P.wm = wmax[L.wmax_up_off + min(lane, L.nwmax_up - 1)];
 #pragma unroll
   for (int k = 0; k < 4; ++k) P.sv[k] = s[L.s_off + min(lane + 64 * k, L.D - 1)];
-  P.slam = s[L.s_off + min((int)threadIdx.x, L.D - 1)];
+  P.slam = s[L.s_off + min(tix, L.D - 1)];
 }
 
 // Column shift of pair L: maxa = max_j alpha_{l+1}[j], reduced over the
 // per-workgroup maxima the pass that wrote alpha_{l+1} left in wmax (one lane per
 // partial, then a wave reduction; exact, so the order does not matter).
-__device__ __forceinline__ double pair_maxa(const LayerDev& L, const double* __restrict__ wmax,
+__device__ __forceinline__ double pair_maxa(int tix, const LayerDev& L, const double* __restrict__ wmax,
                                             const PairPre& P) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tix & 63;
   double m = (lane < L.nwmax_up) ? P.wm : -INFINITY;
   for (int k = lane + 64; k < L.nwmax_up; k += 64) m = nan_max(m, wmax[L.wmax_up_off + k]);
   m = wave_max(m);
@@ -286,8 +286,8 @@ __device__ __forceinline__ double pair_maxa(const LayerDev& L, const double* __r
 
 // c = -sum_d s_d - D/2 ln 2 pi of pair L in FP64 (fixed order: lane-strided partial
 // sums, then a butterfly over the wave), complete in every lane of the calling wave.
-__device__ __forceinline__ double pair_const(const LayerDev& L, const PairPre& P) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ double pair_const(int tix, const LayerDev& L, const PairPre& P) {
+  const int lane = tix & 63;
   double a = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) a += (lane + 64 * k < L.D) ? (double)P.sv[k] : 0.0;
@@ -419,8 +419,8 @@ __device__ __forceinline__ int tile_perm(int r) {
 
 // lam into LDS (thread d holds s_d, DT <= blockDim; zeros past D).
 template <class TS>
-__device__ __forceinline__ void tile_init(TS& T, const LayerDev& L, const PairPre& P) {
-  const int d = threadIdx.x;
+__device__ __forceinline__ void tile_init(int tix, TS& T, const LayerDev& L, const PairPre& P) {
+  const int d = tix;
   if (d < TS::DT) {
     const float lf = d < L.D ? expf(-2.0f * P.slam) : 0.0f;
     T.lamf[d] = lf;
@@ -458,11 +458,11 @@ struct TilePrefetch {
 
 // Column tiles of pair L: mu rows r0.. (samples of layer l+1) and their alpha.
 template <int NKC, int NS, int WV>
-__device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS, WV>& pf, const LayerDev& L,
+__device__ __forceinline__ void fetch_cols(int tix, TilePrefetch<NKC, NS, WV>& pf, const LayerDev& L,
                                            const float* __restrict__ mu,
                                            const double* __restrict__ alpha, int r0) {
   constexpr int TPR = TilePrefetch<NKC, NS, WV>::TPR, NFT = TilePrefetch<NKC, NS, WV>::NFT;
-  const int t = threadIdx.x, sub = t % TPR;
+  const int t = tix, sub = t % TPR;
   const bool vec = (L.D % 4 == 0) && (L.mu_off % 4 == 0);
   pf.rem = L.Kc - r0;
   if (vec) {
@@ -494,14 +494,14 @@ __device__ __forceinline__ void fetch_cols(TilePrefetch<NKC, NS, WV>& pf, const 
 
 // Row tiles of pair L (samples of layer l): z rows r0.. and their shifts Lam.
 template <int NKC, int NS, int WV>
-__device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS, WV>& pf, const LayerDev& L,
+__device__ __forceinline__ void fetch_rows(int tix, TilePrefetch<NKC, NS, WV>& pf, const LayerDev& L,
                                            const float* __restrict__ z,
                                            const float* __restrict__ lamrow, int r0,
                                            const float* __restrict__ ev = nullptr,
                                            const float* __restrict__ pl = nullptr,
                                            bool dzw = false) {
   constexpr int TPR = TilePrefetch<NKC, NS, WV>::TPR, NFT = TilePrefetch<NKC, NS, WV>::NFT;
-  const int t = threadIdx.x, sub = t % TPR;
+  const int t = tix, sub = t % TPR;
   const bool vec = (L.D % 4 == 0) && (L.z_off % 4 == 0);
   const int rr = r0 + (t & (32 * NS - 1));
   pf.rem = L.K - r0;
@@ -550,10 +550,10 @@ __device__ __forceinline__ void fetch_rows(TilePrefetch<NKC, NS, WV>& pf, const 
 // tile_store_part writes float4 column m of subtile sb and adds its terms to the
 // partials qa; tile_store_norm completes a subtile's norm; tile_store does it all.
 template <class TS, int NKC, bool Q, int WV>
-__device__ __forceinline__ void tile_store_part(TS& T, int b, const TilePrefetch<NKC, TS::NS, WV>& pf,
+__device__ __forceinline__ void tile_store_part(int tix, TS& T, int b, const TilePrefetch<NKC, TS::NS, WV>& pf,
                                                 bool scale, int sb, int m, double (&qa)[2]) {
   constexpr int TPR = TilePrefetch<NKC, TS::NS, WV>::TPR;
-  const int t = threadIdx.x, r = t / TPR, sub = t % TPR;
+  const int t = tix, r = t / TPR, sub = t % TPR;
   const int pr = tile_perm(r);
   // d < DT always (the row stride and the lam tables cover DT, so no thread
   // branches here); slots past the data are harmless (see TilePrefetch)
@@ -619,14 +619,14 @@ __device__ __forceinline__ double tile_store_norm(const double (&qa)[2]) {
 }
 
 template <class TS, int NKC, bool Q, int WV>
-__device__ __forceinline__ void tile_store(TS& T, int b, const TilePrefetch<NKC, TS::NS, WV>& pf,
+__device__ __forceinline__ void tile_store(int tix, TS& T, int b, const TilePrefetch<NKC, TS::NS, WV>& pf,
                                            bool scale, double (&q)[TS::NS]) {
   constexpr int NFT = TilePrefetch<NKC, TS::NS, WV>::NFT;
 #pragma unroll
   for (int sb = 0; sb < TS::NS; ++sb) {
     double qa[2] = {0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < NFT; ++m) tile_store_part<TS, NKC, Q, WV>(T, b, pf, scale, sb, m, qa);
+    for (int m = 0; m < NFT; ++m) tile_store_part<TS, NKC, Q, WV>(tix, T, b, pf, scale, sb, m, qa);
     if constexpr (Q) q[sb] = tile_store_norm<WV>(qa);
   }
 }
@@ -639,8 +639,8 @@ __device__ __forceinline__ float col_gamma(double q, double a, int j, int Kc, do
 
 // Fragment of staged row (lane % 32) of subtile sb for d chunk kc (d = 16 kc + 8 h + s).
 template <class TS, int PREC>
-__device__ __forceinline__ void tile_row_frag(const TS& T, int b, int sb, int kc, Frag<PREC>& f) {
-  const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+__device__ __forceinline__ void tile_row_frag(int tix, const TS& T, int b, int sb, int kc, Frag<PREC>& f) {
+  const int lane = tix & 63, r = lane & 31, h = lane >> 5;
   const int o = sb * TS::ROWN + r * TS::RS + kc * 16 + 8 * h;
   if constexpr (TS::BF) {
     f.hi = *reinterpret_cast<const bf16x8*>(&T.row[b][0][o]);
@@ -655,8 +655,8 @@ __device__ __forceinline__ void tile_row_frag(const TS& T, int b, int sb, int kc
 
 // Transposed fragment of subtile sb for d block q (lane -> d = 32 q + lane % 32).
 template <class TS, int PREC>
-__device__ __forceinline__ void tile_col_frag(const TS& T, int b, int sb, int q, TFrag<PREC>& f) {
-  const int lane = threadIdx.x & 63, h = lane >> 5;
+__device__ __forceinline__ void tile_col_frag(int tix, const TS& T, int b, int sb, int q, TFrag<PREC>& f) {
+  const int lane = tix & 63, h = lane >> 5;
   const int o = sb * TS::COLN + (32 * q + (lane & 31)) * TS::CS + 8 * h;
   if constexpr (TS::BF) {
 #pragma unroll
@@ -687,11 +687,11 @@ __device__ __forceinline__ bf16x4 lds_read_tr16(const __bf16* p) {
 // 16 t + 8 half + 4 (l / 32) + e, e = 0..3, of column d = 32 q + l % 32: for k-step t,
 // slots 4 half + e, the k order of an accumulator column (see TFrag).
 template <class TS, bool FROM_RAW = false>
-__device__ __forceinline__ void tile_rowT_frag(const TS& T, int b, int sb, int q,
+__device__ __forceinline__ void tile_rowT_frag(int tix, const TS& T, int b, int sb, int q,
                                                TFrag<TMC_BF16X3>& f) {
   const __bf16* hi = FROM_RAW ? &T.raw[b][0][0] : &T.row[b][0][0];
   const __bf16* lo = FROM_RAW ? &T.raw[b][1][0] : &T.row[b][1][0];
-  const int lane = threadIdx.x & 63;
+  const int lane = tix & 63;
   const int rb = 4 * (lane >> 5) + ((lane & 15) >> 2);
   const int cb = 32 * q + 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
 #pragma unroll
@@ -708,9 +708,9 @@ __device__ __forceinline__ void tile_rowT_frag(const TS& T, int b, int sb, int q
 // The wave's own 32 rows of a row-major [n][D] block as raw values: x[kc] holds
 // row (lane % 32), d = 16 kc + 8 (lane / 32) + s.  Rows past n read the last row.
 template <int NKC>
-__device__ __forceinline__ void wave_load(const float* __restrict__ base, int64_t off, int n, int D,
+__device__ __forceinline__ void wave_load(int tix, const float* __restrict__ base, int64_t off, int n, int D,
                                           int r0, float (&x)[NKC][8]) {
-  const int lane = threadIdx.x & 63, h = lane >> 5;
+  const int lane = tix & 63, h = lane >> 5;
   const int r = min(r0 + (lane & 31), n - 1);
   const float* row = base + off + (int64_t)r * D;
   if ((D % 4 == 0) && (off % 4 == 0)) {
@@ -759,7 +759,7 @@ template <int PREC, int NKC, bool GRAD, int NS>
 using FwdSmem = TileSmem<PREC, NKC, NS, kStages<PREC, NKC, NS>, GRAD && PREC != TMC_BF16X3>;
 
 template <int PREC, int NKC, bool GRAD, int NS, int WV>
-__device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const Item it,
+__device__ __forceinline__ void fwd_item(int tix, FwdSmem<PREC, NKC, GRAD, NS>& T, const Item it,
                                          const LayerDev& L, const FwdArgs& args) {
   using TS = FwdSmem<PREC, NKC, GRAD, NS>;
   constexpr int NB = TS::NB;
@@ -773,7 +773,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   double* __restrict__ wmax = args.wmax;
   float* __restrict__ rl = args.rl;
   float* __restrict__ ev = args.ev;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, ir = lane & 31;
+  const int tid = tix, w = tid >> 6, lane = tid & 63, h = lane >> 5, ir = lane & 31;
   const int i0 = it.start + 32 * w;
   const bool active = i0 < L.K;
   const int i = i0 + ir;
@@ -782,15 +782,15 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   // small inputs first, then the bulk operand loads; consuming the small ones waits
   // for them alone
   PairPre pre;
-  pair_preload(L, wmax, s, pre);
+  pair_preload(tix, L, wmax, s, pre);
   const float u_i = u[L.u_off + min(i, L.K - 1)];
   float xz[NKC][8];
-  wave_load<NKC>(z, L.z_off, L.K, L.D, i0, xz);
+  wave_load<NKC>(tix, z, L.z_off, L.K, L.D, i0, xz);
   TilePrefetch<NKC, NS, WV> pf;
-  fetch_cols(pf, L, mu, alpha, 0);
-  const double maxa = pair_maxa(L, wmax, pre);
-  const double cs = pair_const(L, pre);
-  tile_init(T, L, pre);
+  fetch_cols(tix, pf, L, mu, alpha, 0);
+  const double maxa = pair_maxa(tix, L, wmax, pre);
+  const double cs = pair_const(tix, L, pre);
+  tile_init(tix, T, L, pre);
   lds_barrier();
 
   // row operand a_i = log2(e) lam z_i as fragments, r_i = -1/2 sum_d lam_d z_id^2 (FP64)
@@ -817,7 +817,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
   // same norm and write the same gamma.  The norms are returned for the q store, which is
   // kept apart (a divergent store would split the block the stage is scheduled in).
   auto stage = [&](int b, int j0, double (&qs)[NS]) {
-    tile_store<TS, NKC, true, WV>(T, b, pf, false, qs);
+    tile_store<TS, NKC, true, WV>(tix, T, b, pf, false, qs);
 #pragma unroll
     for (int sb = 0; sb < NS; ++sb)
       T.gam[b][32 * sb + srow] = col_gamma(qs[sb], pf.a[sb], j0 + 32 * sb + srow, L.Kc, maxa, L.kappa);
@@ -847,7 +847,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
 #pragma unroll
       for (int sb = 0; sb < NS; ++sb) {
         Frag<PREC> Bf;
-        tile_row_frag<TS, PREC>(T, cur, sb, kc, Bf);
+        tile_row_frag<TS, PREC>(tix, T, cur, sb, kc, Bf);
         mma_chunk<PREC>(S[sb], Bf, A[kc]);     // S[j][i]
       }
   };
@@ -911,9 +911,9 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       for (int sb = 0; sb < NS; ++sb) {
         TFrag<PREC> Tf;
         if constexpr (PREC == TMC_BF16X3)
-          tile_rowT_frag<TS>(T, cur, sb, q, Tf);   // transpose reads of the row copy
+          tile_rowT_frag<TS>(tix, T, cur, sb, q, Tf);   // transpose reads of the row copy
         else
-          tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+          tile_col_frag<TS, PREC>(tix, T, cur, sb, q, Tf);
         mma_t<PREC>(O[q], Tf, P[sb]);
       }
   };
@@ -941,11 +941,11 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
 #pragma unroll
       for (int v = 0; v < 16; ++v) Sn[0][v] = 0.0f;
       Frag<PREC> B3[3];
-      tile_row_frag<TS, PREC>(T, nb, 0, 0, B3[0]);
-      tile_row_frag<TS, PREC>(T, nb, 0, 1, B3[1]);
+      tile_row_frag<TS, PREC>(tix, T, nb, 0, 0, B3[0]);
+      tile_row_frag<TS, PREC>(tix, T, nb, 0, 1, B3[1]);
 #pragma unroll
       for (int kc = 0; kc < NKC; ++kc) {
-        if (kc + 2 < NKC) tile_row_frag<TS, PREC>(T, nb, 0, kc + 2, B3[(kc + 2) % 3]);
+        if (kc + 2 < NKC) tile_row_frag<TS, PREC>(tix, T, nb, 0, kc + 2, B3[(kc + 2) % 3]);
         mma_chunk<PREC>(Sn[0], B3[kc % 3], A[kc]);
 #pragma unroll
         for (int e = 2 * kc; e < 2 * kc + 2; ++e) {
@@ -971,21 +971,21 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       const int j0 = 32 * (t + 2);
       double qa[2] = {0.0, 0.0};
       TFrag<PREC> T2[2];
-      tile_rowT_frag<TS>(T, cb, 0, 0, T2[0]);
+      tile_rowT_frag<TS>(tix, T, cb, 0, 0, T2[0]);
 #pragma unroll
       for (int q = 0; q < ND32; ++q) {
-        if (q + 1 < ND32) tile_rowT_frag<TS>(T, cb, 0, q + 1, T2[(q + 1) & 1]);
+        if (q + 1 < ND32) tile_rowT_frag<TS>(tix, T, cb, 0, q + 1, T2[(q + 1) & 1]);
         mma_t<PREC>(O[q], T2[q & 1], P[0]);
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
           if (k * ND32 / NA != q) continue;
           if (k < NFT) {
-            tile_store_part<TS, NKC, true, WV>(T, b, pf, false, 0, k, qa);
+            tile_store_part<TS, NKC, true, WV>(tix, T, b, pf, false, 0, k, qa);
           } else if (k == NFT) {
             qs[0] = tile_store_norm<WV>(qa);
             T.gam[b][srow] = col_gamma(qs[0], pf.a[0], j0 + srow, L.Kc, maxa, L.kappa);
           } else {
-            fetch_cols(pf, L, mu, alpha, 32 * (t + 3));
+            fetch_cols(tix, pf, L, mu, alpha, 32 * (t + 3));
           }
         }
       }
@@ -1006,14 +1006,14 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       stage(0, 0, qs);
       store_q(0, qs);
     }
-    fetch_cols(pf, L, mu, alpha, 32 * NS);
+    fetch_cols(tix, pf, L, mu, alpha, 32 * NS);
     lds_barrier();                                   // tile 0 visible
     {
       double qs[NS];
       stage(1, 32 * NS, qs);
       store_q(32 * NS, qs);
     }
-    fetch_cols(pf, L, mu, alpha, 64 * NS);
+    fetch_cols(tix, pf, L, mu, alpha, 64 * NS);
     f32x16 S[NS];
     s_gemm(0, S);
     lds_barrier();                                   // tile 1 visible
@@ -1037,7 +1037,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
         // phase B
         if (GRAD) o_gemm(cur, P);
         stage(stg, 32 * NS * (t + 2), qs);
-        fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 3));
+        fetch_cols(tix, pf, L, mu, alpha, 32 * NS * (t + 3));
         if (GRAD) interleave_phase_b<ND32 * NS * 2 * (PREC == TMC_BF16X3 ? 3 : 8)>();
       }
       store_q(32 * NS * (t + 2), qs);
@@ -1052,7 +1052,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
       stage(0, 0, qs);
       store_q(0, qs);
     }
-    if (nt > 1) fetch_cols(pf, L, mu, alpha, 32 * NS);
+    if (nt > 1) fetch_cols(tix, pf, L, mu, alpha, 32 * NS);
     lds_barrier();
     // One tile.  Double-buffered: the S MFMAs are issued first, and the next stage is
     // written to the idle buffer behind them (straight-line code, so the scheduler can
@@ -1067,11 +1067,11 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
           s_gemm(cur, S);
           stage(cur ^ 1, 32 * NS * (t + 1), qs);
           interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
-          if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
+          if (t + 2 < nt) fetch_cols(tix, pf, L, mu, alpha, 32 * NS * (t + 2));
           softmax_e(cur, S);
         } else {
           stage(cur ^ 1, 32 * NS * (t + 1), qs);
-          if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
+          if (t + 2 < nt) fetch_cols(tix, pf, L, mu, alpha, 32 * NS * (t + 2));
         }
         store_q(32 * NS * (t + 1), qs);
         lds_barrier();
@@ -1086,7 +1086,7 @@ __device__ __forceinline__ void fwd_item(FwdSmem<PREC, NKC, GRAD, NS>& T, const 
           double qs[NS];
           stage(0, 32 * NS * (t + 1), qs);
           store_q(32 * NS * (t + 1), qs);
-          if (t + 2 < nt) fetch_cols(pf, L, mu, alpha, 32 * NS * (t + 2));
+          if (t + 2 < nt) fetch_cols(tix, pf, L, mu, alpha, 32 * NS * (t + 2));
           lds_barrier();
         }
       }
@@ -1175,7 +1175,19 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 ? 1 : (NKC <= 8 ? 2 : 1))) void k
   __shared__ __align__(16) FwdSmem<PREC, NKC, GRAD, NS> T;
   const Item it = args.items[xcd_item(blockIdx.x, gridDim.x)];
   const LayerDev L = args.Ls[it.layer];
-  fwd_item<PREC, NKC, GRAD, NS, WV>(T, it, L, args);
+  fwd_item<PREC, NKC, GRAD, NS, WV>((int)threadIdx.x, T, it, L, args);
+}
+
+// The thread index of a 256-thread workgroup as a value the compiler cannot treat as
+// invariant: the persistent kernels take it afresh for every item, so the addressing the
+// sweep derives from it stays inside the item.  (With threadIdx.x itself it was hoisted out
+// of the chain and pair loops, held across the whole loop nest and spilled: hundreds of
+// VGPRs.)  The helpers of the sweep take the thread index as an argument for this reason.
+__device__ __forceinline__ int item_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  __builtin_assume(t >= 0 && t < 256);
+  return t;
 }
 
 // Persistent launch: each workgroup takes whole chains from the queue and runs their
@@ -1197,7 +1209,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_fwd_persist(F
     for (int l = ch.top - 1; l >= ch.first; --l) {
       const LayerDev L = args.Ls[l];
       for (int x = 0; x < L.K; x += kFusedRowsPerGroup) {
-        fwd_item<PREC, NKC, GRAD, NS, 4>(T, Item{l, x}, L, args);
+        fwd_item<PREC, NKC, GRAD, NS, 4>(item_tid(), T, Item{l, x}, L, args);
         __syncthreads();
       }
     }
@@ -1224,7 +1236,7 @@ template <int PREC, int NKC, int NS>
 using BwdSmem = TileSmem<PREC, NKC, NS, kStages<PREC, NKC, NS>, PREC != TMC_BF16X3>;
 
 template <int PREC, int NKC, int NS, int WV>
-__device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD, const Item it,
+__device__ __forceinline__ void bwd_item(int tix, BwdSmem<PREC, NKC, NS>& T, float* accD, const Item it,
                                          const LayerDev& L, const BwdArgs& args) {
   using TS = BwdSmem<PREC, NKC, NS>;
   constexpr int NB = TS::NB;
@@ -1242,7 +1254,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   float* __restrict__ dmu = args.dmu;
   float* __restrict__ du = args.du;
   float* __restrict__ dsp = args.dsp;
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, h = lane >> 5, jr = lane & 31;
+  const int tid = tix, w = tid >> 6, lane = tid & 63, h = lane >> 5, jr = lane & 31;
   const int jw = it.start + 32 * w;
   const bool active = jw < L.Kc;
   const int j = jw + jr;
@@ -1270,16 +1282,16 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   // prologue loads: the wave's own column operands (mu rows), their column terms and
   // the first row tile
   PairPre pre;
-  pair_preload(L, wmax, s, pre);
+  pair_preload(tix, L, wmax, s, pre);
   const double qj = qcol[L.q_off + jc];
   const double aj = alpha[L.alpha_up_off + jc];
   const double gl = dlogp[L.chain] * L.kappa;   // d/d(kappa log w) -> d/d(log w)
   float xm[NKC][8];
-  wave_load<NKC>(mu, L.mu_off, L.Kc, L.D, jw, xm);
+  wave_load<NKC>(tix, mu, L.mu_off, L.Kc, L.D, jw, xm);
   TilePrefetch<NKC, NS, WV> pf;
-  fetch_rows(pf, L, z, lamrow, 0, evp, p, own(0));
-  const double maxa = pair_maxa(L, wmax, pre);
-  tile_init(T, L, pre);
+  fetch_rows(tix, pf, L, z, lamrow, 0, evp, p, own(0));
+  const double maxa = pair_maxa(tix, L, wmax, pre);
+  tile_init(tix, T, L, pre);
   for (int d = tid; d < (WV / 4) * TS::DT; d += blockDim.x) accD[d] = 0.0f;
   lds_barrier();
 
@@ -1326,7 +1338,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
   };
   auto stage = [&](int b, bool fresh) {
     double qs[NS];
-    tile_store<TS, NKC, false, WV>(T, b, pf, true, qs);
+    tile_store<TS, NKC, false, WV>(tix, T, b, pf, true, qs);
     const int rr = tid & (32 * NS - 1);
     T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
     row_terms(fresh);
@@ -1349,7 +1361,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
 #pragma unroll
       for (int sb = 0; sb < NS; ++sb) {
         Frag<PREC> Af;
-        tile_row_frag<TS, PREC>(T, cur, sb, kc, Af);
+        tile_row_frag<TS, PREC>(tix, T, cur, sb, kc, Af);
         mma_chunk<PREC>(S[sb], Af, Bf[kc]);    // S[i][j]
       }
   };
@@ -1381,9 +1393,9 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       for (int sb = 0; sb < NS; ++sb) {
         TFrag<PREC> Tf;
         if constexpr (PREC == TMC_BF16X3)
-          tile_rowT_frag<TS>(T, cur, sb, q, Tf);   // (log2e lam z)^T: transpose reads
+          tile_rowT_frag<TS>(tix, T, cur, sb, q, Tf);   // (log2e lam z)^T: transpose reads
         else
-          tile_col_frag<TS, PREC>(T, cur, sb, q, Tf);
+          tile_col_frag<TS, PREC>(tix, T, cur, sb, q, Tf);
         mma_t<PREC>(GT[q], Tf, P[sb]);
       }
   };
@@ -1406,13 +1418,13 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
 #pragma unroll
       for (int v = 0; v < 16; ++v) Sn[0][v] = 0.0f;
       Frag<PREC> B3[3];
-      tile_row_frag<TS, PREC>(T, nb, 0, 0, B3[0]);
-      tile_row_frag<TS, PREC>(T, nb, 0, 1, B3[1]);
+      tile_row_frag<TS, PREC>(tix, T, nb, 0, 0, B3[0]);
+      tile_row_frag<TS, PREC>(tix, T, nb, 0, 1, B3[1]);
       float2 l2[2];
       l2[0] = *reinterpret_cast<const float2*>(&T.lamT[cb][4 * h]);
 #pragma unroll
       for (int kc = 0; kc < NKC; ++kc) {
-        if (kc + 2 < NKC) tile_row_frag<TS, PREC>(T, nb, 0, kc + 2, B3[(kc + 2) % 3]);
+        if (kc + 2 < NKC) tile_row_frag<TS, PREC>(tix, T, nb, 0, kc + 2, B3[(kc + 2) % 3]);
         if (kc + 1 < NKC)   // row shifts of entries 2 kc + 2, 2 kc + 3
           l2[(kc + 1) & 1] = *reinterpret_cast<const float2*>(
               &T.lamT[cb][8 * ((kc + 1) / 2) + 4 * h + 2 * ((kc + 1) % 2)]);
@@ -1439,22 +1451,22 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
       constexpr int NA = NFT + 2;   // staging parts: NFT columns, row shifts + row terms, fetch
       double qa[2] = {0.0, 0.0};
       TFrag<PREC> T2[2];
-      tile_rowT_frag<TS>(T, cb, 0, 0, T2[0]);
+      tile_rowT_frag<TS>(tix, T, cb, 0, 0, T2[0]);
 #pragma unroll
       for (int q = 0; q < ND32; ++q) {
-        if (q + 1 < ND32) tile_rowT_frag<TS>(T, cb, 0, q + 1, T2[(q + 1) & 1]);
+        if (q + 1 < ND32) tile_rowT_frag<TS>(tix, T, cb, 0, q + 1, T2[(q + 1) & 1]);
         mma_t<PREC>(GT[q], T2[q & 1], P[0]);
 #pragma unroll
         for (int k = 0; k < NA; ++k) {
           if (k * ND32 / NA != q) continue;
           if (k < NFT) {
-            tile_store_part<TS, NKC, false, WV>(T, b, pf, true, 0, k, qa);
+            tile_store_part<TS, NKC, false, WV>(tix, T, b, pf, true, 0, k, qa);
           } else if (k == NFT) {
             const int rr = tid & 31;
             T.lamT[b][rr] = (rr < pf.rem) ? pf.lam : INFINITY;
             row_terms(fresh);
           } else {
-            fetch_rows(pf, L, z, lamrow, r3, evp, p, fresh3);
+            fetch_rows(tix, pf, L, z, lamrow, r3, evp, p, fresh3);
           }
         }
       }
@@ -1468,10 +1480,10 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
     // the fetch of tile t+3 between them.  Columns past Kc compute on clamped columns
     // with gamma = -inf (zero marginals) and are discarded in the epilogue.
     stage(0, own(0));
-    fetch_rows(pf, L, z, lamrow, 32 * NS, evp, p, nt > 1 && own(1));
+    fetch_rows(tix, pf, L, z, lamrow, 32 * NS, evp, p, nt > 1 && own(1));
     lds_barrier();                                   // tile 0 visible
     stage(1, nt > 1 && own(1));
-    fetch_rows(pf, L, z, lamrow, 64 * NS, evp, p, nt > 2 && own(2));
+    fetch_rows(tix, pf, L, z, lamrow, 64 * NS, evp, p, nt > 2 && own(2));
     f32x16 S[NS];
     s_gemm(0, S);
     lds_barrier();                                   // tile 1 visible
@@ -1492,7 +1504,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
         // phase B
         gt_gemm(cur, P);
         stage(stg, t + 2 < nt && own(t + 2));
-        fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 3), evp, p, t + 3 < nt && own(t + 3));
+        fetch_rows(tix, pf, L, z, lamrow, 32 * NS * (t + 3), evp, p, t + 3 < nt && own(t + 3));
         interleave_phase_b<ND32 * NS * 2 * (PREC == TMC_BF16X3 ? 3 : 8)>();
       }
       lds_barrier();
@@ -1502,7 +1514,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
     }
   } else {
     stage(0, own(0));
-    if (nt > 1) fetch_rows(pf, L, z, lamrow, 32 * NS, evp, p, own(1));
+    if (nt > 1) fetch_rows(tix, pf, L, z, lamrow, 32 * NS, evp, p, own(1));
     lds_barrier();
     // One tile (see the forward: S MFMAs first, the next stage behind them).
     auto tile = [&](auto bc, int t) {
@@ -1513,11 +1525,11 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
           s_gemm(cur, S);
           stage(cur ^ 1, t + 1 < nt && own(t + 1));
           interleave_mfma<kGemmMfma<PREC, NKC> * NS>();
-          if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
+          if (t + 2 < nt) fetch_rows(tix, pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
           marg(cur, S);
         } else {
           stage(cur ^ 1, t + 1 < nt && own(t + 1));
-          if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
+          if (t + 2 < nt) fetch_rows(tix, pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
         }
         lds_barrier();
       } else {
@@ -1529,7 +1541,7 @@ __device__ __forceinline__ void bwd_item(BwdSmem<PREC, NKC, NS>& T, float* accD,
         lds_barrier();
         if (t + 1 < nt) {
           stage(0, own(t + 1));
-          if (t + 2 < nt) fetch_rows(pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
+          if (t + 2 < nt) fetch_rows(tix, pf, L, z, lamrow, 32 * NS * (t + 2), evp, p, own(t + 2));
           lds_barrier();
         }
       }
@@ -1697,7 +1709,7 @@ __global__ __launch_bounds__(64 * WV, (WV == 8 ? 1 : (NKC <= 8 ? 2 : 1))) void k
   __shared__ float accD[(WV / 4) * BwdSmem<PREC, NKC, NS>::DT];
   const Item it = args.items[xcd_item(blockIdx.x, gridDim.x)];
   const LayerDev L = args.Ls[it.layer];
-  bwd_item<PREC, NKC, NS, WV>(T, accD, it, L, args);
+  bwd_item<PREC, NKC, NS, WV>((int)threadIdx.x, T, accD, it, L, args);
 }
 
 // Persistent backward: each workgroup takes whole chains and runs their pairs
@@ -1719,7 +1731,7 @@ __global__ __launch_bounds__(256, (NKC <= 8 ? 2 : 1)) void k_fused_bwd_persist(B
     for (int l = ch.first; l < ch.top; ++l) {
       const LayerDev L = args.Ls[l];
       for (int x = 0; x < L.Kc; x += kFusedBwdColsDev) {
-        bwd_item<PREC, NKC, NS, 4>(T, accD, Item{l, x}, L, args);
+        bwd_item<PREC, NKC, NS, 4>(item_tid(), T, accD, Item{l, x}, L, args);
         __syncthreads();
       }
     }
