@@ -218,6 +218,36 @@ def test_wide_workgroups_bitwise_equal_narrow(prec, tmp_path, monkeypatch):
     _check(outs[(1, 1)], chains, prec)
 
 
+def test_forward_only_launch_shapes_bitwise_equal(tmp_path, monkeypatch):
+    """Forward without gradients (TMC_FLAG_FORWARD_ONLY) in BF16X3, every launch shape forced
+    through the tuning cache -- 4 or 8 waves, one or two staged subtiles -- on widths
+    d = 97..128 with row counts on and off the 256 boundary: log P bitwise equal between 4
+    and 8 waves with one subtile per stage (one summation order), and every shape within
+    the BF16X3 bound of the oracle (two subtiles per stage merge the online log-sum-exp in
+    another order)."""
+    from paper_1806_08593_amd import tmc as T
+    rng = np.random.default_rng(131)
+    shapes = [((300, 256, 257), (100, 112, 128)), ((257, 300), (128, 97)),
+              ((256, 64, 256), (104, 100, 120)), ((129, 520), (128, 100)),
+              ((64, 600), (128, 64))]
+    chains = cast_chains([_rand_chain(rng, Ks, Ds) for Ks, Ds in shapes], "fp32")
+    sig = _shape_signature(shapes, "bf16x3", flags=T.TMC_FLAG_FORWARD_ONLY)
+    outs = {}
+    for wf in (0, 1):
+        for ns in (1, 2):
+            cache = tmp_path / f"tune_fo_{wf}{ns}.txt"
+            cache.write_text(f"{sig} 0 1 {ns} {wf} 0\n")
+            monkeypatch.setenv("TMC_TUNE_CACHE", str(cache))
+            out = run_gauss(chains, "bf16x3", engine="fused", flags=T.TMC_FLAG_FORWARD_ONLY, bwd=False)
+            assert out["info"]["tuned"] == 1, "cache line not matched"
+            outs[(wf, ns)] = out["logp"]
+    assert np.array_equal(outs[(1, 1)], outs[(0, 1)])
+    refs = [O.gauss_chain_logp(c.z, c.mu, c.s, c.u) for c in chains]
+    for key, lps in outs.items():
+        for lp, ref in zip(lps, refs):
+            assert abs(lp - ref) < 2e-3, (key, lp, ref)
+
+
 def test_ragged_autograd_wrapper():
     """torch.autograd over a ragged batch: the weighted sum of log P differentiates to the
     weighted oracle gradients of every chain (weights 1..n through dlogp)."""
