@@ -1018,7 +1018,7 @@ __device__ __forceinline__ void fwd_item(int tix, FwdSmem<PREC, NKC, GRAD, NS>& 
     s_gemm(0, S);
     lds_barrier();                                   // tile 1 visible
     int cur = 0;
-    for (int t = 0; t < nt; ++t) {
+    for (int t = 0; t + 1 < nt; ++t) {
       const int nxt = cur == 2 ? 0 : cur + 1;
       const int stg = nxt == 2 ? 0 : nxt + 1;
       float x[NS][16];
@@ -1046,6 +1046,8 @@ __device__ __forceinline__ void fwd_item(int tix, FwdSmem<PREC, NKC, GRAD, NS>& 
       for (int sb = 0; sb < NS; ++sb) S[sb] = Sn[sb];
       cur = nxt;
     }
+    // the last tile: no next tile to multiply, stage or fetch
+    softmax_e(cur, S);
   } else {
     {
       double qs[NS];
@@ -1488,7 +1490,7 @@ __device__ __forceinline__ void bwd_item(int tix, BwdSmem<PREC, NKC, NS>& T, flo
     s_gemm(0, S);
     lds_barrier();                                   // tile 1 visible
     int cur = 0;
-    for (int t = 0; t < nt; ++t) {
+    for (int t = 0; t + 1 < nt; ++t) {
       const int nxt = cur == 2 ? 0 : cur + 1;
       const int stg = nxt == 2 ? 0 : nxt + 1;
       f32x16 Sn[NS];
@@ -1512,6 +1514,8 @@ __device__ __forceinline__ void bwd_item(int tix, BwdSmem<PREC, NKC, NS>& T, flo
       for (int sb = 0; sb < NS; ++sb) S[sb] = Sn[sb];
       cur = nxt;
     }
+    // the last tile: no next tile to multiply, stage or fetch
+    marg(cur, S);
   } else {
     stage(0, own(0));
     if (nt > 1) fetch_rows(tix, pf, L, z, lamrow, 32 * NS, evp, p, own(1));
