@@ -66,10 +66,12 @@ tmc_status fused_build(FusedPlan& F, int prec, int flags, std::vector<LayerDev>&
         const int L = chains[d.chain].L;
         const bool in_step = dir == 0 ? d.depth == L - 2 - t : d.depth == t;
         if (!in_step) continue;
-        // 8 waves (256 rows / columns per workgroup) for wide layers of gradient plans
+        // 8 waves (256 rows / columns per workgroup) for wide layers of gradient plans;
+        // 4-wave gradient sweeps of the narrow buckets share one launch per step
         const int nkc = nkc_bucket(d.D), n = dir == 0 ? d.K : d.Kc;
         const int waves = (wide && grad && fused_wide_ok(nkc) && n >= kFusedWideMin) ? 8 : 4;
-        groups[{nkc, waves}].push_back(l);
+        const bool multi = grad && waves == 4 && nkc <= kFusedMultiMax;
+        groups[{multi ? kFusedMulti : nkc, waves}].push_back(l);
       }
       for (auto& kv : groups) {
         FusedLaunch fl;
@@ -171,6 +173,8 @@ int fused_capacity(int dir, int nkc, bool grad, int ns) {
 template <int PREC>
 hipError_t launch_fused_fwd(int nkc, int waves, bool grad, int ns, const FusedFwdPtrs& a,
                             const Item* items, int n, const FusedQueue* q, hipStream_t st) {
+  if (nkc == kFusedMulti)
+    return (grad && waves == 4 && !q) ? launch_fused_fwd_multi<PREC>(a, items, n, st) : hipErrorInvalidValue;
 #define TMC_CALL(N) launch_fused_fwd_n<PREC, N>(waves, grad, ns, a, items, n, q, st)
   TMC_NKC_SWITCH(nkc, TMC_CALL)
 #undef TMC_CALL
@@ -180,6 +184,8 @@ hipError_t launch_fused_fwd(int nkc, int waves, bool grad, int ns, const FusedFw
 template <int PREC>
 hipError_t launch_fused_bwd(int nkc, int waves, const FusedBwdPtrs& a, const Item* items, int n,
                             const FusedQueue* q, hipStream_t st) {
+  if (nkc == kFusedMulti)
+    return (waves == 4 && !q) ? launch_fused_bwd_multi<PREC>(a, items, n, st) : hipErrorInvalidValue;
 #define TMC_CALL(N) launch_fused_bwd_n<PREC, N>(waves, a, items, n, q, st)
   TMC_NKC_SWITCH(nkc, TMC_CALL)
 #undef TMC_CALL

@@ -21,6 +21,12 @@ struct FusedLaunch {
   int off = 0, n = 0, nkc = 0, waves = 4;
 };
 
+// A gradient launch of 4-wave workgroups that mixes the chunk buckets 1..kFusedMultiMax
+// of one depth step (each workgroup runs its item's bucket; k_fused_multi.hip) has this
+// chunk count in its FusedLaunch.
+constexpr int kFusedMulti = 0;
+constexpr int kFusedMultiMax = 4;
+
 // Chunk counts with an 8-wave kernel (256 rows or columns per workgroup, one workgroup
 // per compute unit): the widest ones with a double-buffered stage (d 97..128), whose
 // 4-wave kernels already run at two waves per SIMD, so the wider workgroup costs no
@@ -119,6 +125,11 @@ hipError_t launch_fused_fwd_n(int waves, bool grad, int ns, const FusedFwdPtrs& 
 template <int PREC, int NKC>
 hipError_t launch_fused_bwd_n(int waves, const FusedBwdPtrs& a, const Item* items, int n,
                               const FusedQueue* q, hipStream_t st);
+// the mixed-bucket gradient launches (k_fused_multi.hip)
+template <int PREC>
+hipError_t launch_fused_fwd_multi(const FusedFwdPtrs& a, const Item* items, int n, hipStream_t st);
+template <int PREC>
+hipError_t launch_fused_bwd_multi(const FusedBwdPtrs& a, const Item* items, int n, hipStream_t st);
 // dispatch over the runtime chunk count (fused.cpp)
 template <int PREC>
 int fused_capacity(int dir, int nkc, bool grad, int ns);
