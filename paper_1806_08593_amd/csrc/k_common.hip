@@ -86,40 +86,43 @@ __global__ __launch_bounds__(256) void k_bwd_init(const ChainDev* __restrict__ c
 
 // ds[s block] = sum of the partial rows that belong to the block, in a fixed order:
 // part_off[slot_start[sl] .. slot_start[sl+1]) are element offsets of [D] partial
-// rows in dsp.  Workgroup = (slot, 16 d): 64 groups of 16 threads split the parts
-// (group g takes parts g, g + 64, ..), then the 64 group sums are combined in LDS in
-// two fixed-order steps (8 x 8).
+// rows in dsp.  Workgroup = (slot, 16 d), 256 threads: 16 groups of 16 threads split the
+// parts (group g takes parts g, g + 16, ..), then the 16 group sums are combined in LDS
+// in two fixed-order steps (4 x 4).  Most slots of a ragged batch hold a few parts, so
+// the workgroup is small (many resident at once) and one whose 16 d lie past the slot's
+// width ends at once.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_ds_reduce(const int64_t* __restrict__ part_off,
-                                                   const int* __restrict__ slot_start,
-                                                   const int64_t* __restrict__ slot_soff,
-                                                   const int* __restrict__ slot_D,
-                                                   const T* __restrict__ dsp, T* __restrict__ ds) {
-  __shared__ double red[64][16];
-  __shared__ double red2[8][16];
+__global__ __launch_bounds__(256) void k_ds_reduce(const int64_t* __restrict__ part_off,
+                                                  const int* __restrict__ slot_start,
+                                                  const int64_t* __restrict__ slot_soff,
+                                                  const int* __restrict__ slot_D,
+                                                  const T* __restrict__ dsp, T* __restrict__ ds) {
+  __shared__ double red[16][16];
+  __shared__ double red2[4][16];
   const int sl = blockIdx.x;
-  const int b = slot_start[sl], e = slot_start[sl + 1];
   const int D = slot_D[sl];
+  if (blockIdx.y * 16 >= D) return;   // (uniform)
+  const int b = slot_start[sl], e = slot_start[sl + 1];
   const int dl = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int d = blockIdx.y * 16 + dl;
   double acc = 0.0;
   if (d < D) {
-#pragma unroll 8
-    for (int q = b + g; q < e; q += 64) acc += (double)dsp[part_off[q] + d];
+#pragma unroll 4
+    for (int q = b + g; q < e; q += 16) acc += (double)dsp[part_off[q] + d];
   }
   red[g][dl] = acc;
   __syncthreads();
-  if (g < 8) {
+  if (g < 4) {
     double t = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) t += red[8 * g + k][dl];
+    for (int k = 0; k < 4; ++k) t += red[4 * g + k][dl];
     red2[g][dl] = t;
   }
   __syncthreads();
   if (g == 0 && d < D) {
     double t = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) t += red2[k][dl];
+    for (int k = 0; k < 4; ++k) t += red2[k][dl];
     ds[slot_soff[sl] + d] = (T)t;
   }
 }
@@ -157,7 +160,7 @@ hipError_t launch_ds_reduce(const int64_t* part_off, const int* slot_start, cons
                             const int* slot_D, int n_slots, int max_D, const T* dsp, T* ds,
                             hipStream_t st) {
   if (n_slots <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ds_reduce<T>, dim3(n_slots, (max_D + 15) / 16), dim3(1024), 0, st, part_off,
+  hipLaunchKernelGGL(k_ds_reduce<T>, dim3(n_slots, (max_D + 15) / 16), dim3(256), 0, st, part_off,
                      slot_start, slot_soff, slot_D, dsp, ds);
   return hipGetLastError();
 }
