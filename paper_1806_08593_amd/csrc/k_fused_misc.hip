@@ -86,7 +86,9 @@ __global__ __launch_bounds__(256) void k_fused_bwd_init(const ChainDev* __restri
 }
 
 // Row part of the backward of one pair, 64 rows of layer l per workgroup, with e_i the
-// softmax-weighted mean of mu left by the forward and p the marginals:
+// softmax-weighted mean of mu left by the forward and p the marginals (cw lanes of 4
+// columns per row, cw the smallest power of two from 4 to 32 with 4 cw >= D, so narrow
+// layers keep every lane busy; 256 / cw rows at a time):
 //   dz_i = -dlogp * lam * p_i (z_i - e_i)
 //   ds row part = dlogp * (lam_d * sum_i p_i z_id^2 - sum_i p_i)
 // (the partial row follows the pair's column parts; fixed summation order).
@@ -99,12 +101,15 @@ __global__ __launch_bounds__(256) void k_fused_dz(const LayerDev* __restrict__ L
                                                   const double* __restrict__ dlogp,
                                                   float* __restrict__ dz, float* __restrict__ dsp) {
   __shared__ float lam[kFusedMaxD];
-  __shared__ float4 red[8][32];
+  __shared__ float4 red[256];
   __shared__ float redp[kMaxWaves];
   const Item it = items[blockIdx.x];
   const LayerDev& L = Ls[it.layer];
   const int D = L.D, K = L.K, r0 = it.start;
-  const int tid = threadIdx.x, c4 = tid & 31, rg = tid >> 5;
+  int cw = 4;
+  while (cw < 32 && 4 * cw < D) cw *= 2;
+  const int tid = threadIdx.x, c4 = tid & (cw - 1), rg = tid / cw;
+  const int nrg = 256 / cw, nrr = kFusedDzRows / nrg;
   for (int d = tid; d < D; d += blockDim.x) lam[d] = expf(-2.0f * s[L.s_off + d]);
   const float* pr = p + L.p_off;
   const float g = (float)(dlogp[L.chain] * L.kappa);
@@ -114,13 +119,12 @@ __global__ __launch_bounds__(256) void k_fused_dz(const LayerDev* __restrict__ L
   const bool vec = (D % 4 == 0) && (L.z_off % 4 == 0) && (L.ev_off % 4 == 0);
   const int ncol = (L.Kc + kFusedBwdCols - 1) / kFusedBwdCols;
   float* part = dsp ? dsp + L.dsp_off + (int64_t)(ncol + r0 / kFusedDzRows) * D : nullptr;
-  for (int d0 = 0; d0 < D; d0 += 128) {
+  for (int d0 = 0; d0 < D; d0 += 4 * cw) {
     const int d = d0 + 4 * c4;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (d < D) {
-#pragma unroll
-      for (int rr = 0; rr < kFusedDzRows / 8; ++rr) {
-        const int i = r0 + rg + 8 * rr;
+      for (int rr = 0; rr < nrr; ++rr) {
+        const int i = r0 + rg + nrg * rr;
         if (i < K) {
           const float pi = pr[i];
           const int64_t o = (int64_t)i * D + d;
@@ -159,12 +163,13 @@ __global__ __launch_bounds__(256) void k_fused_dz(const LayerDev* __restrict__ L
         }
       }
     }
-    red[rg][c4] = acc;
+    red[rg * cw + c4] = acc;
     __syncthreads();
     if (rg == 0 && d < D && part) {
-      float4 t = red[0][c4];
-      for (int q = 1; q < 8; ++q) {
-        t.x += red[q][c4].x; t.y += red[q][c4].y; t.z += red[q][c4].z; t.w += red[q][c4].w;
+      float4 t = red[c4];
+      for (int q = 1; q < nrg; ++q) {
+        const float4 u = red[q * cw + c4];
+        t.x += u.x; t.y += u.y; t.z += u.z; t.w += u.w;
       }
       const float tv[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll

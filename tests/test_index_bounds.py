@@ -285,15 +285,20 @@ def fused_bwd_item(B, L, start, wv, prec, rows):
 
 def fused_dz_item(B, L, r0):
     tid = np.arange(256)
-    c4, rg = tid & 31, tid >> 5
     D, K = L["D"], L["K"]
+    cw = 4
+    while cw < 32 and 4 * cw < D:
+        cw *= 2
+    c4, rg = tid & (cw - 1), tid // cw
+    nrg = 256 // cw
+    assert 64 % nrg == 0
     B.check("s", L["s_off"] + np.arange(D))
     B.check("p", L["alpha_off"] + r0 + tid, mask=(tid < 64) & (r0 + tid < K))
     vec = D % 4 == 0 and L["z_off"] % 4 == 0 and L["ev_off"] % 4 == 0
-    for d0 in range(0, D, 128):
+    for d0 in range(0, D, 4 * cw):
         d = d0 + 4 * c4
-        for rr in range(8):
-            i = r0 + rg + 8 * rr
+        for rr in range(64 // nrg):
+            i = r0 + rg + nrg * rr
             ok = (d < D) & (i < K)
             B.check("p", L["alpha_off"] + i, mask=ok)
             o = i * D + d
